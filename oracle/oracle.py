@@ -1,0 +1,156 @@
+"""ctypes binding of the FP64 oracle (``quadswarm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  Nothing here is imported by the GPU
+library, and this file imports nothing from it.
+
+All arrays cross as float64 (state, params, actions, goals), uint64
+(contact masks) and uint32 (event bits); the caller's arrays are not
+modified except ``state``, which ``step`` returns updated as a new array.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "quadswarm_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+EV_WALL, EV_FLOOR_HIT, EV_FRICTION, EV_TAKEOFF, EV_PAIR_RESPONSE, EV_CONTACT = 1, 2, 4, 8, 16, 32
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (IEEE double, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+            "-Wno-unused-parameter", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("n_envs", C.c_int32), ("env_offsets", C.POINTER(C.c_int32)),
+        ("dt", C.c_double), ("gravity", C.c_double), ("arm_length", C.c_double),
+        ("k_tau", C.c_double), ("drag_coef", C.c_double), ("floor_mu", C.c_double),
+        ("motor_noise_decay", C.c_double), ("motor_noise_std", C.c_double),
+        ("room_min", C.c_double * 3), ("room_max", C.c_double * 3),
+        ("wall_restitution", C.c_double),
+        ("col_dist", C.c_double), ("col_decay", C.c_double),
+        ("col_noise_v", C.c_double), ("col_noise_w", C.c_double),
+        ("k_neighbors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _lib.or_step.restype = C.c_int
+        _lib.or_observe.restype = C.c_int
+        _lib.or_uniform_from_u32.restype = C.c_double
+        _lib.or_uniform_from_u32.argtypes = [C.c_uint32]
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class Oracle:
+    """FP64 stepper over one set of environments.
+
+    ``consts`` holds the global constants (dt, gravity, arm_length, k_tau,
+    drag_coef, floor_mu, motor_noise_decay, motor_noise_std, room_min,
+    room_max, wall_restitution, col_dist, col_decay, col_noise_v,
+    col_noise_w); ``params`` is [Q][6] (mass, ixx, iyy, izz,
+    thrust_to_weight, motor_tau).
+    """
+
+    def __init__(self, env_offsets, consts: dict, params, k_neighbors: int,
+                 flags: int, seed: int):
+        self.offs = np.ascontiguousarray(env_offsets, dtype=np.int32)
+        self.params = np.ascontiguousarray(params, dtype=np.float64)
+        self.Q = int(self.offs[-1])
+        self.K = int(k_neighbors)
+        d = _Desc()
+        d.n_envs = self.offs.shape[0] - 1
+        d.env_offsets = _p(self.offs, C.c_int32)
+        for k in ("dt", "gravity", "arm_length", "k_tau", "drag_coef", "floor_mu",
+                  "motor_noise_decay", "motor_noise_std", "wall_restitution",
+                  "col_dist", "col_decay", "col_noise_v", "col_noise_w"):
+            setattr(d, k, float(consts[k]))
+        d.room_min = (C.c_double * 3)(*[float(v) for v in consts["room_min"]])
+        d.room_max = (C.c_double * 3)(*[float(v) for v in consts["room_max"]])
+        d.k_neighbors = self.K
+        d.flags = int(flags)
+        d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        self.desc = d
+
+    @classmethod
+    def from_workload(cls, w) -> "Oracle":
+        return cls(w.env_offsets, w.consts, w.params.astype(np.float64),
+                   w.k_neighbors, w.flags, w.rng_key)
+
+    def step(self, state, actions, n_sub: int = 1, t0: int = 0):
+        """Returns (new_state [Q][27] f64, contacts [Q] u64, events [Q] u32)."""
+        s = np.array(state, dtype=np.float64, order="C", copy=True)
+        a = np.ascontiguousarray(actions, dtype=np.float64)
+        assert s.shape == (self.Q, 27) and a.shape == (self.Q, 4)
+        contacts = np.zeros(self.Q, dtype=np.uint64)
+        events = np.zeros(self.Q, dtype=np.uint32)
+        rc = lib().or_step(C.byref(self.desc), _p(self.params, C.c_double),
+                           _p(s, C.c_double), _p(a, C.c_double), C.c_int(n_sub),
+                           C.c_uint64(t0), _p(contacts, C.c_uint64),
+                           _p(events, C.c_uint32))
+        if rc != 0:
+            raise ValueError("or_step rejected its arguments")
+        return s, contacts, events
+
+    def observe(self, state, goals):
+        """Returns (obs [Q][18+6K] f64, neighbour local indices [Q][K] i32)."""
+        s = np.ascontiguousarray(state, dtype=np.float64)
+        g = np.ascontiguousarray(goals, dtype=np.float64)
+        obs = np.zeros((self.Q, 18 + 6 * self.K))
+        nbr = np.full((self.Q, max(self.K, 1)), -1, dtype=np.int32)
+        rc = lib().or_observe(C.byref(self.desc), _p(s, C.c_double),
+                              _p(g, C.c_double), _p(obs, C.c_double),
+                              _p(nbr, C.c_int32))
+        if rc != 0:
+            raise ValueError("or_observe rejected its arguments")
+        return obs, nbr[:, :self.K]
+
+
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def normal4(seed: int, quad: int, t: int, stream: int, draw: int):
+    z = (C.c_double * 4)()
+    lib().or_normal4(C.c_uint64(seed), C.c_uint32(quad), C.c_uint64(t),
+                     C.c_uint32(stream), C.c_uint32(draw), z)
+    return np.array(list(z))
+
+
+def uniform_from_u32(r: int) -> float:
+    return float(lib().or_uniform_from_u32(C.c_uint32(r)))
+
+
+def flag_values():
+    o = (C.c_uint32 * 6)()
+    lib().or_flag_values(o)
+    return [int(v) for v in o]

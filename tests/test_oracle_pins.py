@@ -1,0 +1,568 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here checks the oracle against something other than itself: a
+closed form derived by hand from the paper's equations, a conservation law,
+a brute-force recomputation, or published test vectors.  Each is chosen so
+that a plausible slip in the oracle (a dropped term, a wrong sign or index, a
+transposed operand, a world/body frame mix-up) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import oracle as O
+from paper_2306_09537_amd import workloads as W
+from tests.helpers import blank_state, consts, nominal_params, rot_x, rot_y, rot_z
+
+G = 9.81
+DT = 0.005
+M = W.NOMINAL["mass"]
+ARM_D = 0.046 / math.sqrt(2.0)
+K_TAU = 0.006
+
+
+def make(q, flags=0, k=0, env_sizes=None, params=None, seed=7, **c):
+    sizes = env_sizes if env_sizes is not None else [1] * q
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    p = params if params is not None else nominal_params(int(offs[-1]))
+    return O.Oracle(offs, consts(**c), p, k, flags, seed)
+
+
+def run(orc, s, a, n, t0=0):
+    traj = [s]
+    for i in range(n):
+        s, _, _ = orc.step(s, a, 1, t0 + i)
+        traj.append(s)
+    return traj
+
+
+# --------------------------------------------------------------------------- RNG
+def test_philox_known_answers():
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert O.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_uniform_map_open_interval():
+    assert O.uniform_from_u32(0) == 2.0 ** -24
+    assert O.uniform_from_u32(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+    assert O.uniform_from_u32(0x80000000) == 0.5 + 2.0 ** -24
+    # every value is an odd multiple of 2^-24 (exact in float32 as well)
+    for r in (1, 511, 512, 12345678, 0xDEADBEEF):
+        u = O.uniform_from_u32(r)
+        k = u * 2 ** 24
+        assert k == int(k) and int(k) % 2 == 1
+
+
+def test_box_muller_is_standard_normal():
+    z = np.concatenate([O.normal4(1234, q, t, 0, 0) for q in range(200) for t in range(150)])
+    assert z.size == 120000
+    se = 1.0 / math.sqrt(z.size)
+    assert abs(z.mean()) < 4 * se
+    assert abs(z.var() - 1.0) < 4 * math.sqrt(2.0) * se
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # independent streams and draws differ
+    a = O.normal4(1, 3, 5, 0, 0)
+    assert not np.allclose(a, O.normal4(1, 3, 5, 1, 0))
+    assert not np.allclose(a, O.normal4(1, 3, 5, 0, 1))
+    assert not np.allclose(a, O.normal4(2, 3, 5, 0, 0))
+
+
+# ------------------------------------------------------------- motors and mix
+@pytest.mark.parametrize("unit", [False, True])
+def test_hover_equilibrium(unit):
+    """Each rotor at m g / 4 gives zero net acceleration (spec pin)."""
+    q = 3
+    s = blank_state(q)
+    s[:, W.SU:W.SU + 4] = math.sqrt(0.5)  # hover command at thrust-to-weight 2
+    a = np.full((q, 4), 0.5 if unit else 0.0)
+    orc = make(q, flags=W.QS_ACT_UNIT if unit else 0)
+    out = run(orc, s, a, 50)[-1]
+    np.testing.assert_allclose(out[:, 0:3], s[:, 0:3], atol=1e-12)
+    np.testing.assert_allclose(out[:, W.SV:W.SV + 3], 0.0, atol=1e-12)
+    np.testing.assert_allclose(out[:, W.SW:W.SW + 3], 0.0, atol=1e-12)
+
+
+def test_tilted_thrust_direction():
+    """Thrust acts along the body z axis, i.e. the third column of R: one step
+    at hover thrust from a tilted attitude gives v = dt g (R e_z - e_z)."""
+    Rt = rot_z(0.3) @ rot_x(0.4) @ rot_y(-0.25)
+    s = blank_state(1)
+    s[:, W.SR:W.SR + 9] = Rt.reshape(9)
+    s[:, W.SU:W.SU + 4] = math.sqrt(0.5)
+    out, _, _ = make(1).step(s, np.zeros((1, 4)), 1, 0)
+    np.testing.assert_allclose(out[0, W.SV:W.SV + 3], DT * G * (Rt[:, 2] - [0, 0, 1]), atol=1e-14)
+
+
+def test_motor_lag_closed_form_and_settling():
+    """u_n = uhat + (u0 - uhat)(1 - alpha)^n with alpha = 1 - exp(-dt/tau);
+    the 2 % band is first reached after 12 substeps for tau = 15 ms."""
+    q = 1
+    s = blank_state(q)
+    s[:, W.SU:W.SU + 4] = 0.0
+    a = np.full((q, 4), 1.0)  # uhat = 1
+    traj = run(make(q), s, a, 40)
+    alpha = 1.0 - math.exp(-DT / 0.015)
+    for n, st in enumerate(traj):
+        np.testing.assert_allclose(st[0, W.SU:W.SU + 4], 1.0 - (1.0 - alpha) ** n, rtol=0, atol=1e-14)
+    inside = [n for n, st in enumerate(traj) if abs(st[0, W.SU] - 1.0) <= 0.02]
+    assert inside[0] == math.ceil(math.log(0.02) / math.log(1.0 - alpha)) == 12
+
+
+def test_motor_noise_ar1_statistics():
+    """eps_t = a_nd eps_{t-1} + a_ns N(0,1): stationary std sigma f_max and
+    lag-1 autocorrelation a_nd."""
+    q, n, burn = 2048, 120, 40
+    s = blank_state(q, z=5.0)
+    s[:, W.SU:W.SU + 4] = math.sqrt(0.5)
+    orc = make(q, flags=W.QS_MOTOR_NOISE)
+    traj = run(orc, s, np.zeros((q, 4)), n)
+    eps = np.stack([t[:, W.SE:W.SE + 4] for t in traj[burn:]])  # [T][Q][4]
+    f_max = 0.25 * M * G * 2.0
+    sd = 0.05 * f_max
+    x = eps.reshape(-1)
+    assert abs(x.mean()) < 5 * sd / math.sqrt(x.size / 10)
+    assert abs(x.std() / sd - 1.0) < 0.02
+    a0, a1 = eps[:-1].reshape(-1), eps[1:].reshape(-1)
+    rho = np.corrcoef(a0, a1)[0, 1]
+    assert abs(rho - 0.9) < 0.01
+    # the first step from eps = 0 is exactly a_ns * z with the documented counter
+    s1, _, _ = orc.step(s, np.zeros((q, 4)), 1, 0)
+    a_ns = 0.05 * f_max * math.sqrt(1 - 0.81)
+    for qq in (0, 17, 2047):
+        np.testing.assert_allclose(s1[qq, W.SE:W.SE + 4], a_ns * O.normal4(7, qq, 0, 0, 0), rtol=1e-15)
+
+
+def test_equal_thrusts_give_zero_torque_exactly():
+    q = 4
+    rng = np.random.default_rng(0)
+    s = blank_state(q)
+    for i in range(q):
+        s[i, W.SR:W.SR + 9] = (rot_z(rng.uniform(0, 6)) @ rot_x(rng.uniform(-1, 1))).reshape(9)
+    s[:, W.SU:W.SU + 4] = rng.uniform(0.2, 0.9, size=(q, 1))
+    a = np.repeat(rng.uniform(-1, 1, size=(q, 1)), 4, axis=1)
+    out, _, _ = make(q).step(s, a, 1, 0)
+    assert np.all(out[:, W.SW:W.SW + 3] == 0.0)
+
+
+@pytest.mark.parametrize("rotor", [0, 1, 2, 3])
+def test_single_rotor_torque(rotor):
+    """Thrust on rotor i alone: tau = r_i x (f e_z) + k_tau s_i f e_z, with the
+    X layout FR, BR, BL, FL in a forward-left-up body frame."""
+    pos = ARM_D * np.array([[1, -1, 0], [-1, -1, 0], [-1, 1, 0], [1, 1, 0]], dtype=float)
+    spin = [1, -1, 1, -1]
+    J = np.array([1.5e-5, 1.8e-5, 2.9e-5])
+    p = nominal_params(1, ixx=J[0], iyy=J[1], izz=J[2])
+    s = blank_state(1)
+    s[0, W.SU:W.SU + 4] = 0.0
+    s[0, W.SU + rotor] = 1.0
+    a = -np.ones((1, 4))
+    a[0, rotor] = 1.0
+    out, _, _ = make(1, params=p).step(s, a, 1, 0)
+    f = 0.25 * M * G * 2.0
+    tau = np.cross(pos[rotor], [0, 0, f]) + np.array([0, 0, K_TAU * spin[rotor] * f])
+    np.testing.assert_allclose(out[0, W.SW:W.SW + 3], DT * tau / J, rtol=1e-13, atol=1e-15)
+
+
+# ------------------------------------------------------------ translation
+def test_free_fall_discrete_closed_form():
+    q = 2
+    s = blank_state(q, z=50.0)
+    s[:, W.SU:W.SU + 4] = 0.0
+    s[0, W.SV:W.SV + 3] = [0.3, -0.2, 1.1]
+    a = -np.ones((q, 4))
+    traj = run(make(q), s, a, 100)
+    ez = np.array([0, 0, 1.0])
+    for n in (1, 10, 100):
+        v = s[:, W.SV:W.SV + 3] - n * G * DT * ez
+        x = s[:, 0:3] + n * DT * s[:, W.SV:W.SV + 3] - G * DT * DT * n * (n + 1) / 2 * ez
+        np.testing.assert_allclose(traj[n][:, W.SV:W.SV + 3], v, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(traj[n][:, 0:3], x, rtol=1e-12, atol=1e-12)
+
+
+def test_linear_drag_closed_form():
+    cd = 0.01
+    q = 1
+    s = blank_state(q, z=500.0)
+    s[:, W.SU:W.SU + 4] = 0.0
+    s[0, W.SV:W.SV + 3] = [2.0, -1.0, 3.0]
+    traj = run(make(q, drag_coef=cd), s, -np.ones((q, 4)), 200)
+    vinf = np.array([0, 0, -M * G / cd])
+    for n in (1, 50, 200):
+        v = vinf + (s[0, W.SV:W.SV + 3] - vinf) * (1 - cd * DT / M) ** n
+        np.testing.assert_allclose(traj[n][0, W.SV:W.SV + 3], v, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- rotation
+def test_principal_spin_yaw_advances_by_atan():
+    w = 3.0
+    psi0 = 0.7
+    s = blank_state(1)
+    s[0, W.SR:W.SR + 9] = rot_z(psi0).reshape(9)
+    s[0, W.SW:W.SW + 3] = [0, 0, w]
+    s[0, W.SU:W.SU + 4] = 0.0
+    traj = run(make(1, gravity=0.0), s, -np.ones((1, 4)), 300)
+    for n in (1, 100, 300):
+        np.testing.assert_allclose(traj[n][0, W.SW:W.SW + 3], [0, 0, w], atol=1e-13)
+        np.testing.assert_allclose(traj[n][0, W.SR:W.SR + 9].reshape(3, 3),
+                                   rot_z(psi0 + n * math.atan(w * DT)), atol=1e-12)
+
+
+def test_body_rate_rotates_about_body_axis():
+    """omega is a body rate: from a tilted attitude R0, a pure body-z spin gives
+    R_n = R0 Rz(n atan(w dt)) (a world-frame update would give Rz(.) R0)."""
+    w = -2.0
+    R0 = rot_x(0.9) @ rot_y(0.4)
+    s = blank_state(1)
+    s[0, W.SR:W.SR + 9] = R0.reshape(9)
+    s[0, W.SW:W.SW + 3] = [0, 0, w]
+    s[0, W.SU:W.SU + 4] = 0.0
+    J = dict(ixx=1.66e-5, iyy=1.66e-5, izz=2.93e-5)
+    traj = run(make(1, gravity=0.0, params=nominal_params(1, **J)), s, -np.ones((1, 4)), 120)
+    for n in (1, 60, 120):
+        np.testing.assert_allclose(traj[n][0, W.SR:W.SR + 9].reshape(3, 3),
+                                   R0 @ rot_z(n * math.atan(w * DT)), atol=1e-12)
+
+
+def test_symmetric_top_precession():
+    """Jx = Jy, no torque: w_z constant and w_xy rotates by atan(kappa) per step
+    while growing by sqrt(1 + kappa^2), kappa = dt w_z (Jz - Jx)/Jx."""
+    Jx, Jz = 1.66e-5, 2.93e-5
+    w0 = np.array([0.4, -0.3, 5.0])
+    s = blank_state(1)
+    s[0, W.SW:W.SW + 3] = w0
+    s[0, W.SU:W.SU + 4] = 0.0
+    traj = run(make(1, gravity=0.0), s, -np.ones((1, 4)), 200)
+    kap = DT * w0[2] * (Jz - Jx) / Jx
+    for n in (1, 50, 200):
+        ang = n * math.atan(kap)
+        rot = np.array([[math.cos(ang), -math.sin(ang)], [math.sin(ang), math.cos(ang)]])
+        wxy = (1 + kap * kap) ** (n / 2) * rot @ w0[:2]
+        np.testing.assert_allclose(traj[n][0, W.SW:W.SW + 2], wxy, rtol=1e-11)
+        assert traj[n][0, W.SW + 2] == pytest.approx(w0[2], abs=1e-13)
+
+
+def test_torque_free_energy_and_world_momentum():
+    """General inertia, no torque: kinetic energy w.J.w and world angular
+    momentum R J w are conserved up to the integrator's O(dt^2) per step.
+    A wrong inertia index or frame breaks them at O(dt)."""
+    J = np.array([1.2e-5, 1.9e-5, 3.1e-5])
+    dt = 1e-5
+    s = blank_state(1)
+    s[0, W.SR:W.SR + 9] = (rot_x(0.5) @ rot_z(1.0)).reshape(9)
+    s[0, W.SW:W.SW + 3] = [3.0, -2.0, 4.0]
+    s[0, W.SU:W.SU + 4] = 0.0
+    p = nominal_params(1, ixx=J[0], iyy=J[1], izz=J[2])
+    traj = run(make(1, gravity=0.0, dt=dt, params=p), s, -np.ones((1, 4)), 2000)
+
+    def energy(st):
+        w = st[0, W.SW:W.SW + 3]
+        return float(w @ (J * w))
+
+    def mom(st):
+        return st[0, W.SR:W.SR + 9].reshape(3, 3) @ (J * st[0, W.SW:W.SW + 3])
+
+    e0, L0 = energy(traj[0]), mom(traj[0])
+    e1, L1 = energy(traj[-1]), mom(traj[-1])
+    assert abs(e1 - e0) / e0 < 2e-4
+    assert np.linalg.norm(L1 - L0) / np.linalg.norm(L0) < 2e-4
+    # and the motion is not trivial: w itself changed by far more than that
+    assert np.linalg.norm(traj[-1][0, W.SW:W.SW + 3] - s[0, W.SW:W.SW + 3]) > 0.05
+
+
+def test_orthonormality_through_chaotic_flight():
+    w = W.swarm8(seed=3, n_envs=8).with_(flags=W.QS_MOTOR_NOISE)
+    orc = O.Oracle.from_workload(w)
+    s = w.state0.astype(np.float64)
+    for t in range(200):
+        s, _, _ = orc.step(s, w.actions(t), 1, t)
+        R = s[:, W.SR:W.SR + 9].reshape(-1, 3, 3)
+        err = np.abs(np.einsum("qki,qkj->qij", R, R) - np.eye(3)).max()
+        assert err < 1e-14
+        assert np.all(np.abs(np.linalg.det(R) - 1.0) < 1e-14)
+    assert np.abs(s[:, W.SW:W.SW + 3]).max() > 1.0  # it did tumble
+
+
+# -------------------------------------------------------------- room, floor
+@pytest.mark.parametrize("axis,side", [(0, -1), (0, 1), (1, -1), (1, 1), (2, 1)])
+def test_wall_and_ceiling_bounce(axis, side):
+    lo, hi = np.array([-5.0, -5.0, 0.0]), np.array([5.0, 5.0, 10.0])
+    s = blank_state(2, z=5.0)
+    s[:, W.SU:W.SU + 4] = math.sqrt(0.5)
+    v = np.array([0.7, -0.4, 0.25])
+    v[axis] = side * 3.0
+    s[:, W.SV:W.SV + 3] = v
+    wall = hi[axis] if side > 0 else lo[axis]
+    s[0, axis] = wall - side * 0.001        # crosses the wall in this substep
+    s[1, axis] = wall + side * 0.02         # already outside but moving inward
+    s[1, W.SV + axis] = -side * 1.0
+    out, _, ev = make(2, flags=W.QS_ROOM, gravity=0.0).step(s, np.zeros((2, 4)), 1, 0)
+    assert out[0, axis] == wall and out[1, axis] == wall
+    vr = v.copy()
+    vr[axis] = -v[axis]
+    np.testing.assert_allclose(out[0, W.SV:W.SV + 3], vr, rtol=1e-15)
+    assert math.isclose(np.linalg.norm(out[0, W.SV:W.SV + 3]), np.linalg.norm(v), rel_tol=1e-15)
+    assert out[1, W.SV + axis] == -side * 1.0   # clamped, not reflected
+    assert ev[0] & O.EV_WALL and not ev[1] & O.EV_WALL
+
+
+def test_floor_hit_resets_and_keeps_yaw():
+    psi = 1.1
+    R0 = rot_z(psi) @ rot_x(0.5)
+    s = blank_state(1, z=0.002)
+    s[0, W.SR:W.SR + 9] = R0.reshape(9)
+    s[0, W.SV:W.SV + 3] = [0.5, 0.2, -1.0]
+    s[0, W.SU:W.SU + 4] = 0.0
+    s2 = s.copy()
+    s2[0, W.SW:W.SW + 3] = [1.0, 2.0, 3.0]   # spinning when it lands
+    out2, _, _ = make(1, flags=W.QS_FLOOR).step(s2, -np.ones((1, 4)), 1, 0)
+    assert np.all(out2[0, W.SW:W.SW + 3] == 0.0) and out2[0, W.SF] == 1.0
+    # no spin: R is unchanged by the substep, so the yaw to keep is R0's
+    out, _, ev = make(1, flags=W.QS_FLOOR).step(s, -np.ones((1, 4)), 1, 0)
+    assert ev[0] & O.EV_FLOOR_HIT
+    assert out[0, 2] == 0.0 and out[0, W.SF] == 1.0
+    assert np.all(out[0, W.SV:W.SV + 3] == 0.0) and np.all(out[0, W.SW:W.SW + 3] == 0.0)
+    R = out[0, W.SR:W.SR + 9].reshape(3, 3)
+    np.testing.assert_allclose(R @ [0, 0, 1], [0, 0, 1], atol=0)
+    # yaw of the body x axis projected on the floor is unchanged
+    assert math.isclose(math.atan2(R[1, 0], R[0, 0]), math.atan2(R0[1, 0], R0[0, 0]), abs_tol=1e-14)
+    np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-15)
+
+
+def test_floor_static_hold_keeps_position():
+    s = blank_state(1, z=0.0)
+    s[0, W.SF] = 1.0
+    s[0, 0:2] = [1.25, -0.5]
+    s[0, W.SR:W.SR + 9] = rot_z(0.3).reshape(9)
+    s[0, W.SU:W.SU + 4] = 0.3
+    orc = make(1, flags=W.QS_FLOOR)
+    traj = run(orc, s, np.full((1, 4), -0.2), 100)  # thrust below m g
+    for st in traj:
+        assert np.all(st[0, 0:3] == s[0, 0:3])
+        assert st[0, W.SF] == 1.0
+
+
+def test_floor_kinetic_friction_and_stop():
+    """Sliding on the floor with no thrust: |v_xy| drops by mu g dt per substep
+    along -v_hat and stops at zero without reversing."""
+    s = blank_state(1, z=0.0)
+    s[0, W.SF] = 1.0
+    s[0, W.SU:W.SU + 4] = 0.0
+    v0 = np.array([0.3, -0.4])
+    s[0, W.SV:W.SV + 2] = v0
+    traj = run(make(1, flags=W.QS_FLOOR), s, -np.ones((1, 4)), 40)
+    dv = 0.6 * G * DT
+    vhat = v0 / np.linalg.norm(v0)
+    for n in range(1, 17):
+        np.testing.assert_allclose(traj[n][0, W.SV:W.SV + 2], vhat * (0.5 - n * dv), rtol=1e-12, atol=1e-14)
+        assert traj[n][0, 2] == 0.0 and traj[n][0, W.SV + 2] == 0.0
+    assert 0.5 - 17 * dv < 0  # the 17th substep would overshoot: guard stops it
+    assert np.all(traj[17][0, W.SV:W.SV + 3] == 0.0)
+    assert np.all(traj[40][0, 0:3] == traj[17][0, 0:3])
+
+
+def test_takeoff_when_thrust_exceeds_weight():
+    s = blank_state(1, z=0.0)
+    s[0, W.SF] = 1.0
+    s[0, W.SU:W.SU + 4] = 1.0
+    orc = make(1, flags=W.QS_FLOOR)
+    out, _, ev = orc.step(s, np.ones((1, 4)), 1, 0)
+    assert ev[0] & O.EV_TAKEOFF and out[0, W.SF] == 0.0
+    # a = g (t2w - 1) upward for full thrust
+    assert out[0, W.SV + 2] == pytest.approx(DT * G * (2.0 - 1.0), rel=1e-13)
+    assert out[0, 2] > 0.0
+
+
+# ------------------------------------------------------------------- pairs
+def _brute_contacts(pos, sizes, dcol):
+    out = np.zeros(pos.shape[0], dtype=np.uint64)
+    q0 = 0
+    for n in sizes:
+        for i in range(n):
+            for j in range(n):
+                if i != j and np.sum((pos[q0 + i] - pos[q0 + j]) ** 2) < dcol * dcol:
+                    out[q0 + i] |= np.uint64(1) << np.uint64(j)
+        q0 += n
+    return out
+
+
+def test_contact_sets_match_brute_force():
+    rng = np.random.default_rng(11)
+    sizes = [1, 2, 3, 5, 8, 8, 8, 4]
+    q = sum(sizes)
+    s = blank_state(q, z=5.0)
+    q0 = 0
+    for n in sizes:  # tight clusters so that many pairs sit near 0.1 m
+        c = rng.uniform(-1, 1, 3)
+        s[q0:q0 + n, 0:3] = c + rng.uniform(-0.07, 0.07, size=(n, 3))
+        q0 += n
+    # contrived placements at d_col +- 1e-3
+    s[sizes[0], 0:3] = [0, 0, 5.0]
+    s[sizes[0] + 1, 0:3] = [0.1 - 1e-3, 0, 5.0]
+    s[3, 0:3] = [2, 2, 5.0]
+    s[4, 0:3] = [2, 2 + 0.1 + 1e-3, 5.0]
+    s[:, W.SV:W.SV + 3] = rng.normal(0, 0.5, size=(q, 3))
+    s[[1, 2, 3, 4], W.SV:W.SV + 3] = 0.0  # the contrived pairs do not move
+    s[:, W.SU:W.SU + 4] = 0.0
+    flags = W.QS_COLLIDE | W.QS_APPROACH_ONLY
+    out, contacts, _ = make(q, flags=flags, env_sizes=sizes, gravity=0.0).step(
+        s, -np.ones((q, 4)), 1, 0)
+    assert np.array_equal(contacts, _brute_contacts(out[:, 0:3], sizes, 0.1))
+    assert contacts[sizes[0]] & np.uint64(2)
+    assert not contacts[3] & np.uint64(1 << 4)
+    assert bin(int(np.bitwise_or.reduce(contacts))).count("1") > 4
+
+
+def test_head_on_exchange():
+    s = blank_state(2, z=5.0)
+    s[0, 0:3] = [0.0, 0.0, 5.0]
+    s[1, 0:3] = [0.08, 0.0, 5.0]
+    # equal tangential parts keep the line of centres along x during the substep
+    s[0, W.SV:W.SV + 3] = [1.0, 0.3, -0.2]
+    s[1, W.SV:W.SV + 3] = [-0.5, 0.3, -0.2]
+    s[:, W.SU:W.SU + 4] = 0.0
+    flags = W.QS_COLLIDE | W.QS_APPROACH_ONLY
+    out, c, ev = make(2, flags=flags, env_sizes=[2], gravity=0.0).step(s, -np.ones((2, 4)), 1, 0)
+    assert c[0] == 2 and c[1] == 1
+    # normal along x: normal components swap, tangential components kept
+    np.testing.assert_allclose(out[0, W.SV:W.SV + 3], [-0.5, 0.3, -0.2], atol=1e-15)
+    np.testing.assert_allclose(out[1, W.SV:W.SV + 3], [1.0, 0.3, -0.2], atol=1e-15)
+
+
+def test_separating_pair_is_left_alone():
+    s = blank_state(2, z=5.0)
+    s[1, 0] = 0.05
+    s[0, W.SV] = -1.0
+    s[1, W.SV] = 1.0
+    s[:, W.SU:W.SU + 4] = 0.0
+    flags = W.QS_COLLIDE | W.QS_APPROACH_ONLY
+    out, c, ev = make(2, flags=flags, env_sizes=[2], gravity=0.0).step(s, -np.ones((2, 4)), 1, 0)
+    assert c[0] == 2  # detected ...
+    assert out[0, W.SV] == -1.0 and out[1, W.SV] == 1.0  # ... but no response
+    assert not ev[0] & O.EV_PAIR_RESPONSE
+    # without the approach check the pair is exchanged anyway
+    out2, _, _ = make(2, flags=W.QS_COLLIDE, env_sizes=[2], gravity=0.0).step(s, -np.ones((2, 4)), 1, 0)
+    assert out2[0, W.SV] == 1.0 and out2[1, W.SV] == -1.0
+
+
+def test_momentum_conserved_with_many_contacts():
+    rng = np.random.default_rng(5)
+    n = 12
+    s = blank_state(n, z=5.0)
+    s[:, 0:3] = [0, 0, 5.0] + rng.uniform(-0.05, 0.05, size=(n, 3))
+    s[:, W.SV:W.SV + 3] = rng.normal(0, 1.0, size=(n, 3))
+    s[:, W.SU:W.SU + 4] = 0.0
+    flags = W.QS_COLLIDE | W.QS_APPROACH_ONLY
+    out, c, ev = make(n, flags=flags, env_sizes=[n], gravity=0.0).step(s, -np.ones((n, 4)), 1, 0)
+    assert sum(bin(int(x)).count("1") for x in c) > 2 * n  # many simultaneous contacts
+    assert np.sum(ev & O.EV_PAIR_RESPONSE > 0) > 4
+    np.testing.assert_allclose(out[:, W.SV:W.SV + 3].sum(0), s[:, W.SV:W.SV + 3].sum(0), atol=1e-14)
+    assert not np.allclose(out[:, W.SV:W.SV + 3], s[:, W.SV:W.SV + 3])
+
+
+def test_energy_conserved_single_contact():
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        s = blank_state(2, z=5.0)
+        d = rng.normal(size=3)
+        d *= 0.06 / np.linalg.norm(d)
+        s[1, 0:3] = s[0, 0:3] + d
+        s[:, W.SV:W.SV + 3] = rng.normal(0, 1.0, size=(2, 3))
+        s[:, W.SU:W.SU + 4] = 0.0
+        out, c, ev = make(2, flags=W.QS_COLLIDE, env_sizes=[2], gravity=0.0).step(s, -np.ones((2, 4)), 1, 0)
+        ke0 = np.sum(s[:, W.SV:W.SV + 3] ** 2)
+        ke1 = np.sum(out[:, W.SV:W.SV + 3] ** 2)
+        assert ke1 == pytest.approx(ke0, rel=1e-13)
+
+
+def test_coincident_pair_uses_vertical_normal():
+    s = blank_state(2, z=5.0)
+    s[:, W.SV:W.SV + 3] = [[0.0, 0.0, -1.0], [0.0, 0.0, 1.0]]
+    s[:, W.SU:W.SU + 4] = 0.0
+    # pre-shift so that both land on the same point after the substep
+    s[0, 2] = 5.0 + DT * 1.0
+    s[1, 2] = 5.0 - DT * 1.0
+    out, c, _ = make(2, flags=W.QS_COLLIDE | W.QS_APPROACH_ONLY, env_sizes=[2],
+                     gravity=0.0).step(s, -np.ones((2, 4)), 1, 0)
+    assert abs(out[0, 2] - out[1, 2]) < 1e-12
+    # n = +e_z for the lower index: (v1 - v0).n = 2 > 0 -> exchange
+    np.testing.assert_allclose(out[:, W.SV + 2], [1.0, -1.0])
+
+
+# ------------------------------------------------------------- observation
+def test_knn_matches_full_sort_and_pads():
+    rng = np.random.default_rng(2)
+    sizes = [1, 2, 4, 7, 8, 16, 32]
+    q = sum(sizes)
+    K = 6
+    s = blank_state(q)
+    s[:, 0:3] = rng.uniform(-2, 2, size=(q, 3))
+    s[:, W.SV:W.SV + 3] = rng.normal(size=(q, 3))
+    goals = rng.uniform(-1, 1, size=(q, 3))
+    orc = make(q, k=K, env_sizes=sizes)
+    obs, nbr = orc.observe(s, goals)
+    q0 = 0
+    for n in sizes:
+        for i in range(n):
+            d2 = np.sum((s[q0:q0 + n, 0:3] - s[q0 + i, 0:3]) ** 2, axis=1)
+            order = [j for j in np.lexsort((np.arange(n), d2)) if j != i][:K]
+            got = [int(j) for j in nbr[q0 + i] if j >= 0]
+            assert got == order
+            o = obs[q0 + i]
+            for k in range(K):
+                slot = o[18 + 6 * k: 24 + 6 * k]
+                if k < len(order):
+                    j = q0 + order[k]
+                    np.testing.assert_allclose(slot[:3], s[j, 0:3] - s[q0 + i, 0:3], rtol=0, atol=0)
+                    np.testing.assert_allclose(slot[3:], s[j, W.SV:W.SV + 3] - s[q0 + i, W.SV:W.SV + 3], rtol=0, atol=0)
+                else:
+                    assert np.all(slot == 0.0)
+        q0 += n
+
+
+def test_obs_layout():
+    s = blank_state(1)
+    R = rot_z(0.4) @ rot_x(0.7)
+    s[0, W.SR:W.SR + 9] = R.reshape(9)
+    s[0, 0:3] = [1.0, 2.0, 3.0]
+    s[0, W.SV:W.SV + 3] = [4.0, 5.0, 6.0]
+    s[0, W.SW:W.SW + 3] = [7.0, 8.0, 9.0]
+    obs, _ = make(1).observe(s, np.array([[0.5, 0.25, 0.125]]))
+    np.testing.assert_array_equal(obs[0, 0:3], [0.5, 1.75, 2.875])
+    np.testing.assert_array_equal(obs[0, 3:6], [4.0, 5.0, 6.0])
+    np.testing.assert_array_equal(obs[0, 6:15], R.reshape(9))  # row-major
+    assert obs[0, 7] == R[0, 1] and obs[0, 9] == R[1, 0]
+    np.testing.assert_array_equal(obs[0, 15:18], [7.0, 8.0, 9.0])
+
+
+# ------------------------------------------------------------- composition
+def test_multi_substep_call_equals_single_calls():
+    w = W.swarm8(seed=1, n_envs=16)
+    orc = O.Oracle.from_workload(w)
+    s = w.state0.astype(np.float64)
+    a = w.actions(0)
+    s5, c5, _ = orc.step(s, a, 5, 100)
+    s1 = s
+    for t in range(5):
+        s1, c1, _ = orc.step(s1, a, 1, 100 + t)
+    assert np.array_equal(s5, s1) and np.array_equal(c5, c1)
+
+
+def test_flag_values_agree_with_interface():
+    assert O.flag_values() == [W.QS_ROOM, W.QS_FLOOR, W.QS_COLLIDE, W.QS_MOTOR_NOISE,
+                               W.QS_APPROACH_ONLY, W.QS_ACT_UNIT]
+
+
+def test_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        O.Oracle(np.array([0, 65], dtype=np.int32), consts(), nominal_params(65), 0, 0, 0).step(
+            blank_state(65), np.zeros((65, 4)))
+    with pytest.raises(ValueError):
+        O.Oracle(np.array([0, 0], dtype=np.int32), consts(), nominal_params(0), 0, 0, 0).step(
+            np.zeros((0, 27)), np.zeros((0, 4)))
