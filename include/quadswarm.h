@@ -1,0 +1,189 @@
+/*
+ * quadswarm.h -- C ABI of the MI355X batched quadrotor-swarm stepper.
+ *
+ * The library advances E independent environments, each holding a swarm of
+ * 1..64 Crazyflie-class quadrotors (Q quads in total), with the dynamics of
+ * Huang et al., "QuadSwarm" (arXiv 2306.09537), §III-A (rigid body, motor lag
+ * and noise) and §III-B (walls, ceiling, floor, quad-quad collisions), and
+ * produces the §III-C observation with the K nearest swarm-mates.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns QS_OK (0) or a negative QS_ERR_* code and never
+ *    throws.  qs_error_string() turns a code into a static string.
+ *  - Pointers named h_* are host memory, read only during the call.
+ *    Pointers named d_* are device memory owned by the caller, borrowed for
+ *    the duration of the (stream-ordered) work the call enqueues.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *    All device work of a call is enqueued on that stream and the call
+ *    returns without waiting, except where noted.  A handle is not
+ *    thread-safe; calls on one handle must be ordered by the caller.
+ *  - Argument errors are detected on the host before anything is enqueued.
+ *    Device-side errors (a non-finite value produced in the state, or a
+ *    non-finite action) are sticky in the handle and are returned by the
+ *    next qs_sync().
+ *  - All device arithmetic is IEEE float32.
+ *
+ * Canonical layouts (row-major, float32):
+ *  state  [Q][27] = x(3) v(3) R(9, row-major, body->world) omega(3, body)
+ *                   u_f(4, filtered rotor speed) eps(4, motor noise, N)
+ *                   resting-on-floor flag(1: 0 or 1)
+ *  params [Q][6]  = mass (kg), ixx, iyy, izz (kg m^2), thrust_to_weight,
+ *                   motor time constant tau_m (s)          (qs_quad_params)
+ *  action [Q][4]  = per-rotor normalised thrust command a (§III-A.1),
+ *                   rotors front-right, back-right, back-left, front-left
+ *  goal   [Q][3]  = goal position (m)
+ *  obs    [Q][18+6K] = x - goal, v, R (row-major), omega, then K slots of
+ *                   (x_j - x_i, v_j - v_i) for the K nearest swarm-mates in
+ *                   order of (distance, index); zero slots when n_e - 1 < K.
+ * Quads of one environment are contiguous: env e owns quads
+ * [env_offsets[e], env_offsets[e+1]).
+ */
+#ifndef QUADSWARM_H
+#define QUADSWARM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define QS_OK 0
+#define QS_ERR_NULL (-1)          /* a required pointer is NULL */
+#define QS_ERR_INVALID (-2)       /* a count, size or constant is out of range */
+#define QS_ERR_ENV_SIZE (-3)      /* env_offsets not CSR, or a swarm of 0 or >64 */
+#define QS_ERR_HIP (-4)           /* a HIP runtime call failed */
+#define QS_ERR_NONFINITE (-5)     /* sticky: non-finite action or state on device */
+#define QS_ERR_NOMEM (-6)         /* device or host allocation failed */
+#define QS_ERR_ALIGN (-7)         /* a device pointer is not 4-byte aligned */
+#define QS_ERR_UNSUPPORTED (-8)   /* valid request this build does not handle */
+
+/* ---- physics switches (qs_desc.flags) ---- */
+#define QS_ROOM 1u            /* §III-B.2 walls and ceiling bounce the quad */
+#define QS_FLOOR 2u           /* §III-B.3 floor hit, resting, friction, take-off */
+#define QS_COLLIDE 4u         /* §III-B.1 in-env pair detection and response */
+#define QS_MOTOR_NOISE 8u     /* §III-A.2 AR(1) motor noise */
+#define QS_APPROACH_ONLY 16u  /* pair response only while the pair approaches */
+#define QS_ACT_UNIT 32u       /* f_hat = clip(a,0,1) instead of (clip(a,-1,1)+1)/2 */
+
+#define QS_STATE_DIM 27
+#define QS_PARAM_DIM 6
+#define QS_MAX_SWARM 64
+
+typedef struct qs_handle qs_handle;
+
+/*
+ * Global constants of one handle.  env_offsets is a host array of n_envs+1
+ * non-decreasing int32 (CSR), env_offsets[0] == 0, every swarm 1..64 quads.
+ *  dt               substep length (s), > 0 (200 Hz simulation: 0.005)
+ *  gravity          g (m/s^2), acts along -z
+ *  arm_length       rotor distance from the centre (m); X layout
+ *  k_tau            propeller reaction torque per newton of thrust (m)
+ *  drag_coef        linear world-frame drag c_d (N s/m), >= 0
+ *  floor_mu         floor friction coefficient, >= 0
+ *  motor_noise_decay alpha_nd in [0,1); motor_noise_std sigma >= 0 in units
+ *                   of f_max (stationary std of the noise is sigma f_max)
+ *  room_min/max     room box (m); room_min[2] is the floor height
+ *  wall_restitution e in [0,1] (1: the normal velocity is mirrored)
+ *  col_dist         centre distance below which two quads are in contact (m)
+ *  col_decay        velocity decay alpha after a collision (1: none)
+ *  col_noise_v/w    std of the velocity / body-rate noise added on a
+ *                   collision (m/s, rad/s), >= 0
+ *  k_neighbors      K >= 0, at most 63
+ *  flags            OR of QS_* switches above
+ *  seed             key of the counter-based noise (Philox4x32-10)
+ */
+typedef struct {
+  int32_t n_envs;
+  const int32_t* env_offsets;
+  float dt, gravity, arm_length, k_tau, drag_coef, floor_mu;
+  float motor_noise_decay, motor_noise_std;
+  float room_min[3], room_max[3], wall_restitution;
+  float col_dist, col_decay, col_noise_v, col_noise_w;
+  int32_t k_neighbors;
+  uint32_t flags;
+  uint64_t seed;
+} qs_desc;
+
+/* Per-quad domain-randomised physical parameters (§I, §III-A). */
+typedef struct {
+  float mass, ixx, iyy, izz, thrust_to_weight, motor_tau;
+} qs_quad_params;
+
+/*
+ * Create a handle on the current HIP device: validates desc, h_params [Q]
+ * and h_state0 [Q][27] (all finite; mass, inertia, thrust-to-weight and
+ * tau_m > 0), derives f_max = m g t2w / 4 and alpha_lag = 1 - exp(-dt/tau_m)
+ * per quad, allocates the private device state and uploads it (synchronous).
+ * The substep counter starts at 0.  On error *out is left NULL.
+ */
+int qs_create(const qs_desc* desc, const qs_quad_params* h_params,
+              const float* h_state0, qs_handle** out);
+
+/* Free the handle and its device memory (synchronises the device). NULL is OK. */
+int qs_destroy(qs_handle* h);
+
+/* Sizes of a handle: number of quads, of environments, and the obs row length. */
+int qs_sizes(const qs_handle* h, int32_t* n_quads, int32_t* n_envs, int32_t* obs_dim);
+
+/*
+ * Advance every quad by n_substeps substeps of dt, holding d_actions [Q][4]
+ * for all of them (§III-A.1: the policy acts once per control step; the
+ * simulator takes several physics substeps per action).  Each substep runs
+ * motor command, lag and noise, thrust and torque mix, gravity and drag,
+ * semi-implicit Euler with Gram-Schmidt re-orthonormalisation, walls,
+ * ceiling and floor, then the in-env pair pass.  n_substeps >= 0.
+ */
+int qs_step(qs_handle* h, const float* d_actions, int32_t n_substeps, void* stream);
+
+/* §III-C observation of the current state into d_obs [Q][18+6K]. */
+int qs_observe(qs_handle* h, const float* d_goals, float* d_obs, void* stream);
+
+/*
+ * qs_step followed by qs_observe, in one launch: the state stays in
+ * registers across the substeps and the observation is written from them.
+ * Results are identical to the two calls made one after the other.
+ */
+int qs_step_observe(qs_handle* h, const float* d_actions, int32_t n_substeps,
+                    const float* d_goals, float* d_obs, void* stream);
+
+/*
+ * Copy the state into d_state [Q][27] (canonical layout) and return the
+ * substep counter (number of substeps enqueued so far; host value).
+ * substep_index may be NULL.
+ */
+int qs_get_state(qs_handle* h, float* d_state, uint64_t* substep_index, void* stream);
+
+/*
+ * Load d_state [Q][27] for the environments whose d_env_mask[e] != 0
+ * (d_env_mask NULL: all) and set the substep counter, which keys the noise.
+ * Values are taken as given (not validated on the device).
+ */
+int qs_set_state(qs_handle* h, const float* d_state, uint64_t substep_index,
+                 const uint8_t* d_env_mask, void* stream);
+
+/*
+ * Enable (enable != 0) or disable recording of the contact sets.  While
+ * enabled, every qs_step / qs_step_observe writes, for each quad, the mask
+ * of swarm-mates it was in contact with (|x_i - x_j| < col_dist) at its last
+ * substep; qs_debug_contacts copies it to d_mask [Q] (bit j = the
+ * environment's j-th quad).  Recording costs 8 bytes per quad per call.
+ */
+int qs_record_contacts(qs_handle* h, int32_t enable);
+int qs_debug_contacts(qs_handle* h, uint64_t* d_mask, void* stream);
+
+/*
+ * Wait for the handle's work on `stream` and return the sticky device error
+ * (QS_ERR_NONFINITE) if one was raised since the last qs_sync, else QS_OK.
+ * Synchronous.  The error is cleared by the call that reports it.
+ */
+int qs_sync(qs_handle* h, void* stream);
+
+/* Static description of a return code. */
+const char* qs_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUADSWARM_H */

@@ -46,6 +46,7 @@ class _Desc(C.Structure):
         ("col_dist", C.c_double), ("col_decay", C.c_double),
         ("col_noise_v", C.c_double), ("col_noise_w", C.c_double),
         ("k_neighbors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64),
+        ("quad_id_offset", C.c_uint32),
     ]
 
 
@@ -78,7 +79,7 @@ class Oracle:
     """
 
     def __init__(self, env_offsets, consts: dict, params, k_neighbors: int,
-                 flags: int, seed: int):
+                 flags: int, seed: int, quad_id_offset: int = 0):
         self.offs = np.ascontiguousarray(env_offsets, dtype=np.int32)
         self.params = np.ascontiguousarray(params, dtype=np.float64)
         self.Q = int(self.offs[-1])
@@ -95,26 +96,36 @@ class Oracle:
         d.k_neighbors = self.K
         d.flags = int(flags)
         d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        d.quad_id_offset = int(quad_id_offset)
         self.desc = d
 
     @classmethod
-    def from_workload(cls, w) -> "Oracle":
-        return cls(w.env_offsets, w.consts, w.params.astype(np.float64),
-                   w.k_neighbors, w.flags, w.rng_key)
+    def from_workload(cls, w, env_begin: int = 0, env_end=None) -> "Oracle":
+        """Oracle over the environments [env_begin, env_end) of a workload;
+        their quads keep their global indices for the noise counters."""
+        e1 = w.n_envs if env_end is None else env_end
+        offs = w.env_offsets[env_begin:e1 + 1]
+        q0, q1 = int(offs[0]), int(offs[-1])
+        return cls(offs - q0, w.consts, w.params[q0:q1].astype(np.float64),
+                   w.k_neighbors, w.flags, w.rng_key, quad_id_offset=q0)
 
-    def step(self, state, actions, n_sub: int = 1, t0: int = 0):
-        """Returns (new_state [Q][27] f64, contacts [Q] u64, events [Q] u32)."""
+    def step(self, state, actions, n_sub: int = 1, t0: int = 0, margins: bool = False):
+        """Returns (new_state [Q][27] f64, contacts [Q] u64, events [Q] u32),
+        plus the per-quad threshold margins [Q] f64 when ``margins``."""
         s = np.array(state, dtype=np.float64, order="C", copy=True)
         a = np.ascontiguousarray(actions, dtype=np.float64)
         assert s.shape == (self.Q, 27) and a.shape == (self.Q, 4)
         contacts = np.zeros(self.Q, dtype=np.uint64)
         events = np.zeros(self.Q, dtype=np.uint32)
+        mg = np.zeros(self.Q, dtype=np.float64)
         rc = lib().or_step(C.byref(self.desc), _p(self.params, C.c_double),
                            _p(s, C.c_double), _p(a, C.c_double), C.c_int(n_sub),
                            C.c_uint64(t0), _p(contacts, C.c_uint64),
-                           _p(events, C.c_uint32))
+                           _p(events, C.c_uint32), _p(mg, C.c_double))
         if rc != 0:
             raise ValueError("or_step rejected its arguments")
+        if margins:
+            return s, contacts, events, mg
         return s, contacts, events
 
     def observe(self, state, goals):

@@ -87,6 +87,7 @@ typedef struct {
   int32_t k_neighbors;
   uint32_t flags;
   uint64_t seed;
+  uint32_t quad_id_offset; /* global index of quad 0 (noise counter) */
 } or_desc;
 
 /* ------------------------------------------------------------------------ */
@@ -144,9 +145,16 @@ static double clampd(double a, double lo, double hi) {
   return a < lo ? lo : (a > hi ? hi : a);
 }
 
+static void upd_margin(double* mg, double v) {
+  v = fabs(v);
+  if (v < *mg) *mg = v;
+}
+
+/* mg: smallest distance of any threshold decision of this substep from its
+ * threshold (diagnostic only; it does not change the arithmetic). */
 static void quad_substep(const or_desc* d, const double* p, double* s,
                          const double* act, uint32_t q, uint64_t t,
-                         uint32_t* ev) {
+                         uint32_t* ev, double* mg) {
   const double dt = d->dt, g = d->gravity;
   const double m = p[PM], jx = p[PJX], jy = p[PJY], jz = p[PJZ];
   const double f_max = 0.25 * m * g * p[PT2W];              /* §III-A.2 */
@@ -190,6 +198,7 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
   double F[3] = {T * R[2], T * R[5], T * R[8]};
 
   int friction = (d->flags & OR_FLOOR) && s[IF] != 0.0 && F[2] <= m * g;
+  if ((d->flags & OR_FLOOR) && s[IF] != 0.0) upd_margin(mg, (F[2] - m * g) / (m * g));
   if (!friction) {
     if (s[IF] != 0.0) *ev |= EV_TAKEOFF;
     s[IF] = 0.0;
@@ -252,7 +261,10 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     v[0] += dt * acc[0];
     v[1] += dt * acc[1];
     v[2] = 0.0;
-    if (v[0] * vxy0[0] + v[1] * vxy0[1] < 0.0) { v[0] = 0.0; v[1] = 0.0; }
+    double dot = v[0] * vxy0[0] + v[1] * vxy0[1];
+    if (vxy0[0] != 0.0 || vxy0[1] != 0.0)
+      upd_margin(mg, dot / (vxy0[0] * vxy0[0] + vxy0[1] * vxy0[1]));
+    if (dot < 0.0) { v[0] = 0.0; v[1] = 0.0; }
     for (int k = 0; k < 3; ++k) x[k] += dt * v[k];
     w[0] = w[1] = w[2] = 0.0;
   }
@@ -262,6 +274,8 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     int bounced = 0;
     const double e = d->wall_restitution;
     for (int k = 0; k < 3; ++k) {
+      if (k < 2) upd_margin(mg, x[k] - d->room_min[k]);
+      upd_margin(mg, x[k] - d->room_max[k]);
       if (k < 2 && x[k] < d->room_min[k]) {
         x[k] = d->room_min[k];
         if (v[k] < 0.0) { v[k] = -e * v[k]; bounced = 1; }
@@ -286,6 +300,7 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
   }
 
   /* §III-B.3: floor hit */
+  if ((d->flags & OR_FLOOR) && s[IF] == 0.0) upd_margin(mg, x[2] - d->room_min[2]);
   if ((d->flags & OR_FLOOR) && x[2] < d->room_min[2]) {
     *ev |= EV_FLOOR_HIT;
     x[2] = d->room_min[2];
@@ -316,7 +331,7 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
 
 /* §III-B.1: pair pass of one environment after every quad moved. */
 static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
-                      uint64_t* contacts, uint32_t* events) {
+                      uint64_t* contacts, uint32_t* events, double* mg) {
   double dv[64][3];
   int marked[64];
   memset(dv, 0, sizeof(dv));
@@ -328,6 +343,9 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
       const double* sj = S + (size_t)(q0 + j) * NS;
       double dx[3] = {si[IX] - sj[IX], si[IX + 1] - sj[IX + 1], si[IX + 2] - sj[IX + 2]};
       double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+      double dm = sqrt(d2) - d->col_dist;
+      upd_margin(&mg[q0 + i], dm);
+      upd_margin(&mg[q0 + j], dm);
       if (!(d2 < dc2)) continue;
       if (contacts) {
         contacts[q0 + i] |= 1ull << j;
@@ -344,6 +362,10 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
       }
       double sp = 0.0;
       for (int k = 0; k < 3; ++k) sp += (sj[IV + k] - si[IV + k]) * nrm[k];
+      if (d->flags & OR_APPROACH_ONLY) {
+        upd_margin(&mg[q0 + i], sp);
+        upd_margin(&mg[q0 + j], sp);
+      }
       if ((d->flags & OR_APPROACH_ONLY) && !(sp > 0.0)) continue;
       for (int k = 0; k < 3; ++k) {
         dv[i][k] += sp * nrm[k];
@@ -358,8 +380,8 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
     events[q0 + i] |= EV_PAIR_RESPONSE;
     double zv[4] = {0, 0, 0, 0}, zw[4] = {0, 0, 0, 0};
     if (d->col_noise_v > 0.0 || d->col_noise_w > 0.0) {
-      or_normal4(d->seed, (uint32_t)(q0 + i), t, STREAM_PAIR, 0, zv);
-      or_normal4(d->seed, (uint32_t)(q0 + i), t, STREAM_PAIR, 1, zw);
+      or_normal4(d->seed, d->quad_id_offset + (uint32_t)(q0 + i), t, STREAM_PAIR, 0, zv);
+      or_normal4(d->seed, d->quad_id_offset + (uint32_t)(q0 + i), t, STREAM_PAIR, 1, zw);
     }
     for (int k = 0; k < 3; ++k) {
       si[IV + k] = d->col_decay * (si[IV + k] + dv[i][k] + d->col_noise_v * zv[k]);
@@ -384,17 +406,28 @@ static int check_desc(const or_desc* d) {
  * is updated in place; substep t0 + s draws the noise of step s.  contacts
  * (optional) receives, per quad, the contact bitmask of the last substep
  * (bit j = in contact with the env's quad j).  events (optional) receives
- * the OR of the EV_* bits over the call.  Returns 0, or -1 on bad arguments.
+ * the OR of the EV_* bits over the call.  margin (optional) receives, per
+ * quad, the smallest distance of any threshold decision taken for it during
+ * the call from its threshold (metres for walls, floor and contact
+ * distance; m/s for the approach test; relative for the take-off test and
+ * the friction zero-crossing) -- a diagnostic for comparisons at a
+ * different precision.  Returns 0, or -1 on bad arguments.
  */
 int or_step(const or_desc* d, const double* params, double* state,
             const double* actions, int n_sub, uint64_t t0, uint64_t* contacts,
-            uint32_t* events) {
+            uint32_t* events, double* margin) {
   if (check_desc(d) || !params || !state || !actions || n_sub < 0) return -1;
   const int E = d->n_envs;
   const int Q = d->env_offsets[E];
-  uint32_t* ev = events ? events : (uint32_t*)calloc((size_t)Q, sizeof(uint32_t));
-  if (!ev) return -1;
+  uint32_t* ev = events ? events : (uint32_t*)calloc((size_t)Q + 1, sizeof(uint32_t));
+  double* mg = margin ? margin : (double*)malloc(((size_t)Q + 1) * sizeof(double));
+  if (!ev || !mg) {
+    if (!events) free(ev);
+    if (!margin) free(mg);
+    return -1;
+  }
   if (events) memset(events, 0, (size_t)Q * sizeof(uint32_t));
+  for (int q = 0; q < Q; ++q) mg[q] = INFINITY;
   for (int sub = 0; sub < n_sub; ++sub) {
     const uint64_t t = t0 + (uint64_t)sub;
     if (contacts) memset(contacts, 0, (size_t)Q * sizeof(uint64_t));
@@ -404,12 +437,14 @@ int or_step(const or_desc* d, const double* params, double* state,
       for (int i = 0; i < n; ++i) {
         const int q = q0 + i;
         quad_substep(d, params + (size_t)q * NP, state + (size_t)q * NS,
-                     actions + (size_t)q * 4, (uint32_t)q, t, &ev[q]);
+                     actions + (size_t)q * 4, d->quad_id_offset + (uint32_t)q, t,
+                     &ev[q], &mg[q]);
       }
-      if ((d->flags & OR_COLLIDE) && n > 1) env_pairs(d, state, q0, n, t, contacts, ev);
+      if ((d->flags & OR_COLLIDE) && n > 1) env_pairs(d, state, q0, n, t, contacts, ev, mg);
     }
   }
   if (!events) free(ev);
+  if (!margin) free(mg);
   return 0;
 }
 

@@ -1,0 +1,403 @@
+// Host side of the C ABI declared in include/quadswarm.h: argument checks,
+// the handle, the environment-to-workgroup partition and the launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "quadswarm.h"
+#include "qs_kernels.h"
+
+using qs::Consts;
+using qs::Ptrs;
+
+struct qs_handle {
+  int dev = 0;
+  int E = 0, Q = 0, Qp = 0, K = 0, OD = 0;
+  int bs = 64, nblk = 0;
+  Consts c{};
+  float* d_st = nullptr;
+  float* d_par = nullptr;
+  uint32_t* d_sw = nullptr;
+  int2* d_blk = nullptr;
+  int32_t* d_qenv = nullptr;
+  unsigned long long* d_contacts = nullptr;
+  int* d_err = nullptr;
+  int* h_err = nullptr;  // pinned
+  uint64_t t = 0;
+  bool record = false;
+};
+
+namespace {
+
+bool finite(float v) { return std::isfinite(v); }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int check_desc(const qs_desc* d) {
+  if (!d || !d->env_offsets) return QS_ERR_NULL;
+  if (d->n_envs < 1) return QS_ERR_INVALID;
+  if (d->env_offsets[0] != 0) return QS_ERR_ENV_SIZE;
+  for (int e = 0; e < d->n_envs; ++e) {
+    const int n = d->env_offsets[e + 1] - d->env_offsets[e];
+    if (n < 1 || n > QS_MAX_SWARM) return QS_ERR_ENV_SIZE;
+  }
+  const float vals[] = {d->dt, d->gravity, d->arm_length, d->k_tau, d->drag_coef, d->floor_mu,
+                        d->motor_noise_decay, d->motor_noise_std, d->room_min[0], d->room_min[1],
+                        d->room_min[2], d->room_max[0], d->room_max[1], d->room_max[2],
+                        d->wall_restitution, d->col_dist, d->col_decay, d->col_noise_v,
+                        d->col_noise_w};
+  for (float v : vals)
+    if (!finite(v)) return QS_ERR_INVALID;
+  if (!(d->dt > 0.f) || d->arm_length < 0.f || d->drag_coef < 0.f || d->floor_mu < 0.f)
+    return QS_ERR_INVALID;
+  if (d->motor_noise_decay < 0.f || d->motor_noise_decay >= 1.f || d->motor_noise_std < 0.f)
+    return QS_ERR_INVALID;
+  for (int k = 0; k < 3; ++k)
+    if (!(d->room_min[k] < d->room_max[k])) return QS_ERR_INVALID;
+  if (d->wall_restitution < 0.f || d->wall_restitution > 1.f || d->col_dist < 0.f ||
+      d->col_noise_v < 0.f || d->col_noise_w < 0.f)
+    return QS_ERR_INVALID;
+  if (d->k_neighbors < 0 || d->k_neighbors >= QS_MAX_SWARM) return QS_ERR_INVALID;
+  if (d->flags & ~63u) return QS_ERR_INVALID;
+  return QS_OK;
+}
+
+int pick_block(int Q) {
+  if (const char* e = std::getenv("QS_BLOCK_SIZE")) {
+    const int b = std::atoi(e);
+    if (b == 64 || b == 128 || b == 256) return b;
+  }
+  if (Q >= 128 * 2048) return 128;
+  return 64;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  if (count == 0) count = 1;
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return QS_ERR_NOMEM;
+  }
+  return QS_OK;
+}
+
+void free_all(qs_handle* h) {
+  (void)hipFree(h->d_st);
+  (void)hipFree(h->d_par);
+  (void)hipFree(h->d_sw);
+  (void)hipFree(h->d_blk);
+  (void)hipFree(h->d_qenv);
+  (void)hipFree(h->d_contacts);
+  (void)hipFree(h->d_err);
+  if (h->h_err) (void)hipHostFree(h->h_err);
+}
+
+Ptrs ptrs(qs_handle* h) {
+  Ptrs p;
+  p.st = h->d_st;
+  p.par = h->d_par;
+  p.sw = h->d_sw;
+  p.blk = h->d_blk;
+  p.contacts = h->record ? h->d_contacts : nullptr;
+  p.err = h->d_err;
+  p.Qp = h->Qp;
+  return p;
+}
+
+// Launch the step kernel.  mode: -2 step only, otherwise with observation.
+template <int BS>
+int launch_bs(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
+              bool with_obs, hipStream_t s) {
+  const Ptrs p = ptrs(h);
+  const dim3 grid(h->nblk), block(BS);
+  if (!with_obs) {
+    hipLaunchKernelGGL((qs::step_kernel<BS, -2>), grid, block, 0, s, h->c, p, act, nsub,
+                       (unsigned long long)h->t, goals, obs, 0);
+  } else {
+    // stage the observation rows in LDS when the tile and the rows fit in
+    // 64 KiB per workgroup; otherwise each lane writes its own row
+    const int odp = h->OD | 1;
+    const size_t lds = (size_t)BS * odp * sizeof(float);
+    const size_t tile = sizeof(float) * 2 * 9 * BS;
+    const bool stage = lds + tile <= 64 * 1024;
+    const size_t dyn = stage ? lds : 0;
+    if (h->K == 0)
+      hipLaunchKernelGGL((qs::step_kernel<BS, 0>), grid, block, dyn, s, h->c, p, act, nsub,
+                         (unsigned long long)h->t, goals, obs, stage ? 1 : 0);
+    else if (h->K == 6)
+      hipLaunchKernelGGL((qs::step_kernel<BS, 6>), grid, block, dyn, s, h->c, p, act, nsub,
+                         (unsigned long long)h->t, goals, obs, stage ? 1 : 0);
+    else
+      hipLaunchKernelGGL((qs::step_kernel<BS, -1>), grid, block, dyn, s, h->c, p, act, nsub,
+                         (unsigned long long)h->t, goals, obs, stage ? 1 : 0);
+  }
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+}
+
+int launch(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
+           bool with_obs, hipStream_t s) {
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  int rc;
+  switch (h->bs) {
+    case 256: rc = launch_bs<256>(h, act, nsub, goals, obs, with_obs, s); break;
+    case 128: rc = launch_bs<128>(h, act, nsub, goals, obs, with_obs, s); break;
+    default: rc = launch_bs<64>(h, act, nsub, goals, obs, with_obs, s); break;
+  }
+  if (rc == QS_OK) h->t += (uint64_t)nsub;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* h_state0,
+              qs_handle** out) {
+  if (!out) return QS_ERR_NULL;
+  *out = nullptr;
+  if (!h_params || !h_state0) return QS_ERR_NULL;
+  int rc = check_desc(desc);
+  if (rc != QS_OK) return rc;
+  const int E = desc->n_envs;
+  const int Q = desc->env_offsets[E];
+  for (int q = 0; q < Q; ++q) {
+    const qs_quad_params& p = h_params[q];
+    const float v[] = {p.mass, p.ixx, p.iyy, p.izz, p.thrust_to_weight, p.motor_tau};
+    for (float x : v)
+      if (!finite(x) || !(x > 0.f)) return QS_ERR_INVALID;
+  }
+  for (size_t i = 0; i < (size_t)Q * QS_STATE_DIM; ++i)
+    if (!finite(h_state0[i])) return QS_ERR_INVALID;
+
+  qs_handle* h = new (std::nothrow) qs_handle();
+  if (!h) return QS_ERR_NOMEM;
+  if (hipGetDevice(&h->dev) != hipSuccess) {
+    delete h;
+    return QS_ERR_HIP;
+  }
+  h->E = E;
+  h->Q = Q;
+  h->Qp = (Q + 63) / 64 * 64;
+  h->K = desc->k_neighbors;
+  h->OD = 18 + 6 * h->K;
+  h->bs = pick_block(Q);
+
+  // constants (derived in double, rounded once)
+  Consts& c = h->c;
+  c.dt = desc->dt;
+  c.g = desc->gravity;
+  c.arm_d = (float)((double)desc->arm_length / std::sqrt(2.0));
+  c.k_tau = desc->k_tau;
+  c.drag = desc->drag_coef;
+  c.mu = desc->floor_mu;
+  c.a_nd = desc->motor_noise_decay;
+  const double and_ = desc->motor_noise_decay;
+  c.ns_scale = (float)((double)desc->motor_noise_std * std::sqrt(1.0 - and_ * and_));
+  c.rmin0 = desc->room_min[0];
+  c.rmin1 = desc->room_min[1];
+  c.rmin2 = desc->room_min[2];
+  c.rmax0 = desc->room_max[0];
+  c.rmax1 = desc->room_max[1];
+  c.rmax2 = desc->room_max[2];
+  c.e_wall = desc->wall_restitution;
+  c.dcol2 = (float)((double)desc->col_dist * (double)desc->col_dist);
+  c.col_decay = desc->col_decay;
+  c.col_nv = desc->col_noise_v;
+  c.col_nw = desc->col_noise_w;
+  c.flags = desc->flags;
+  c.key0 = (uint32_t)desc->seed;
+  c.key1 = (uint32_t)(desc->seed >> 32);
+  c.K = h->K;
+  c.obs_dim = h->OD;
+
+  // environment -> workgroup partition (environments are never split)
+  std::vector<int2> blk;
+  std::vector<uint32_t> sw((size_t)h->Qp, 0u);
+  std::vector<int32_t> qenv((size_t)Q, 0);
+  int cur_begin = 0, cur_cnt = 0;
+  for (int e = 0; e < E; ++e) {
+    const int q0 = desc->env_offsets[e], n = desc->env_offsets[e + 1] - q0;
+    if (cur_cnt + n > h->bs) {
+      blk.push_back(make_int2(cur_begin, cur_cnt));
+      cur_begin = q0;
+      cur_cnt = 0;
+    }
+    for (int i = 0; i < n; ++i) {
+      sw[(size_t)q0 + i] = ((uint32_t)(q0 - cur_begin) << 8) | (uint32_t)n;
+      qenv[(size_t)q0 + i] = e;
+    }
+    cur_cnt += n;
+  }
+  blk.push_back(make_int2(cur_begin, cur_cnt));
+  h->nblk = (int)blk.size();
+
+  // derived per-quad parameters and SoA state
+  std::vector<float> par((size_t)qs::NPARAM * h->Qp, 1.0f);
+  std::vector<float> st((size_t)qs::NSTATE * h->Qp, 0.0f);
+  for (int q = 0; q < Q; ++q) {
+    const qs_quad_params& p = h_params[q];
+    par[(size_t)qs::P_M * h->Qp + q] = p.mass;
+    par[(size_t)qs::P_JX * h->Qp + q] = p.ixx;
+    par[(size_t)qs::P_JY * h->Qp + q] = p.iyy;
+    par[(size_t)qs::P_JZ * h->Qp + q] = p.izz;
+    par[(size_t)qs::P_FMAX * h->Qp + q] =
+        (float)(0.25 * (double)p.mass * (double)desc->gravity * (double)p.thrust_to_weight);
+    par[(size_t)qs::P_ALAG * h->Qp + q] =
+        (float)(1.0 - std::exp(-(double)desc->dt / (double)p.motor_tau));
+    for (int f = 0; f < qs::NSTATE; ++f)
+      st[(size_t)f * h->Qp + q] = h_state0[(size_t)q * QS_STATE_DIM + f];
+  }
+
+  rc = QS_OK;
+  if (rc == QS_OK) rc = dalloc(&h->d_st, st.size());
+  if (rc == QS_OK) rc = dalloc(&h->d_par, par.size());
+  if (rc == QS_OK) rc = dalloc(&h->d_sw, sw.size());
+  if (rc == QS_OK) rc = dalloc(&h->d_blk, blk.size());
+  if (rc == QS_OK) rc = dalloc(&h->d_qenv, qenv.size());
+  if (rc == QS_OK) rc = dalloc(&h->d_contacts, (size_t)h->Qp);
+  if (rc == QS_OK) rc = dalloc(&h->d_err, 1);
+  if (rc == QS_OK && hipHostMalloc((void**)&h->h_err, sizeof(int)) != hipSuccess) {
+    h->h_err = nullptr;
+    rc = QS_ERR_NOMEM;
+  }
+  if (rc == QS_OK) {
+    bool ok = hipMemcpy(h->d_st, st.data(), st.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(h->d_par, par.data(), par.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(h->d_sw, sw.data(), sw.size() * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(h->d_blk, blk.data(), blk.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess;
+    if (Q > 0)
+      ok = ok && hipMemcpy(h->d_qenv, qenv.data(), qenv.size() * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(h->d_contacts, 0, (size_t)h->Qp * sizeof(unsigned long long)) == hipSuccess;
+    ok = ok && hipMemset(h->d_err, 0, sizeof(int)) == hipSuccess;
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) rc = QS_ERR_HIP;
+  }
+  if (rc != QS_OK) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  *h->h_err = 0;
+  *out = h;
+  return QS_OK;
+}
+
+int qs_destroy(qs_handle* h) {
+  if (!h) return QS_OK;
+  (void)hipSetDevice(h->dev);
+  (void)hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+  return QS_OK;
+}
+
+int qs_sizes(const qs_handle* h, int32_t* n_quads, int32_t* n_envs, int32_t* obs_dim) {
+  if (!h) return QS_ERR_NULL;
+  if (n_quads) *n_quads = h->Q;
+  if (n_envs) *n_envs = h->E;
+  if (obs_dim) *obs_dim = h->OD;
+  return QS_OK;
+}
+
+int qs_step(qs_handle* h, const float* d_actions, int32_t n_substeps, void* stream) {
+  if (!h || !d_actions) return QS_ERR_NULL;
+  if (n_substeps < 0) return QS_ERR_INVALID;
+  if (!aligned(d_actions, 16)) return QS_ERR_ALIGN;
+  if (n_substeps == 0) return QS_OK;
+  return launch(h, d_actions, n_substeps, nullptr, nullptr, false, (hipStream_t)stream);
+}
+
+int qs_observe(qs_handle* h, const float* d_goals, float* d_obs, void* stream) {
+  if (!h || !d_goals || !d_obs) return QS_ERR_NULL;
+  if (!aligned(d_goals, 4) || !aligned(d_obs, 4)) return QS_ERR_ALIGN;
+  return launch(h, nullptr, 0, d_goals, d_obs, true, (hipStream_t)stream);
+}
+
+int qs_step_observe(qs_handle* h, const float* d_actions, int32_t n_substeps,
+                    const float* d_goals, float* d_obs, void* stream) {
+  if (!h || !d_actions || !d_goals || !d_obs) return QS_ERR_NULL;
+  if (n_substeps < 0) return QS_ERR_INVALID;
+  if (!aligned(d_actions, 16) || !aligned(d_goals, 4) || !aligned(d_obs, 4)) return QS_ERR_ALIGN;
+  return launch(h, d_actions, n_substeps, d_goals, d_obs, true, (hipStream_t)stream);
+}
+
+int qs_get_state(qs_handle* h, float* d_state, uint64_t* substep_index, void* stream) {
+  if (!h || !d_state) return QS_ERR_NULL;
+  if (!aligned(d_state, 4)) return QS_ERR_ALIGN;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  const long long n = (long long)h->Q * qs::NSTATE;
+  const int tb = 256;
+  hipLaunchKernelGGL(qs::get_state_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0,
+                     (hipStream_t)stream, h->d_st, h->Qp, h->Q, d_state);
+  if (hipGetLastError() != hipSuccess) return QS_ERR_HIP;
+  if (substep_index) *substep_index = h->t;
+  return QS_OK;
+}
+
+int qs_set_state(qs_handle* h, const float* d_state, uint64_t substep_index,
+                 const uint8_t* d_env_mask, void* stream) {
+  if (!h || !d_state) return QS_ERR_NULL;
+  if (!aligned(d_state, 4)) return QS_ERR_ALIGN;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  const long long n = (long long)h->Q * qs::NSTATE;
+  const int tb = 256;
+  hipLaunchKernelGGL(qs::set_state_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0,
+                     (hipStream_t)stream, h->d_st, h->Qp, h->Q, d_state, h->d_qenv, d_env_mask);
+  if (hipGetLastError() != hipSuccess) return QS_ERR_HIP;
+  h->t = substep_index;
+  return QS_OK;
+}
+
+int qs_record_contacts(qs_handle* h, int32_t enable) {
+  if (!h) return QS_ERR_NULL;
+  h->record = enable != 0;
+  return QS_OK;
+}
+
+int qs_debug_contacts(qs_handle* h, uint64_t* d_mask, void* stream) {
+  if (!h || !d_mask) return QS_ERR_NULL;
+  if (!aligned(d_mask, 8)) return QS_ERR_ALIGN;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  if (hipMemcpyAsync(d_mask, h->d_contacts, (size_t)h->Q * sizeof(uint64_t),
+                     hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
+    return QS_ERR_HIP;
+  return QS_OK;
+}
+
+int qs_sync(qs_handle* h, void* stream) {
+  if (!h) return QS_ERR_NULL;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(h->h_err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return QS_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return QS_ERR_HIP;
+  if (*h->h_err != 0) {
+    *h->h_err = 0;
+    if (hipMemsetAsync(h->d_err, 0, sizeof(int), s) != hipSuccess) return QS_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return QS_ERR_HIP;
+    return QS_ERR_NONFINITE;
+  }
+  return QS_OK;
+}
+
+const char* qs_error_string(int code) {
+  switch (code) {
+    case QS_OK: return "ok";
+    case QS_ERR_NULL: return "a required pointer is NULL";
+    case QS_ERR_INVALID: return "a count, size or constant is out of range";
+    case QS_ERR_ENV_SIZE: return "env_offsets is not CSR or a swarm has 0 or more than 64 quads";
+    case QS_ERR_HIP: return "a HIP runtime call failed";
+    case QS_ERR_NONFINITE: return "a non-finite action or state value was produced on the device";
+    case QS_ERR_NOMEM: return "allocation failed";
+    case QS_ERR_ALIGN: return "a device pointer is misaligned";
+    case QS_ERR_UNSUPPORTED: return "request not supported by this build";
+    default: return "unknown error code";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,274 @@
+// Device-side building blocks of the quadrotor-swarm step (gfx950, wave64).
+//
+// One lane owns one quad.  Its state lives in VGPRs for the whole call; a
+// workgroup owns whole environments (never split), so the in-env pair pass
+// and the nearest-neighbour search read swarm-mates' positions and
+// velocities from LDS after a workgroup barrier.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qs {
+
+enum : uint32_t {
+  F_ROOM = 1u, F_FLOOR = 2u, F_COLLIDE = 4u, F_NOISE = 8u, F_APPROACH = 16u, F_ACT_UNIT = 32u
+};
+enum : int { NSTATE = 27, NPARAM = 6 };
+// SoA field index of the private state: x3 v3 R9 (row-major) w3 u4 eps4 floor
+enum : int { S_X = 0, S_V = 3, S_R = 6, S_W = 15, S_U = 18, S_E = 22, S_F = 26 };
+// SoA field index of the derived parameters
+enum : int { P_M = 0, P_JX = 1, P_JY = 2, P_JZ = 3, P_FMAX = 4, P_ALAG = 5 };
+// noise streams: fourth Philox counter word = stream << 8 | draw
+enum : uint32_t { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2 };
+enum : int { ERRBIT_STATE = 1, ERRBIT_ACTION = 2 };
+
+struct Consts {
+  float dt, g, arm_d, k_tau, drag, mu;
+  float a_nd, ns_scale;  // motor noise: eps <- a_nd eps + ns_scale f_max z
+  float rmin0, rmin1, rmin2, rmax0, rmax1, rmax2, e_wall;
+  float dcol2, col_decay, col_nv, col_nw;
+  uint32_t flags;
+  uint32_t key0, key1;
+  int32_t K;
+  int32_t obs_dim;
+};
+
+struct Ptrs {
+  float* st;                    // [27][Qp] private SoA state
+  const float* par;             // [6][Qp] m, jx, jy, jz, f_max, alpha_lag
+  const uint32_t* sw;           // [Qp] (env start within the block << 8) | n_e
+  const int2* blk;              // [nblk] (first quad, quad count)
+  unsigned long long* contacts; // [Qp] or nullptr
+  int* err;                     // sticky error bits
+  int Qp;
+};
+
+// Philox4x32-10, Salmon et al. SC'11: ten rounds of two 32x32->64 products
+// with a Weyl-sequence key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Uniform (2 (r >> 9) + 1) 2^-24 in (0,1): exact in float32.
+__device__ __forceinline__ float u01(uint32_t r) {
+  return (float)(((r >> 9) << 1) | 1u) * 5.9604644775390625e-8f;
+}
+
+// Four N(0,1) draws by Box-Muller for (quad, substep, stream, draw).
+__device__ __forceinline__ void normal4(const Consts& c, uint32_t q, uint64_t t,
+                                        uint32_t stream, uint32_t draw, float z[4]) {
+  uint32_t r0 = q, r1 = (uint32_t)t, r2 = (uint32_t)(t >> 32), r3 = (stream << 8) | draw;
+  philox4x32_10(r0, r1, r2, r3, c.key0, c.key1);
+  float s, co;
+  float rad = sqrtf(-2.0f * logf(u01(r0)));
+  sincospif(2.0f * u01(r1), &s, &co);
+  z[0] = rad * co;
+  z[1] = rad * s;
+  rad = sqrtf(-2.0f * logf(u01(r2)));
+  sincospif(2.0f * u01(r3), &s, &co);
+  z[2] = rad * co;
+  z[3] = rad * s;
+}
+
+// Per-quad registers.  xo/inc are the substep's start position and
+// displacement: the pair pass measures separations as
+// (xo_i - xo_j) + (inc_i - inc_j), which keeps ~1e-9 m accuracy for
+// centimetre gaps between quads several metres from the origin, where the
+// difference of the rounded end positions would be off by ~1e-6 m.
+struct Quad {
+  float x[3], v[3], R[9], w[3], u[4], e[4];
+  float fl;
+  float xo[3], inc[3];
+};
+
+struct QuadPar {
+  float m, inv_m, jx, jy, jz, ijx, ijy, ijz, f_max, a_lag, a_ns;
+};
+
+__device__ __forceinline__ float clampf(float a, float lo, float hi) {
+  return fminf(fmaxf(a, lo), hi);
+}
+
+// §III-A.1: rotor-speed command from the normalised thrust action.
+__device__ __forceinline__ float rotor_cmd(float a, bool unit) {
+  const float fh = unit ? clampf(a, 0.0f, 1.0f) : 0.5f * (clampf(a, -1.0f, 1.0f) + 1.0f);
+  return sqrtf(fh);
+}
+
+// One substep of one quad up to (not including) the in-env pair pass:
+// motor lag and noise, thrust and torque mix, floor-rest or free-flight
+// dynamics with semi-implicit Euler and Gram-Schmidt, walls and floor.
+__device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, Quad& s,
+                                             const float uhat[4], uint32_t q, uint64_t t) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s.xo[k] = s.x[k];
+  // §III-A.1 motor lag
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s.u[i] = fmaf(p.a_lag, uhat[i] - s.u[i], s.u[i]);
+  // §III-A.2 motor noise, AR(1)
+  if (c.flags & F_NOISE) {
+    float z[4];
+    normal4(c, q, t, STREAM_MOTOR, 0, z);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s.e[i] = fmaf(c.a_nd, s.e[i], p.a_ns * z[i]);
+  }
+  // §III-A.2 per-rotor thrust, §III-A mix (X layout FR, BR, BL, FL)
+  float f[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f[i] = fmaf(p.f_max * s.u[i], s.u[i], s.e[i]);
+  const float T = (f[0] + f[1]) + (f[2] + f[3]);
+  const float tx = c.arm_d * ((f[2] + f[3]) - (f[0] + f[1]));
+  const float ty = c.arm_d * ((f[1] + f[2]) - (f[0] + f[3]));
+  const float tz = c.k_tau * ((f[0] + f[2]) - (f[1] + f[3]));
+  // world-frame thrust = T * third column of R
+  const float Fx = T * s.R[2], Fy = T * s.R[5], Fz = T * s.R[8];
+
+  const bool rest = (c.flags & F_FLOOR) && s.fl != 0.0f && Fz <= p.m * c.g;
+  if (!rest) {
+    s.fl = 0.0f;
+    const float dm = c.drag * p.inv_m;
+    const float ax = fmaf(Fx, p.inv_m, -dm * s.v[0]);
+    const float ay = fmaf(Fy, p.inv_m, -dm * s.v[1]);
+    const float az = fmaf(Fz, p.inv_m, -dm * s.v[2]) - c.g;
+    // Euler's equation with the start-of-substep body rate
+    const float Lx = p.jx * s.w[0], Ly = p.jy * s.w[1], Lz = p.jz * s.w[2];
+    const float cx = s.w[1] * Lz - s.w[2] * Ly;
+    const float cy = s.w[2] * Lx - s.w[0] * Lz;
+    const float cz = s.w[0] * Ly - s.w[1] * Lx;
+    const float wdx = (tx - cx) * p.ijx, wdy = (ty - cy) * p.ijy, wdz = (tz - cz) * p.ijz;
+    // semi-implicit Euler
+    s.v[0] = fmaf(c.dt, ax, s.v[0]);
+    s.v[1] = fmaf(c.dt, ay, s.v[1]);
+    s.v[2] = fmaf(c.dt, az, s.v[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.inc[k] = c.dt * s.v[k];
+      s.x[k] = fmaf(c.dt, s.v[k], s.x[k]);
+    }
+    s.w[0] = fmaf(c.dt, wdx, s.w[0]);
+    s.w[1] = fmaf(c.dt, wdy, s.w[1]);
+    s.w[2] = fmaf(c.dt, wdz, s.w[2]);
+    // R <- R + dt R [w]x (body rate), then Gram-Schmidt on the columns
+    const float hx = c.dt * s.w[0], hy = c.dt * s.w[1], hz = c.dt * s.w[2];
+    float c0[3], c1[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float r0 = s.R[3 * r], r1 = s.R[3 * r + 1], r2 = s.R[3 * r + 2];
+      c0[r] = r0 + (r1 * hz - r2 * hy);
+      c1[r] = r1 + (r2 * hx - r0 * hz);
+    }
+    const float i0 = rsqrtf(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) c0[r] *= i0;
+    const float dp = c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) c1[r] = fmaf(-dp, c0[r], c1[r]);
+    const float i1 = rsqrtf(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) c1[r] *= i1;
+    s.R[0] = c0[0]; s.R[3] = c0[1]; s.R[6] = c0[2];
+    s.R[1] = c1[0]; s.R[4] = c1[1]; s.R[7] = c1[2];
+    s.R[2] = c0[1] * c1[2] - c0[2] * c1[1];
+    s.R[5] = c0[2] * c1[0] - c0[0] * c1[2];
+    s.R[8] = c0[0] * c1[1] - c0[1] * c1[0];
+  } else {
+    // §III-B.3 resting on the floor: friction in xy, no vertical motion,
+    // no rotation; static friction when still, kinetic when sliding.
+    const float mu_n = c.mu * (p.m * c.g - Fz);
+    float fbx, fby;
+    const float vx0 = s.v[0], vy0 = s.v[1];
+    if (vx0 == 0.0f && vy0 == 0.0f) {
+      const float nf = sqrtf(Fx * Fx + Fy * Fy);
+      const float mag = fmaxf(nf - mu_n, 0.0f);
+      const float sc = nf > 0.0f ? mag / nf : 0.0f;
+      fbx = sc * Fx;
+      fby = sc * Fy;
+    } else {
+      const float iv = mu_n / sqrtf(vx0 * vx0 + vy0 * vy0);
+      fbx = Fx - iv * vx0;
+      fby = Fy - iv * vy0;
+    }
+    s.v[0] = fmaf(c.dt, (fbx - c.drag * vx0) * p.inv_m, vx0);
+    s.v[1] = fmaf(c.dt, (fby - c.drag * vy0) * p.inv_m, vy0);
+    s.v[2] = 0.0f;
+    if (s.v[0] * vx0 + s.v[1] * vy0 < 0.0f) { s.v[0] = 0.0f; s.v[1] = 0.0f; }
+    s.inc[0] = c.dt * s.v[0];
+    s.inc[1] = c.dt * s.v[1];
+    s.inc[2] = 0.0f;
+    s.x[0] = fmaf(c.dt, s.v[0], s.x[0]);
+    s.x[1] = fmaf(c.dt, s.v[1], s.x[1]);
+    s.w[0] = s.w[1] = s.w[2] = 0.0f;
+  }
+
+  // §III-B.2 walls and ceiling: the quad meets its mirror image
+  if (c.flags & F_ROOM) {
+    bool b = false;
+    const float lo[2] = {c.rmin0, c.rmin1};
+    const float hi[3] = {c.rmax0, c.rmax1, c.rmax2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k < 2 && s.x[k] < lo[k]) {
+        s.x[k] = lo[k];
+        s.inc[k] = s.x[k] - s.xo[k];
+        if (s.v[k] < 0.0f) { s.v[k] = -c.e_wall * s.v[k]; b = true; }
+      }
+      if (s.x[k] > hi[k]) {
+        s.x[k] = hi[k];
+        s.inc[k] = s.x[k] - s.xo[k];
+        if (s.v[k] > 0.0f) { s.v[k] = -c.e_wall * s.v[k]; b = true; }
+      }
+    }
+    if (b) {
+      float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
+      if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
+        normal4(c, q, t, STREAM_WALL, 0, zv);
+        normal4(c, q, t, STREAM_WALL, 1, zw);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        s.v[k] = c.col_decay * fmaf(c.col_nv, zv[k], s.v[k]);
+        s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
+      }
+    }
+  }
+
+  // §III-B.3 floor hit: stop, level the body keeping its heading, rest
+  if ((c.flags & F_FLOOR) && s.x[2] < c.rmin2) {
+    s.x[2] = c.rmin2;
+    s.inc[2] = s.x[2] - s.xo[2];
+    s.v[0] = s.v[1] = s.v[2] = 0.0f;
+    s.w[0] = s.w[1] = s.w[2] = 0.0f;
+    s.fl = 1.0f;
+    const float hx = s.R[0], hy = s.R[3];
+    const float nh = sqrtf(hx * hx + hy * hy);
+    float ax, ay;  // unit heading of body x in the floor plane
+    if (nh >= 1e-6f) {
+      ax = hx / nh;
+      ay = hy / nh;
+    } else {
+      const float kx = s.R[1], ky = s.R[4];
+      const float nk = sqrtf(kx * kx + ky * ky);
+      const float bx = nk > 0.0f ? kx / nk : 0.0f, by = nk > 0.0f ? ky / nk : 1.0f;
+      ax = by;   // body x = body y x e_z
+      ay = -bx;
+    }
+    s.R[0] = ax;  s.R[1] = -ay; s.R[2] = 0.0f;
+    s.R[3] = ay;  s.R[4] = ax;  s.R[5] = 0.0f;
+    s.R[6] = 0.0f; s.R[7] = 0.0f; s.R[8] = 1.0f;
+  }
+}
+
+}  // namespace qs

@@ -1,0 +1,298 @@
+// Kernels of the batched quadrotor-swarm step.
+//
+// Grid: one workgroup per "block" of whole environments (host-built
+// partition, at most BS quads); one lane per quad.  The state is loaded
+// from the SoA arrays once (coalesced), kept in VGPRs for all substeps of
+// the call, and stored once.  Per substep, lanes exchange positions and
+// velocities through a double-buffered LDS tile for the in-env pair pass
+// (one barrier per substep).  The observation epilogue ranks swarm-mates
+// from the same tile, stages the output rows in LDS and writes them with
+// contiguous stores.
+#pragma once
+#include "qs_device.h"
+
+namespace qs {
+
+// KT: -2 step only; -1 observation with runtime K (selection); >= 0 observation
+// with compile-time K (register insertion network).
+template <int BS, int KT>
+__global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
+                                                  const float* __restrict__ act, int nsub,
+                                                  unsigned long long t0,
+                                                  const float* __restrict__ goals,
+                                                  float* __restrict__ obs, int stage_obs) {
+  constexpr bool OBS = KT != -2;
+  // rows 0-2: start position (pair pass) or position (observation),
+  // rows 3-5: substep displacement, rows 6-8: velocity
+  __shared__ float sxv[2][9][BS];
+  extern __shared__ float st_obs[];
+
+  const int tid = threadIdx.x;
+  const int2 bq = p.blk[blockIdx.x];
+  const bool live = tid < bq.y;
+  const int q = bq.x + (live ? tid : 0);
+  const uint32_t swd = live ? p.sw[q] : 0u;
+  const int ls = (int)(swd >> 8), n = (int)(swd & 0xffu);
+  const int Qp = p.Qp;
+  const float* __restrict__ S = p.st;
+
+  Quad s;
+  QuadPar pp;
+  float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.x[k] = S[(S_X + k) * Qp + q];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.v[k] = S[(S_V + k) * Qp + q];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s.R[k] = S[(S_R + k) * Qp + q];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.w[k] = S[(S_W + k) * Qp + q];
+    if (nsub > 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s.u[k] = S[(S_U + k) * Qp + q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s.e[k] = S[(S_E + k) * Qp + q];
+      s.fl = S[S_F * Qp + q];
+      pp.m = p.par[P_M * Qp + q];
+      pp.jx = p.par[P_JX * Qp + q];
+      pp.jy = p.par[P_JY * Qp + q];
+      pp.jz = p.par[P_JZ * Qp + q];
+      pp.f_max = p.par[P_FMAX * Qp + q];
+      pp.a_lag = p.par[P_ALAG * Qp + q];
+      pp.inv_m = 1.0f / pp.m;
+      pp.ijx = 1.0f / pp.jx;
+      pp.ijy = 1.0f / pp.jy;
+      pp.ijz = 1.0f / pp.jz;
+      pp.a_ns = c.ns_scale * pp.f_max;
+      const float4 a4 = reinterpret_cast<const float4*>(act)[q];
+      const bool unit = (c.flags & F_ACT_UNIT) != 0;
+      uhat[0] = rotor_cmd(a4.x, unit);
+      uhat[1] = rotor_cmd(a4.y, unit);
+      uhat[2] = rotor_cmd(a4.z, unit);
+      uhat[3] = rotor_cmd(a4.w, unit);
+      if (!(isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z) && isfinite(a4.w)))
+        __hip_atomic_fetch_or(p.err, ERRBIT_ACTION, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+
+  const bool collide = (c.flags & F_COLLIDE) != 0;
+  unsigned long long cmask = 0ull;
+  for (int sub = 0; sub < nsub; ++sub) {
+    const unsigned long long t = t0 + (unsigned long long)sub;
+    if (live) quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+    if (collide) {
+      // §III-B.1 in-env pair pass (Jacobi: every response from the
+      // pre-response velocities of this substep)
+      float(*tile)[BS] = sxv[sub & 1];
+      if (live) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          tile[k][tid] = s.xo[k];
+          tile[3 + k][tid] = s.inc[k];
+          tile[6 + k][tid] = s.v[k];
+        }
+      }
+      __syncthreads();
+      if (live && n > 1) {
+        float dvx = 0.f, dvy = 0.f, dvz = 0.f;
+        bool hit = false;
+        cmask = 0ull;
+        const int me = tid - ls;
+        for (int jj = 0; jj < n; ++jj) {
+          if (jj == me) continue;
+          const int j = ls + jj;
+          const float dx = (s.xo[0] - tile[0][j]) + (s.inc[0] - tile[3][j]);
+          const float dy = (s.xo[1] - tile[1][j]) + (s.inc[1] - tile[4][j]);
+          const float dz = (s.xo[2] - tile[2][j]) + (s.inc[2] - tile[5][j]);
+          const float d2 = dx * dx + dy * dy + dz * dz;
+          if (d2 < c.dcol2) {
+            cmask |= 1ull << jj;
+            float nx, ny, nz;
+            if (d2 < 1e-12f) {
+              nx = 0.f; ny = 0.f; nz = me < jj ? 1.f : -1.f;
+            } else {
+              const float id = rsqrtf(d2);
+              nx = dx * id; ny = dy * id; nz = dz * id;
+            }
+            const float sp = (tile[6][j] - s.v[0]) * nx + (tile[7][j] - s.v[1]) * ny +
+                             (tile[8][j] - s.v[2]) * nz;
+            if (!(c.flags & F_APPROACH) || sp > 0.f) {
+              dvx = fmaf(sp, nx, dvx);
+              dvy = fmaf(sp, ny, dvy);
+              dvz = fmaf(sp, nz, dvz);
+              hit = true;
+            }
+          }
+        }
+        if (hit) {
+          float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
+          if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
+            normal4(c, (uint32_t)q, t, STREAM_PAIR, 0, zv);
+            normal4(c, (uint32_t)q, t, STREAM_PAIR, 1, zw);
+          }
+          s.v[0] = c.col_decay * (s.v[0] + dvx + c.col_nv * zv[0]);
+          s.v[1] = c.col_decay * (s.v[1] + dvy + c.col_nv * zv[1]);
+          s.v[2] = c.col_decay * (s.v[2] + dvz + c.col_nv * zv[2]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
+        }
+      } else {
+        cmask = 0ull;
+      }
+    }
+  }
+
+  if (live && nsub > 0) {
+    float* St = p.st;
+    float chk = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { St[(S_X + k) * Qp + q] = s.x[k]; chk += s.x[k]; }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { St[(S_V + k) * Qp + q] = s.v[k]; chk += s.v[k]; }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { St[(S_R + k) * Qp + q] = s.R[k]; chk += s.R[k]; }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { St[(S_W + k) * Qp + q] = s.w[k]; chk += s.w[k]; }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { St[(S_U + k) * Qp + q] = s.u[k]; chk += s.u[k]; }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { St[(S_E + k) * Qp + q] = s.e[k]; chk += s.e[k]; }
+    St[S_F * Qp + q] = s.fl;
+    if (!isfinite(chk))
+      __hip_atomic_fetch_or(p.err, ERRBIT_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p.contacts) p.contacts[q] = cmask;
+  }
+
+  if constexpr (OBS) {
+    // §III-C observation from the post-collision state
+    const int OD = KT >= 0 ? 18 + 6 * KT : c.obs_dim;
+    const int K = KT >= 0 ? KT : c.K;
+    float(*tile)[BS] = sxv[nsub & 1];
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        tile[k][tid] = s.x[k];
+        tile[6 + k][tid] = s.v[k];
+      }
+    }
+    __syncthreads();
+    const int ODP = OD | 1;  // odd LDS row stride: conflict-free staging
+    float* row = stage_obs ? st_obs + tid * ODP : obs + (size_t)q * OD;
+    if (live) {
+      const float g0 = goals[3 * q], g1 = goals[3 * q + 1], g2 = goals[3 * q + 2];
+      row[0] = s.x[0] - g0;
+      row[1] = s.x[1] - g1;
+      row[2] = s.x[2] - g2;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) row[3 + k] = s.v[k];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) row[6 + k] = s.R[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) row[15 + k] = s.w[k];
+      const int me = tid - ls;
+      if constexpr (KT > 0) {
+        // sorted (d^2, index) list of the KT nearest, kept in registers
+        float bd[KT];
+        int bj[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) { bd[k] = INFINITY; bj[k] = -1; }
+        for (int jj = 0; jj < n; ++jj) {
+          if (jj == me) continue;
+          const int j = ls + jj;
+          const float rx = tile[0][j] - s.x[0], ry = tile[1][j] - s.x[1], rz = tile[2][j] - s.x[2];
+          const float d2 = rx * rx + ry * ry + rz * rz;
+#pragma unroll
+          for (int k = KT - 1; k > 0; --k) {
+            const bool shift = bd[k - 1] > d2;
+            const bool here = bd[k] > d2;
+            bd[k] = shift ? bd[k - 1] : (here ? d2 : bd[k]);
+            bj[k] = shift ? bj[k - 1] : (here ? jj : bj[k]);
+          }
+          if (bd[0] > d2) { bd[0] = d2; bj[0] = jj; }
+        }
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+          float* o = row + 18 + 6 * k;
+          if (bj[k] >= 0) {
+            const int j = ls + bj[k];
+            o[0] = tile[0][j] - s.x[0];
+            o[1] = tile[1][j] - s.x[1];
+            o[2] = tile[2][j] - s.x[2];
+            o[3] = tile[6][j] - s.v[0];
+            o[4] = tile[7][j] - s.v[1];
+            o[5] = tile[8][j] - s.v[2];
+          } else {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) o[m] = 0.f;
+          }
+        }
+      } else if constexpr (KT == -1) {
+        // runtime K: K passes of selection of the next (d^2, index) pair
+        float pd = -1.0f;
+        int pj = -1;
+        for (int k = 0; k < K; ++k) {
+          float bd = INFINITY;
+          int bj = -1;
+          for (int jj = 0; jj < n; ++jj) {
+            if (jj == me) continue;
+            const int j = ls + jj;
+            const float rx = tile[0][j] - s.x[0], ry = tile[1][j] - s.x[1], rz = tile[2][j] - s.x[2];
+            const float d2 = rx * rx + ry * ry + rz * rz;
+            const bool after = d2 > pd || (d2 == pd && jj > pj);
+            const bool better = d2 < bd || (d2 == bd && jj < bj);
+            if (after && better) { bd = d2; bj = jj; }
+          }
+          float* o = row + 18 + 6 * k;
+          if (bj >= 0) {
+            const int j = ls + bj;
+            o[0] = tile[0][j] - s.x[0];
+            o[1] = tile[1][j] - s.x[1];
+            o[2] = tile[2][j] - s.x[2];
+            o[3] = tile[6][j] - s.v[0];
+            o[4] = tile[7][j] - s.v[1];
+            o[5] = tile[8][j] - s.v[2];
+            pd = bd;
+            pj = bj;
+          } else {
+            for (int m = 0; m < 6; ++m) o[m] = 0.f;
+            pd = INFINITY;
+            pj = 1 << 30;
+          }
+        }
+      }
+    }
+    if (stage_obs) {
+      __syncthreads();
+      float* dst = obs + (size_t)bq.x * OD;
+      const int total = bq.y * OD;
+      for (int i = tid; i < total; i += BS) {
+        const int r = i / OD;
+        dst[i] = st_obs[r * ODP + (i - r * OD)];
+      }
+    }
+  }
+}
+
+// Canonical [Q][27] -> private SoA, for environments selected by env_mask.
+__global__ void set_state_kernel(float* __restrict__ st, int Qp, int Q,
+                                 const float* __restrict__ src,
+                                 const int32_t* __restrict__ qenv,
+                                 const uint8_t* __restrict__ env_mask) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)Q * NSTATE) return;
+  const int q = (int)(i / NSTATE), f = (int)(i - (long long)q * NSTATE);
+  if (env_mask && env_mask[qenv[q]] == 0) return;
+  st[(size_t)f * Qp + q] = src[i];
+}
+
+// Private SoA -> canonical [Q][27].
+__global__ void get_state_kernel(const float* __restrict__ st, int Qp, int Q,
+                                 float* __restrict__ dst) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)Q * NSTATE) return;
+  const int q = (int)(i / NSTATE), f = (int)(i - (long long)q * NSTATE);
+  dst[i] = st[(size_t)f * Qp + q];
+}
+
+}  // namespace qs

@@ -1,0 +1,216 @@
+"""Python binding of the C ABI in include/quadswarm.h (ctypes).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of ``libquadswarm.so``.  PyTorch provides device memory and the
+current stream; nothing here computes on tensors.  If the library is not
+built, :func:`lib` raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libquadswarm.so")
+
+QS_OK = 0
+ERRORS = {-1: "QS_ERR_NULL", -2: "QS_ERR_INVALID", -3: "QS_ERR_ENV_SIZE", -4: "QS_ERR_HIP",
+          -5: "QS_ERR_NONFINITE", -6: "QS_ERR_NOMEM", -7: "QS_ERR_ALIGN", -8: "QS_ERR_UNSUPPORTED"}
+
+# every entry point of include/quadswarm.h
+EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_step", "qs_observe", "qs_step_observe",
+           "qs_get_state", "qs_set_state", "qs_record_contacts", "qs_debug_contacts", "qs_sync",
+           "qs_error_string")
+
+
+class QuadSwarmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib().qs_error_string(code).decode()
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({msg})")
+
+
+class qs_desc(C.Structure):
+    _fields_ = [
+        ("n_envs", C.c_int32), ("env_offsets", C.POINTER(C.c_int32)),
+        ("dt", C.c_float), ("gravity", C.c_float), ("arm_length", C.c_float),
+        ("k_tau", C.c_float), ("drag_coef", C.c_float), ("floor_mu", C.c_float),
+        ("motor_noise_decay", C.c_float), ("motor_noise_std", C.c_float),
+        ("room_min", C.c_float * 3), ("room_max", C.c_float * 3),
+        ("wall_restitution", C.c_float),
+        ("col_dist", C.c_float), ("col_decay", C.c_float),
+        ("col_noise_v", C.c_float), ("col_noise_w", C.c_float),
+        ("k_neighbors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libquadswarm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2306_09537_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u64 = C.c_void_p, C.c_int32, C.c_uint64
+        L.qs_create.argtypes = [C.POINTER(qs_desc), vp, vp, C.POINTER(vp)]
+        L.qs_destroy.argtypes = [vp]
+        L.qs_sizes.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.qs_step.argtypes = [vp, vp, i32, vp]
+        L.qs_observe.argtypes = [vp, vp, vp, vp]
+        L.qs_step_observe.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.qs_get_state.argtypes = [vp, vp, C.POINTER(u64), vp]
+        L.qs_set_state.argtypes = [vp, vp, u64, vp, vp]
+        L.qs_record_contacts.argtypes = [vp, i32]
+        L.qs_debug_contacts.argtypes = [vp, vp, vp]
+        L.qs_sync.argtypes = [vp, vp]
+        L.qs_error_string.argtypes = [C.c_int]
+        L.qs_error_string.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "qs_error_string":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != QS_OK:
+        raise QuadSwarmError(rc, where)
+
+
+def make_desc(env_offsets: np.ndarray, consts: dict, k_neighbors: int, flags: int,
+              seed: int) -> qs_desc:
+    d = qs_desc()
+    d.n_envs = int(env_offsets.shape[0] - 1)
+    d.env_offsets = env_offsets.ctypes.data_as(C.POINTER(C.c_int32))
+    for k in ("dt", "gravity", "arm_length", "k_tau", "drag_coef", "floor_mu",
+              "motor_noise_decay", "motor_noise_std", "wall_restitution", "col_dist",
+              "col_decay", "col_noise_v", "col_noise_w"):
+        setattr(d, k, float(consts[k]))
+    d.room_min = (C.c_float * 3)(*[float(v) for v in consts["room_min"]])
+    d.room_max = (C.c_float * 3)(*[float(v) for v in consts["room_max"]])
+    d.k_neighbors = int(k_neighbors)
+    d.flags = int(flags)
+    d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    return d
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class QuadSwarm:
+    """One handle: E environments of swarms, Q quads, on the current device."""
+
+    def __init__(self, env_offsets, consts: dict, params, state0, k_neighbors: int,
+                 flags: int, seed: int):
+        import torch
+        self._offs = np.ascontiguousarray(env_offsets, dtype=np.int32)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        s0 = np.ascontiguousarray(state0, dtype=np.float32)
+        desc = make_desc(self._offs, consts, k_neighbors, flags, seed)
+        h = C.c_void_p()
+        _check(lib().qs_create(C.byref(desc), p.ctypes.data, s0.ctypes.data, C.byref(h)),
+               "qs_create")
+        self._h = h
+        q, e, od = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().qs_sizes(h, C.byref(q), C.byref(e), C.byref(od)), "qs_sizes")
+        self.n_quads, self.n_envs, self.obs_dim = q.value, e.value, od.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_workload(cls, w: "W.Workload") -> "QuadSwarm":
+        return cls(w.env_offsets, w.consts, w.params, w.state0, w.k_neighbors, w.flags,
+                   w.rng_key)
+
+    # -- helpers -----------------------------------------------------------
+    def _dev(self, t, shape, dtype=None):
+        import torch
+        dtype = dtype or torch.float32
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype
+                and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected a contiguous CUDA {dtype} tensor of shape {shape}")
+        return t
+
+    # -- API ---------------------------------------------------------------
+    def step(self, actions, n_substeps: int = 1) -> None:
+        a = self._dev(actions, (self.n_quads, 4))
+        _check(lib().qs_step(self._h, _ptr(a), int(n_substeps), _stream()), "qs_step")
+
+    def observe(self, goals, out=None):
+        import torch
+        g = self._dev(goals, (self.n_quads, 3))
+        o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
+                                                    device=self.device)
+        self._dev(o, (self.n_quads, self.obs_dim))
+        _check(lib().qs_observe(self._h, _ptr(g), _ptr(o), _stream()), "qs_observe")
+        return o
+
+    def step_observe(self, actions, n_substeps: int, goals, out=None):
+        import torch
+        a = self._dev(actions, (self.n_quads, 4))
+        g = self._dev(goals, (self.n_quads, 3))
+        o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
+                                                    device=self.device)
+        self._dev(o, (self.n_quads, self.obs_dim))
+        _check(lib().qs_step_observe(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
+                                     _stream()), "qs_step_observe")
+        return o
+
+    def get_state(self, out=None):
+        import torch
+        o = out if out is not None else torch.empty((self.n_quads, 27), device=self.device)
+        self._dev(o, (self.n_quads, 27))
+        t = C.c_uint64()
+        _check(lib().qs_get_state(self._h, _ptr(o), C.byref(t), _stream()), "qs_get_state")
+        return o, int(t.value)
+
+    def set_state(self, state, substep: int, env_mask=None) -> None:
+        import torch
+        s = self._dev(state, (self.n_quads, 27))
+        m = None
+        if env_mask is not None:
+            m = self._dev(env_mask, (self.n_envs,), torch.uint8)
+        _check(lib().qs_set_state(self._h, _ptr(s), C.c_uint64(int(substep)),
+                                  None if m is None else _ptr(m), _stream()), "qs_set_state")
+
+    def record_contacts(self, enable: bool = True) -> None:
+        _check(lib().qs_record_contacts(self._h, 1 if enable else 0), "qs_record_contacts")
+
+    def debug_contacts(self):
+        import torch
+        o = torch.empty(self.n_quads, dtype=torch.int64, device=self.device)
+        _check(lib().qs_debug_contacts(self._h, _ptr(o), _stream()), "qs_debug_contacts")
+        return o
+
+    def sync(self) -> None:
+        _check(lib().qs_sync(self._h, _stream()), "qs_sync")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().qs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

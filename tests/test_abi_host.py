@@ -1,0 +1,127 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the header declares, agrees with the interface constants,
+and rejects bad arguments with the documented codes before touching HIP."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2306_09537_amd import quadswarm as QS
+from paper_2306_09537_amd import workloads as W
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "quadswarm.h")
+
+
+def header_text():
+    return open(HEADER).read()
+
+
+def test_library_exports_every_declared_symbol():
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(qs_\w+)\s*\(", header_text(), re.M))
+    assert declared == set(QS.EXPORTS)
+    L = QS.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_header_constants_match_interface():
+    t = header_text()
+    val = {m.group(1): int(m.group(2), 0) for m in re.finditer(r"#define (QS_\w+) \(?(-?\w+?)u?\)?\s", t)}
+    assert val["QS_ROOM"] == W.QS_ROOM == O.flag_values()[0]
+    assert val["QS_FLOOR"] == W.QS_FLOOR
+    assert val["QS_COLLIDE"] == W.QS_COLLIDE
+    assert val["QS_MOTOR_NOISE"] == W.QS_MOTOR_NOISE
+    assert val["QS_APPROACH_ONLY"] == W.QS_APPROACH_ONLY
+    assert val["QS_ACT_UNIT"] == W.QS_ACT_UNIT
+    assert val["QS_STATE_DIM"] == W.STATE_DIM and val["QS_PARAM_DIM"] == W.PARAM_DIM
+    for code, name in QS.ERRORS.items():
+        assert val[name] == code
+
+
+def test_desc_struct_layout_matches_c_compiler(tmp_path):
+    """The ctypes mirror of qs_desc has the C compiler's size and offsets."""
+    import subprocess
+    fields = [f[0] for f in QS.qs_desc._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "quadswarm.h"', 'int main(void){',
+             'printf("%zu\\n", sizeof(qs_desc));']
+    lines += [f'printf("%zu\\n", offsetof(qs_desc, {f}));' for f in fields]
+    lines += ['printf("%zu\\n", sizeof(qs_quad_params)); return 0; }']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == C.sizeof(QS.qs_desc)
+    assert vals[1:-1] == [getattr(QS.qs_desc, f).offset for f in fields]
+    assert vals[-1] == 4 * W.PARAM_DIM
+
+
+def test_error_strings():
+    L = QS.lib()
+    assert L.qs_error_string(0) == b"ok"
+    for code in QS.ERRORS:
+        s = L.qs_error_string(code)
+        assert s and s != b"unknown error code"
+    assert L.qs_error_string(12345) == b"unknown error code"
+
+
+def _create(w, offs=None, consts=None, k=None, flags=None, params=None, state0=None):
+    offs = np.ascontiguousarray(w.env_offsets if offs is None else offs, dtype=np.int32)
+    d = QS.make_desc(offs, consts or w.consts, w.k_neighbors if k is None else k,
+                     w.flags if flags is None else flags, w.rng_key)
+    p = np.ascontiguousarray(w.params if params is None else params, dtype=np.float32)
+    s = np.ascontiguousarray(w.state0 if state0 is None else state0, dtype=np.float32)
+    h = C.c_void_p()
+    rc = QS.lib().qs_create(C.byref(d), p.ctypes.data, s.ctypes.data, C.byref(h))
+    return rc, h
+
+
+def test_create_rejects_bad_arguments_before_any_hip_call():
+    L = QS.lib()
+    w = W.swarm8(n_envs=4)
+    h = C.c_void_p()
+    d = QS.make_desc(w.env_offsets, w.consts, 6, w.flags, 1)
+    assert L.qs_create(None, w.params.ctypes.data, w.state0.ctypes.data, C.byref(h)) == -1
+    assert L.qs_create(C.byref(d), None, w.state0.ctypes.data, C.byref(h)) == -1
+    assert L.qs_create(C.byref(d), w.params.ctypes.data, w.state0.ctypes.data, None) == -1
+    # swarm of 0, of 65, non-CSR start
+    assert _create(w, offs=[0, 8, 8, 16, 24, 32])[0] == -3
+    w65 = W.custom([65], k=0)
+    assert _create(w65)[0] == -3
+    assert _create(w, offs=[1, 8, 16, 24, 32])[0] == -3
+    # constants
+    for key, bad in (("dt", 0.0), ("dt", float("nan")), ("motor_noise_decay", 1.0),
+                     ("wall_restitution", 1.5), ("col_dist", -0.1), ("drag_coef", -1.0)):
+        c = dict(w.consts)
+        c[key] = bad
+        assert _create(w, consts=c)[0] == -2, key
+    c = dict(w.consts)
+    c["room_min"] = (5.0, -5.0, 0.0)
+    assert _create(w, consts=c)[0] == -2
+    assert _create(w, k=-1)[0] == -2
+    assert _create(w, k=64)[0] == -2
+    assert _create(w, flags=64)[0] == -2
+    p = w.params.copy()
+    p[3, 0] = 0.0
+    assert _create(w, params=p)[0] == -2
+    s = w.state0.copy()
+    s[5, 7] = np.inf
+    assert _create(w, state0=s)[0] == -2
+
+
+def test_calls_on_null_handle():
+    L = QS.lib()
+    assert L.qs_step(None, None, 1, None) == -1
+    assert L.qs_observe(None, None, None, None) == -1
+    assert L.qs_step_observe(None, None, 1, None, None, None) == -1
+    assert L.qs_get_state(None, None, None, None) == -1
+    assert L.qs_set_state(None, None, 0, None, None) == -1
+    assert L.qs_debug_contacts(None, None, None) == -1
+    assert L.qs_record_contacts(None, 1) == -1
+    assert L.qs_sync(None, None) == -1
+    assert L.qs_sizes(None, None, None, None) == -1
+    assert L.qs_destroy(None) == 0

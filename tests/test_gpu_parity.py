@@ -1,0 +1,371 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Teacher-forced: after every call the oracle restarts from the GPU's float32
+state (exact in float64) and takes the same substeps; the GPU's next state
+must agree to a relative 1e-5 per state block (floors 1 m, 1 m/s, 1, 1 rad/s,
+f_max for the motor noise).  Quads whose call took a threshold decision
+(wall, floor, take-off, contact, approach, friction stop) within 1e-5 of its
+threshold are excluded and counted.  Contact sets must be equal apart from
+pairs within 1e-6 m of the contact distance; neighbour lists equal apart
+from distance ties below 1e-6 m.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2306_09537_amd import workloads as W  # noqa: E402
+from paper_2306_09537_amd.quadswarm import QuadSwarm, QuadSwarmError  # noqa: E402
+from tests import gpu_util as U  # noqa: E402
+from tests.helpers import blank_state, consts, nominal_params, rot_x, rot_z  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def teacher_forced(w, n_calls, nsub=1, fused=False, env_range=None, check_obs=True,
+                   record=True, action_fn=None, tol=U.TOL):
+    sim = QuadSwarm.from_workload(w)
+    sim.record_contacts(record)
+    e0, e1 = env_range or (0, w.n_envs)
+    orc = O.Oracle.from_workload(w, e0, e1)
+    q0, q1 = int(w.env_offsets[e0]), int(w.env_offsets[e1])
+    offs = (w.env_offsets[e0:e1 + 1] - q0).astype(np.int64)
+    fmax = U.fmax_of(w.params[q0:q1])
+    goals_d = dev(w.goals)
+    goals = w.goals[q0:q1].astype(np.float64)
+    prev = w.state0[q0:q1].astype(np.float64)
+    st = dict(calls=0, excluded=0, max_err=0.0, contacts=0, contact_ties=0, obs_ties=0, events=0)
+    for call in range(n_calls):
+        a = action_fn(call) if action_fn else w.actions(call)
+        a_d = dev(a)
+        if fused:
+            obs_d = sim.step_observe(a_d, nsub, goals_d)
+        else:
+            sim.step(a_d, nsub)
+            obs_d = sim.observe(goals_d) if check_obs else None
+        s_d, t = sim.get_state()
+        c_d = sim.debug_contacts() if record else None
+        sim.sync()
+        assert t == (call + 1) * nsub
+        s_gpu = s_d.cpu().numpy()[q0:q1].astype(np.float64)
+        ref, c_ref, ev, mg = orc.step(prev, a[q0:q1], nsub, call * nsub, margins=True)
+        err = U.rel_err(s_gpu, ref, fmax).max(axis=1)
+        near = mg < U.MARGIN
+        bad = (err > tol) & ~near
+        if bad.any():
+            q = int(np.nonzero(bad)[0][0])
+            col = int(np.argmax(U.rel_err(s_gpu, ref, fmax)[q]))
+            raise AssertionError(f"call {call}: quad {q + q0} field {col} gpu {s_gpu[q, col]!r} "
+                                 f"oracle {ref[q, col]!r} err {err[q]:.3g} margin {mg[q]:.3g} "
+                                 f"events {ev[q]}")
+        st["excluded"] += int(((err > tol) & near).sum())
+        if (~near).any():
+            st["max_err"] = max(st["max_err"], float(err[~near].max()))
+        st["events"] += int(np.count_nonzero(ev))
+        if record and w.flags & W.QS_COLLIDE:
+            c_gpu = c_d.cpu().numpy().view(np.uint64)[q0:q1]
+            ok = ~near
+            # compare envs with no excluded quad
+            env_of = np.searchsorted(offs, np.arange(q1 - q0), side="right") - 1
+            env_bad = np.zeros(len(offs) - 1, bool)
+            env_bad[env_of[near]] = True
+            sel = ~env_bad[env_of]
+            st["contact_ties"] += U.check_contacts(
+                np.where(sel, c_gpu, 0), np.where(sel, c_ref, 0), s_gpu[:, 0:3], ref[:, 0:3],
+                offs, w.consts["col_dist"])
+            st["contacts"] += int(sum(bin(int(x)).count("1") for x in c_ref[ok & (c_ref != 0)]))
+        if obs_d is not None:
+            o_ref, _ = orc.observe(s_gpu, goals)
+            st["obs_ties"] += U.check_obs(obs_d.cpu().numpy()[q0:q1], o_ref, s_gpu, offs,
+                                          w.k_neighbors)
+        prev = s_gpu
+        st["calls"] += 1
+    sim.close()
+    return st
+
+
+# ----------------------------------------------------------------- plain
+@pytest.mark.parametrize("noise", [False, True])
+def test_plain_teacher_forced_1000(noise):
+    w = W.plain(seed=0, noise=noise)
+    st = teacher_forced(w, 1000)
+    print("plain", noise, st)
+    assert st["max_err"] <= U.TOL
+
+
+def test_plain_free_run_100():
+    """64 x 1, no room: both programs run on their own for 100 steps."""
+    w = W.plain(seed=1)
+    sim = QuadSwarm.from_workload(w)
+    orc = O.Oracle.from_workload(w)
+    s = w.state0.astype(np.float64)
+    worst = 0.0
+    for t in range(100):
+        a = w.actions(t)
+        sim.step(dev(a), 1)
+        s, _, ev = orc.step(s, a, 1, t)
+        assert not ev.any()
+        g, _ = sim.get_state()
+        worst = max(worst, float(np.abs(g.cpu().numpy()[:, 0:3] - s[:, 0:3]).max()))
+    sim.sync()
+    print("free-run max |dx| =", worst)
+    assert worst <= 1e-4
+
+
+# ----------------------------------------------------------------- swarms
+def test_swarm8_teacher_forced_subset():
+    w = W.swarm8(seed=0, n_envs=256)
+    st = teacher_forced(w, 600)
+    print("swarm8/256", st)
+    assert st["contacts"] > 0 and st["events"] > 0
+    assert st["max_err"] <= U.TOL
+
+
+def test_swarm8_full_size_bench_config_sampled():
+    """4096 x 8 at full size in the benchmark's launch configuration (one
+    qs_step_observe launch per substep); envs 1000..1255 and 3840..4095
+    checked against the oracle after every call."""
+    w = W.swarm8(seed=1)
+    for rng in ((1000, 1256), (3840, 4096)):
+        st = teacher_forced(w, 100, nsub=1, fused=True, env_range=rng)
+        print("swarm8 full", rng, st)
+        assert st["max_err"] <= U.TOL
+
+
+def test_swarm8_full_size_fused10_sampled():
+    """Fused 10-substep calls: the oracle is re-seeded only every 10
+    substeps, so the bound is 10 x the per-substep bound."""
+    w = W.swarm8(seed=2)
+    st = teacher_forced(w, 20, nsub=10, fused=True, env_range=(2000, 2256), tol=10 * U.TOL)
+    print("swarm8 full fused10", st)
+    assert st["max_err"] <= 10 * U.TOL
+
+
+def test_dense_swarms_many_contacts():
+    """Swarms of 32 packed into 0.6 m cubes: many simultaneous contacts."""
+    w = W.custom([32] * 16, seed=3, k=6, name="dense")
+    rng = np.random.default_rng(3)
+    s0 = w.state0.copy()
+    for e in range(16):
+        c = rng.uniform(-2, 2, 3) + [0, 0, 4]
+        s0[32 * e:32 * e + 32, 0:3] = c + rng.uniform(-0.3, 0.3, size=(32, 3))
+    w = w.with_(state0=s0.astype(np.float32))
+    st = teacher_forced(w, 200)
+    print("dense", st)
+    assert st["contacts"] > 200
+    assert st["max_err"] <= U.TOL
+
+
+@pytest.mark.parametrize("block", ["64", "128", "256"])
+@pytest.mark.parametrize("k", [3, 6])
+def test_uneven_swarms(block, k, monkeypatch):
+    monkeypatch.setenv("QS_BLOCK_SIZE", block)
+    w = W.uneven(seed=2, n_envs=300).with_(k_neighbors=k)
+    st = teacher_forced(w, 40)
+    print("uneven", block, k, st)
+    assert st["max_err"] <= U.TOL
+
+
+def test_ragged_and_extreme_sizes():
+    sizes = [64, 1, 3, 5, 7, 64, 2]  # maximum swarm, singletons, ragged tail
+    w = W.custom(sizes, seed=5, k=6, name="ragged")
+    st = teacher_forced(w, 60)
+    assert st["max_err"] <= U.TOL
+    w1 = W.custom([1], seed=6, k=6, name="one")  # K > n - 1: all slots padded
+    st = teacher_forced(w1, 30)
+    assert st["max_err"] <= U.TOL
+
+
+def test_action_unit_mapping():
+    w = W.swarm8(seed=7, n_envs=64).with_(flags=W.SWARM_FLAGS | W.QS_ACT_UNIT)
+    st = teacher_forced(w, 100)
+    assert st["max_err"] <= U.TOL
+
+
+def test_collision_and_wall_noise_streams():
+    w = W.swarm8(seed=8, n_envs=64)
+    c = dict(w.consts, col_noise_v=0.05, col_noise_w=0.2, col_decay=0.9, drag_coef=0.002)
+    rng = np.random.default_rng(8)
+    s0 = w.state0.copy()
+    s0[:, 0:3] = np.repeat(rng.uniform(-4, 4, size=(64, 3)), 8, axis=0) + rng.uniform(
+        -0.15, 0.15, size=(512, 3))
+    s0[:, 2] = np.abs(s0[:, 2]) + 0.2
+    w = w.with_(consts=c, state0=s0.astype(np.float32))
+    st = teacher_forced(w, 150)
+    assert st["contacts"] > 0
+    assert st["max_err"] <= U.TOL
+
+
+# ------------------------------------------------------- equivalences
+def test_fused_equals_separate_calls_bitwise():
+    w = W.swarm8(seed=9, n_envs=128)
+    a = dev(w.actions(0))
+    g = dev(w.goals)
+    s1 = QuadSwarm.from_workload(w)
+    s2 = QuadSwarm.from_workload(w)
+    s3 = QuadSwarm.from_workload(w)
+    o1 = s1.step_observe(a, 10, g)
+    s2.step(a, 10)
+    o2 = s2.observe(g)
+    for _ in range(10):
+        s3.step(a, 1)
+    o3 = s3.observe(g)
+    x1, x2, x3 = s1.get_state()[0], s2.get_state()[0], s3.get_state()[0]
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2) and torch.equal(x1, x2)
+    assert torch.equal(x2, x3) and torch.equal(o2, o3)
+
+
+def test_resume_and_masked_set_state_bitwise():
+    w = W.swarm8(seed=10, n_envs=64)
+    g = dev(w.goals)
+    sim = QuadSwarm.from_workload(w)
+    for t in range(30):
+        sim.step(dev(w.actions(t)), 2)
+    snap, t30 = sim.get_state()
+    snap = snap.clone()
+    for t in range(30, 60):
+        sim.step(dev(w.actions(t)), 2)
+    end_a, _ = sim.get_state()
+    end_a = end_a.clone()
+    sim.set_state(snap, t30)
+    for t in range(30, 60):
+        sim.step(dev(w.actions(t)), 2)
+    end_b, t60 = sim.get_state()
+    torch.cuda.synchronize()
+    assert t30 == 60 and t60 == 120
+    assert torch.equal(end_a, end_b)
+    # masked reset: only even envs take the snapshot
+    mask = torch.zeros(w.n_envs, dtype=torch.uint8, device="cuda")
+    mask[::2] = 1
+    sim.set_state(snap, 120, mask)
+    cur, _ = sim.get_state()
+    torch.cuda.synchronize()
+    env_of = np.repeat(np.arange(w.n_envs), 8)
+    even = torch.from_numpy(env_of % 2 == 0).cuda()
+    assert torch.equal(cur[even], snap[even]) and torch.equal(cur[~even], end_b[~even])
+    sim.sync()
+
+
+def test_determinism_two_runs():
+    w = W.swarm8(seed=11, n_envs=256)
+    outs = []
+    for _ in range(2):
+        sim = QuadSwarm.from_workload(w)
+        for t in range(50):
+            o = sim.step_observe(dev(w.actions(t)), 2, dev(w.goals))
+        outs.append((sim.get_state()[0].cpu(), o.cpu()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_zero_substeps_is_noop():
+    w = W.swarm8(seed=12, n_envs=16)
+    sim = QuadSwarm.from_workload(w)
+    before, t0 = sim.get_state()
+    before = before.clone()
+    sim.step(dev(w.actions(0)), 0)
+    after, t1 = sim.get_state()
+    torch.cuda.synchronize()
+    assert t0 == t1 == 0 and torch.equal(before, after)
+
+
+# ----------------------------------------------------------- errors
+def test_nonfinite_action_is_sticky_error():
+    w = W.swarm8(seed=13, n_envs=8)
+    sim = QuadSwarm.from_workload(w)
+    a = w.actions(0)
+    a[5, 2] = np.nan
+    sim.step(dev(a), 1)
+    with pytest.raises(QuadSwarmError) as ei:
+        sim.sync()
+    assert ei.value.code == -5
+    sim.sync()  # cleared
+    with pytest.raises(QuadSwarmError) as ei:
+        sim.step(dev(w.actions(0)), -1)
+    assert ei.value.code == -2
+    with pytest.raises(ValueError):
+        sim.step(torch.zeros(3, 4, device="cuda"), 1)
+
+
+# --------------------------------------------------- closed forms on GPU
+def _custom_sim(state, params=None, flags=0, k=0, sizes=None, **c):
+    q = state.shape[0]
+    sizes = sizes or [1] * q
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    p = params if params is not None else nominal_params(q)
+    return QuadSwarm(offs, consts(**c), p, state, k, flags, 3)
+
+
+def test_gpu_hover_and_free_fall():
+    s = blank_state(2, z=50.0)
+    s[0, W.SU:W.SU + 4] = math.sqrt(0.5)
+    s[1, W.SU:W.SU + 4] = 0.0
+    sim = _custom_sim(s)
+    a = np.array([[0.0] * 4, [-1.0] * 4])
+    for _ in range(100):
+        sim.step(dev(a), 1)
+    out = sim.get_state()[0].cpu().numpy().astype(np.float64)
+    assert np.abs(out[0, W.SV:W.SV + 3]).max() < 1e-5        # hover: no acceleration
+    n, dt, g = 100, 0.005, 9.81
+    assert out[1, W.SV + 2] == pytest.approx(-n * g * dt, rel=1e-6)
+    assert out[1, 2] == pytest.approx(50.0 - g * dt * dt * n * (n + 1) / 2, rel=1e-6)
+
+
+def test_gpu_rotation_stays_orthonormal():
+    w = W.swarm8(seed=14, n_envs=64)
+    sim = QuadSwarm.from_workload(w)
+    for t in range(1000):
+        sim.step(dev(w.actions(t % 50)), 1)
+    R = sim.get_state()[0].cpu().numpy()[:, W.SR:W.SR + 9].reshape(-1, 3, 3).astype(np.float64)
+    assert np.abs(np.einsum("qki,qkj->qij", R, R) - np.eye(3)).max() < 2e-6
+    assert np.abs(np.linalg.det(R) - 1).max() < 3e-6
+
+
+def test_gpu_momentum_conserved_in_pile_up():
+    rng = np.random.default_rng(15)
+    n = 32
+    s = blank_state(n, z=5.0)
+    s[:, 0:3] = [0, 0, 5.0] + rng.uniform(-0.1, 0.1, size=(n, 3))
+    s[:, W.SV:W.SV + 3] = rng.normal(0, 1.0, size=(n, 3))
+    s[:, W.SU:W.SU + 4] = 0.0
+    sim = _custom_sim(s, flags=W.QS_COLLIDE | W.QS_APPROACH_ONLY, sizes=[n], gravity=0.0)
+    sim.record_contacts(True)
+    sim.step(dev(-np.ones((n, 4))), 1)
+    out = sim.get_state()[0].cpu().numpy().astype(np.float64)
+    c = sim.debug_contacts().cpu().numpy().view(np.uint64)
+    assert sum(bin(int(x)).count("1") for x in c) > 2 * n
+    np.testing.assert_allclose(out[:, W.SV:W.SV + 3].sum(0), s[:, W.SV:W.SV + 3].sum(0), atol=2e-5)
+    assert not np.allclose(out[:, W.SV:W.SV + 3], s[:, W.SV:W.SV + 3])
+
+
+def test_gpu_floor_hit_and_rest():
+    s = blank_state(1, z=0.002)
+    s[0, W.SR:W.SR + 9] = (rot_z(1.1) @ rot_x(0.5)).reshape(9)
+    s[0, W.SV:W.SV + 3] = [0.5, 0.2, -1.0]
+    s[0, W.SU:W.SU + 4] = 0.0
+    sim = _custom_sim(s, flags=W.QS_FLOOR)
+    sim.step(dev(-np.ones((1, 4))), 1)
+    hit = sim.get_state()[0].cpu().numpy()[0].astype(np.float64)
+    for _ in range(50):
+        sim.step(dev(np.full((1, 4), -0.2)), 1)
+    rest = sim.get_state()[0].cpu().numpy()[0].astype(np.float64)
+    assert hit[2] == 0.0 and hit[W.SF] == 1.0 and np.all(hit[W.SV:W.SV + 3] == 0.0)
+    R = hit[W.SR:W.SR + 9].reshape(3, 3)
+    np.testing.assert_allclose(R[:, 2], [0, 0, 1], atol=0)
+    assert math.atan2(R[1, 0], R[0, 0]) == pytest.approx(1.1, abs=2e-6)
+    assert np.all(rest[0:3] == hit[0:3]) and rest[W.SF] == 1.0

@@ -566,3 +566,19 @@ def test_rejects_bad_arguments():
     with pytest.raises(ValueError):
         O.Oracle(np.array([0, 0], dtype=np.int32), consts(), nominal_params(0), 0, 0, 0).step(
             np.zeros((0, 27)), np.zeros((0, 4)))
+
+
+def test_env_range_oracle_matches_full_run():
+    """An oracle over a slice of environments reproduces the full run there
+    (noise keyed by global quad index)."""
+    w = W.swarm8(seed=4, n_envs=12)
+    full = O.Oracle.from_workload(w)
+    part = O.Oracle.from_workload(w, 5, 9)
+    q0, q1 = int(w.env_offsets[5]), int(w.env_offsets[9])
+    s = w.state0.astype(np.float64)
+    sp = s[q0:q1]
+    for t in range(20):
+        a = w.actions(t)
+        s, c, _ = full.step(s, a, 1, t)
+        sp, cp, _ = part.step(sp, a[q0:q1], 1, t)
+    assert np.array_equal(s[q0:q1], sp) and np.array_equal(c[q0:q1], cp)
