@@ -5,7 +5,10 @@ physics (motor lag and noise, walls, floor, in-env collisions) and the K = 6
 nearest-neighbour observation, dt = 5 ms.  One timed "step" is one call of
 the whole hot path over the batch: ``qs_step_observe`` with ``--nsub``
 substeps (default 1: every row of the path, including the observation, runs
-once per substep), on inputs already resident in HBM.
+once per substep), on inputs already resident in HBM.  Rollouts are the
+workload's 1000-substep episodes with a fresh action set per call; the
+state is reset to the initial state between episodes outside the timed
+region.
 
 Prints one JSON line.  value = quad-steps/s (quads x substeps / s).
 """
@@ -39,7 +42,7 @@ def algorithmic_bytes_per_quad(k: int, nsub: int, with_obs: bool = True) -> int:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="swarm8",
                     choices=["swarm8", "plain", "uneven", "diff", "scale32", "scale1"])
@@ -52,33 +55,51 @@ def parse():
     return ap.parse_args()
 
 
-def time_calls(sim, acts, goals, obs, nsub, steps, warmup, torch):
-    """Returns (ms per call over the timed region, mean kernel ms from
-    per-launch events)."""
+def time_calls(sim, w, acts, goals, obs, nsub, steps, warmup, torch, episode=1000):
+    """Time ``steps`` calls of qs_step_observe with ``nsub`` substeps.
+
+    Rollouts follow the workload's episodes: the state is reset to the
+    initial state (untimed) whenever ``episode`` substeps have been taken;
+    every call gets its own fresh action set (acts[i]).  Returns (ms per call
+    from HIP events around the timed region on the launch stream -- the
+    kernel is the only work on that stream, so this is its mean launch
+    duration including dispatch gaps -- and host wall ms per call).
+    """
+    per_ep = max(1, episode // nsub)
+    s0 = torch.from_numpy(w.state0).cuda()
+    t_sub = [0]
+
+    def reset():
+        sim.set_state(s0, t_sub[0])
+
+    def call(i):
+        sim.step_observe(acts[i % acts.shape[0]], nsub, goals, obs)
+        t_sub[0] += nsub
+
+    reset()
     for i in range(warmup):
-        sim.step_observe(acts[i % acts.shape[0]], nsub, goals, obs)
-    torch.cuda.synchronize()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record()
-    for i in range(steps):
-        sim.step_observe(acts[(warmup + i) % acts.shape[0]], nsub, goals, obs)
-    end.record()
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3
-    ms = start.elapsed_time(end)
-    # per-launch duration: events bracketing each launch on the same stream
-    n = min(steps, 200)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(n)]
-    for i in range(n):
-        ev[i][0].record()
-        sim.step_observe(acts[i % acts.shape[0]], nsub, goals, obs)
-        ev[i][1].record()
-    torch.cuda.synchronize()
-    kern = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        if i and i % per_ep == 0:
+            reset()
+        call(i)
     sim.sync()
-    return ms / steps, kern, wall / steps
+    total_ms, wall = 0.0, 0.0
+    done = 0
+    while done < steps:
+        reset()
+        n = min(per_ep, steps - done)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record()
+        for i in range(n):
+            call(done + i)
+        end.record()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        total_ms += start.elapsed_time(end)
+        done += n
+    sim.sync()
+    return total_ms / steps, wall * 1e3 / steps
 
 
 def cpu_baseline(w, target_s: float):
@@ -86,13 +107,16 @@ def cpu_baseline(w, target_s: float):
     bounded number of substeps of the same workload."""
     from oracle import oracle as O
     orc = O.Oracle.from_workload(w)
-    s = w.state0.astype(np.float64)
+    s0 = w.state0.astype(np.float64)
+    s = s0
     g = w.goals.astype(np.float64)
-    a = w.actions(0).astype(np.float64)
+    acts = [w.actions(i).astype(np.float64) for i in range(100)]
     t0 = time.perf_counter()
     n = 0
     while True:
-        s, _, _ = orc.step(s, a, 1, n)
+        if n and n % 1000 == 0:
+            s = s0  # episode reset, as on the GPU
+        s, _, _ = orc.step(s, acts[n % 100], 1, n)
         orc.observe(s, g)
         n += 1
         if time.perf_counter() - t0 >= target_s:
@@ -119,13 +143,14 @@ def main():
     torch.cuda.set_device(0)
     w = W.WORKLOADS[args.workload](seed=0)
     sim = QuadSwarm.from_workload(w)
-    n_act = min(args.steps + args.warmup, 256)
-    acts = torch.from_numpy(w.action_sequence(n_act)).cuda()
+    n_act = args.steps + args.warmup
+    acts = torch.from_numpy(w.action_sequence(n_act)).cuda()  # a fresh action set per call
     goals = torch.from_numpy(w.goals).cuda()
     obs = torch.empty((w.n_quads, w.obs_dim), device="cuda")
 
-    ms, kern_ms, wall_ms = time_calls(sim, acts, goals, obs, args.nsub, args.steps,
-                                      args.warmup, torch)
+    ms, wall_ms = time_calls(sim, w, acts, goals, obs, args.nsub, args.steps,
+                             args.warmup, torch, w.substeps)
+    kern_ms = ms
     Q = w.n_quads
     value = Q * args.nsub / (ms * 1e-3)
     bpq = algorithmic_bytes_per_quad(w.k_neighbors, args.nsub)
@@ -137,11 +162,11 @@ def main():
         if ns == args.nsub:
             continue
         sim2 = QuadSwarm.from_workload(w)
-        m2, k2, _ = time_calls(sim2, acts, goals, obs, ns, max(args.steps // ns, 20),
-                               args.warmup // 2, torch)
+        m2, _ = time_calls(sim2, w, acts, goals, obs, ns, max(args.steps // ns, 20),
+                           max(args.warmup // ns, 5), torch, w.substeps)
         sim2.close()
         extra[f"fused_nsub{ns}"] = dict(
-            value=Q * ns / (m2 * 1e-3), ms_per_call=m2, kernel_ms=k2,
+            value=Q * ns / (m2 * 1e-3), ms_per_call=m2,
             speedup_vs_plain=(Q * ns / (m2 * 1e-3)) / value)
 
     line = {

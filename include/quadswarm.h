@@ -22,6 +22,8 @@
  *    non-finite action) are sticky in the handle and are returned by the
  *    next qs_sync().
  *  - All device arithmetic is IEEE float32.
+ *  - Device pointers: d_actions 16-byte aligned, d_obs and d_mask 8-byte
+ *    aligned, others 4-byte aligned (QS_ERR_ALIGN otherwise).
  *
  * Canonical layouts (row-major, float32):
  *  state  [Q][27] = x(3) v(3) R(9, row-major, body->world) omega(3, body)
@@ -55,7 +57,7 @@ extern "C" {
 #define QS_ERR_HIP (-4)           /* a HIP runtime call failed */
 #define QS_ERR_NONFINITE (-5)     /* sticky: non-finite action or state on device */
 #define QS_ERR_NOMEM (-6)         /* device or host allocation failed */
-#define QS_ERR_ALIGN (-7)         /* a device pointer is not 4-byte aligned */
+#define QS_ERR_ALIGN (-7)         /* a device pointer is misaligned (see above) */
 #define QS_ERR_UNSUPPORTED (-8)   /* valid request this build does not handle */
 
 /* ---- physics switches (qs_desc.flags) ---- */

@@ -19,6 +19,7 @@ struct qs_handle {
   int dev = 0;
   int E = 0, Q = 0, Qp = 0, K = 0, OD = 0;
   int bs = 64, nblk = 0;
+  int uniform_n = 0;  // every swarm holds this many quads (power of two), else 0
   Consts c{};
   float* d_st = nullptr;
   float* d_par = nullptr;
@@ -70,7 +71,7 @@ int check_desc(const qs_desc* d) {
 int pick_block(int Q) {
   if (const char* e = std::getenv("QS_BLOCK_SIZE")) {
     const int b = std::atoi(e);
-    if (b == 64 || b == 128 || b == 256) return b;
+    if (b == 64 || b == 128) return b;
   }
   if (Q >= 128 * 2048) return 128;
   return 64;
@@ -106,36 +107,56 @@ Ptrs ptrs(qs_handle* h) {
   p.contacts = h->record ? h->d_contacts : nullptr;
   p.err = h->d_err;
   p.Qp = h->Qp;
+  p.Q = h->Q;
   return p;
 }
 
-// Launch the step kernel.  mode: -2 step only, otherwise with observation.
+// Launch one instantiation.  Observation rows are staged in LDS when the
+// staging area and the pair tile fit in 64 KiB per workgroup.
+template <int BS, int KT, int N>
+void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
+        hipStream_t s) {
+  size_t dyn = 0;
+  int stage = 0;
+  if constexpr (KT >= 0) {
+    const size_t lds = (size_t)BS * (18 + 6 * KT) * sizeof(float);
+    if (lds + sizeof(float) * 2 * 9 * BS <= 64 * 1024) {
+      dyn = lds;
+      stage = 1;
+    }
+  }
+  hipLaunchKernelGGL((qs::step_kernel<BS, KT, N>), dim3(h->nblk), dim3(BS), dyn, s, h->c,
+                     ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, stage);
+}
+
+template <int BS, int KT>
+void go_n(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
+          hipStream_t s) {
+  switch (h->uniform_n) {
+    case 1: go<BS, KT, 1>(h, act, nsub, goals, obs, s); break;
+    case 2: go<BS, KT, 2>(h, act, nsub, goals, obs, s); break;
+    case 4: go<BS, KT, 4>(h, act, nsub, goals, obs, s); break;
+    case 8: go<BS, KT, 8>(h, act, nsub, goals, obs, s); break;
+    case 16: go<BS, KT, 16>(h, act, nsub, goals, obs, s); break;
+    case 32: go<BS, KT, 32>(h, act, nsub, goals, obs, s); break;
+    case 64: go<BS, KT, 64>(h, act, nsub, goals, obs, s); break;
+    default: go<BS, KT, 0>(h, act, nsub, goals, obs, s); break;
+  }
+}
+
 template <int BS>
 int launch_bs(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
               bool with_obs, hipStream_t s) {
-  const Ptrs p = ptrs(h);
-  const dim3 grid(h->nblk), block(BS);
-  if (!with_obs) {
-    hipLaunchKernelGGL((qs::step_kernel<BS, -2>), grid, block, 0, s, h->c, p, act, nsub,
-                       (unsigned long long)h->t, goals, obs, 0);
-  } else {
-    // stage the observation rows in LDS when the tile and the rows fit in
-    // 64 KiB per workgroup; otherwise each lane writes its own row
-    const int odp = h->OD | 1;
-    const size_t lds = (size_t)BS * odp * sizeof(float);
-    const size_t tile = sizeof(float) * 2 * 9 * BS;
-    const bool stage = lds + tile <= 64 * 1024;
-    const size_t dyn = stage ? lds : 0;
-    if (h->K == 0)
-      hipLaunchKernelGGL((qs::step_kernel<BS, 0>), grid, block, dyn, s, h->c, p, act, nsub,
-                         (unsigned long long)h->t, goals, obs, stage ? 1 : 0);
-    else if (h->K == 6)
-      hipLaunchKernelGGL((qs::step_kernel<BS, 6>), grid, block, dyn, s, h->c, p, act, nsub,
-                         (unsigned long long)h->t, goals, obs, stage ? 1 : 0);
-    else
-      hipLaunchKernelGGL((qs::step_kernel<BS, -1>), grid, block, dyn, s, h->c, p, act, nsub,
-                         (unsigned long long)h->t, goals, obs, stage ? 1 : 0);
-  }
+  if (!with_obs)
+    go_n<BS, -2>(h, act, nsub, goals, obs, s);
+  else if (h->K == 6)
+    go_n<BS, 6>(h, act, nsub, goals, obs, s);
+  else if (h->K == 0 && h->uniform_n == 1)
+    go<BS, 0, 1>(h, act, nsub, goals, obs, s);
+  else if (h->K == 0)
+    go<BS, 0, 0>(h, act, nsub, goals, obs, s);
+  else
+    go<BS, -1, 0>(h, act, nsub, goals, obs, s);
   return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
 }
 
@@ -144,7 +165,6 @@ int launch(qs_handle* h, const float* act, int nsub, const float* goals, float* 
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
   int rc;
   switch (h->bs) {
-    case 256: rc = launch_bs<256>(h, act, nsub, goals, obs, with_obs, s); break;
     case 128: rc = launch_bs<128>(h, act, nsub, goals, obs, with_obs, s); break;
     default: rc = launch_bs<64>(h, act, nsub, goals, obs, with_obs, s); break;
   }
@@ -235,6 +255,14 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   }
   blk.push_back(make_int2(cur_begin, cur_cnt));
   h->nblk = (int)blk.size();
+  // uniform power-of-two swarms: the greedy packing above is then exactly
+  // "workgroup b owns quads [b bs, (b+1) bs)", which the specialised kernels use
+  {
+    const int n0 = desc->env_offsets[1] - desc->env_offsets[0];
+    bool uni = (n0 & (n0 - 1)) == 0 && h->bs % n0 == 0;
+    for (int e = 1; uni && e < E; ++e) uni = desc->env_offsets[e + 1] - desc->env_offsets[e] == n0;
+    h->uniform_n = uni ? n0 : 0;
+  }
 
   // derived per-quad parameters and SoA state
   std::vector<float> par((size_t)qs::NPARAM * h->Qp, 1.0f);
@@ -314,7 +342,7 @@ int qs_step(qs_handle* h, const float* d_actions, int32_t n_substeps, void* stre
 
 int qs_observe(qs_handle* h, const float* d_goals, float* d_obs, void* stream) {
   if (!h || !d_goals || !d_obs) return QS_ERR_NULL;
-  if (!aligned(d_goals, 4) || !aligned(d_obs, 4)) return QS_ERR_ALIGN;
+  if (!aligned(d_goals, 4) || !aligned(d_obs, 8)) return QS_ERR_ALIGN;
   return launch(h, nullptr, 0, d_goals, d_obs, true, (hipStream_t)stream);
 }
 
@@ -322,7 +350,7 @@ int qs_step_observe(qs_handle* h, const float* d_actions, int32_t n_substeps,
                     const float* d_goals, float* d_obs, void* stream) {
   if (!h || !d_actions || !d_goals || !d_obs) return QS_ERR_NULL;
   if (n_substeps < 0) return QS_ERR_INVALID;
-  if (!aligned(d_actions, 16) || !aligned(d_goals, 4) || !aligned(d_obs, 4)) return QS_ERR_ALIGN;
+  if (!aligned(d_actions, 16) || !aligned(d_goals, 4) || !aligned(d_obs, 8)) return QS_ERR_ALIGN;
   return launch(h, d_actions, n_substeps, d_goals, d_obs, true, (hipStream_t)stream);
 }
 

@@ -40,7 +40,8 @@ struct Ptrs {
   const int2* blk;              // [nblk] (first quad, quad count)
   unsigned long long* contacts; // [Qp] or nullptr
   int* err;                     // sticky error bits
-  int Qp;
+  int Qp;                       // padded quad count (SoA field stride)
+  int Q;                        // quad count
 };
 
 // Philox4x32-10, Salmon et al. SC'11: ten rounds of two 32x32->64 products

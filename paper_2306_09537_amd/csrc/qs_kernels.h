@@ -15,24 +15,43 @@ namespace qs {
 
 // KT: -2 step only; -1 observation with runtime K (selection); >= 0 observation
 // with compile-time K (register insertion network).
-template <int BS, int KT>
+// N: 0 for any mix of swarm sizes (host-built workgroup table); N > 0 when
+// every environment holds N quads (BS a multiple of N): workgroup b then
+// owns quads [b BS, (b+1) BS) and the in-swarm loops unroll completely.
+template <int BS, int KT, int N>
 __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
                                                   const float* __restrict__ act, int nsub,
                                                   unsigned long long t0,
                                                   const float* __restrict__ goals,
                                                   float* __restrict__ obs, int stage_obs) {
+  static_assert(N == 0 || BS % N == 0, "workgroups hold whole swarms");
   constexpr bool OBS = KT != -2;
   // rows 0-2: start position (pair pass) or position (observation),
   // rows 3-5: substep displacement, rows 6-8: velocity
   __shared__ float sxv[2][9][BS];
-  extern __shared__ float st_obs[];
+  extern __shared__ float4 st_obs4[];  // staged observation rows (stride OD)
+  float* st_obs = reinterpret_cast<float*>(st_obs4);
 
   const int tid = threadIdx.x;
-  const int2 bq = p.blk[blockIdx.x];
-  const bool live = tid < bq.y;
-  const int q = bq.x + (live ? tid : 0);
-  const uint32_t swd = live ? p.sw[q] : 0u;
-  const int ls = (int)(swd >> 8), n = (int)(swd & 0xffu);
+  int qb, cnt, ls, n;
+  if constexpr (N > 0) {
+    qb = blockIdx.x * BS;
+    cnt = min(BS, p.Q - qb);
+    ls = (tid / N) * N;
+    n = N;
+  } else {
+    const int2 bq = p.blk[blockIdx.x];
+    qb = bq.x;
+    cnt = bq.y;
+  }
+  const bool live = tid < cnt;
+  const int q = qb + (live ? tid : 0);
+  if constexpr (N == 0) {
+    const uint32_t swd = live ? p.sw[q] : 0u;
+    ls = (int)(swd >> 8);
+    n = (int)(swd & 0xffu);
+  }
+  const int me = tid - ls;  // index within the swarm
   const int Qp = p.Qp;
   const float* __restrict__ S = p.st;
 
@@ -76,7 +95,7 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
     }
   }
 
-  const bool collide = (c.flags & F_COLLIDE) != 0;
+  const bool collide = N != 1 && (c.flags & F_COLLIDE) != 0;
   unsigned long long cmask = 0ull;
   for (int sub = 0; sub < nsub; ++sub) {
     const unsigned long long t = t0 + (unsigned long long)sub;
@@ -94,19 +113,17 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
         }
       }
       __syncthreads();
-      if (live && n > 1) {
+      cmask = 0ull;
+      if (live) {
         float dvx = 0.f, dvy = 0.f, dvz = 0.f;
         bool hit = false;
-        cmask = 0ull;
-        const int me = tid - ls;
-        for (int jj = 0; jj < n; ++jj) {
-          if (jj == me) continue;
+        auto pair = [&](int jj) {
           const int j = ls + jj;
           const float dx = (s.xo[0] - tile[0][j]) + (s.inc[0] - tile[3][j]);
           const float dy = (s.xo[1] - tile[1][j]) + (s.inc[1] - tile[4][j]);
           const float dz = (s.xo[2] - tile[2][j]) + (s.inc[2] - tile[5][j]);
           const float d2 = dx * dx + dy * dy + dz * dz;
-          if (d2 < c.dcol2) {
+          if (d2 < c.dcol2 && jj != me) {
             cmask |= 1ull << jj;
             float nx, ny, nz;
             if (d2 < 1e-12f) {
@@ -124,6 +141,12 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
               hit = true;
             }
           }
+        };
+        if constexpr (N > 0) {
+#pragma unroll
+          for (int jj = 0; jj < N; ++jj) pair(jj);
+        } else {
+          for (int jj = 0; jj < n; ++jj) pair(jj);
         }
         if (hit) {
           float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
@@ -137,8 +160,6 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
 #pragma unroll
           for (int k = 0; k < 3; ++k) s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
         }
-      } else {
-        cmask = 0ull;
       }
     }
   }
@@ -166,8 +187,6 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
 
   if constexpr (OBS) {
     // §III-C observation from the post-collision state
-    const int OD = KT >= 0 ? 18 + 6 * KT : c.obs_dim;
-    const int K = KT >= 0 ? KT : c.K;
     float(*tile)[BS] = sxv[nsub & 1];
     if (live) {
 #pragma unroll
@@ -177,31 +196,34 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
       }
     }
     __syncthreads();
-    const int ODP = OD | 1;  // odd LDS row stride: conflict-free staging
-    float* row = stage_obs ? st_obs + tid * ODP : obs + (size_t)q * OD;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
     if (live) {
-      const float g0 = goals[3 * q], g1 = goals[3 * q + 1], g2 = goals[3 * q + 2];
-      row[0] = s.x[0] - g0;
-      row[1] = s.x[1] - g1;
-      row[2] = s.x[2] - g2;
+      g0 = goals[3 * q];
+      g1 = goals[3 * q + 1];
+      g2 = goals[3 * q + 2];
+    }
+    if constexpr (KT >= 0) {
+      constexpr int OD = 18 + 6 * KT;
+      float ov[OD];
+      ov[0] = s.x[0] - g0;
+      ov[1] = s.x[1] - g1;
+      ov[2] = s.x[2] - g2;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) row[3 + k] = s.v[k];
+      for (int k = 0; k < 3; ++k) ov[3 + k] = s.v[k];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) row[6 + k] = s.R[k];
+      for (int k = 0; k < 9; ++k) ov[6 + k] = s.R[k];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) row[15 + k] = s.w[k];
-      const int me = tid - ls;
+      for (int k = 0; k < 3; ++k) ov[15 + k] = s.w[k];
       if constexpr (KT > 0) {
         // sorted (d^2, index) list of the KT nearest, kept in registers
         float bd[KT];
         int bj[KT];
 #pragma unroll
         for (int k = 0; k < KT; ++k) { bd[k] = INFINITY; bj[k] = -1; }
-        for (int jj = 0; jj < n; ++jj) {
-          if (jj == me) continue;
+        auto cand = [&](int jj) {
           const int j = ls + jj;
           const float rx = tile[0][j] - s.x[0], ry = tile[1][j] - s.x[1], rz = tile[2][j] - s.x[2];
-          const float d2 = rx * rx + ry * ry + rz * rz;
+          const float d2 = jj == me ? INFINITY : rx * rx + ry * ry + rz * rz;
 #pragma unroll
           for (int k = KT - 1; k > 0; --k) {
             const bool shift = bd[k - 1] > d2;
@@ -210,25 +232,71 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
             bj[k] = shift ? bj[k - 1] : (here ? jj : bj[k]);
           }
           if (bd[0] > d2) { bd[0] = d2; bj[0] = jj; }
+        };
+        if constexpr (N > 1) {
+#pragma unroll
+          for (int jj = 0; jj < N; ++jj) cand(jj);
+        } else if constexpr (N == 0) {
+          if (live)
+            for (int jj = 0; jj < n; ++jj) cand(jj);
         }
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-          float* o = row + 18 + 6 * k;
-          if (bj[k] >= 0) {
-            const int j = ls + bj[k];
-            o[0] = tile[0][j] - s.x[0];
-            o[1] = tile[1][j] - s.x[1];
-            o[2] = tile[2][j] - s.x[2];
-            o[3] = tile[6][j] - s.v[0];
-            o[4] = tile[7][j] - s.v[1];
-            o[5] = tile[8][j] - s.v[2];
-          } else {
-#pragma unroll
-            for (int m = 0; m < 6; ++m) o[m] = 0.f;
-          }
+          const bool have = bj[k] >= 0;
+          const int j = ls + (have ? bj[k] : 0);
+          ov[18 + 6 * k + 0] = have ? tile[0][j] - s.x[0] : 0.f;
+          ov[18 + 6 * k + 1] = have ? tile[1][j] - s.x[1] : 0.f;
+          ov[18 + 6 * k + 2] = have ? tile[2][j] - s.x[2] : 0.f;
+          ov[18 + 6 * k + 3] = have ? tile[6][j] - s.v[0] : 0.f;
+          ov[18 + 6 * k + 4] = have ? tile[7][j] - s.v[1] : 0.f;
+          ov[18 + 6 * k + 5] = have ? tile[8][j] - s.v[2] : 0.f;
         }
-      } else if constexpr (KT == -1) {
-        // runtime K: K passes of selection of the next (d^2, index) pair
+      }
+      if (stage_obs) {
+        if (live) {
+          float2* r2 = reinterpret_cast<float2*>(st_obs + tid * OD);
+#pragma unroll
+          for (int k = 0; k < OD / 2; ++k) r2[k] = make_float2(ov[2 * k], ov[2 * k + 1]);
+        }
+        __syncthreads();
+        // contiguous copy of the workgroup's rows: 16-byte stores when the
+        // destination allows, else 8-byte stores
+        const int total = cnt * OD;
+        float* dst = obs + (size_t)qb * OD;
+        if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+          const int n4 = total >> 2;
+          float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll 4
+          for (int i = tid; i < n4; i += BS) d4[i] = st_obs4[i];
+          if ((total & 3) && tid == 0)
+            reinterpret_cast<float2*>(dst)[2 * n4] = reinterpret_cast<float2*>(st_obs)[2 * n4];
+        } else {
+          const int n2 = total >> 1;
+          float2* d2p = reinterpret_cast<float2*>(dst);
+          const float2* s2p = reinterpret_cast<const float2*>(st_obs);
+#pragma unroll 4
+          for (int i = tid; i < n2; i += BS) d2p[i] = s2p[i];
+        }
+      } else if (live) {
+        float2* r2 = reinterpret_cast<float2*>(obs + (size_t)q * OD);
+#pragma unroll
+        for (int k = 0; k < OD / 2; ++k) r2[k] = make_float2(ov[2 * k], ov[2 * k + 1]);
+      }
+    } else {
+      // runtime K (rare sizes): K passes of selection of the next
+      // (d^2, index) pair; each lane writes its own row
+      const int K = c.K, OD = c.obs_dim;
+      if (live) {
+        float* row = obs + (size_t)q * OD;
+        row[0] = s.x[0] - g0;
+        row[1] = s.x[1] - g1;
+        row[2] = s.x[2] - g2;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) row[3 + k] = s.v[k];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) row[6 + k] = s.R[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) row[15 + k] = s.w[k];
         float pd = -1.0f;
         int pj = -1;
         for (int k = 0; k < K; ++k) {
@@ -260,15 +328,6 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
             pj = 1 << 30;
           }
         }
-      }
-    }
-    if (stage_obs) {
-      __syncthreads();
-      float* dst = obs + (size_t)bq.x * OD;
-      const int total = bq.y * OD;
-      for (int i = tid; i < total; i += BS) {
-        const int r = i / OD;
-        dst[i] = st_obs[r * ODP + (i - r * OD)];
       }
     }
   }
