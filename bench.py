@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+KERNEL_SOURCES = ("paper_2306_09537_amd/csrc/qs_device.h", "paper_2306_09537_amd/csrc/qs_kernels.h")
 STATE_B, PARAM_B, ACT_B, GOAL_B = 108, 24, 16, 12
 
 
@@ -37,6 +38,31 @@ def algorithmic_bytes_per_quad(k: int, nsub: int, with_obs: bool = True) -> int:
     if with_obs:
         b += GOAL_B + 4 * (18 + 6 * k)
     return b
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    m = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def measured_traffic(profile: str):
+    """HBM bytes per launch from the committed counter summary, or None if
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    if kernel_source_hash() not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return int(line.split(":")[1])
+    return None
 
 
 def parse():
@@ -52,6 +78,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (a kernel of "
+                         "known traffic for scaling HBM counters) and exit")
     return ap.parse_args()
 
 
@@ -137,6 +166,16 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4}))
+        return
+
     from paper_2306_09537_amd import workloads as W
     from paper_2306_09537_amd.quadswarm import QuadSwarm
 
@@ -186,7 +225,9 @@ def main():
                    "k_neighbors": w.k_neighbors, "substeps_per_call": args.nsub,
                    "dt": w.consts["dt"], "entry": "qs_step_observe"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic("step_kernel_swarm4096x8_plain.md")
+                                 if (args.workload, args.nsub) == ("swarm8", 1) else None),
                      "kernel": "step_kernel (fused step + observe)",
                      "kernel_ms": kern_ms, "bytes_per_launch": launch_bytes,
                      "bytes_per_quad": bpq},
