@@ -128,6 +128,48 @@ class Oracle:
             return s, contacts, events, mg
         return s, contacts, events
 
+    def rollout(self, state, actions, n_sub: int = 1, t0: int = 0, beta=None):
+        """n_calls = actions.shape[0] calls of n_sub substeps.  Returns
+        (final state [Q][27], penalty [Q] or None); the penalty is each quad's
+        share of sum softplus(beta (d_col - d_ij))/beta over substeps and pairs."""
+        s = np.array(state, dtype=np.float64, order="C", copy=True)
+        a = np.ascontiguousarray(actions, dtype=np.float64)
+        assert a.ndim == 3 and a.shape[1:] == (self.Q, 4)
+        pen = np.zeros(self.Q) if beta is not None else None
+        rc = lib().or_rollout(C.byref(self.desc), _p(self.params, C.c_double), _p(s, C.c_double),
+                              _p(a, C.c_double), C.c_int(a.shape[0]), C.c_int(n_sub),
+                              C.c_uint64(t0), None if pen is None else _p(pen, C.c_double),
+                              C.c_double(beta or 0.0))
+        if rc != 0:
+            raise ValueError("or_rollout rejected its arguments")
+        return s, pen
+
+    def rollout_vjp(self, state0, actions, n_sub, t0, gstate, gpen=None, beta=None):
+        """Reverse pass of rollout: returns (dL/d state0 [Q][27],
+        dL/d actions [n_calls][Q][4], dL/d params [Q][6])."""
+        s0 = np.ascontiguousarray(state0, dtype=np.float64)
+        a = np.ascontiguousarray(actions, dtype=np.float64)
+        g = np.array(gstate, dtype=np.float64, order="C", copy=True)
+        gp = None if gpen is None else np.ascontiguousarray(gpen, dtype=np.float64)
+        gact = np.zeros_like(a)
+        gpar = np.zeros((self.Q, 6))
+        rc = lib().or_rollout_vjp(C.byref(self.desc), _p(self.params, C.c_double),
+                                  _p(s0, C.c_double), _p(a, C.c_double), C.c_int(a.shape[0]),
+                                  C.c_int(n_sub), C.c_uint64(t0), _p(g, C.c_double),
+                                  None if gp is None else _p(gp, C.c_double),
+                                  C.c_double(beta or 0.0), _p(gact, C.c_double),
+                                  _p(gpar, C.c_double))
+        if rc != 0:
+            raise ValueError("or_rollout_vjp rejected its arguments")
+        return g, gact, gpar
+
+    def with_params(self, params) -> "Oracle":
+        """Same environments and constants, other per-quad parameters."""
+        o = Oracle.__new__(Oracle)
+        o.__dict__.update(self.__dict__)
+        o.params = np.ascontiguousarray(params, dtype=np.float64)
+        return o
+
     def observe(self, state, goals):
         """Returns (obs [Q][18+6K] f64, neighbour local indices [Q][K] i32)."""
         s = np.ascontiguousarray(state, dtype=np.float64)

@@ -150,11 +150,30 @@ static void upd_margin(double* mg, double v) {
   if (v < *mg) *mg = v;
 }
 
+/* Intermediates of one substep of one quad, kept for the reverse sweep. */
+typedef struct {
+  double uhat[4], u0[4], e0[4], z[4], u1[4], f[4];
+  double f_max, alpha_lag, T, F[3], P[9], w0[3], v0[3];
+  int noise, rest;
+  /* free flight */
+  double Jw[3], wxJw[3], wdot[3], w1[3], A0[3], A1[3], n0, c0[3], dp, n1, c1[3];
+  /* resting on the floor */
+  int statik, guard;
+  double mu_n, fb[2], nv, nf, mag;
+  /* walls and floor */
+  int clamp[3], flip[3], bounced, hit, fallback;
+  double hx, hy, nh, kx, ky, nk;
+} or_rec;
+
 /* mg: smallest distance of any threshold decision of this substep from its
- * threshold (diagnostic only; it does not change the arithmetic). */
+ * threshold (diagnostic only; it does not change the arithmetic).
+ * rec (optional) receives the substep's intermediates. */
 static void quad_substep(const or_desc* d, const double* p, double* s,
                          const double* act, uint32_t q, uint64_t t,
-                         uint32_t* ev, double* mg) {
+                         uint32_t* ev, double* mg, or_rec* rec) {
+  or_rec scratch_rec;
+  or_rec* r = rec ? rec : &scratch_rec;
+  memset(r, 0, sizeof(*r));
   const double dt = d->dt, g = d->gravity;
   const double m = p[PM], jx = p[PJX], jy = p[PJY], jz = p[PJZ];
   const double f_max = 0.25 * m * g * p[PT2W];              /* §III-A.2 */
@@ -170,6 +189,18 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
                                            : 0.5 * (clampd(act[i], -1.0, 1.0) + 1.0);
     uhat[i] = sqrt(fhat);
   }
+  r->f_max = f_max;
+  r->alpha_lag = alpha_lag;
+  for (int i = 0; i < 4; ++i) {
+    r->uhat[i] = uhat[i];
+    r->u0[i] = s[IU + i];
+    r->e0[i] = s[IE + i];
+  }
+  for (int k = 0; k < 9; ++k) r->P[k] = s[IR + k];
+  for (int k = 0; k < 3; ++k) {
+    r->w0[k] = s[IW + k];
+    r->v0[k] = s[IV + k];
+  }
   /* §III-A.1: first-order low-pass motor lag */
   for (int i = 0; i < 4; ++i) s[IU + i] = alpha_lag * (uhat[i] - s[IU + i]) + s[IU + i];
   /* §III-A.2: AR(1) motor noise */
@@ -177,10 +208,16 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     double z[4];
     or_normal4(d->seed, q, t, STREAM_MOTOR, 0, z);
     for (int i = 0; i < 4; ++i) s[IE + i] = a_nd * s[IE + i] + a_ns * z[i];
+    r->noise = 1;
+    for (int i = 0; i < 4; ++i) r->z[i] = z[i];
   }
   /* §III-A.2: per-motor thrust */
   double f[4];
   for (int i = 0; i < 4; ++i) f[i] = f_max * s[IU + i] * s[IU + i] + s[IE + i];
+  for (int i = 0; i < 4; ++i) {
+    r->u1[i] = s[IU + i];
+    r->f[i] = f[i];
+  }
 
   /* §III-A: total thrust and torque = thrust moments + propeller reaction */
   double T = (f[0] + f[1]) + (f[2] + f[3]);
@@ -196,8 +233,11 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
 
   /* §III-A: world-frame thrust force R (0,0,T) */
   double F[3] = {T * R[2], T * R[5], T * R[8]};
+  r->T = T;
+  for (int k = 0; k < 3; ++k) r->F[k] = F[k];
 
   int friction = (d->flags & OR_FLOOR) && s[IF] != 0.0 && F[2] <= m * g;
+  r->rest = friction;
   if ((d->flags & OR_FLOOR) && s[IF] != 0.0) upd_margin(mg, (F[2] - m * g) / (m * g));
   if (!friction) {
     if (s[IF] != 0.0) *ev |= EV_TAKEOFF;
@@ -216,6 +256,12 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     for (int k = 0; k < 3; ++k) v[k] += dt * acc[k];
     for (int k = 0; k < 3; ++k) x[k] += dt * v[k];
     for (int k = 0; k < 3; ++k) w[k] += dt * wdot[k];
+    for (int k = 0; k < 3; ++k) {
+      r->Jw[k] = Jw[k];
+      r->wxJw[k] = wxJw[k];
+      r->wdot[k] = wdot[k];
+      r->w1[k] = w[k];
+    }
     /* attitude: R <- R + dt R [w]x, with the new omega */
     double W[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
     double Rn[9];
@@ -227,12 +273,23 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
       }
     /* Gram-Schmidt on the columns: c0, c1 orthonormalised, c2 = c0 x c1 */
     double c0[3] = {Rn[0], Rn[3], Rn[6]}, c1[3] = {Rn[1], Rn[4], Rn[7]};
+    for (int k = 0; k < 3; ++k) {
+      r->A0[k] = c0[k];
+      r->A1[k] = c1[k];
+    }
     double n0 = sqrt(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
     for (int k = 0; k < 3; ++k) c0[k] /= n0;
     double dp = c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2];
     for (int k = 0; k < 3; ++k) c1[k] -= dp * c0[k];
     double n1 = sqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
     for (int k = 0; k < 3; ++k) c1[k] /= n1;
+    r->n0 = n0;
+    r->dp = dp;
+    r->n1 = n1;
+    for (int k = 0; k < 3; ++k) {
+      r->c0[k] = c0[k];
+      r->c1[k] = c1[k];
+    }
     double c2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2],
                     c0[0] * c1[1] - c0[1] * c1[0]};
     for (int r = 0; r < 3; ++r) {
@@ -252,11 +309,18 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
       double mag = nf - mu_n > 0.0 ? nf - mu_n : 0.0;
       fb[0] = nf > 0.0 ? mag * F[0] / nf : 0.0;
       fb[1] = nf > 0.0 ? mag * F[1] / nf : 0.0;
+      r->statik = 1;
+      r->nf = nf;
+      r->mag = nf > 0.0 ? mag : 0.0;
     } else {
       double nv = sqrt(v[0] * v[0] + v[1] * v[1]);
       fb[0] = F[0] - mu_n * v[0] / nv;
       fb[1] = F[1] - mu_n * v[1] / nv;
+      r->nv = nv;
     }
+    r->mu_n = mu_n;
+    r->fb[0] = fb[0];
+    r->fb[1] = fb[1];
     double acc[2] = {(fb[0] - d->drag_coef * v[0]) / m, (fb[1] - d->drag_coef * v[1]) / m};
     v[0] += dt * acc[0];
     v[1] += dt * acc[1];
@@ -264,7 +328,7 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     double dot = v[0] * vxy0[0] + v[1] * vxy0[1];
     if (vxy0[0] != 0.0 || vxy0[1] != 0.0)
       upd_margin(mg, dot / (vxy0[0] * vxy0[0] + vxy0[1] * vxy0[1]));
-    if (dot < 0.0) { v[0] = 0.0; v[1] = 0.0; }
+    if (dot < 0.0) { v[0] = 0.0; v[1] = 0.0; r->guard = 1; }
     for (int k = 0; k < 3; ++k) x[k] += dt * v[k];
     w[0] = w[1] = w[2] = 0.0;
   }
@@ -278,13 +342,16 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
       upd_margin(mg, x[k] - d->room_max[k]);
       if (k < 2 && x[k] < d->room_min[k]) {
         x[k] = d->room_min[k];
-        if (v[k] < 0.0) { v[k] = -e * v[k]; bounced = 1; }
+        r->clamp[k] = 1;
+        if (v[k] < 0.0) { v[k] = -e * v[k]; bounced = 1; r->flip[k] = 1; }
       }
       if (x[k] > d->room_max[k]) {
         x[k] = d->room_max[k];
-        if (v[k] > 0.0) { v[k] = -e * v[k]; bounced = 1; }
+        r->clamp[k] = 1;
+        if (v[k] > 0.0) { v[k] = -e * v[k]; bounced = 1; r->flip[k] = 1; }
       }
     }
+    r->bounced = bounced;
     if (bounced) {
       *ev |= EV_WALL;
       double zv[4] = {0, 0, 0, 0}, zw[4] = {0, 0, 0, 0};
@@ -310,6 +377,14 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     double hx = R[0], hy = R[3];
     double nh = sqrt(hx * hx + hy * hy);
     double c0[3], c1[3];
+    r->hit = 1;
+    r->hx = hx;
+    r->hy = hy;
+    r->nh = nh;
+    r->fallback = !(nh >= 1e-6);
+    r->kx = R[1];
+    r->ky = R[4];
+    r->nk = sqrt(R[1] * R[1] + R[4] * R[4]);
     if (nh >= 1e-6) {
       c0[0] = hx / nh; c0[1] = hy / nh; c0[2] = 0.0;
       c1[0] = -c0[1]; c1[1] = c0[0]; c1[2] = 0.0;       /* e_z x c0 */
@@ -330,8 +405,14 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
 }
 
 /* §III-B.1: pair pass of one environment after every quad moved. */
+static double softplus(double x) { return x > 30.0 ? x : log1p(exp(x)); }
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* pen (optional): each quad's half of the smoothed collision penalty
+ * softplus(beta (d_col - d_ij)) / beta over every pair of its env, added. */
 static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
-                      uint64_t* contacts, uint32_t* events, double* mg) {
+                      uint64_t* contacts, uint32_t* events, double* mg,
+                      double* pen, double beta) {
   double dv[64][3];
   int marked[64];
   memset(dv, 0, sizeof(dv));
@@ -346,7 +427,12 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
       double dm = sqrt(d2) - d->col_dist;
       upd_margin(&mg[q0 + i], dm);
       upd_margin(&mg[q0 + j], dm);
-      if (!(d2 < dc2)) continue;
+      if (pen) {
+        double h = 0.5 * softplus(beta * (d->col_dist - sqrt(d2))) / beta;
+        pen[q0 + i] += h;
+        pen[q0 + j] += h;
+      }
+      if (!(d->flags & OR_COLLIDE) || !(d2 < dc2)) continue;
       if (contacts) {
         contacts[q0 + i] |= 1ull << j;
         contacts[q0 + j] |= 1ull << i;
@@ -438,9 +524,10 @@ int or_step(const or_desc* d, const double* params, double* state,
         const int q = q0 + i;
         quad_substep(d, params + (size_t)q * NP, state + (size_t)q * NS,
                      actions + (size_t)q * 4, d->quad_id_offset + (uint32_t)q, t,
-                     &ev[q], &mg[q]);
+                     &ev[q], &mg[q], NULL);
       }
-      if ((d->flags & OR_COLLIDE) && n > 1) env_pairs(d, state, q0, n, t, contacts, ev, mg);
+      if ((d->flags & OR_COLLIDE) && n > 1)
+        env_pairs(d, state, q0, n, t, contacts, ev, mg, NULL, 0.0);
     }
   }
   if (!events) free(ev);
@@ -496,6 +583,430 @@ int or_observe(const or_desc* d, const double* state, const double* goals,
       }
     }
   }
+  return 0;
+}
+
+
+/* ======================================================================== */
+/* Differentiation (reverse mode, double precision).                         */
+/*                                                                          */
+/* The loss is any function of the state after the rollout plus a weighted  */
+/* sum of each quad's smoothed collision penalty                             */
+/*   pen_i = sum over substeps, env-mates j of 1/2 softplus(beta(d_col -    */
+/*           d_ij))/beta, with d_ij the centre distance after the motion of */
+/*   the substep (before the pair response).                                */
+/* Events (walls, floor, contacts, friction regime) take the derivative of  */
+/* the branch that was taken; the resting flag carries no derivative.       */
+/* ======================================================================== */
+
+static void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Reverse of one quad's substep up to the pair pass.  lam[27] holds dL/d
+ * (state after the floor step) on entry and dL/d(state at the start of the
+ * substep) on exit; guhat[4] accumulates dL/d(rotor-speed command) and
+ * gp[6] dL/d(mass, ixx, iyy, izz, thrust_to_weight, motor_tau). */
+static void quad_vjp(const or_desc* d, const double* p, const or_rec* r, double* lam,
+                     double* guhat, double* gp) {
+  const double dt = d->dt, g = d->gravity, m = p[PM];
+  const double J[3] = {p[PJX], p[PJY], p[PJZ]};
+  const double arm_d = d->arm_length / sqrt(2.0);
+  double lx[3], lv[3], lR[9], lw[3], lu[4], le[4];
+  for (int k = 0; k < 3; ++k) {
+    lx[k] = lam[IX + k];
+    lv[k] = lam[IV + k];
+    lw[k] = lam[IW + k];
+  }
+  for (int k = 0; k < 9; ++k) lR[k] = lam[IR + k];
+  for (int k = 0; k < 4; ++k) {
+    lu[k] = lam[IU + k];
+    le[k] = lam[IE + k];
+  }
+
+  /* floor hit: z, v, omega set to constants; R levelled from its heading */
+  if (r->hit) {
+    lx[2] = 0.0;
+    for (int k = 0; k < 3; ++k) lv[k] = lw[k] = 0.0;
+    double gr[2] = {0.0, 0.0};
+    if (!r->fallback) {
+      /* column 0 = h = (hx, hy)/nh, column 1 = (-h_y, h_x) */
+      double h[2] = {r->hx / r->nh, r->hy / r->nh};
+      double gh[2] = {lR[0] + lR[4], lR[3] - lR[1]};
+      double dd = gh[0] * h[0] + gh[1] * h[1];
+      gr[0] = (gh[0] - dd * h[0]) / r->nh;
+      gr[1] = (gh[1] - dd * h[1]) / r->nh;
+      for (int k = 0; k < 9; ++k) lR[k] = 0.0;
+      lR[0] = gr[0];
+      lR[3] = gr[1];
+    } else {
+      /* column 1 = k = (kx, ky)/nk, column 0 = (k_y, -k_x) */
+      double gk[2] = {0.0, 0.0};
+      if (r->nk > 0.0) {
+        double k[2] = {r->kx / r->nk, r->ky / r->nk};
+        double gkk[2] = {lR[1] - lR[3], lR[4] + lR[0]};
+        double dd = gkk[0] * k[0] + gkk[1] * k[1];
+        gk[0] = (gkk[0] - dd * k[0]) / r->nk;
+        gk[1] = (gkk[1] - dd * k[1]) / r->nk;
+      }
+      for (int k = 0; k < 9; ++k) lR[k] = 0.0;
+      lR[1] = gk[0];
+      lR[4] = gk[1];
+    }
+  }
+  /* walls: decay once, then per-axis mirror and clamp */
+  if (r->bounced)
+    for (int k = 0; k < 3; ++k) lv[k] *= d->col_decay;
+  for (int k = 0; k < 3; ++k) {
+    if (r->flip[k]) lv[k] *= -d->wall_restitution;
+    if (r->clamp[k]) lx[k] = 0.0;
+  }
+
+  double lT = 0.0, lF[3] = {0.0, 0.0, 0.0}, ltau[3] = {0.0, 0.0, 0.0};
+  double lm = 0.0, lJ[3] = {0.0, 0.0, 0.0};
+  double lP[9], lx0[3], lv0[3], lw0[3];
+  const double* P = r->P;
+  for (int k = 0; k < 3; ++k) lx0[k] = lx[k];
+  if (!r->rest) {
+    /* R = Gram-Schmidt(A): c2 = c0 x c1, c1 = b/|b|, b = A1 - (c0.A1) c0, c0 = A0/|A0| */
+    double lc0[3] = {lR[0], lR[3], lR[6]}, lc1[3] = {lR[1], lR[4], lR[7]};
+    double lc2[3] = {lR[2], lR[5], lR[8]}, tmp[3];
+    cross3(r->c1, lc2, tmp);
+    for (int k = 0; k < 3; ++k) lc0[k] += tmp[k];
+    cross3(lc2, r->c0, tmp);
+    for (int k = 0; k < 3; ++k) lc1[k] += tmp[k];
+    double lb[3], dd = dot3(lc1, r->c1);
+    for (int k = 0; k < 3; ++k) lb[k] = (lc1[k] - dd * r->c1[k]) / r->n1;
+    double lA1[3], ldp = -dot3(lb, r->c0);
+    for (int k = 0; k < 3; ++k) {
+      lA1[k] = lb[k] + ldp * r->c0[k];
+      lc0[k] += -r->dp * lb[k] + ldp * r->A1[k];
+    }
+    double lA0[3];
+    dd = dot3(lc0, r->c0);
+    for (int k = 0; k < 3; ++k) lA0[k] = (lc0[k] - dd * r->c0[k]) / r->n0;
+    /* A0 = P0 + dt (P1 w1z - P2 w1y), A1 = P1 + dt (P2 w1x - P0 w1z) (columns) */
+    const double* w1 = r->w1;
+    double P0[3] = {P[0], P[3], P[6]}, P1[3] = {P[1], P[4], P[7]}, P2[3] = {P[2], P[5], P[8]};
+    double lw1[3] = {lw[0] + dt * dot3(P2, lA1), lw[1] - dt * dot3(P2, lA0),
+                     lw[2] + dt * (dot3(P1, lA0) - dot3(P0, lA1))};
+    for (int rr = 0; rr < 3; ++rr) {
+      lP[3 * rr + 0] = lA0[rr] - dt * w1[2] * lA1[rr];
+      lP[3 * rr + 1] = lA1[rr] + dt * w1[2] * lA0[rr];
+      lP[3 * rr + 2] = -dt * w1[1] * lA0[rr] + dt * w1[0] * lA1[rr];
+    }
+    /* w1 = w0 + dt wdot, wdot_k = (tau_k - (w0 x J w0)_k) / J_k */
+    double lwd[3], lc[3], lJw[3];
+    for (int k = 0; k < 3; ++k) {
+      lw0[k] = lw1[k];
+      lwd[k] = dt * lw1[k];
+      ltau[k] = lwd[k] / J[k];
+      lc[k] = -lwd[k] / J[k];
+      lJ[k] += -lwd[k] * r->wdot[k] / J[k];
+    }
+    cross3(r->Jw, lc, tmp);
+    for (int k = 0; k < 3; ++k) lw0[k] += tmp[k];
+    cross3(lc, r->w0, lJw);
+    for (int k = 0; k < 3; ++k) {
+      lw0[k] += J[k] * lJw[k];
+      lJ[k] += r->w0[k] * lJw[k];
+    }
+    /* x1 = x0 + dt v1, v1 = v0 + dt acc, acc = F/m - c_d v0/m - g e_z */
+    double lacc[3];
+    for (int k = 0; k < 3; ++k) {
+      double lv1 = lv[k] + dt * lx[k];
+      lacc[k] = dt * lv1;
+      lv0[k] = lv1 - d->drag_coef / m * lacc[k];
+      lF[k] = lacc[k] / m;
+      lm += -(r->F[k] - d->drag_coef * r->v0[k]) * lacc[k] / (m * m);
+    }
+  } else {
+    /* resting: R held, omega zeroed, v_z zeroed, x_z unchanged */
+    for (int k = 0; k < 9; ++k) lP[k] = lR[k];
+    for (int k = 0; k < 3; ++k) lw0[k] = 0.0;
+    lv0[0] = lv0[1] = lv0[2] = 0.0;
+    if (!r->guard) {
+      double lv1[2] = {lv[0] + dt * lx[0], lv[1] + dt * lx[1]};
+      double lfb[2] = {dt * lv1[0] / m, dt * lv1[1] / m};
+      for (int k = 0; k < 2; ++k) {
+        lv0[k] = lv1[k] * (1.0 - dt * d->drag_coef / m);
+        lm += -dt * (r->fb[k] - d->drag_coef * r->v0[k]) * lv1[k] / (m * m);
+      }
+      double lmu = 0.0;
+      if (r->statik) {
+        if (r->mag > 0.0) {
+          double Fh[2] = {r->F[0] / r->nf, r->F[1] / r->nf};
+          double dd = lfb[0] * Fh[0] + lfb[1] * Fh[1];
+          for (int k = 0; k < 2; ++k) lF[k] += lfb[k] - r->mu_n * (lfb[k] - dd * Fh[k]) / r->nf;
+          lmu = -dd;
+        }
+      } else {
+        double vh[2] = {r->v0[0] / r->nv, r->v0[1] / r->nv};
+        for (int k = 0; k < 2; ++k) lF[k] += lfb[k];
+        lmu = -(lfb[0] * vh[0] + lfb[1] * vh[1]);
+        double lvh[2] = {-r->mu_n * lfb[0], -r->mu_n * lfb[1]};
+        double dd = lvh[0] * vh[0] + lvh[1] * vh[1];
+        for (int k = 0; k < 2; ++k) lv0[k] += (lvh[k] - dd * vh[k]) / r->nv;
+      }
+      /* mu_n = mu (m g - F_z) */
+      lm += d->floor_mu * g * lmu;
+      lF[2] += -d->floor_mu * lmu;
+    }
+  }
+  /* F = T * (third column of R) */
+  lT += lF[0] * P[2] + lF[1] * P[5] + lF[2] * P[8];
+  lP[2] += r->T * lF[0];
+  lP[5] += r->T * lF[1];
+  lP[8] += r->T * lF[2];
+  /* total thrust and torques from the rotor thrusts */
+  static const double sx[4] = {-1, -1, 1, 1}, sy[4] = {-1, 1, 1, -1}, sz[4] = {1, -1, 1, -1};
+  double lf[4], lfmax = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    lf[i] = lT + arm_d * (sx[i] * ltau[0] + sy[i] * ltau[1]) + d->k_tau * sz[i] * ltau[2];
+    lu[i] += 2.0 * r->f_max * r->u1[i] * lf[i];
+    le[i] += lf[i];
+    lfmax += r->u1[i] * r->u1[i] * lf[i];
+  }
+  /* motor noise and lag */
+  double le0[4], lu0[4], lalag = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    if (r->noise) {
+      le0[i] = d->motor_noise_decay * le[i];
+      lfmax += d->motor_noise_std * sqrt(1.0 - d->motor_noise_decay * d->motor_noise_decay) *
+               r->z[i] * le[i];
+    } else {
+      le0[i] = le[i];
+    }
+    lu0[i] = (1.0 - r->alpha_lag) * lu[i];
+    guhat[i] += r->alpha_lag * lu[i];
+    lalag += (r->uhat[i] - r->u0[i]) * lu[i];
+  }
+  /* f_max = m g t2w / 4, alpha_lag = 1 - exp(-dt/tau) */
+  lm += 0.25 * g * p[PT2W] * lfmax;
+  gp[PT2W] += 0.25 * m * g * lfmax;
+  gp[PTAU] += lalag * (-exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));
+  gp[PM] += lm;
+  for (int k = 0; k < 3; ++k) gp[PJX + k] += lJ[k];
+
+  for (int k = 0; k < 3; ++k) {
+    lam[IX + k] = lx0[k];
+    lam[IV + k] = lv0[k];
+    lam[IW + k] = lw0[k];
+  }
+  for (int k = 0; k < 9; ++k) lam[IR + k] = lP[k];
+  for (int k = 0; k < 4; ++k) {
+    lam[IU + k] = lu0[k];
+    lam[IE + k] = le0[k];
+  }
+  lam[IF] = 0.0;
+}
+
+/* Reverse of the pair response and of the penalty of one environment.
+ * S1 holds the env's states after the floor step (before the response);
+ * lam (state adjoints of the env's quads) enters as dL/d(state after the
+ * response) and leaves as dL/d(state before the response). */
+static void env_pairs_vjp(const or_desc* d, const double* S1, double* lam, int q0, int n,
+                          const double* gpen, double beta) {
+  double ldv[64][3];
+  int marked[64];
+  memset(marked, 0, sizeof(marked));
+  const double dc2 = d->col_dist * d->col_dist;
+  const int collide = (d->flags & OR_COLLIDE) != 0;
+  /* which quads responded (recomputed exactly as in the forward pass) */
+  if (collide) {
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        const double* si = S1 + (size_t)(q0 + i) * NS;
+        const double* sj = S1 + (size_t)(q0 + j) * NS;
+        double dx[3] = {si[IX] - sj[IX], si[IX + 1] - sj[IX + 1], si[IX + 2] - sj[IX + 2]};
+        double d2 = dot3(dx, dx);
+        if (!(d2 < dc2)) continue;
+        double nrm[3];
+        if (d2 < 1e-12) { nrm[0] = nrm[1] = 0.0; nrm[2] = 1.0; }
+        else for (int k = 0; k < 3; ++k) nrm[k] = dx[k] / sqrt(d2);
+        double sp = 0.0;
+        for (int k = 0; k < 3; ++k) sp += (sj[IV + k] - si[IV + k]) * nrm[k];
+        if ((d->flags & OR_APPROACH_ONLY) && !(sp > 0.0)) continue;
+        marked[i] = marked[j] = 1;
+      }
+  }
+  /* v2 = decay (v1 + dv + noise) for responding quads */
+  for (int i = 0; i < n; ++i) {
+    double* li = lam + (size_t)(q0 + i) * NS;
+    for (int k = 0; k < 3; ++k) {
+      ldv[i][k] = marked[i] ? d->col_decay * li[IV + k] : 0.0;
+      if (marked[i]) li[IV + k] *= d->col_decay;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double* si = S1 + (size_t)(q0 + i) * NS;
+      const double* sj = S1 + (size_t)(q0 + j) * NS;
+      double* li = lam + (size_t)(q0 + i) * NS;
+      double* lj = lam + (size_t)(q0 + j) * NS;
+      double dx[3] = {si[IX] - sj[IX], si[IX + 1] - sj[IX + 1], si[IX + 2] - sj[IX + 2]};
+      double d2 = dot3(dx, dx), dd = sqrt(d2);
+      /* penalty: d/dx_i of w_ij softplus(beta (dc - d))/beta = -w_ij sigmoid(.) n */
+      if (gpen && dd > 0.0) {
+        double coef = -0.5 * (gpen[q0 + i] + gpen[q0 + j]) * sigmoid(beta * (d->col_dist - dd));
+        for (int k = 0; k < 3; ++k) {
+          li[IX + k] += coef * dx[k] / dd;
+          lj[IX + k] -= coef * dx[k] / dd;
+        }
+      }
+      if (!collide || !(d2 < dc2)) continue;
+      double nrm[3];
+      int coincident = d2 < 1e-12;
+      if (coincident) { nrm[0] = nrm[1] = 0.0; nrm[2] = 1.0; }
+      else for (int k = 0; k < 3; ++k) nrm[k] = dx[k] / dd;
+      double wv[3];
+      for (int k = 0; k < 3; ++k) wv[k] = sj[IV + k] - si[IV + k];
+      double sp = dot3(wv, nrm);
+      if ((d->flags & OR_APPROACH_ONLY) && !(sp > 0.0)) continue;
+      /* dv_i = sp n, dv_j = -sp n, sp = (v_j - v_i).n, n = (x_i - x_j)/d */
+      double mu[3];
+      for (int k = 0; k < 3; ++k) mu[k] = ldv[i][k] - ldv[j][k];
+      double mn = dot3(mu, nrm);
+      for (int k = 0; k < 3; ++k) {
+        li[IV + k] += -mn * nrm[k];
+        lj[IV + k] += mn * nrm[k];
+      }
+      if (!coincident) {
+        double gn[3];
+        for (int k = 0; k < 3; ++k) gn[k] = sp * mu[k] + mn * wv[k];
+        double gnn = dot3(gn, nrm);
+        for (int k = 0; k < 3; ++k) {
+          double gx = (gn[k] - gnn * nrm[k]) / dd;
+          li[IX + k] += gx;
+          lj[IX + k] -= gx;
+        }
+      }
+    }
+}
+
+static double dfhat_da(const or_desc* d, double a) {
+  if (d->flags & OR_ACT_UNIT) return (a > 0.0 && a < 1.0) ? 1.0 : 0.0;
+  return (a > -1.0 && a < 1.0) ? 0.5 : 0.0;
+}
+
+/*
+ * Rollout of n_calls calls of n_sub substeps each from state[Q][27] (updated
+ * in place), actions [n_calls][Q][4], first substep index t0.  pen
+ * (optional, [Q]) accumulates each quad's penalty share (see above).
+ */
+int or_rollout(const or_desc* d, const double* params, double* state, const double* actions,
+               int n_calls, int n_sub, uint64_t t0, double* pen, double beta) {
+  if (check_desc(d) || !params || !state || !actions || n_calls < 0 || n_sub < 0) return -1;
+  const int E = d->n_envs, Q = d->env_offsets[E];
+  uint32_t* ev = (uint32_t*)calloc((size_t)Q + 1, sizeof(uint32_t));
+  double* mg = (double*)malloc(((size_t)Q + 1) * sizeof(double));
+  if (!ev || !mg) { free(ev); free(mg); return -1; }
+  for (int c = 0; c < n_calls; ++c)
+    for (int sub = 0; sub < n_sub; ++sub) {
+      const uint64_t t = t0 + (uint64_t)c * n_sub + sub;
+#pragma omp parallel for schedule(static)
+      for (int e = 0; e < E; ++e) {
+        const int q0 = d->env_offsets[e], n = d->env_offsets[e + 1] - q0;
+        for (int i = 0; i < n; ++i) {
+          const int q = q0 + i;
+          quad_substep(d, params + (size_t)q * NP, state + (size_t)q * NS,
+                       actions + ((size_t)c * Q + q) * 4, d->quad_id_offset + (uint32_t)q, t,
+                       &ev[q], &mg[q], NULL);
+        }
+        if (n > 1 && ((d->flags & OR_COLLIDE) || pen))
+          env_pairs(d, state, q0, n, t, NULL, ev, mg, pen, beta);
+      }
+    }
+  free(ev);
+  free(mg);
+  return 0;
+}
+
+/*
+ * Reverse pass of or_rollout (same arguments; state0 is the state the
+ * rollout started from and is not modified).  gstate [Q][27] enters as
+ * dL/d(final state) and leaves as dL/d(initial state); gpen (optional, [Q])
+ * is dL/d(pen); gact [n_calls][Q][4] receives dL/d(actions); gparams [Q][6]
+ * receives dL/d(mass, ixx, iyy, izz, thrust_to_weight, motor_tau).  The
+ * whole trajectory is kept in memory (no checkpointing).
+ */
+int or_rollout_vjp(const or_desc* d, const double* params, const double* state0,
+                   const double* actions, int n_calls, int n_sub, uint64_t t0,
+                   double* gstate, const double* gpen, double beta, double* gact,
+                   double* gparams) {
+  if (check_desc(d) || !params || !state0 || !actions || !gstate || !gact || !gparams ||
+      n_calls < 0 || n_sub < 0)
+    return -1;
+  const int E = d->n_envs, Q = d->env_offsets[E];
+  const size_t S = (size_t)n_calls * n_sub;
+  const size_t QS = (size_t)Q * NS;
+  double* traj = (double*)malloc((S + 1) * QS * sizeof(double));
+  double* S1 = (double*)malloc(QS * sizeof(double));
+  or_rec* rec = (or_rec*)malloc(((size_t)Q + 1) * sizeof(or_rec));
+  double* gu = (double*)calloc((size_t)Q * 4 + 1, sizeof(double));
+  uint32_t* ev = (uint32_t*)calloc((size_t)Q + 1, sizeof(uint32_t));
+  double* mg = (double*)malloc(((size_t)Q + 1) * sizeof(double));
+  if (!traj || !S1 || !rec || !gu || !ev || !mg) {
+    free(traj); free(S1); free(rec); free(gu); free(ev); free(mg);
+    return -1;
+  }
+  /* forward, keeping the state at the start of every substep */
+  memcpy(traj, state0, QS * sizeof(double));
+  for (size_t k = 0; k < S; ++k) {
+    memcpy(traj + (k + 1) * QS, traj + k * QS, QS * sizeof(double));
+    const int c = (int)(k / (size_t)n_sub);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < E; ++e) {
+      const int q0 = d->env_offsets[e], n = d->env_offsets[e + 1] - q0;
+      double* st = traj + (k + 1) * QS;
+      for (int i = 0; i < n; ++i) {
+        const int q = q0 + i;
+        quad_substep(d, params + (size_t)q * NP, st + (size_t)q * NS,
+                     actions + ((size_t)c * Q + q) * 4, d->quad_id_offset + (uint32_t)q,
+                     t0 + k, &ev[q], &mg[q], NULL);
+      }
+      if ((d->flags & OR_COLLIDE) && n > 1) env_pairs(d, st, q0, n, t0 + k, NULL, ev, mg, NULL, 0.0);
+    }
+  }
+  memset(gparams, 0, (size_t)Q * NP * sizeof(double));
+  /* reverse sweep */
+  for (size_t kk = S; kk-- > 0;) {
+    const int c = (int)(kk / (size_t)n_sub);
+    memcpy(S1, traj + kk * QS, QS * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < E; ++e) {
+      const int q0 = d->env_offsets[e], n = d->env_offsets[e + 1] - q0;
+      for (int i = 0; i < n; ++i) {
+        const int q = q0 + i;
+        quad_substep(d, params + (size_t)q * NP, S1 + (size_t)q * NS,
+                     actions + ((size_t)c * Q + q) * 4, d->quad_id_offset + (uint32_t)q,
+                     t0 + kk, &ev[q], &mg[q], &rec[q]);
+      }
+      if (n > 1) env_pairs_vjp(d, S1, gstate, q0, n, gpen, beta);
+      for (int i = 0; i < n; ++i) {
+        const int q = q0 + i;
+        quad_vjp(d, params + (size_t)q * NP, &rec[q], gstate + (size_t)q * NS,
+                 gu + (size_t)q * 4, gparams + (size_t)q * NP);
+      }
+    }
+    if (kk % (size_t)n_sub == 0) {
+      /* first substep of call c: the held command's gradient becomes the action's */
+      for (int q = 0; q < Q; ++q)
+        for (int i = 0; i < 4; ++i) {
+          const double a = actions[((size_t)c * Q + q) * 4 + i];
+          const double uh = rec[q].uhat[i];
+          gact[((size_t)c * Q + q) * 4 + i] =
+              uh > 0.0 ? gu[(size_t)q * 4 + i] * 0.5 / uh * dfhat_da(d, a) : 0.0;
+          gu[(size_t)q * 4 + i] = 0.0;
+        }
+    }
+  }
+  free(traj); free(S1); free(rec); free(gu); free(ev); free(mg);
   return 0;
 }
 
