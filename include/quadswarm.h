@@ -128,6 +128,9 @@ int qs_destroy(qs_handle* h);
 /* Sizes of a handle: number of quads, of environments, and the obs row length. */
 int qs_sizes(const qs_handle* h, int32_t* n_quads, int32_t* n_envs, int32_t* obs_dim);
 
+/* Substep counter: number of substeps enqueued so far (keys the noise). */
+int qs_substep_index(const qs_handle* h, uint64_t* substep_index);
+
 /*
  * Advance every quad by n_substeps substeps of dt, holding d_actions [Q][4]
  * for all of them (§III-A.1: the policy acts once per control step; the
@@ -180,6 +183,56 @@ int qs_debug_contacts(qs_handle* h, uint64_t* d_mask, void* stream);
  * Synchronous.  The error is cleared by the call that reports it.
  */
 int qs_sync(qs_handle* h, void* stream);
+
+/* ---- differentiation (reverse mode) ----------------------------------------
+ * Loss model: L = l(final state) + sum_q gpen[q] * pen[q], where pen[q] is
+ * quad q's half-share of the smoothed collision penalty
+ *     sum over substeps, env-mates j of softplus(beta (col_dist - d_qj)) / beta
+ * (d_qj: centre distance after the substep's motion; a smooth version of
+ * the hinge proximity term of §III-E).  Derivatives are exact for the branch
+ * each event took (walls, floor, contacts, friction regime); the resting
+ * flag carries none.  Checkpoint k of a rollout is the state at the start of
+ * call k * ckpt_every, stored field-major [27][Q] (state row layout, one
+ * field after another).
+ */
+
+/*
+ * Run n_calls calls of n_substeps substeps from the handle's state, the
+ * action of call k being d_actions + k*Q*4 ([n_calls][Q][4], 16-byte
+ * aligned).  d_ckpt (optional): ceil(n_calls/ckpt_every) checkpoints
+ * [..][27][Q].  d_penalty (optional, [Q]): pen[q] is ADDED (beta > 0).
+ * The handle's state and substep counter advance as n_calls qs_step calls
+ * would (bitwise identical states).
+ */
+int qs_rollout(qs_handle* h, const float* d_actions, int32_t n_calls, int32_t n_substeps,
+               int32_t ckpt_every, float* d_ckpt, float* d_penalty, float beta, void* stream);
+
+/*
+ * Reverse pass of a qs_rollout that started at substep substep_index0 with
+ * the same d_actions, n_calls, n_substeps, ckpt_every and its d_ckpt.
+ * d_gstate [Q][27]: dL/d(final state) on entry, dL/d(initial state) on
+ * return.  d_gpenalty (optional, [Q]): dL/d pen.  Writes d_gactions
+ * [n_calls][Q][4] and ADDS dL/d(mass, ixx, iyy, izz, thrust_to_weight,
+ * motor_tau) into d_gparams [Q][6].  Each segment of ckpt_every calls is
+ * recomputed from its checkpoint into a tape of ckpt_every*n_substeps
+ * states (device scratch owned by the handle, grown on first use).  Does not
+ * change the handle's state.
+ */
+int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
+                        int32_t n_substeps, int32_t ckpt_every, const float* d_ckpt,
+                        uint64_t substep_index0, float* d_gstate, const float* d_gpenalty,
+                        float beta, float* d_gactions, float* d_gparams, void* stream);
+
+/*
+ * Vector-Jacobian product of one qs_step call: from d_state_in [Q][27] (the
+ * state before the call), d_actions [Q][4], n_substeps and the call's first
+ * substep index, map d_gstate_out [Q][27] = dL/d(state after) to
+ * d_gstate_in [Q][27] = dL/d(state before) and d_gactions [Q][4], and ADD
+ * dL/d(params) into d_gparams [Q][6].  No penalty term.
+ */
+int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actions,
+                     int32_t n_substeps, uint64_t substep_index, const float* d_gstate_out,
+                     float* d_gstate_in, float* d_gactions, float* d_gparams, void* stream);
 
 /* Static description of a return code. */
 const char* qs_error_string(int code);

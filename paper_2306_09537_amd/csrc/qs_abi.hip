@@ -6,11 +6,13 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
 #include "quadswarm.h"
 #include "qs_kernels.h"
+#include "qs_rollout.h"
 
 using qs::Consts;
 using qs::Ptrs;
@@ -31,6 +33,13 @@ struct qs_handle {
   int* h_err = nullptr;  // pinned
   uint64_t t = 0;
   bool record = false;
+  // adjoint scratch, grown on demand: tape [S][27][Q], adjoint [27][Q],
+  // parameter gradient [6][Q], one checkpoint [27][Q]
+  float* d_tape = nullptr;
+  size_t tape_cap = 0;
+  float* d_lam = nullptr;
+  float* d_gpar = nullptr;
+  float* d_ck1 = nullptr;
 };
 
 namespace {
@@ -95,6 +104,10 @@ void free_all(qs_handle* h) {
   (void)hipFree(h->d_qenv);
   (void)hipFree(h->d_contacts);
   (void)hipFree(h->d_err);
+  (void)hipFree(h->d_tape);
+  (void)hipFree(h->d_lam);
+  (void)hipFree(h->d_gpar);
+  (void)hipFree(h->d_ck1);
   if (h->h_err) (void)hipHostFree(h->h_err);
 }
 
@@ -172,6 +185,111 @@ int launch(qs_handle* h, const float* act, int nsub, const float* goals, float* 
   return rc;
 }
 
+// ---- differentiable rollouts ------------------------------------------------
+template <int BS, int N, bool PEN>
+void go_roll(qs_handle* h, const float* act, int ncalls, int nsub, float* ckpt, int ce, float* pen,
+             float beta, hipStream_t s) {
+  hipLaunchKernelGGL((qs::rollout_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->c, ptrs(h),
+                     act, ncalls, nsub, (unsigned long long)h->t, ckpt, ce, pen, beta);
+}
+
+template <int BS, int N, bool PEN>
+void go_adj(qs_handle* h, const float* ckpt, const float* act, int ncalls, int nsub, uint64_t t0,
+            const float* gpen, float beta, float* gact, hipStream_t s) {
+  hipLaunchKernelGGL((qs::adjoint_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->c,
+                     ptrs(h), ckpt, act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam,
+                     gpen, beta, gact, h->d_gpar);
+}
+
+// Dispatch on (block size, uniform swarm size) for a launcher template F.
+template <template <int, int, bool> class F, bool PEN, typename... A>
+void dispatch(qs_handle* h, A... a) {
+  if (h->bs == 128) {
+    switch (h->uniform_n) {
+      case 1: F<128, 1, PEN>::run(h, a...); break;
+      case 8: F<128, 8, PEN>::run(h, a...); break;
+      case 32: F<128, 32, PEN>::run(h, a...); break;
+      default: F<128, 0, PEN>::run(h, a...); break;
+    }
+  } else {
+    switch (h->uniform_n) {
+      case 1: F<64, 1, PEN>::run(h, a...); break;
+      case 8: F<64, 8, PEN>::run(h, a...); break;
+      case 32: F<64, 32, PEN>::run(h, a...); break;
+      default: F<64, 0, PEN>::run(h, a...); break;
+    }
+  }
+}
+
+template <int BS, int N, bool PEN>
+struct RollF {
+  static void run(qs_handle* h, const float* act, int ncalls, int nsub, float* ckpt, int ce,
+                  float* pen, float beta, hipStream_t s) {
+    go_roll<BS, N, PEN>(h, act, ncalls, nsub, ckpt, ce, pen, beta, s);
+  }
+};
+
+template <int BS, int N, bool PEN>
+struct AdjF {
+  static void run(qs_handle* h, const float* ckpt, const float* act, int ncalls, int nsub,
+                  uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
+    go_adj<BS, N, PEN>(h, ckpt, act, ncalls, nsub, t0, gpen, beta, gact, s);
+  }
+};
+
+int grow(float** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return QS_OK;
+  (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  if (hipMalloc((void**)p, need * sizeof(float)) != hipSuccess) {
+    *p = nullptr;
+    return QS_ERR_NOMEM;
+  }
+  *cap = need;
+  return QS_OK;
+}
+
+int ensure_adjoint_scratch(qs_handle* h, size_t tape_floats) {
+  size_t cap_lam = h->d_lam ? 1 : 0, cap_g = h->d_gpar ? 1 : 0, cap_c = h->d_ck1 ? 1 : 0;
+  int rc = grow(&h->d_tape, &h->tape_cap, tape_floats);
+  if (rc == QS_OK && !h->d_lam) rc = grow(&h->d_lam, &cap_lam, (size_t)qs::NSTATE * h->Q);
+  if (rc == QS_OK && !h->d_gpar) rc = grow(&h->d_gpar, &cap_g, (size_t)6 * h->Q);
+  if (rc == QS_OK && !h->d_ck1) rc = grow(&h->d_ck1, &cap_c, (size_t)qs::NSTATE * h->Q);
+  return rc;
+}
+
+void convert(const float* src, float* dst, int Q, int rows, bool to_row_major, bool acc,
+             hipStream_t s) {
+  const long long n = (long long)Q * rows;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (to_row_major)
+    hipLaunchKernelGGL(qs::fm_to_rm_kernel, grid, block, 0, s, src, dst, Q, rows, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL(qs::rm_to_fm_kernel, grid, block, 0, s, src, dst, Q, rows);
+}
+
+// Reverse sweep over n_calls calls in segments of ce calls, from the
+// checkpoints ckpt ([27][Q] each); lam and gpar scratch already hold the
+// incoming adjoint and zeros.
+int run_adjoint(qs_handle* h, const float* act, int n_calls, int nsub, int ce, const float* ckpt,
+                uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
+  const int nseg = (n_calls + ce - 1) / ce;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int c0 = seg * ce, nc = std::min(ce, n_calls - c0);
+    const float* ck = ckpt + (size_t)seg * qs::NSTATE * h->Q;
+    const float* a = act + (size_t)c0 * h->Q * 4;
+    float* ga = gact + (size_t)c0 * h->Q * 4;
+    const uint64_t ts = t0 + (uint64_t)c0 * nsub;
+    if (gpen)
+      dispatch<AdjF, true>(h, ck, a, nc, nsub, ts, gpen, beta, ga, s);
+    else
+      dispatch<AdjF, false>(h, ck, a, nc, nsub, ts, gpen, beta, ga, s);
+    if (hipGetLastError() != hipSuccess) return QS_ERR_HIP;
+  }
+  return QS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -226,6 +344,7 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   c.rmax2 = desc->room_max[2];
   c.e_wall = desc->wall_restitution;
   c.dcol2 = (float)((double)desc->col_dist * (double)desc->col_dist);
+  c.dcol = desc->col_dist;
   c.col_decay = desc->col_decay;
   c.col_nv = desc->col_noise_v;
   c.col_nw = desc->col_noise_w;
@@ -277,6 +396,8 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
         (float)(0.25 * (double)p.mass * (double)desc->gravity * (double)p.thrust_to_weight);
     par[(size_t)qs::P_ALAG * h->Qp + q] =
         (float)(1.0 - std::exp(-(double)desc->dt / (double)p.motor_tau));
+    par[(size_t)qs::P_T2W * h->Qp + q] = p.thrust_to_weight;
+    par[(size_t)qs::P_TAU * h->Qp + q] = p.motor_tau;
     for (int f = 0; f < qs::NSTATE; ++f)
       st[(size_t)f * h->Qp + q] = h_state0[(size_t)q * QS_STATE_DIM + f];
   }
@@ -329,6 +450,12 @@ int qs_sizes(const qs_handle* h, int32_t* n_quads, int32_t* n_envs, int32_t* obs
   if (n_quads) *n_quads = h->Q;
   if (n_envs) *n_envs = h->E;
   if (obs_dim) *obs_dim = h->OD;
+  return QS_OK;
+}
+
+int qs_substep_index(const qs_handle* h, uint64_t* substep_index) {
+  if (!h || !substep_index) return QS_ERR_NULL;
+  *substep_index = h->t;
   return QS_OK;
 }
 
@@ -411,6 +538,87 @@ int qs_sync(qs_handle* h, void* stream) {
     return QS_ERR_NONFINITE;
   }
   return QS_OK;
+}
+
+int qs_rollout(qs_handle* h, const float* d_actions, int32_t n_calls, int32_t n_substeps,
+               int32_t ckpt_every, float* d_ckpt, float* d_penalty, float beta, void* stream) {
+  if (!h || !d_actions) return QS_ERR_NULL;
+  if (n_calls < 0 || n_substeps < 0) return QS_ERR_INVALID;
+  if (d_ckpt && ckpt_every < 1) return QS_ERR_INVALID;
+  if (d_penalty && !(beta > 0.f && std::isfinite(beta))) return QS_ERR_INVALID;
+  if (!aligned(d_actions, 16) || (d_ckpt && !aligned(d_ckpt, 4)) ||
+      (d_penalty && !aligned(d_penalty, 4)))
+    return QS_ERR_ALIGN;
+  if (n_calls == 0 || n_substeps == 0) return QS_OK;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (d_penalty)
+    dispatch<RollF, true>(h, d_actions, (int)n_calls, (int)n_substeps, d_ckpt, (int)ckpt_every,
+                          d_penalty, beta, s);
+  else
+    dispatch<RollF, false>(h, d_actions, (int)n_calls, (int)n_substeps, d_ckpt,
+                           (int)std::max(ckpt_every, 1), d_penalty, beta, s);
+  if (hipGetLastError() != hipSuccess) return QS_ERR_HIP;
+  h->t += (uint64_t)n_calls * (uint64_t)n_substeps;
+  return QS_OK;
+}
+
+int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
+                        int32_t n_substeps, int32_t ckpt_every, const float* d_ckpt,
+                        uint64_t substep_index0, float* d_gstate, const float* d_gpenalty,
+                        float beta, float* d_gactions, float* d_gparams, void* stream) {
+  if (!h || !d_actions || !d_ckpt || !d_gstate || !d_gactions || !d_gparams) return QS_ERR_NULL;
+  if (n_calls < 0 || n_substeps < 0 || ckpt_every < 1) return QS_ERR_INVALID;
+  if (d_gpenalty && !(beta > 0.f && std::isfinite(beta))) return QS_ERR_INVALID;
+  if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_ckpt, 4) ||
+      !aligned(d_gstate, 4) || !aligned(d_gparams, 4) || (d_gpenalty && !aligned(d_gpenalty, 4)))
+    return QS_ERR_ALIGN;
+  if (n_calls == 0 || n_substeps == 0) return QS_OK;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  const size_t tape = (size_t)std::min<int32_t>(ckpt_every, n_calls) * n_substeps * qs::NSTATE * h->Q;
+  int rc = ensure_adjoint_scratch(h, tape);
+  if (rc != QS_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  convert(d_gstate, h->d_lam, h->Q, qs::NSTATE, false, false, s);
+  hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((6LL * h->Q + 255) / 256)), dim3(256), 0, s,
+                     h->d_gpar, 6LL * h->Q, 0.0f);
+  rc = run_adjoint(h, d_actions, n_calls, n_substeps, ckpt_every, d_ckpt, substep_index0,
+                   d_gpenalty, beta, d_gactions, s);
+  if (rc != QS_OK) return rc;
+  convert(h->d_lam, d_gstate, h->Q, qs::NSTATE, true, false, s);
+  convert(h->d_gpar, d_gparams, h->Q, 6, true, true, s);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+}
+
+int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actions,
+                     int32_t n_substeps, uint64_t substep_index, const float* d_gstate_out,
+                     float* d_gstate_in, float* d_gactions, float* d_gparams, void* stream) {
+  if (!h || !d_state_in || !d_actions || !d_gstate_out || !d_gstate_in || !d_gactions ||
+      !d_gparams)
+    return QS_ERR_NULL;
+  if (n_substeps < 0) return QS_ERR_INVALID;
+  if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_state_in, 4) ||
+      !aligned(d_gstate_out, 4) || !aligned(d_gstate_in, 4) || !aligned(d_gparams, 4))
+    return QS_ERR_ALIGN;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  int rc = ensure_adjoint_scratch(h, (size_t)std::max(n_substeps, 1) * qs::NSTATE * h->Q);
+  if (rc != QS_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  convert(d_state_in, h->d_ck1, h->Q, qs::NSTATE, false, false, s);
+  convert(d_gstate_out, h->d_lam, h->Q, qs::NSTATE, false, false, s);
+  hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((6LL * h->Q + 255) / 256)), dim3(256), 0, s,
+                     h->d_gpar, 6LL * h->Q, 0.0f);
+  if (n_substeps > 0) {
+    rc = run_adjoint(h, d_actions, 1, n_substeps, 1, h->d_ck1, substep_index, nullptr, 0.f,
+                     d_gactions, s);
+    if (rc != QS_OK) return rc;
+  } else {
+    hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((4LL * h->Q + 255) / 256)), dim3(256), 0,
+                       s, d_gactions, 4LL * h->Q, 0.0f);
+  }
+  convert(h->d_lam, d_gstate_in, h->Q, qs::NSTATE, true, false, s);
+  convert(h->d_gpar, d_gparams, h->Q, 6, true, true, s);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
 }
 
 const char* qs_error_string(int code) {

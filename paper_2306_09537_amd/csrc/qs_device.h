@@ -13,11 +13,11 @@ namespace qs {
 enum : uint32_t {
   F_ROOM = 1u, F_FLOOR = 2u, F_COLLIDE = 4u, F_NOISE = 8u, F_APPROACH = 16u, F_ACT_UNIT = 32u
 };
-enum : int { NSTATE = 27, NPARAM = 6 };
+enum : int { NSTATE = 27, NPARAM = 8 };
 // SoA field index of the private state: x3 v3 R9 (row-major) w3 u4 eps4 floor
 enum : int { S_X = 0, S_V = 3, S_R = 6, S_W = 15, S_U = 18, S_E = 22, S_F = 26 };
-// SoA field index of the derived parameters
-enum : int { P_M = 0, P_JX = 1, P_JY = 2, P_JZ = 3, P_FMAX = 4, P_ALAG = 5 };
+// SoA field index of the per-quad parameters (the forward reads the first six)
+enum : int { P_M = 0, P_JX = 1, P_JY = 2, P_JZ = 3, P_FMAX = 4, P_ALAG = 5, P_T2W = 6, P_TAU = 7 };
 // noise streams: fourth Philox counter word = stream << 8 | draw
 enum : uint32_t { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2 };
 enum : int { ERRBIT_STATE = 1, ERRBIT_ACTION = 2 };
@@ -26,7 +26,7 @@ struct Consts {
   float dt, g, arm_d, k_tau, drag, mu;
   float a_nd, ns_scale;  // motor noise: eps <- a_nd eps + ns_scale f_max z
   float rmin0, rmin1, rmin2, rmax0, rmax1, rmax2, e_wall;
-  float dcol2, col_decay, col_nv, col_nw;
+  float dcol2, dcol, col_decay, col_nv, col_nw;
   uint32_t flags;
   uint32_t key0, key1;
   int32_t K;
@@ -35,7 +35,7 @@ struct Consts {
 
 struct Ptrs {
   float* st;                    // [27][Qp] private SoA state
-  const float* par;             // [6][Qp] m, jx, jy, jz, f_max, alpha_lag
+  const float* par;             // [8][Qp] m, jx, jy, jz, f_max, alpha_lag, t2w, tau
   const uint32_t* sw;           // [Qp] (env start within the block << 8) | n_e
   const int2* blk;              // [nblk] (first quad, quad count)
   unsigned long long* contacts; // [Qp] or nullptr
@@ -109,11 +109,41 @@ __device__ __forceinline__ float rotor_cmd(float a, bool unit) {
   return sqrtf(fh);
 }
 
+// Intermediates of one substep kept for the reverse sweep (adjoint).
+struct Rec {
+  float z[4], u0[4], u1[4], P[9], w0[3], v0[3], T, F[3];
+  float wdot[3], w1[3], A1[3], n0, c0[3], dp, n1, c1[3];
+  float mu_n, fb[2], nv, nf, mag;
+  float hx, hy, nh, kx, ky, nk;
+  bool rest, statik, guard, bounced, hit, fallback;
+  bool clamp[3], flip[3];
+};
+
 // One substep of one quad up to (not including) the in-env pair pass:
 // motor lag and noise, thrust and torque mix, floor-rest or free-flight
 // dynamics with semi-implicit Euler and Gram-Schmidt, walls and floor.
+// REC: also record the intermediates the adjoint needs into *r.
+template <bool REC = false>
 __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, Quad& s,
-                                             const float uhat[4], uint32_t q, uint64_t t) {
+                                             const float uhat[4], uint32_t q, uint64_t t,
+                                             Rec* r = nullptr) {
+  if constexpr (REC) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      r->u0[i] = s.u[i];
+      r->z[i] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r->P[k] = s.R[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      r->w0[k] = s.w[k];
+      r->v0[k] = s.v[k];
+      r->clamp[k] = false;
+      r->flip[k] = false;
+    }
+    r->statik = r->guard = r->bounced = r->hit = r->fallback = false;
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) s.xo[k] = s.x[k];
   // §III-A.1 motor lag
@@ -125,6 +155,10 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     normal4(c, q, t, STREAM_MOTOR, 0, z);
 #pragma unroll
     for (int i = 0; i < 4; ++i) s.e[i] = fmaf(c.a_nd, s.e[i], p.a_ns * z[i]);
+    if constexpr (REC) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r->z[i] = z[i];
+    }
   }
   // §III-A.2 per-rotor thrust, §III-A mix (X layout FR, BR, BL, FL)
   float f[4];
@@ -138,6 +172,15 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
   const float Fx = T * s.R[2], Fy = T * s.R[5], Fz = T * s.R[8];
 
   const bool rest = (c.flags & F_FLOOR) && s.fl != 0.0f && Fz <= p.m * c.g;
+  if constexpr (REC) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r->u1[i] = s.u[i];
+    r->T = T;
+    r->F[0] = Fx;
+    r->F[1] = Fy;
+    r->F[2] = Fz;
+    r->rest = rest;
+  }
   if (!rest) {
     s.fl = 0.0f;
     const float dm = c.drag * p.inv_m;
@@ -162,24 +205,45 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     s.w[0] = fmaf(c.dt, wdx, s.w[0]);
     s.w[1] = fmaf(c.dt, wdy, s.w[1]);
     s.w[2] = fmaf(c.dt, wdz, s.w[2]);
+    if constexpr (REC) {
+      r->wdot[0] = wdx;
+      r->wdot[1] = wdy;
+      r->wdot[2] = wdz;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r->w1[k] = s.w[k];
+    }
     // R <- R + dt R [w]x (body rate), then Gram-Schmidt on the columns
     const float hx = c.dt * s.w[0], hy = c.dt * s.w[1], hz = c.dt * s.w[2];
     float c0[3], c1[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const float r0 = s.R[3 * r], r1 = s.R[3 * r + 1], r2 = s.R[3 * r + 2];
-      c0[r] = r0 + (r1 * hz - r2 * hy);
-      c1[r] = r1 + (r2 * hx - r0 * hz);
+    for (int k = 0; k < 3; ++k) {
+      const float r0 = s.R[3 * k], r1 = s.R[3 * k + 1], r2 = s.R[3 * k + 2];
+      c0[k] = r0 + (r1 * hz - r2 * hy);
+      c1[k] = r1 + (r2 * hx - r0 * hz);
+    }
+    if constexpr (REC) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r->A1[k] = c1[k];
     }
     const float i0 = rsqrtf(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) c0[r] *= i0;
+    for (int k = 0; k < 3; ++k) c0[k] *= i0;
     const float dp = c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) c1[r] = fmaf(-dp, c0[r], c1[r]);
+    for (int k = 0; k < 3; ++k) c1[k] = fmaf(-dp, c0[k], c1[k]);
     const float i1 = rsqrtf(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) c1[r] *= i1;
+    for (int k = 0; k < 3; ++k) c1[k] *= i1;
+    if constexpr (REC) {
+      r->n0 = 1.0f / i0;
+      r->n1 = 1.0f / i1;
+      r->dp = dp;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        r->c0[k] = c0[k];
+        r->c1[k] = c1[k];
+      }
+    }
     s.R[0] = c0[0]; s.R[3] = c0[1]; s.R[6] = c0[2];
     s.R[1] = c1[0]; s.R[4] = c1[1]; s.R[7] = c1[2];
     s.R[2] = c0[1] * c1[2] - c0[2] * c1[1];
@@ -197,15 +261,31 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
       const float sc = nf > 0.0f ? mag / nf : 0.0f;
       fbx = sc * Fx;
       fby = sc * Fy;
+      if constexpr (REC) {
+        r->statik = true;
+        r->nf = nf;
+        r->mag = nf > 0.0f ? mag : 0.0f;
+      }
     } else {
-      const float iv = mu_n / sqrtf(vx0 * vx0 + vy0 * vy0);
+      const float nv = sqrtf(vx0 * vx0 + vy0 * vy0);
+      const float iv = mu_n / nv;
       fbx = Fx - iv * vx0;
       fby = Fy - iv * vy0;
+      if constexpr (REC) r->nv = nv;
+    }
+    if constexpr (REC) {
+      r->mu_n = mu_n;
+      r->fb[0] = fbx;
+      r->fb[1] = fby;
     }
     s.v[0] = fmaf(c.dt, (fbx - c.drag * vx0) * p.inv_m, vx0);
     s.v[1] = fmaf(c.dt, (fby - c.drag * vy0) * p.inv_m, vy0);
     s.v[2] = 0.0f;
-    if (s.v[0] * vx0 + s.v[1] * vy0 < 0.0f) { s.v[0] = 0.0f; s.v[1] = 0.0f; }
+    if (s.v[0] * vx0 + s.v[1] * vy0 < 0.0f) {
+      s.v[0] = 0.0f;
+      s.v[1] = 0.0f;
+      if constexpr (REC) r->guard = true;
+    }
     s.inc[0] = c.dt * s.v[0];
     s.inc[1] = c.dt * s.v[1];
     s.inc[2] = 0.0f;
@@ -224,14 +304,25 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
       if (k < 2 && s.x[k] < lo[k]) {
         s.x[k] = lo[k];
         s.inc[k] = s.x[k] - s.xo[k];
-        if (s.v[k] < 0.0f) { s.v[k] = -c.e_wall * s.v[k]; b = true; }
+        if constexpr (REC) r->clamp[k] = true;
+        if (s.v[k] < 0.0f) {
+          s.v[k] = -c.e_wall * s.v[k];
+          b = true;
+          if constexpr (REC) r->flip[k] = true;
+        }
       }
       if (s.x[k] > hi[k]) {
         s.x[k] = hi[k];
         s.inc[k] = s.x[k] - s.xo[k];
-        if (s.v[k] > 0.0f) { s.v[k] = -c.e_wall * s.v[k]; b = true; }
+        if constexpr (REC) r->clamp[k] = true;
+        if (s.v[k] > 0.0f) {
+          s.v[k] = -c.e_wall * s.v[k];
+          b = true;
+          if constexpr (REC) r->flip[k] = true;
+        }
       }
     }
+    if constexpr (REC) r->bounced = b;
     if (b) {
       float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
       if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
@@ -255,6 +346,16 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     s.fl = 1.0f;
     const float hx = s.R[0], hy = s.R[3];
     const float nh = sqrtf(hx * hx + hy * hy);
+    if constexpr (REC) {
+      r->hit = true;
+      r->hx = hx;
+      r->hy = hy;
+      r->nh = nh;
+      r->fallback = !(nh >= 1e-6f);
+      r->kx = s.R[1];
+      r->ky = s.R[4];
+      r->nk = sqrtf(s.R[1] * s.R[1] + s.R[4] * s.R[4]);
+    }
     float ax, ay;  // unit heading of body x in the floor plane
     if (nh >= 1e-6f) {
       ax = hx / nh;
@@ -271,5 +372,41 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     s.R[6] = 0.0f; s.R[7] = 0.0f; s.R[8] = 1.0f;
   }
 }
+
+// Geometry of the pair (i, j) for the in-env pass, from the tile of start
+// positions (rows 0-2), displacements (rows 3-5) and velocities (rows 6-8).
+// Returns true when the pair is in contact; then n is the unit normal from
+// j to i and sp = (v_j - v_i).n.  Shared by the forward pass and the
+// adjoint's recomputation so both take identical decisions.
+template <int BS>
+__device__ __forceinline__ bool pair_geom(const Consts& c, const float (*tile)[BS], const Quad& s,
+                                          int j, int jj, int me, float& dx, float& dy,
+                                          float& dz, float& d2) {
+  dx = (s.xo[0] - tile[0][j]) + (s.inc[0] - tile[3][j]);
+  dy = (s.xo[1] - tile[1][j]) + (s.inc[1] - tile[4][j]);
+  dz = (s.xo[2] - tile[2][j]) + (s.inc[2] - tile[5][j]);
+  d2 = dx * dx + dy * dy + dz * dz;
+  return d2 < c.dcol2 && jj != me;
+}
+
+template <int BS>
+__device__ __forceinline__ void pair_normal(const float (*tile)[BS], const Quad& s, int j, int jj,
+                                            int me, float dx, float dy, float dz, float d2,
+                                            float n[3], float& sp) {
+  if (d2 < 1e-12f) {
+    n[0] = 0.f;
+    n[1] = 0.f;
+    n[2] = me < jj ? 1.f : -1.f;
+  } else {
+    const float id = rsqrtf(d2);
+    n[0] = dx * id;
+    n[1] = dy * id;
+    n[2] = dz * id;
+  }
+  sp = (tile[6][j] - s.v[0]) * n[0] + (tile[7][j] - s.v[1]) * n[1] + (tile[8][j] - s.v[2]) * n[2];
+}
+
+__device__ __forceinline__ float softplusf(float x) { return x > 20.f ? x : log1pf(expf(x)); }
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
 }  // namespace qs

@@ -119,25 +119,15 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
         bool hit = false;
         auto pair = [&](int jj) {
           const int j = ls + jj;
-          const float dx = (s.xo[0] - tile[0][j]) + (s.inc[0] - tile[3][j]);
-          const float dy = (s.xo[1] - tile[1][j]) + (s.inc[1] - tile[4][j]);
-          const float dz = (s.xo[2] - tile[2][j]) + (s.inc[2] - tile[5][j]);
-          const float d2 = dx * dx + dy * dy + dz * dz;
-          if (d2 < c.dcol2 && jj != me) {
+          float dx, dy, dz, d2;
+          if (pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2)) {
             cmask |= 1ull << jj;
-            float nx, ny, nz;
-            if (d2 < 1e-12f) {
-              nx = 0.f; ny = 0.f; nz = me < jj ? 1.f : -1.f;
-            } else {
-              const float id = rsqrtf(d2);
-              nx = dx * id; ny = dy * id; nz = dz * id;
-            }
-            const float sp = (tile[6][j] - s.v[0]) * nx + (tile[7][j] - s.v[1]) * ny +
-                             (tile[8][j] - s.v[2]) * nz;
+            float nn[3], sp;
+            pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
             if (!(c.flags & F_APPROACH) || sp > 0.f) {
-              dvx = fmaf(sp, nx, dvx);
-              dvy = fmaf(sp, ny, dvy);
-              dvz = fmaf(sp, nz, dvz);
+              dvx = fmaf(sp, nn[0], dvx);
+              dvy = fmaf(sp, nn[1], dvy);
+              dvz = fmaf(sp, nn[2], dvz);
               hit = true;
             }
           }

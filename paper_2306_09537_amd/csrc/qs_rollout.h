@@ -1,0 +1,493 @@
+// Differentiable rollouts: a multi-call forward kernel (a fresh action per
+// call, checkpoints of the state, the smoothed collision penalty) and the
+// segment adjoint kernel that recomputes a segment from its checkpoint,
+// keeps the per-substep states in a tape, and sweeps it in reverse.
+//
+// Layouts: checkpoints, tape and adjoint scratch are field-major [27][Q]
+// (coalesced per field); actions and their gradients are [call][Q][4].
+#pragma once
+#include "qs_adjoint.h"
+
+namespace qs {
+
+// Workgroup -> quads mapping shared by the kernels (see step_kernel).
+template <int BS, int N>
+__device__ __forceinline__ void block_map(const Ptrs& p, int tid, int& qb, int& cnt, int& ls,
+                                          int& n) {
+  if constexpr (N > 0) {
+    qb = blockIdx.x * BS;
+    cnt = min(BS, p.Q - qb);
+    ls = (tid / N) * N;
+    n = N;
+  } else {
+    const int2 bq = p.blk[blockIdx.x];
+    qb = bq.x;
+    cnt = bq.y;
+    const uint32_t swd = tid < cnt ? p.sw[qb + tid] : 0u;
+    ls = (int)(swd >> 8);
+    n = (int)(swd & 0xffu);
+  }
+}
+
+__device__ __forceinline__ void load_state(const float* __restrict__ S, long long ld, int q,
+                                           Quad& s) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s.x[k] = S[(S_X + k) * ld + q];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s.v[k] = S[(S_V + k) * ld + q];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s.R[k] = S[(S_R + k) * ld + q];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s.w[k] = S[(S_W + k) * ld + q];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.u[k] = S[(S_U + k) * ld + q];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.e[k] = S[(S_E + k) * ld + q];
+  s.fl = S[S_F * ld + q];
+}
+
+__device__ __forceinline__ void store_state(float* __restrict__ S, long long ld, int q,
+                                            const Quad& s) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S[(S_X + k) * ld + q] = s.x[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S[(S_V + k) * ld + q] = s.v[k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) S[(S_R + k) * ld + q] = s.R[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S[(S_W + k) * ld + q] = s.w[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) S[(S_U + k) * ld + q] = s.u[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) S[(S_E + k) * ld + q] = s.e[k];
+  S[S_F * ld + q] = s.fl;
+}
+
+__device__ __forceinline__ void load_params(const Ptrs& p, const Consts& c, int q, QuadPar& pp,
+                                            ParAdj& pa) {
+  const int Qp = p.Qp;
+  pp.m = p.par[P_M * Qp + q];
+  pp.jx = p.par[P_JX * Qp + q];
+  pp.jy = p.par[P_JY * Qp + q];
+  pp.jz = p.par[P_JZ * Qp + q];
+  pp.f_max = p.par[P_FMAX * Qp + q];
+  pp.a_lag = p.par[P_ALAG * Qp + q];
+  pp.inv_m = 1.0f / pp.m;
+  pp.ijx = 1.0f / pp.jx;
+  pp.ijy = 1.0f / pp.jy;
+  pp.ijz = 1.0f / pp.jz;
+  pp.a_ns = c.ns_scale * pp.f_max;
+  pa.m = pp.m;
+  pa.jx = pp.jx;
+  pa.jy = pp.jy;
+  pa.jz = pp.jz;
+  pa.t2w = p.par[P_T2W * Qp + q];
+  pa.tau = p.par[P_TAU * Qp + q];
+}
+
+__device__ __forceinline__ void load_uhat(const Consts& c, const Ptrs& p, const float* act, int q,
+                                          float uhat[4], float4& a4) {
+  a4 = reinterpret_cast<const float4*>(act)[q];
+  const bool unit = (c.flags & F_ACT_UNIT) != 0;
+  uhat[0] = rotor_cmd(a4.x, unit);
+  uhat[1] = rotor_cmd(a4.y, unit);
+  uhat[2] = rotor_cmd(a4.z, unit);
+  uhat[3] = rotor_cmd(a4.w, unit);
+  if (!(isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z) && isfinite(a4.w)))
+    __hip_atomic_fetch_or(p.err, ERRBIT_ACTION, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// d uhat / d a for one action component (0 where the clip is active or the
+// command is zero).
+__device__ __forceinline__ float duhat_da(const Consts& c, float a, float uhat) {
+  if (!(uhat > 0.f)) return 0.f;
+  if (c.flags & F_ACT_UNIT) return (a > 0.f && a < 1.f) ? 0.5f / uhat : 0.f;
+  return (a > -1.f && a < 1.f) ? 0.25f / uhat : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Forward rollout: ncalls calls of nsub substeps from the handle's state,
+// action of call k at act + k Q 4.  ckpt (optional): the state at the start
+// of every ckpt_every-th call, checkpoint k at ckpt + k 27 Q.  pen
+// (optional, PEN): each quad's share of the smoothed collision penalty,
+// sum over substeps and env-mates of softplus(beta (d_col - d))/(2 beta).
+// ---------------------------------------------------------------------------
+template <int BS, int N, bool PEN>
+__global__ __launch_bounds__(BS) void rollout_kernel(Consts c, Ptrs p,
+                                                     const float* __restrict__ act, int ncalls,
+                                                     int nsub, unsigned long long t0,
+                                                     float* __restrict__ ckpt, int ckpt_every,
+                                                     float* __restrict__ pen, float beta) {
+  __shared__ float sxv[2][9][BS];
+  const int tid = threadIdx.x;
+  int qb, cnt, ls, n;
+  block_map<BS, N>(p, tid, qb, cnt, ls, n);
+  const bool live = tid < cnt;
+  const int q = qb + (live ? tid : 0);
+  const int me = tid - ls;
+  const long long Q = p.Q;
+
+  Quad s;
+  QuadPar pp;
+  ParAdj pa;
+  if (live) {
+    load_state(p.st, p.Qp, q, s);
+    load_params(p, c, q, pp, pa);
+  }
+  const bool collide = (c.flags & F_COLLIDE) != 0;
+  const bool pairs = N != 1 && (collide || PEN);
+  float pacc = 0.f;
+  int sidx = 0;
+  for (int call = 0; call < ncalls; ++call) {
+    if (ckpt && call % ckpt_every == 0 && live)
+      store_state(ckpt + (long long)(call / ckpt_every) * NSTATE * Q, Q, q, s);
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a4;
+    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
+    for (int sub = 0; sub < nsub; ++sub, ++sidx) {
+      const unsigned long long t = t0 + (unsigned long long)sidx;
+      if (live) quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+      if (pairs) {
+        float(*tile)[BS] = sxv[sidx & 1];
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            tile[k][tid] = s.xo[k];
+            tile[3 + k][tid] = s.inc[k];
+            tile[6 + k][tid] = s.v[k];
+          }
+        }
+        __syncthreads();
+        if (live) {
+          float dv[3] = {0.f, 0.f, 0.f};
+          bool hit = false;
+          auto pair = [&](int jj) {
+            const int j = ls + jj;
+            float dx, dy, dz, d2;
+            const bool con = pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2);
+            if constexpr (PEN) {
+              if (jj != me) pacc += 0.5f * softplusf(beta * (c.dcol - sqrtf(d2))) / beta;
+            }
+            if (collide && con) {
+              float nn[3], sp;
+              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+              if (!(c.flags & F_APPROACH) || sp > 0.f) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dv[k] = fmaf(sp, nn[k], dv[k]);
+                hit = true;
+              }
+            }
+          };
+          if constexpr (N > 0) {
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj) pair(jj);
+          } else {
+            for (int jj = 0; jj < n; ++jj) pair(jj);
+          }
+          if (hit) {
+            float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
+            if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
+              normal4(c, (uint32_t)q, t, STREAM_PAIR, 0, zv);
+              normal4(c, (uint32_t)q, t, STREAM_PAIR, 1, zw);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              s.v[k] = c.col_decay * (s.v[k] + dv[k] + c.col_nv * zv[k]);
+              s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (live) {
+    store_state(p.st, p.Qp, q, s);
+    float chk = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) chk += s.x[k] + s.v[k] + s.w[k];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) chk += s.R[k];
+    if (!isfinite(chk))
+      __hip_atomic_fetch_or(p.err, ERRBIT_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (PEN) pen[q] += pacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of one segment of ncalls calls x nsub substeps.
+//  ckpt: state at the segment start ([27][Q]); act/gact: the segment's
+//  first call; tape: scratch [ncalls nsub][27][Q]; lam: [27][Q] adjoint of
+//  the state, dL/d(segment end) in, dL/d(segment start) out; gpen: dL/d pen
+//  (PEN); gpar: [6][Q] dL/d(m, ixx, iyy, izz, t2w, tau), accumulated.
+// ---------------------------------------------------------------------------
+template <int BS, int N, bool PEN>
+__global__ __launch_bounds__(BS) void adjoint_kernel(Consts c, Ptrs p,
+                                                     const float* __restrict__ ckpt,
+                                                     const float* __restrict__ act, int ncalls,
+                                                     int nsub, unsigned long long t0,
+                                                     float* __restrict__ tape,
+                                                     float* __restrict__ lam,
+                                                     const float* __restrict__ gpen, float beta,
+                                                     float* __restrict__ gact,
+                                                     float* __restrict__ gpar) {
+  // rows 0-8 as in the forward tile; 9-11: adjoint of the collision
+  // velocity change; 12: penalty weight dL/d pen
+  __shared__ float tl[13][BS];
+  const int tid = threadIdx.x;
+  int qb, cnt, ls, n;
+  block_map<BS, N>(p, tid, qb, cnt, ls, n);
+  const bool live = tid < cnt;
+  const int q = qb + (live ? tid : 0);
+  const int me = tid - ls;
+  const long long Q = p.Q;
+  const bool collide = (c.flags & F_COLLIDE) != 0;
+  const bool pairs = N != 1 && (collide || PEN);
+  float(*tile)[BS] = tl;
+
+  Quad s;
+  QuadPar pp;
+  ParAdj pa;
+  if (live) {
+    load_state(ckpt, Q, q, s);
+    load_params(p, c, q, pp, pa);
+  }
+  if constexpr (PEN) {
+    tl[12][tid] = live ? gpen[q] : 0.f;
+  }
+  // ---- recompute the segment, taping the state at each substep's start
+  int sidx = 0;
+  for (int call = 0; call < ncalls; ++call) {
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a4;
+    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
+    for (int sub = 0; sub < nsub; ++sub, ++sidx) {
+      const unsigned long long t = t0 + (unsigned long long)sidx;
+      if (live) {
+        store_state(tape + (long long)sidx * NSTATE * Q, Q, q, s);
+        quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+      }
+      if (collide && N != 1) {
+        __syncthreads();  // previous readers of the tile are done
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            tile[k][tid] = s.xo[k];
+            tile[3 + k][tid] = s.inc[k];
+            tile[6 + k][tid] = s.v[k];
+          }
+        }
+        __syncthreads();
+        if (live) {
+          float dv[3] = {0.f, 0.f, 0.f};
+          bool hit = false;
+          auto pair = [&](int jj) {
+            const int j = ls + jj;
+            float dx, dy, dz, d2;
+            if (pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2)) {
+              float nn[3], sp;
+              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+              if (!(c.flags & F_APPROACH) || sp > 0.f) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dv[k] = fmaf(sp, nn[k], dv[k]);
+                hit = true;
+              }
+            }
+          };
+          if constexpr (N > 0) {
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj) pair(jj);
+          } else {
+            for (int jj = 0; jj < n; ++jj) pair(jj);
+          }
+          if (hit) {
+            float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
+            if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
+              normal4(c, (uint32_t)q, t, STREAM_PAIR, 0, zv);
+              normal4(c, (uint32_t)q, t, STREAM_PAIR, 1, zw);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              s.v[k] = c.col_decay * (s.v[k] + dv[k] + c.col_nv * zv[k]);
+              s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // ---- reverse sweep
+  Adj l;
+  float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      l.x[k] = lam[(S_X + k) * Q + q];
+      l.v[k] = lam[(S_V + k) * Q + q];
+      l.w[k] = lam[(S_W + k) * Q + q];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) l.R[k] = lam[(S_R + k) * Q + q];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      l.u[k] = lam[(S_U + k) * Q + q];
+      l.e[k] = lam[(S_E + k) * Q + q];
+    }
+  }
+  for (int call = ncalls - 1; call >= 0; --call) {
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f}, gu[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
+    for (int sub = nsub - 1; sub >= 0; --sub) {
+      const int k_s = call * nsub + sub;
+      const unsigned long long t = t0 + (unsigned long long)k_s;
+      Rec r;
+      if (live) {
+        load_state(tape + (long long)k_s * NSTATE * Q, Q, q, s);
+        quad_substep<true>(c, pp, s, uhat, (uint32_t)q, t, &r);
+      }
+      if (pairs) {
+        __syncthreads();  // previous readers of the tile are done
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            tile[k][tid] = s.xo[k];
+            tile[3 + k][tid] = s.inc[k];
+            tile[6 + k][tid] = s.v[k];
+          }
+        }
+        __syncthreads();
+        // which quads responded, and the adjoint of their velocity change
+        bool hit = false;
+        if (live && collide) {
+          auto mark = [&](int jj) {
+            const int j = ls + jj;
+            float dx, dy, dz, d2;
+            if (pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2)) {
+              float nn[3], sp;
+              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+              if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
+            }
+          };
+          if constexpr (N > 0) {
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj) mark(jj);
+          } else {
+            for (int jj = 0; jj < n; ++jj) mark(jj);
+          }
+        }
+        float ldv[3] = {0.f, 0.f, 0.f};
+        if (live && hit) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            ldv[k] = c.col_decay * l.v[k];
+            l.v[k] = ldv[k];
+          }
+        }
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) tile[9 + k][tid] = ldv[k];
+        }
+        __syncthreads();
+        if (live) {
+          auto pvjp = [&](int jj) {
+            const int j = ls + jj;
+            float dx, dy, dz, d2;
+            const bool con = pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2);
+            if constexpr (PEN) {
+              if (jj != me && d2 > 0.f) {
+                const float dd = sqrtf(d2);
+                const float coef = -0.5f * (tile[12][tid] + tile[12][j]) *
+                                   sigmoidf(beta * (c.dcol - dd)) / dd;
+                l.x[0] = fmaf(coef, dx, l.x[0]);
+                l.x[1] = fmaf(coef, dy, l.x[1]);
+                l.x[2] = fmaf(coef, dz, l.x[2]);
+              }
+            }
+            if (collide && con) {
+              float nn[3], sp;
+              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+              if (!(c.flags & F_APPROACH) || sp > 0.f) {
+                const float mu[3] = {ldv[0] - tile[9][j], ldv[1] - tile[10][j],
+                                     ldv[2] - tile[11][j]};
+                const float mn = dot3f(mu, nn);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) l.v[k] = fmaf(-mn, nn[k], l.v[k]);
+                if (!(d2 < 1e-12f)) {
+                  const float wv[3] = {tile[6][j] - s.v[0], tile[7][j] - s.v[1],
+                                       tile[8][j] - s.v[2]};
+                  float gn[3];
+#pragma unroll
+                  for (int k = 0; k < 3; ++k) gn[k] = fmaf(sp, mu[k], mn * wv[k]);
+                  const float gnn = dot3f(gn, nn);
+                  const float id = rsqrtf(d2);
+#pragma unroll
+                  for (int k = 0; k < 3; ++k) l.x[k] = fmaf(gn[k] - gnn * nn[k], id, l.x[k]);
+                }
+              }
+            }
+          };
+          if constexpr (N > 0) {
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj) pvjp(jj);
+          } else {
+            for (int jj = 0; jj < n; ++jj) pvjp(jj);
+          }
+        }
+      }
+      if (live) quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
+    }
+    if (live) {
+      float4 g;
+      g.x = gu[0] * duhat_da(c, a4.x, uhat[0]);
+      g.y = gu[1] * duhat_da(c, a4.y, uhat[1]);
+      g.z = gu[2] * duhat_da(c, a4.z, uhat[2]);
+      g.w = gu[3] * duhat_da(c, a4.w, uhat[3]);
+      reinterpret_cast<float4*>(gact + (long long)call * Q * 4)[q] = g;
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lam[(S_X + k) * Q + q] = l.x[k];
+      lam[(S_V + k) * Q + q] = l.v[k];
+      lam[(S_W + k) * Q + q] = l.w[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) lam[(S_R + k) * Q + q] = l.R[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lam[(S_U + k) * Q + q] = l.u[k];
+      lam[(S_E + k) * Q + q] = l.e[k];
+    }
+    lam[S_F * Q + q] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gpar[k * Q + q] += gp[k];
+  }
+}
+
+// [rows][Q] field-major <-> [Q][rows] row-major conversions (optionally
+// adding into the destination).
+__global__ void fm_to_rm_kernel(const float* __restrict__ src, float* __restrict__ dst, int Q,
+                                int rows, int accumulate) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)Q * rows) return;
+  const int q = (int)(i / rows), f = (int)(i - (long long)q * rows);
+  const float v = src[(long long)f * Q + q];
+  dst[i] = accumulate ? dst[i] + v : v;
+}
+
+__global__ void rm_to_fm_kernel(const float* __restrict__ src, float* __restrict__ dst, int Q,
+                                int rows) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)Q * rows) return;
+  const int q = (int)(i / rows), f = (int)(i - (long long)q * rows);
+  dst[(long long)f * Q + q] = src[i];
+}
+
+__global__ void fill_kernel(float* __restrict__ dst, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+
+}  // namespace qs

@@ -22,9 +22,10 @@ ERRORS = {-1: "QS_ERR_NULL", -2: "QS_ERR_INVALID", -3: "QS_ERR_ENV_SIZE", -4: "Q
           -5: "QS_ERR_NONFINITE", -6: "QS_ERR_NOMEM", -7: "QS_ERR_ALIGN", -8: "QS_ERR_UNSUPPORTED"}
 
 # every entry point of include/quadswarm.h
-EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_step", "qs_observe", "qs_step_observe",
-           "qs_get_state", "qs_set_state", "qs_record_contacts", "qs_debug_contacts", "qs_sync",
-           "qs_error_string")
+EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_substep_index", "qs_step", "qs_observe",
+           "qs_step_observe", "qs_get_state", "qs_set_state", "qs_record_contacts",
+           "qs_debug_contacts", "qs_sync", "qs_rollout", "qs_rollout_backward",
+           "qs_step_backward", "qs_error_string")
 
 
 class QuadSwarmError(RuntimeError):
@@ -71,6 +72,11 @@ def lib() -> C.CDLL:
         L.qs_record_contacts.argtypes = [vp, i32]
         L.qs_debug_contacts.argtypes = [vp, vp, vp]
         L.qs_sync.argtypes = [vp, vp]
+        L.qs_substep_index.argtypes = [vp, C.POINTER(u64)]
+        f32 = C.c_float
+        L.qs_rollout.argtypes = [vp, vp, i32, i32, i32, vp, vp, f32, vp]
+        L.qs_rollout_backward.argtypes = [vp, vp, i32, i32, i32, vp, u64, vp, vp, f32, vp, vp, vp]
+        L.qs_step_backward.argtypes = [vp, vp, vp, i32, u64, vp, vp, vp, vp, vp]
         L.qs_error_string.argtypes = [C.c_int]
         L.qs_error_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -195,6 +201,56 @@ class QuadSwarm:
         _check(lib().qs_debug_contacts(self._h, _ptr(o), _stream()), "qs_debug_contacts")
         return o
 
+    @property
+    def substep(self) -> int:
+        t = C.c_uint64()
+        _check(lib().qs_substep_index(self._h, C.byref(t)), "qs_substep_index")
+        return int(t.value)
+
+    def rollout(self, actions, n_substeps: int, ckpt_every: int = 0, ckpt=None, penalty=None,
+                beta: float = 0.0) -> None:
+        """qs_rollout over actions [n_calls][Q][4]."""
+        a = actions
+        n_calls = a.shape[0]
+        self._dev(a, (n_calls, self.n_quads, 4))
+        if ckpt is not None:
+            n_ck = (n_calls + ckpt_every - 1) // ckpt_every
+            self._dev(ckpt, (n_ck, 27, self.n_quads))
+        if penalty is not None:
+            self._dev(penalty, (self.n_quads,))
+        _check(lib().qs_rollout(self._h, _ptr(a), n_calls, int(n_substeps), int(ckpt_every),
+                                None if ckpt is None else _ptr(ckpt),
+                                None if penalty is None else _ptr(penalty), float(beta),
+                                _stream()), "qs_rollout")
+
+    def rollout_backward(self, actions, n_substeps: int, ckpt_every: int, ckpt,
+                         substep_index0: int, gstate, gpenalty, beta: float, gactions,
+                         gparams) -> None:
+        """qs_rollout_backward (gstate is overwritten with dL/d initial state)."""
+        n_calls = actions.shape[0]
+        self._dev(actions, (n_calls, self.n_quads, 4))
+        self._dev(gactions, (n_calls, self.n_quads, 4))
+        self._dev(gstate, (self.n_quads, 27))
+        self._dev(gparams, (self.n_quads, 6))
+        if gpenalty is not None:
+            self._dev(gpenalty, (self.n_quads,))
+        _check(lib().qs_rollout_backward(
+            self._h, _ptr(actions), n_calls, int(n_substeps), int(ckpt_every), _ptr(ckpt),
+            C.c_uint64(int(substep_index0)), _ptr(gstate),
+            None if gpenalty is None else _ptr(gpenalty), float(beta), _ptr(gactions),
+            _ptr(gparams), _stream()), "qs_rollout_backward")
+
+    def step_backward(self, state_in, actions, n_substeps: int, substep_index: int,
+                      gstate_out, gstate_in, gactions, gparams) -> None:
+        Q = self.n_quads
+        for tns, shp in ((state_in, (Q, 27)), (actions, (Q, 4)), (gstate_out, (Q, 27)),
+                         (gstate_in, (Q, 27)), (gactions, (Q, 4)), (gparams, (Q, 6))):
+            self._dev(tns, shp)
+        _check(lib().qs_step_backward(self._h, _ptr(state_in), _ptr(actions), int(n_substeps),
+                                      C.c_uint64(int(substep_index)), _ptr(gstate_out),
+                                      _ptr(gstate_in), _ptr(gactions), _ptr(gparams),
+                                      _stream()), "qs_step_backward")
+
     def sync(self) -> None:
         _check(lib().qs_sync(self._h, _stream()), "qs_sync")
 
@@ -214,3 +270,63 @@ class QuadSwarm:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _make_rollout_fn():
+    import torch
+
+    class RolloutFn(torch.autograd.Function):
+        """Differentiable rollout through the HIP forward and adjoint kernels.
+
+        forward(state0 [Q][27], actions [T][Q][4], params [Q][6], sim,
+        n_substeps, ckpt_every, beta) -> (final state [Q][27], penalty [Q]).
+        ``params`` must hold the parameters the handle was created with; it is
+        an input only so that autograd can return dL/d params.  The forward
+        keeps ceil(T / ckpt_every) checkpoints; the backward recomputes each
+        segment from its checkpoint.
+        """
+
+        @staticmethod
+        def forward(ctx, state0, actions, params, sim, n_substeps, ckpt_every, beta):
+            T = actions.shape[0]
+            t0 = sim.substep
+            sim.set_state(state0.detach().contiguous(), t0)
+            n_ck = (T + ckpt_every - 1) // ckpt_every
+            ckpt = torch.empty((n_ck, 27, sim.n_quads), device=state0.device)
+            pen = torch.zeros(sim.n_quads, device=state0.device)
+            acts = actions.detach().contiguous()
+            sim.rollout(acts, n_substeps, ckpt_every, ckpt, pen if beta > 0 else None, beta)
+            sT, _ = sim.get_state()
+            ctx.save_for_backward(acts, ckpt)
+            ctx.sim, ctx.nsub, ctx.ce, ctx.beta, ctx.t0 = sim, n_substeps, ckpt_every, beta, t0
+            return sT, pen
+
+        @staticmethod
+        def backward(ctx, g_state, g_pen):
+            acts, ckpt = ctx.saved_tensors
+            sim = ctx.sim
+            Q = sim.n_quads
+            gstate = (g_state.contiguous().clone() if g_state is not None
+                      else torch.zeros((Q, 27), device=acts.device))
+            gpen = None
+            if g_pen is not None and ctx.beta > 0:
+                gpen = g_pen.contiguous()
+            gact = torch.empty_like(acts)
+            gpar = torch.zeros((Q, 6), device=acts.device)
+            sim.rollout_backward(acts, ctx.nsub, ctx.ce, ckpt, ctx.t0, gstate, gpen, ctx.beta,
+                                 gact, gpar)
+            return gstate, gact, gpar, None, None, None, None
+
+    return RolloutFn
+
+
+_ROLLOUT_FN = None
+
+
+def rollout(sim: QuadSwarm, state0, actions, params, n_substeps: int = 1, ckpt_every: int = 20,
+            beta: float = 100.0):
+    """Differentiable rollout: returns (final state, per-quad penalty)."""
+    global _ROLLOUT_FN
+    if _ROLLOUT_FN is None:
+        _ROLLOUT_FN = _make_rollout_fn()
+    return _ROLLOUT_FN.apply(state0, actions, params, sim, n_substeps, ckpt_every, beta)

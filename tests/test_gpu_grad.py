@@ -1,0 +1,195 @@
+"""GPU differentiation parity: the HIP rollout and adjoint kernels (through
+the C ABI) against the FP64 oracle's reverse-mode derivative, which the CPU
+tests pin to central differences.
+
+Tolerance: the GPU integrates and differentiates in float32, so its
+trajectory drifts from the float64 one by the chaos of the tumbling swarm.
+The comparison is norm-wise, ||g_gpu - g_orc|| / ||g_orc||, against a bound
+derived from the oracle itself: the change of the oracle's own gradient
+when its initial state is rounded to float32 and perturbed by 2^-23
+relative noise (the size of one float32 rounding), times 10, floored at
+1e-4.  Per-entry checks would flag entries that are near zero.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2306_09537_amd import workloads as W  # noqa: E402
+from paper_2306_09537_amd.quadswarm import QuadSwarm, rollout  # noqa: E402
+from tests.test_oracle_grad import dense_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+BETA = 100.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def problem(seed, T, n_envs=4, **kw):
+    w, s0 = dense_problem(seed, n_envs=n_envs, **kw)
+    w = w.with_(state0=s0.astype(np.float32))
+    rng = np.random.default_rng(seed + 100)
+    acts = rng.uniform(0.05, 0.95, size=(T, w.n_quads, 4)).astype(np.float32)
+    Wt = rng.normal(size=(w.n_quads, 27)).astype(np.float32)
+    Wt[:, 26] = 0
+    gpen = rng.uniform(0.5, 2.0, size=w.n_quads).astype(np.float32)
+    return w, acts, Wt, gpen
+
+
+def oracle_grads(w, acts, nsub, Wt, gpen, s0=None, env_range=None):
+    orc = O.Oracle.from_workload(w, *(env_range or (0, w.n_envs)))
+    q0 = int(w.env_offsets[env_range[0]]) if env_range else 0
+    q1 = int(w.env_offsets[env_range[1]]) if env_range else w.n_quads
+    s = (w.state0 if s0 is None else s0)[q0:q1].astype(np.float64)
+    return orc.rollout_vjp(s, acts[:, q0:q1].astype(np.float64), nsub, 0,
+                           Wt[q0:q1].astype(np.float64), gpen[q0:q1].astype(np.float64), BETA)
+
+
+def bound(w, acts, nsub, Wt, gpen, g_ref, seed=0, env_range=None):
+    """10x the oracle's own gradient change under float32-sized noise."""
+    rng = np.random.default_rng(seed)
+    s0 = w.state0.astype(np.float64)
+    s0p = s0 * (1 + rng.uniform(-1, 1, size=s0.shape) * 2.0 ** -23)
+    g2 = oracle_grads(w, acts, nsub, Wt, gpen, s0=s0p, env_range=env_range)
+    return [max(1e-4, 10 * relerr(a, b)) for a, b in zip(g2, g_ref)]
+
+
+def gpu_grads(w, acts, nsub, Wt, gpen, ce):
+    sim = QuadSwarm.from_workload(w)
+    T = acts.shape[0]
+    a = dev(acts)
+    n_ck = (T + ce - 1) // ce
+    ckpt = torch.empty((n_ck, 27, w.n_quads), device="cuda")
+    pen = torch.zeros(w.n_quads, device="cuda")
+    sim.rollout(a, nsub, ce, ckpt, pen, BETA)
+    sT, tT = sim.get_state()
+    gs = dev(Wt).clone()
+    gact = torch.empty_like(a)
+    gpar = torch.zeros((w.n_quads, 6), device="cuda")
+    sim.rollout_backward(a, nsub, ce, ckpt, 0, gs, dev(gpen), BETA, gact, gpar)
+    sim.sync()
+    out = (gs.cpu().numpy(), gact.cpu().numpy(), gpar.cpu().numpy(), sT.cpu().numpy(),
+           pen.cpu().numpy(), ckpt.cpu().numpy(), tT)
+    sim.close()
+    return out
+
+
+def test_rollout_forward_matches_steps_and_oracle_penalty():
+    w, acts, Wt, gpen = problem(0, 24)
+    T, nsub, ce = 24, 2, 5
+    sim = QuadSwarm.from_workload(w)
+    ckpt = torch.empty((5, 27, w.n_quads), device="cuda")
+    pen = torch.zeros(w.n_quads, device="cuda")
+    sim.rollout(dev(acts), nsub, ce, ckpt, pen, BETA)
+    sT, t = sim.get_state()
+    ref = QuadSwarm.from_workload(w)
+    cks = []
+    for c in range(T):
+        if c % ce == 0:
+            cks.append(ref.get_state()[0].clone())
+        ref.step(dev(acts[c]), nsub)
+    sR, _ = ref.get_state()
+    torch.cuda.synchronize()
+    assert t == T * nsub
+    assert torch.equal(sT, sR)
+    for k, s in enumerate(cks):
+        assert torch.equal(ckpt[k].T.contiguous(), s)
+    _, pen_o = O.Oracle.from_workload(w).rollout(w.state0.astype(np.float64),
+                                                 acts.astype(np.float64), nsub, 0, beta=BETA)
+    assert pen_o.max() > 1e-3
+    np.testing.assert_allclose(pen.cpu().numpy(), pen_o, rtol=2e-4, atol=1e-7)
+
+
+@pytest.mark.parametrize("seed,T,nsub,ce", [(0, 30, 2, 7), (1, 60, 1, 20), (3, 20, 5, 3)])
+def test_adjoint_matches_oracle(seed, T, nsub, ce):
+    w, acts, Wt, gpen = problem(seed, T)
+    g_ref = oracle_grads(w, acts, nsub, Wt, gpen)
+    tol = bound(w, acts, nsub, Wt, gpen, g_ref, seed)
+    gs, gact, gpar, *_ = gpu_grads(w, acts, nsub, Wt, gpen, ce)
+    errs = [relerr(gs, g_ref[0]), relerr(gact, g_ref[1]), relerr(gpar, g_ref[2])]
+    print("adjoint rel err (state0, actions, params):", errs, "bounds:", tol)
+    for e, b in zip(errs, tol):
+        assert e <= b
+
+
+def test_step_backward_matches_oracle():
+    w, acts, Wt, gpen = problem(5, 1)
+    nsub = 3
+    sim = QuadSwarm.from_workload(w)
+    s_in, _ = sim.get_state()
+    gin = torch.empty((w.n_quads, 27), device="cuda")
+    gact = torch.empty((w.n_quads, 4), device="cuda")
+    gpar = torch.zeros((w.n_quads, 6), device="cuda")
+    sim.step_backward(s_in, dev(acts[0]), nsub, 0, dev(Wt), gin, gact, gpar)
+    sim.sync()
+    orc = O.Oracle.from_workload(w)
+    g0, ga, gp = orc.rollout_vjp(w.state0.astype(np.float64), acts.astype(np.float64), nsub, 0,
+                                 Wt.astype(np.float64), None, None)
+    assert relerr(gin.cpu().numpy(), g0) < 1e-4
+    assert relerr(gact.cpu().numpy(), ga[0]) < 1e-4
+    assert relerr(gpar.cpu().numpy(), gp) < 1e-4
+
+
+def test_autograd_function_matches_direct_calls():
+    w, acts, Wt, gpen = problem(2, 12)
+    sim = QuadSwarm.from_workload(w)
+    s0 = dev(w.state0).requires_grad_(True)
+    a = dev(acts).requires_grad_(True)
+    p = dev(w.params).requires_grad_(True)
+    sT, pen = rollout(sim, s0, a, p, n_substeps=2, ckpt_every=4, beta=BETA)
+    loss = (sT * dev(Wt)).sum() + (pen * dev(gpen)).sum()
+    loss.backward()
+    gs, gact, gpar, *_ = gpu_grads(w, acts, 2, Wt, gpen, 4)
+    np.testing.assert_allclose(s0.grad.cpu().numpy(), gs, rtol=0, atol=0)
+    np.testing.assert_allclose(a.grad.cpu().numpy(), gact, rtol=0, atol=0)
+    np.testing.assert_allclose(p.grad.cpu().numpy(), gpar, rtol=0, atol=0)
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    """Recomputation from checkpoints reproduces the forward bit for bit, so
+    state and action gradients are identical for any checkpoint interval;
+    parameter gradients are summed per segment, so only their rounding
+    (summation grouping) may differ."""
+    w, acts, Wt, gpen = problem(4, 40)
+    g1 = gpu_grads(w, acts, 1, Wt, gpen, 40)
+    g2 = gpu_grads(w, acts, 1, Wt, gpen, 7)
+    np.testing.assert_array_equal(g1[0], g2[0])
+    np.testing.assert_array_equal(g1[1], g2[1])
+    np.testing.assert_allclose(g1[2], g2[2], rtol=1e-5, atol=1e-6 * np.abs(g1[2]).max())
+
+
+def test_diff_workload_full_size_sampled():
+    """1024 envs x 8 quads, 200-substep horizon, checkpoint every 20 calls:
+    envs 100..103 checked against the oracle's derivative."""
+    w = W.diff(seed=0)
+    T, nsub, ce = 200, 1, 20
+    rng = np.random.default_rng(9)
+    acts = rng.uniform(0.05, 0.95, size=(T, w.n_quads, 4)).astype(np.float32)
+    Wt = rng.normal(size=(w.n_quads, 27)).astype(np.float32)
+    Wt[:, 26] = 0
+    gpen = rng.uniform(0.5, 2.0, size=w.n_quads).astype(np.float32)
+    gs, gact, gpar, *_ = gpu_grads(w, acts, nsub, Wt, gpen, ce)
+    assert np.isfinite(gs).all() and np.isfinite(gact).all() and np.isfinite(gpar).all()
+    e0, e1 = 100, 104
+    q0, q1 = int(w.env_offsets[e0]), int(w.env_offsets[e1])
+    g_ref = oracle_grads(w, acts, nsub, Wt, gpen, env_range=(e0, e1))
+    tol = bound(w, acts, nsub, Wt, gpen, g_ref, 9, env_range=(e0, e1))
+    errs = [relerr(gs[q0:q1], g_ref[0]), relerr(gact[:, q0:q1], g_ref[1]),
+            relerr(gpar[q0:q1], g_ref[2])]
+    print("full-size sampled rel err:", errs, "bounds:", tol)
+    for e, b in zip(errs, tol):
+        assert e <= b
