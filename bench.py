@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fwdbwd", default="diff", help="workload of the fwd+bwd leg ('' to skip)")
+    ap.add_argument("--fwdbwd-horizon", type=int, default=200)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of "
                          "known traffic for scaling HBM counters) and exit")
@@ -129,6 +131,60 @@ def time_calls(sim, w, acts, goals, obs, nsub, steps, warmup, torch, episode=100
         done += n
     sim.sync()
     return total_ms / steps, wall * 1e3 / steps
+
+
+def time_fwd_bwd(w, torch, horizon: int, nsub: int, ckpt_every: int, reps: int, beta=100.0):
+    """Differentiable rollout of ``horizon`` calls (checkpoints every
+    ``ckpt_every`` calls, smoothed collision penalty) and its reverse pass,
+    each timed with HIP events on the launch stream; the state is reset to
+    the initial state (untimed) before each repetition."""
+    from paper_2306_09537_amd.quadswarm import QuadSwarm
+    sim = QuadSwarm.from_workload(w)
+    Q = w.n_quads
+    acts = torch.from_numpy(w.action_sequence(horizon)).cuda()
+    s0 = torch.from_numpy(w.state0).cuda()
+    n_ck = (horizon + ckpt_every - 1) // ckpt_every
+    ckpt = torch.empty((n_ck, 27, Q), device="cuda")
+    pen = torch.zeros(Q, device="cuda")
+    gs0 = torch.randn((Q, 27), device="cuda")
+    gs0[:, 26] = 0
+    gpen = torch.ones(Q, device="cuda")
+    gstate = torch.empty_like(gs0)
+    gact = torch.empty_like(acts)
+    gpar = torch.zeros((Q, 6), device="cuda")
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        t0 = r * horizon * nsub
+        sim.set_state(s0, t0)
+        gstate.copy_(gs0)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        sim.rollout(acts, nsub, ckpt_every, ckpt, pen, beta)
+        e[1].record()
+        sim.rollout_backward(acts, nsub, ckpt_every, ckpt, t0, gstate, gpen, beta, gact, gpar)
+        e[2].record()
+        torch.cuda.synchronize()
+        if r:  # the first repetition warms up (scratch allocation)
+            fwd.append(e[0].elapsed_time(e[1]))
+            bwd.append(e[1].elapsed_time(e[2]))
+    sim.sync()
+    sim.close()
+    f, b = float(np.median(fwd)), float(np.median(bwd))
+    steps = Q * horizon * nsub
+    # algorithmic bytes of the reverse pass per quad-substep: tape write and
+    # read (2 x 108), actions read twice (2 x 16), action gradient (16);
+    # per segment: checkpoint (108), adjoint in/out (216), parameters and
+    # their gradient (32 + 48)
+    seg = ckpt_every * nsub
+    bwd_bytes = Q * horizon * nsub * (216 + 32 + 16) + Q * (horizon // ckpt_every) * (108 + 216 + 80)
+    return dict(workload=w.name, quads=Q, horizon_substeps=horizon * nsub, ckpt_every=ckpt_every,
+                value=steps / ((f + b) * 1e-3), unit="quad-steps/s (fwd+bwd)",
+                fwd_ms=f, bwd_ms=b, fwd_value=steps / (f * 1e-3),
+                bwd_roofline={"bound": "hbm", "achieved": bwd_bytes / (b * 1e-3) / 1e9,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": bwd_bytes / (b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "bytes": bwd_bytes, "segment_substeps": seg})
 
 
 def cpu_baseline(w, target_s: float):
@@ -234,6 +290,9 @@ def main():
         "host_ms_per_step": wall_ms,
         "fused": extra,
     }
+    if args.fwdbwd:
+        wd = W.WORKLOADS[args.fwdbwd](seed=0)
+        line["fwd_bwd"] = time_fwd_bwd(wd, torch, args.fwdbwd_horizon, 1, 20, 3)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     sim.close()
