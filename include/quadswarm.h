@@ -234,6 +234,37 @@ int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actio
                      int32_t n_substeps, uint64_t substep_index, const float* d_gstate_out,
                      float* d_gstate_in, float* d_gactions, float* d_gparams, void* stream);
 
+/* ---- batching and scheduling ------------------------------------------------
+ * Swarms of uneven sizes run in one persistent launch: every swarm gets a
+ * slot of the next power of two >= its size, slots of one size are grouped
+ * into work items, and each workgroup strides over the items running code
+ * specialised for the item's slot size (environment QS_BUCKETED=0 at
+ * qs_create falls back to one workgroup per greedy block of swarms).
+ */
+
+/*
+ * Graph mode (enable != 0): every step launch reads the base substep index
+ * from device memory and the last workgroup of the launch advances it, so a
+ * captured hipGraph of qs_step / qs_step_observe calls draws fresh noise on
+ * every replay.  While on, qs_substep_index synchronises the device and
+ * reads the device counter.  qs_rollout/qs_rollout_backward keep using the
+ * host counter.  Synchronises `stream`.
+ */
+int qs_set_graph_mode(qs_handle* h, int32_t enable, void* stream);
+
+/*
+ * Time candidate launch configurations of qs_step_observe (d_goals and d_obs
+ * non-NULL) or qs_step (both NULL) with n_substeps substeps on the handle's
+ * own swarms (each candidate from the same saved state), keep the fastest,
+ * and restore the state, the substep counter and the sticky error word.
+ * Candidates: workgroup size 64 or 128 and, for uneven swarm sizes, the
+ * persistent grid size.  choice (optional, int32[3]) receives (workgroup
+ * size, grid size or 0 for one workgroup per item, bucketed ? 1 : 0).
+ * Not available in graph mode.  Synchronous.
+ */
+int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const float* d_goals,
+                float* d_obs, int32_t* choice, void* stream);
+
 /* Static description of a return code. */
 const char* qs_error_string(int code);
 

@@ -35,6 +35,18 @@ struct qs_handle {
   bool record = false;
   // adjoint scratch, grown on demand: tape [S][27][Q], adjoint [27][Q],
   // parameter gradient [6][Q], one checkpoint [27][Q]
+  // uneven swarm sizes: work items of the persistent bucketed launch
+  std::vector<int> env_start, env_n;  // host copy of the environments
+  int4* d_items = nullptr;
+  int2* d_item_envs = nullptr;
+  int n_items = 0;
+  int item_bs = 64;      // workgroup size of the bucketed launch
+  int item_grid = 0;     // persistent grid size (0: one workgroup per item)
+  bool bucketed = false;
+  // graph-safe substep counter
+  bool graph_mode = false;
+  unsigned long long* d_t = nullptr;
+  unsigned int* d_done = nullptr;
   float* d_tape = nullptr;
   size_t tape_cap = 0;
   float* d_lam = nullptr;
@@ -108,6 +120,10 @@ void free_all(qs_handle* h) {
   (void)hipFree(h->d_lam);
   (void)hipFree(h->d_gpar);
   (void)hipFree(h->d_ck1);
+  (void)hipFree(h->d_items);
+  (void)hipFree(h->d_item_envs);
+  (void)hipFree(h->d_t);
+  (void)hipFree(h->d_done);
   if (h->h_err) (void)hipHostFree(h->h_err);
 }
 
@@ -121,7 +137,79 @@ Ptrs ptrs(qs_handle* h) {
   p.err = h->d_err;
   p.Qp = h->Qp;
   p.Q = h->Q;
+  p.items = h->d_items;
+  p.item_envs = h->d_item_envs;
   return p;
+}
+
+// Greedy packing of whole environments into workgroups of at most bs quads:
+// the workgroup table (first quad, count) and, per quad, its swarm's start
+// within the workgroup and its size.  Sets bs and the workgroup count.
+int build_table(qs_handle* h, int bs) {
+  std::vector<int2> blk;
+  std::vector<uint32_t> sw((size_t)h->Qp, 0u);
+  int cur_begin = 0, cur_cnt = 0;
+  for (size_t e = 0; e < h->env_n.size(); ++e) {
+    const int q0 = h->env_start[e], n = h->env_n[e];
+    if (cur_cnt + n > bs) {
+      blk.push_back(make_int2(cur_begin, cur_cnt));
+      cur_begin = q0;
+      cur_cnt = 0;
+    }
+    for (int i = 0; i < n; ++i) sw[(size_t)q0 + i] = ((uint32_t)(q0 - cur_begin) << 8) | (uint32_t)n;
+    cur_cnt += n;
+  }
+  blk.push_back(make_int2(cur_begin, cur_cnt));
+  (void)hipFree(h->d_blk);
+  (void)hipFree(h->d_sw);
+  h->d_blk = nullptr;
+  h->d_sw = nullptr;
+  if (hipMalloc((void**)&h->d_blk, blk.size() * sizeof(int2)) != hipSuccess ||
+      hipMalloc((void**)&h->d_sw, sw.size() * sizeof(uint32_t)) != hipSuccess)
+    return QS_ERR_NOMEM;
+  if (hipMemcpy(h->d_blk, blk.data(), blk.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_sw, sw.data(), sw.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return QS_ERR_HIP;
+  h->bs = bs;
+  h->nblk = (int)blk.size();
+  return QS_OK;
+}
+
+// Work items of the bucketed launch: every swarm gets a slot of the next
+// power of two >= its size; slots of one size are grouped bs/slot per item;
+// items are ordered by slot size, largest first (heaviest work first).
+int build_items(qs_handle* h, int bs) {
+  std::vector<int4> items;
+  std::vector<int2> envs;
+  for (int N = 64; N >= 1; N >>= 1) {
+    const int per = bs / N;
+    int in_item = 0;
+    for (size_t e = 0; e < h->env_n.size(); ++e) {
+      const int n = h->env_n[e];
+      int slot = 1;
+      while (slot < n) slot <<= 1;
+      if (slot != N) continue;
+      if (in_item == 0) items.push_back(make_int4(N, (int)envs.size(), 0, 0));
+      envs.push_back(make_int2(h->env_start[e], n));
+      items.back().z += 1;
+      if (++in_item == per) in_item = 0;
+    }
+  }
+  (void)hipFree(h->d_items);
+  (void)hipFree(h->d_item_envs);
+  h->d_items = nullptr;
+  h->d_item_envs = nullptr;
+  if (hipMalloc((void**)&h->d_items, items.size() * sizeof(int4)) != hipSuccess ||
+      hipMalloc((void**)&h->d_item_envs, envs.size() * sizeof(int2)) != hipSuccess)
+    return QS_ERR_NOMEM;
+  if (hipMemcpy(h->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(h->d_item_envs, envs.data(), envs.size() * sizeof(int2),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return QS_ERR_HIP;
+  h->n_items = (int)items.size();
+  h->item_bs = bs;
+  return QS_OK;
 }
 
 // Launch one instantiation.  Observation rows are staged in LDS when the
@@ -139,7 +227,30 @@ void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs
     }
   }
   hipLaunchKernelGGL((qs::step_kernel<BS, KT, N>), dim3(h->nblk), dim3(BS), dyn, s, h->c,
-                     ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, stage);
+                     ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, stage,
+                     h->graph_mode ? h->d_t : nullptr, h->d_done);
+}
+
+template <int BS, int KT>
+void go_items(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
+              hipStream_t s) {
+  const int grid = h->item_grid > 0 ? std::min(h->item_grid, h->n_items) : h->n_items;
+  hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), 0, s, h->c,
+                     ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, h->n_items,
+                     h->graph_mode ? h->d_t : nullptr, h->d_done);
+}
+
+template <int BS>
+void launch_items(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
+                  bool with_obs, hipStream_t s) {
+  if (!with_obs)
+    go_items<BS, -2>(h, act, nsub, goals, obs, s);
+  else if (h->K == 6)
+    go_items<BS, 6>(h, act, nsub, goals, obs, s);
+  else if (h->K == 0)
+    go_items<BS, 0>(h, act, nsub, goals, obs, s);
+  else
+    go_items<BS, -1>(h, act, nsub, goals, obs, s);
 }
 
 template <int BS, int KT>
@@ -177,9 +288,17 @@ int launch(qs_handle* h, const float* act, int nsub, const float* goals, float* 
            bool with_obs, hipStream_t s) {
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
   int rc;
-  switch (h->bs) {
-    case 128: rc = launch_bs<128>(h, act, nsub, goals, obs, with_obs, s); break;
-    default: rc = launch_bs<64>(h, act, nsub, goals, obs, with_obs, s); break;
+  if (h->bucketed) {
+    if (h->item_bs == 128)
+      launch_items<128>(h, act, nsub, goals, obs, with_obs, s);
+    else
+      launch_items<64>(h, act, nsub, goals, obs, with_obs, s);
+    rc = hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+  } else {
+    switch (h->bs) {
+      case 128: rc = launch_bs<128>(h, act, nsub, goals, obs, with_obs, s); break;
+      default: rc = launch_bs<64>(h, act, nsub, goals, obs, with_obs, s); break;
+    }
   }
   if (rc == QS_OK) h->t += (uint64_t)nsub;
   return rc;
@@ -355,26 +474,16 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   c.obs_dim = h->OD;
 
   // environment -> workgroup partition (environments are never split)
-  std::vector<int2> blk;
-  std::vector<uint32_t> sw((size_t)h->Qp, 0u);
+  h->env_start.resize(E);
+  h->env_n.resize(E);
   std::vector<int32_t> qenv((size_t)Q, 0);
-  int cur_begin = 0, cur_cnt = 0;
   for (int e = 0; e < E; ++e) {
     const int q0 = desc->env_offsets[e], n = desc->env_offsets[e + 1] - q0;
-    if (cur_cnt + n > h->bs) {
-      blk.push_back(make_int2(cur_begin, cur_cnt));
-      cur_begin = q0;
-      cur_cnt = 0;
-    }
-    for (int i = 0; i < n; ++i) {
-      sw[(size_t)q0 + i] = ((uint32_t)(q0 - cur_begin) << 8) | (uint32_t)n;
-      qenv[(size_t)q0 + i] = e;
-    }
-    cur_cnt += n;
+    h->env_start[e] = q0;
+    h->env_n[e] = n;
+    for (int i = 0; i < n; ++i) qenv[(size_t)q0 + i] = e;
   }
-  blk.push_back(make_int2(cur_begin, cur_cnt));
-  h->nblk = (int)blk.size();
-  // uniform power-of-two swarms: the greedy packing above is then exactly
+  // uniform power-of-two swarms: the greedy packing is then exactly
   // "workgroup b owns quads [b bs, (b+1) bs)", which the specialised kernels use
   {
     const int n0 = desc->env_offsets[1] - desc->env_offsets[0];
@@ -405,11 +514,19 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   rc = QS_OK;
   if (rc == QS_OK) rc = dalloc(&h->d_st, st.size());
   if (rc == QS_OK) rc = dalloc(&h->d_par, par.size());
-  if (rc == QS_OK) rc = dalloc(&h->d_sw, sw.size());
-  if (rc == QS_OK) rc = dalloc(&h->d_blk, blk.size());
   if (rc == QS_OK) rc = dalloc(&h->d_qenv, qenv.size());
   if (rc == QS_OK) rc = dalloc(&h->d_contacts, (size_t)h->Qp);
   if (rc == QS_OK) rc = dalloc(&h->d_err, 1);
+  if (rc == QS_OK) rc = build_table(h, h->bs);
+  if (rc == QS_OK && hipMalloc((void**)&h->d_t, sizeof(unsigned long long)) != hipSuccess)
+    rc = QS_ERR_NOMEM;
+  if (rc == QS_OK && hipMalloc((void**)&h->d_done, sizeof(unsigned int)) != hipSuccess)
+    rc = QS_ERR_NOMEM;
+  if (rc == QS_OK && h->uniform_n == 0) {
+    const char* ev = std::getenv("QS_BUCKETED");
+    h->bucketed = !(ev && ev[0] == '0');
+    if (h->bucketed) rc = build_items(h, 64);
+  }
   if (rc == QS_OK && hipHostMalloc((void**)&h->h_err, sizeof(int)) != hipSuccess) {
     h->h_err = nullptr;
     rc = QS_ERR_NOMEM;
@@ -417,12 +534,12 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   if (rc == QS_OK) {
     bool ok = hipMemcpy(h->d_st, st.data(), st.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(h->d_par, par.data(), par.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemcpy(h->d_sw, sw.data(), sw.size() * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemcpy(h->d_blk, blk.data(), blk.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess;
     if (Q > 0)
       ok = ok && hipMemcpy(h->d_qenv, qenv.data(), qenv.size() * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(h->d_contacts, 0, (size_t)h->Qp * sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMemset(h->d_err, 0, sizeof(int)) == hipSuccess;
+    ok = ok && hipMemset(h->d_t, 0, sizeof(unsigned long long)) == hipSuccess;
+    ok = ok && hipMemset(h->d_done, 0, sizeof(unsigned int)) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (!ok) rc = QS_ERR_HIP;
   }
@@ -455,8 +572,127 @@ int qs_sizes(const qs_handle* h, int32_t* n_quads, int32_t* n_envs, int32_t* obs
 
 int qs_substep_index(const qs_handle* h, uint64_t* substep_index) {
   if (!h || !substep_index) return QS_ERR_NULL;
+  if (h->graph_mode) {
+    unsigned long long v = 0;
+    if (hipSetDevice(h->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&v, h->d_t, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+      return QS_ERR_HIP;
+    *substep_index = v;
+    return QS_OK;
+  }
   *substep_index = h->t;
   return QS_OK;
+}
+
+int qs_set_graph_mode(qs_handle* h, int32_t enable, void* stream) {
+  if (!h) return QS_ERR_NULL;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return QS_ERR_HIP;
+  if (enable && !h->graph_mode) {
+    hipLaunchKernelGGL(qs::set_counter_kernel, dim3(1), dim3(64), 0, s, h->d_t, h->d_done,
+                       (unsigned long long)h->t);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return QS_ERR_HIP;
+    h->graph_mode = true;
+  } else if (!enable && h->graph_mode) {
+    unsigned long long v = 0;
+    if (hipMemcpy(&v, h->d_t, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return QS_ERR_HIP;
+    h->t = v;
+    h->graph_mode = false;
+  }
+  return QS_OK;
+}
+
+int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const float* d_goals,
+                float* d_obs, int32_t* choice, void* stream) {
+  if (!h || !d_actions) return QS_ERR_NULL;
+  if (n_substeps < 1 || (d_goals == nullptr) != (d_obs == nullptr)) return QS_ERR_INVALID;
+  if (!aligned(d_actions, 16) || (d_obs && !aligned(d_obs, 8))) return QS_ERR_ALIGN;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  if (h->graph_mode) return QS_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  const bool with_obs = d_obs != nullptr;
+  // candidates: (workgroup size, persistent grid) -- the grid only matters
+  // for the bucketed launch of uneven swarm sizes
+  struct Cand { int bs, grid; };
+  std::vector<Cand> cands;
+  if (h->bucketed) {
+    for (int bs : {64, 128})
+      for (int g : {0, 1024, 2048, 4096}) cands.push_back({bs, g});
+  } else if (h->uniform_n > 0) {
+    cands.push_back({64, 0});
+    cands.push_back({128, 0});
+  } else {
+    cands.push_back({h->bs, 0});
+  }
+  // the trials must not change the simulation: every candidate starts from
+  // the saved state, and the state, substep counter and sticky error word
+  // are restored afterwards
+  float* saved = nullptr;
+  const size_t st_bytes = (size_t)qs::NSTATE * h->Qp * sizeof(float);
+  if (hipMalloc((void**)&saved, st_bytes + 256) != hipSuccess) return QS_ERR_NOMEM;
+  int* saved_err = reinterpret_cast<int*>(reinterpret_cast<char*>(saved) + st_bytes);
+  const uint64_t t_saved = h->t;
+  int rc = hipMemcpyAsync(saved, h->d_st, st_bytes, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+                   hipMemcpyAsync(saved_err, h->d_err, sizeof(int), hipMemcpyDeviceToDevice, s) ==
+                       hipSuccess
+               ? QS_OK : QS_ERR_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (rc == QS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = QS_ERR_HIP;
+  float best = 1e30f;
+  Cand best_c = cands[0];
+  for (size_t i = 0; rc == QS_OK && i < cands.size(); ++i) {
+    const Cand cd = cands[i];
+    if (h->bucketed) {
+      if (cd.bs != h->item_bs && (rc = build_items(h, cd.bs)) != QS_OK) break;
+      h->item_grid = cd.grid;
+    } else if (h->uniform_n > 0 && cd.bs != h->bs) {
+      if ((rc = build_table(h, cd.bs)) != QS_OK) break;
+    }
+    if (hipMemcpyAsync(h->d_st, saved, st_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      rc = QS_ERR_HIP;
+      break;
+    }
+    h->t = t_saved;
+    for (int w = 0; rc == QS_OK && w < 2; ++w) rc = launch(h, d_actions, n_substeps, d_goals, d_obs, with_obs, s);
+    if (rc != QS_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = QS_ERR_HIP; break; }
+    for (int r = 0; rc == QS_OK && r < 5; ++r) rc = launch(h, d_actions, n_substeps, d_goals, d_obs, with_obs, s);
+    float ms = 0.f;
+    if (rc != QS_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = rc == QS_OK ? QS_ERR_HIP : rc;
+      break;
+    }
+    if (ms < best) {
+      best = ms;
+      best_c = cd;
+    }
+  }
+  if (rc == QS_OK) {
+    if (h->bucketed) {
+      if (best_c.bs != h->item_bs) rc = build_items(h, best_c.bs);
+      h->item_grid = best_c.grid;
+    } else if (h->uniform_n > 0 && best_c.bs != h->bs) {
+      rc = build_table(h, best_c.bs);
+    }
+  }
+  if (hipMemcpyAsync(h->d_st, saved, st_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->d_err, saved_err, sizeof(int), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = QS_ERR_HIP;
+  h->t = t_saved;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(saved);
+  if (rc == QS_OK && choice) {
+    choice[0] = h->bucketed ? h->item_bs : h->bs;
+    choice[1] = h->bucketed ? h->item_grid : h->nblk;
+    choice[2] = h->bucketed ? 1 : 0;
+  }
+  return rc;
 }
 
 int qs_step(qs_handle* h, const float* d_actions, int32_t n_substeps, void* stream) {
@@ -505,7 +741,10 @@ int qs_set_state(qs_handle* h, const float* d_state, uint64_t substep_index,
                      (hipStream_t)stream, h->d_st, h->Qp, h->Q, d_state, h->d_qenv, d_env_mask);
   if (hipGetLastError() != hipSuccess) return QS_ERR_HIP;
   h->t = substep_index;
-  return QS_OK;
+  if (h->graph_mode)
+    hipLaunchKernelGGL(qs::set_counter_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, h->d_t,
+                       h->d_done, (unsigned long long)substep_index);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
 }
 
 int qs_record_contacts(qs_handle* h, int32_t enable) {

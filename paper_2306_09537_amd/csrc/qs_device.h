@@ -42,6 +42,8 @@ struct Ptrs {
   int* err;                     // sticky error bits
   int Qp;                       // padded quad count (SoA field stride)
   int Q;                        // quad count
+  const int4* items;            // uneven sizes: (slot size, first env entry, swarms, -)
+  const int2* item_envs;        // uneven sizes: (first quad, size) per swarm of an item
 };
 
 // Philox4x32-10, Salmon et al. SC'11: ten rounds of two 32x32->64 products

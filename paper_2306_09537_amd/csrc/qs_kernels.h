@@ -13,43 +13,65 @@
 
 namespace qs {
 
+// Mapping of a workgroup's lanes to quads.
+//  MAP_DENSE:  every swarm holds N quads; workgroup b owns quads [b BS, (b+1) BS).
+//  MAP_TABLE:  any sizes; the host-built table gives each workgroup's first quad
+//              and count, and each quad's swarm start (within the workgroup)
+//              and size.
+//  MAP_ITEM:   one work item of the uneven-size bucketing: up to BS/N swarms of
+//              at most N quads each, lane t serving quad t % N of swarm t / N;
+//              lanes past a swarm's size are padding.
+enum : int { MAP_DENSE = 0, MAP_TABLE = 1, MAP_ITEM = 2 };
+
+// Body of one step (+ observation) over one workgroup's quads.
 // KT: -2 step only; -1 observation with runtime K (selection); >= 0 observation
 // with compile-time K (register insertion network).
-// N: 0 for any mix of swarm sizes (host-built workgroup table); N > 0 when
-// every environment holds N quads (BS a multiple of N): workgroup b then
-// owns quads [b BS, (b+1) BS) and the in-swarm loops unroll completely.
-template <int BS, int KT, int N>
-__global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
-                                                  const float* __restrict__ act, int nsub,
-                                                  unsigned long long t0,
-                                                  const float* __restrict__ goals,
-                                                  float* __restrict__ obs, int stage_obs) {
+// N: swarm (slot) size known at compile time (MAP_DENSE, MAP_ITEM), or 0.
+// sxv: LDS tile [2][9][BS]; st_obs: LDS staging of observation rows.
+template <int BS, int KT, int N, int MAP>
+__device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
+                                          const float* __restrict__ act, int nsub,
+                                          unsigned long long t0,
+                                          const float* __restrict__ goals,
+                                          float* __restrict__ obs, int stage_obs,
+                                          float (*sxv)[9][BS], float* st_obs, int item) {
   static_assert(N == 0 || BS % N == 0, "workgroups hold whole swarms");
+  static_assert(MAP != MAP_TABLE || N == 0, "the table mapping has runtime sizes");
   constexpr bool OBS = KT != -2;
-  // rows 0-2: start position (pair pass) or position (observation),
-  // rows 3-5: substep displacement, rows 6-8: velocity
-  __shared__ float sxv[2][9][BS];
-  extern __shared__ float4 st_obs4[];  // staged observation rows (stride OD)
-  float* st_obs = reinterpret_cast<float*>(st_obs4);
+  const float4* st_obs4 = reinterpret_cast<const float4*>(st_obs);
 
   const int tid = threadIdx.x;
-  int qb, cnt, ls, n;
-  if constexpr (N > 0) {
+  int qb = 0, cnt = 0, ls = 0, n = 0;
+  bool live = false;
+  int q = 0;
+  if constexpr (MAP == MAP_DENSE) {
     qb = blockIdx.x * BS;
     cnt = min(BS, p.Q - qb);
     ls = (tid / N) * N;
     n = N;
-  } else {
+    live = tid < cnt;
+    q = qb + (live ? tid : 0);
+  } else if constexpr (MAP == MAP_TABLE) {
     const int2 bq = p.blk[blockIdx.x];
     qb = bq.x;
     cnt = bq.y;
-  }
-  const bool live = tid < cnt;
-  const int q = qb + (live ? tid : 0);
-  if constexpr (N == 0) {
+    live = tid < cnt;
+    q = qb + (live ? tid : 0);
     const uint32_t swd = live ? p.sw[q] : 0u;
     ls = (int)(swd >> 8);
     n = (int)(swd & 0xffu);
+  } else {
+    const int4 it = p.items[item];  // (slot size, first env entry, swarms, -)
+    const int k = tid / N, r = tid - (tid / N) * N;
+    ls = k * N;
+    if (k < it.z) {
+      const int2 e = p.item_envs[it.y + k];  // (first quad, size)
+      n = e.y;
+      if (r < n) {
+        live = true;
+        q = e.x + r;
+      }
+    }
   }
   const int me = tid - ls;  // index within the swarm
   const int Qp = p.Qp;
@@ -110,6 +132,14 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
           tile[k][tid] = s.xo[k];
           tile[3 + k][tid] = s.inc[k];
           tile[6 + k][tid] = s.v[k];
+        }
+      } else if constexpr (MAP == MAP_ITEM) {
+        // padding lane: far away, so it is never in contact
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          tile[k][tid] = 1e30f;
+          tile[3 + k][tid] = 0.f;
+          tile[6 + k][tid] = 0.f;
         }
       }
       __syncthreads();
@@ -183,6 +213,13 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
       for (int k = 0; k < 3; ++k) {
         tile[k][tid] = s.x[k];
         tile[6 + k][tid] = s.v[k];
+      }
+    } else if constexpr (MAP == MAP_ITEM) {
+      // padding lane: never among the nearest
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        tile[k][tid] = 1e30f;
+        tile[6 + k][tid] = 0.f;
       }
     }
     __syncthreads();
@@ -320,6 +357,77 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
         }
       }
     }
+  }
+}
+
+// Graph-safe substep counter: every workgroup reads the base substep index
+// from device memory; the last workgroup to finish advances it by nsub.
+__device__ __forceinline__ void advance_counter(unsigned long long* tdev, unsigned int* done,
+                                                int nsub) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int prev =
+        __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == gridDim.x - 1) {
+      __hip_atomic_fetch_add(tdev, (unsigned long long)nsub, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_exchange(done, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// One workgroup per block of quads (dense or table mapping).
+template <int BS, int KT, int N>
+__global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
+                                                  const float* __restrict__ act, int nsub,
+                                                  unsigned long long t0,
+                                                  const float* __restrict__ goals,
+                                                  float* __restrict__ obs, int stage_obs,
+                                                  unsigned long long* tdev, unsigned int* done) {
+  __shared__ float sxv[2][9][BS];
+  extern __shared__ float4 st_obs4[];
+  if (tdev) t0 = *tdev;
+  constexpr int MAP = (N > 0) ? MAP_DENSE : MAP_TABLE;
+  step_body<BS, KT, N, MAP>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
+                            reinterpret_cast<float*>(st_obs4), 0);
+  if (tdev) advance_counter(tdev, done, nsub);
+}
+
+// Persistent launch over the work items of uneven swarm sizes: items of the
+// same slot size N run the body specialised for N (unrolled in-swarm loops);
+// workgroups stride over the item list.
+template <int BS, int KT>
+__global__ __launch_bounds__(BS) void bucket_kernel(Consts c, Ptrs p,
+                                                    const float* __restrict__ act, int nsub,
+                                                    unsigned long long t0,
+                                                    const float* __restrict__ goals,
+                                                    float* __restrict__ obs, int n_items,
+                                                    unsigned long long* tdev,
+                                                    unsigned int* done) {
+  __shared__ float sxv[2][9][BS];
+  if (tdev) t0 = *tdev;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int N = p.items[it].x;
+    __syncthreads();  // the previous item's readers of the tile are done
+    switch (N) {
+      case 1: step_body<BS, KT, 1, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+      case 2: step_body<BS, KT, 2, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+      case 4: step_body<BS, KT, 4, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+      case 8: step_body<BS, KT, 8, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+      case 16: step_body<BS, KT, 16, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+      case 32: step_body<BS, KT, 32, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+      default: step_body<BS, KT, 64, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+    }
+  }
+  if (tdev) advance_counter(tdev, done, nsub);
+}
+
+__global__ void set_counter_kernel(unsigned long long* tdev, unsigned int* done,
+                                   unsigned long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    __hip_atomic_exchange(tdev, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_exchange(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -25,7 +25,7 @@ ERRORS = {-1: "QS_ERR_NULL", -2: "QS_ERR_INVALID", -3: "QS_ERR_ENV_SIZE", -4: "Q
 EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_substep_index", "qs_step", "qs_observe",
            "qs_step_observe", "qs_get_state", "qs_set_state", "qs_record_contacts",
            "qs_debug_contacts", "qs_sync", "qs_rollout", "qs_rollout_backward",
-           "qs_step_backward", "qs_error_string")
+           "qs_step_backward", "qs_set_graph_mode", "qs_autotune", "qs_error_string")
 
 
 class QuadSwarmError(RuntimeError):
@@ -77,6 +77,8 @@ def lib() -> C.CDLL:
         L.qs_rollout.argtypes = [vp, vp, i32, i32, i32, vp, vp, f32, vp]
         L.qs_rollout_backward.argtypes = [vp, vp, i32, i32, i32, vp, u64, vp, vp, f32, vp, vp, vp]
         L.qs_step_backward.argtypes = [vp, vp, vp, i32, u64, vp, vp, vp, vp, vp]
+        L.qs_set_graph_mode.argtypes = [vp, i32, vp]
+        L.qs_autotune.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.qs_error_string.argtypes = [C.c_int]
         L.qs_error_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -250,6 +252,20 @@ class QuadSwarm:
                                       C.c_uint64(int(substep_index)), _ptr(gstate_out),
                                       _ptr(gstate_in), _ptr(gactions), _ptr(gparams),
                                       _stream()), "qs_step_backward")
+
+    def set_graph_mode(self, enable: bool = True) -> None:
+        _check(lib().qs_set_graph_mode(self._h, 1 if enable else 0, _stream()),
+               "qs_set_graph_mode")
+
+    def autotune(self, actions, n_substeps: int, goals=None, out=None) -> dict:
+        """qs_autotune: returns the chosen (block, grid, bucketed)."""
+        self._dev(actions, (self.n_quads, 4))
+        ch = (C.c_int32 * 3)()
+        _check(lib().qs_autotune(self._h, _ptr(actions), int(n_substeps),
+                                 None if goals is None else _ptr(goals),
+                                 None if out is None else _ptr(out), ch, _stream()),
+               "qs_autotune")
+        return {"block": ch[0], "grid": ch[1], "bucketed": bool(ch[2])}
 
     def sync(self) -> None:
         _check(lib().qs_sync(self._h, _stream()), "qs_sync")
