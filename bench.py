@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fwdbwd", default="diff", help="workload of the fwd+bwd leg ('' to skip)")
     ap.add_argument("--fwdbwd-horizon", type=int, default=200)
+    ap.add_argument("--batched", default="uneven", help="workload of the batched leg ('' to skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of "
                          "known traffic for scaling HBM counters) and exit")
@@ -185,6 +186,66 @@ def time_fwd_bwd(w, torch, horizon: int, nsub: int, ckpt_every: int, reps: int, 
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": bwd_bytes / (b * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "bytes": bwd_bytes, "segment_substeps": seg})
+
+
+def sticky_nonfinite(sim, torch) -> int:
+    """Number of quads whose state is non-finite (the explicit integration of
+    Euler's equation can diverge for a quad driven to very high spin rates);
+    clears the handle's sticky error."""
+    from paper_2306_09537_amd.quadswarm import QuadSwarmError
+    try:
+        sim.sync()
+        return 0
+    except QuadSwarmError:
+        s, _ = sim.get_state()
+        return int((~torch.isfinite(s).all(dim=1)).sum().item())
+
+
+def time_batched(w, torch, calls: int = 100, nsub: int = 10, reps: int = 3):
+    """Uneven swarm sizes: the persistent bucketed launch, autotuned, a
+    rollout of ``calls`` calls of ``nsub`` substeps (observation after each
+    call into its own slot) captured as one graph and replayed once per
+    episode; plus the one-substep launch on the same swarms."""
+    from paper_2306_09537_amd.quadswarm import QuadSwarm
+    sim = QuadSwarm.from_workload(w)
+    Q = w.n_quads
+    acts = torch.from_numpy(w.action_sequence(calls)).cuda()
+    goals = torch.from_numpy(w.goals).cuda()
+    obs = torch.empty((calls, Q, w.obs_dim), device="cuda")
+    s0 = torch.from_numpy(w.state0).cuda()
+    choice = sim.autotune(acts[0], nsub, goals, obs[0])
+    sim.set_graph_mode(True)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for c in range(calls):
+            sim.step_observe(acts[c], nsub, goals, obs[c])
+    times = []
+    for r in range(reps + 1):
+        # episode reset (untimed); every replay runs the same seeded episode
+        sim.set_state(s0, 0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if r:
+            times.append(e0.elapsed_time(e1))
+    nonfinite = sticky_nonfinite(sim, torch)
+    sim.set_graph_mode(False)
+    ms = float(np.median(times))
+    value = Q * calls * nsub / (ms * 1e-3)
+    # the one-substep launch (observation every substep) on the same swarms
+    plain_ms, _ = time_calls(sim, w, acts, goals, obs[0], 1, 500, 20, torch, w.substeps)
+    plain = Q / (plain_ms * 1e-3)
+    sim.close()
+    return dict(workload=w.name, quads=Q, envs=w.n_envs, calls=calls, substeps_per_call=nsub,
+                value=value, unit="quad-steps/s", ms_per_rollout=ms, autotune=choice,
+                nonfinite_quads=nonfinite,
+                form="persistent bucketed launch, 10 substeps per call, 100-call rollout "
+                     "replayed as one captured graph",
+                plain_value=plain, speedup_vs_plain=value / plain)
 
 
 def cpu_baseline(w, target_s: float):
@@ -293,6 +354,8 @@ def main():
     if args.fwdbwd:
         wd = W.WORKLOADS[args.fwdbwd](seed=0)
         line["fwd_bwd"] = time_fwd_bwd(wd, torch, args.fwdbwd_horizon, 1, 20, 3)
+    if args.batched:
+        line["batched"] = time_batched(W.WORKLOADS[args.batched](seed=0), torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     sim.close()

@@ -253,6 +253,13 @@ int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actio
 int qs_set_graph_mode(qs_handle* h, int32_t enable, void* stream);
 
 /*
+ * Set the launch configuration explicitly: workgroup size 64 or 128 and, for
+ * uneven swarm sizes, the persistent grid size (0: one workgroup per work
+ * item).  Synchronises the device.
+ */
+int qs_set_launch(qs_handle* h, int32_t block, int32_t grid);
+
+/*
  * Time candidate launch configurations of qs_step_observe (d_goals and d_obs
  * non-NULL) or qs_step (both NULL) with n_substeps substeps on the handle's
  * own swarms (each candidate from the same saved state), keep the fastest,

@@ -21,6 +21,9 @@ DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("qs_device.h", "qs_kernels.h")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds fuse only within one source expression, so every kernel
+    # specialisation (and the adjoint's recomputation) rounds identically
+    "-ffp-contract=on",
     # no packed-FP32 instructions: plain float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",

@@ -604,6 +604,21 @@ int qs_set_graph_mode(qs_handle* h, int32_t enable, void* stream) {
   return QS_OK;
 }
 
+int qs_set_launch(qs_handle* h, int32_t block, int32_t grid) {
+  if (!h) return QS_ERR_NULL;
+  if ((block != 64 && block != 128) || grid < 0) return QS_ERR_INVALID;
+  if (hipSetDevice(h->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return QS_ERR_HIP;
+  int rc = QS_OK;
+  if (h->bucketed) {
+    if (block != h->item_bs) rc = build_items(h, block);
+    h->item_grid = grid;
+  } else if (block != h->bs) {
+    if (h->uniform_n > 64 || block % std::max(h->uniform_n, 1) != 0) return QS_ERR_INVALID;
+    rc = build_table(h, block);
+  }
+  return rc;
+}
+
 int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const float* d_goals,
                 float* d_obs, int32_t* choice, void* stream) {
   if (!h || !d_actions) return QS_ERR_NULL;
@@ -645,6 +660,11 @@ int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const 
   Cand best_c = cands[0];
   for (size_t i = 0; rc == QS_OK && i < cands.size(); ++i) {
     const Cand cd = cands[i];
+    // no launch may still read the tables that are about to be rebuilt
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      rc = QS_ERR_HIP;
+      break;
+    }
     if (h->bucketed) {
       if (cd.bs != h->item_bs && (rc = build_items(h, cd.bs)) != QS_OK) break;
       h->item_grid = cd.grid;
@@ -671,6 +691,7 @@ int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const 
       best_c = cd;
     }
   }
+  if (rc == QS_OK && hipStreamSynchronize(s) != hipSuccess) rc = QS_ERR_HIP;
   if (rc == QS_OK) {
     if (h->bucketed) {
       if (best_c.bs != h->item_bs) rc = build_items(h, best_c.bs);

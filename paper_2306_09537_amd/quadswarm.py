@@ -25,7 +25,8 @@ ERRORS = {-1: "QS_ERR_NULL", -2: "QS_ERR_INVALID", -3: "QS_ERR_ENV_SIZE", -4: "Q
 EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_substep_index", "qs_step", "qs_observe",
            "qs_step_observe", "qs_get_state", "qs_set_state", "qs_record_contacts",
            "qs_debug_contacts", "qs_sync", "qs_rollout", "qs_rollout_backward",
-           "qs_step_backward", "qs_set_graph_mode", "qs_autotune", "qs_error_string")
+           "qs_step_backward", "qs_set_graph_mode", "qs_set_launch", "qs_autotune",
+           "qs_error_string")
 
 
 class QuadSwarmError(RuntimeError):
@@ -79,6 +80,7 @@ def lib() -> C.CDLL:
         L.qs_step_backward.argtypes = [vp, vp, vp, i32, u64, vp, vp, vp, vp, vp]
         L.qs_set_graph_mode.argtypes = [vp, i32, vp]
         L.qs_autotune.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.qs_set_launch.argtypes = [vp, i32, i32]
         L.qs_error_string.argtypes = [C.c_int]
         L.qs_error_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -256,6 +258,9 @@ class QuadSwarm:
     def set_graph_mode(self, enable: bool = True) -> None:
         _check(lib().qs_set_graph_mode(self._h, 1 if enable else 0, _stream()),
                "qs_set_graph_mode")
+
+    def set_launch(self, block: int, grid: int = 0) -> None:
+        _check(lib().qs_set_launch(self._h, int(block), int(grid)), "qs_set_launch")
 
     def autotune(self, actions, n_substeps: int, goals=None, out=None) -> dict:
         """qs_autotune: returns the chosen (block, grid, bucketed)."""
