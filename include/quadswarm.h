@@ -67,6 +67,7 @@ extern "C" {
 #define QS_MOTOR_NOISE 8u     /* §III-A.2 AR(1) motor noise */
 #define QS_APPROACH_ONLY 16u  /* pair response only while the pair approaches */
 #define QS_ACT_UNIT 32u       /* f_hat = clip(a,0,1) instead of (clip(a,-1,1)+1)/2 */
+#define QS_DOWNWASH 64u       /* §III-B.4 downwash of upper swarm-mates on lower ones */
 
 #define QS_STATE_DIM 27
 #define QS_PARAM_DIM 6
@@ -94,6 +95,14 @@ typedef struct qs_handle qs_handle;
  *  k_neighbors      K >= 0, at most 63
  *  flags            OR of QS_* switches above
  *  seed             key of the counter-based noise (Philox4x32-10)
+ *  dw_*             downwash (QS_DOWNWASH): an airborne quad with a
+ *                   swarm-mate above it, horizontal offset < dw_radius (m) and
+ *                   height difference dz in (0, dw_height) (m), gets the
+ *                   acceleration -dw_k1 (dw_k2 dz + dw_b1) e_z (summed over
+ *                   such swarm-mates) plus N(0, dw_noise_a^2) per axis
+ *                   (m/s^2), and N(0, dw_noise_w^2) angular acceleration
+ *                   (rad/s^2), as a kick of dt times them after the pair
+ *                   response.  Not differentiated.
  */
 typedef struct {
   int32_t n_envs;
@@ -105,6 +114,7 @@ typedef struct {
   int32_t k_neighbors;
   uint32_t flags;
   uint64_t seed;
+  float dw_k1, dw_k2, dw_b1, dw_radius, dw_height, dw_noise_a, dw_noise_w;
 } qs_desc;
 
 /* Per-quad domain-randomised physical parameters (§I, §III-A). */
@@ -191,7 +201,8 @@ int qs_sync(qs_handle* h, void* stream);
  * (d_qj: centre distance after the substep's motion; a smooth version of
  * the hinge proximity term of §III-E).  Derivatives are exact for the branch
  * each event took (walls, floor, contacts, friction regime); the resting
- * flag carries none.  Checkpoint k of a rollout is the state at the start of
+ * flag carries none.  Handles with QS_DOWNWASH return QS_ERR_UNSUPPORTED
+ * from the two backward calls.  Checkpoint k of a rollout is the state at the start of
  * call k * ckpt_every, stored field-major [27][Q] (state row layout, one
  * field after another).
  */

@@ -21,6 +21,7 @@ SRC = os.path.join(HERE, "quadswarm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 EV_WALL, EV_FLOOR_HIT, EV_FRICTION, EV_TAKEOFF, EV_PAIR_RESPONSE, EV_CONTACT = 1, 2, 4, 8, 16, 32
+EV_DOWNWASH = 64
 
 
 def build(force: bool = False) -> str:
@@ -47,6 +48,9 @@ class _Desc(C.Structure):
         ("col_noise_v", C.c_double), ("col_noise_w", C.c_double),
         ("k_neighbors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64),
         ("quad_id_offset", C.c_uint32),
+        ("dw_k1", C.c_double), ("dw_k2", C.c_double), ("dw_b1", C.c_double),
+        ("dw_radius", C.c_double), ("dw_height", C.c_double),
+        ("dw_noise_a", C.c_double), ("dw_noise_w", C.c_double),
     ]
 
 
@@ -97,6 +101,8 @@ class Oracle:
         d.flags = int(flags)
         d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         d.quad_id_offset = int(quad_id_offset)
+        for k in ("dw_k1", "dw_k2", "dw_b1", "dw_radius", "dw_height", "dw_noise_a", "dw_noise_w"):
+            setattr(d, k, float(consts.get(k, 0.0)))
         self.desc = d
 
     @classmethod
@@ -204,6 +210,6 @@ def uniform_from_u32(r: int) -> float:
 
 
 def flag_values():
-    o = (C.c_uint32 * 6)()
+    o = (C.c_uint32 * 7)()
     lib().or_flag_values(o)
     return [int(v) for v in o]

@@ -50,6 +50,12 @@
  *    index when the two positions coincide (|dx|^2 < 1e-12).
  *  - Observation (§III-C): [x - goal, v, R row-major, omega, K slots of
  *    (x_j - x_i, v_j - v_i)] for the K nearest by (d^2, index), zero padding.
+ *  - Downwash (§III-B.4): an airborne quad i below quad j with
+ *    |(x_j - x_i)_xy| < r and 0 < z_j - z_i < h gets the acceleration
+ *    -k1 (k2 (z_j - z_i) + b1) e_z, summed over such j, plus N(0, s_a^2)
+ *    acceleration noise and N(0, s_w^2) angular-acceleration noise, applied
+ *    as a velocity / body-rate kick of dt times them after the pair response
+ *    (evaluated on the post-motion positions).
  */
 #include <math.h>
 #include <stdint.h>
@@ -62,6 +68,7 @@
 #define OR_MOTOR_NOISE 8u
 #define OR_APPROACH_ONLY 16u
 #define OR_ACT_UNIT 32u
+#define OR_DOWNWASH 64u
 
 /* canonical state row: x3 v3 R9 (row-major) w3 u4 eps4 floor1 */
 enum { IX = 0, IV = 3, IR = 6, IW = 15, IU = 18, IE = 22, IF = 26, NS = 27 };
@@ -69,12 +76,12 @@ enum { IX = 0, IV = 3, IR = 6, IW = 15, IU = 18, IE = 22, IF = 26, NS = 27 };
 enum { PM = 0, PJX = 1, PJY = 2, PJZ = 3, PT2W = 4, PTAU = 5, NP = 6 };
 
 /* noise streams (fourth counter word = stream << 8 | draw) */
-enum { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2 };
+enum { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2, STREAM_DOWNWASH = 3 };
 
 /* per-quad event bits reported by or_step (OR over the call's substeps) */
 enum {
   EV_WALL = 1, EV_FLOOR_HIT = 2, EV_FRICTION = 4, EV_TAKEOFF = 8,
-  EV_PAIR_RESPONSE = 16, EV_CONTACT = 32
+  EV_PAIR_RESPONSE = 16, EV_CONTACT = 32, EV_DOWNWASH = 64
 };
 
 typedef struct {
@@ -88,6 +95,9 @@ typedef struct {
   uint32_t flags;
   uint64_t seed;
   uint32_t quad_id_offset; /* global index of quad 0 (noise counter) */
+  /* downwash (§III-B.4): a = -k1 (k2 dz + b1) e_z on the lower quad of a pair
+   * overlapping in xy (|dxy| < dw_radius) with 0 < dz < dw_height */
+  double dw_k1, dw_k2, dw_b1, dw_radius, dw_height, dw_noise_a, dw_noise_w;
 } or_desc;
 
 /* ------------------------------------------------------------------------ */
@@ -460,6 +470,30 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
       marked[i] = marked[j] = 1;
     }
   }
+  /* §III-B.4 downwash: the upper quads' airflow on a lower quad, from the
+   * post-motion positions, applied as a velocity kick after the response */
+  double adw[64];
+  int dwhit[64];
+  memset(adw, 0, sizeof(adw));
+  memset(dwhit, 0, sizeof(dwhit));
+  if (d->flags & OR_DOWNWASH) {
+    for (int i = 0; i < n; ++i) {
+      const double* si = S + (size_t)(q0 + i) * NS;
+      if (si[IF] != 0.0) continue; /* resting on the floor */
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double* sj = S + (size_t)(q0 + j) * NS;
+        double hx = sj[IX] - si[IX], hy = sj[IX + 1] - si[IX + 1], dz = sj[IX + 2] - si[IX + 2];
+        upd_margin(&mg[q0 + i], sqrt(hx * hx + hy * hy) - d->dw_radius);
+        upd_margin(&mg[q0 + i], dz);
+        upd_margin(&mg[q0 + i], dz - d->dw_height);
+        if (hx * hx + hy * hy < d->dw_radius * d->dw_radius && dz > 0.0 && dz < d->dw_height) {
+          adw[i] += -d->dw_k1 * (d->dw_k2 * dz + d->dw_b1);
+          dwhit[i] = 1;
+        }
+      }
+    }
+  }
   for (int i = 0; i < n; ++i) {
     if (!marked[i]) continue;
     double* si = S + (size_t)(q0 + i) * NS;
@@ -472,6 +506,21 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
     for (int k = 0; k < 3; ++k) {
       si[IV + k] = d->col_decay * (si[IV + k] + dv[i][k] + d->col_noise_v * zv[k]);
       si[IW + k] = si[IW + k] + d->col_noise_w * zw[k];
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!dwhit[i]) continue;
+    double* si = S + (size_t)(q0 + i) * NS;
+    events[q0 + i] |= EV_DOWNWASH;
+    double za[4] = {0, 0, 0, 0}, zw[4] = {0, 0, 0, 0};
+    if (d->dw_noise_a > 0.0 || d->dw_noise_w > 0.0) {
+      or_normal4(d->seed, d->quad_id_offset + (uint32_t)(q0 + i), t, STREAM_DOWNWASH, 0, za);
+      or_normal4(d->seed, d->quad_id_offset + (uint32_t)(q0 + i), t, STREAM_DOWNWASH, 1, zw);
+    }
+    for (int k = 0; k < 3; ++k) {
+      double a = (k == 2 ? adw[i] : 0.0) + d->dw_noise_a * za[k];
+      si[IV + k] += d->dt * a;
+      si[IW + k] += d->dt * d->dw_noise_w * zw[k];
     }
   }
 }
@@ -526,7 +575,7 @@ int or_step(const or_desc* d, const double* params, double* state,
                      actions + (size_t)q * 4, d->quad_id_offset + (uint32_t)q, t,
                      &ev[q], &mg[q], NULL);
       }
-      if ((d->flags & OR_COLLIDE) && n > 1)
+      if ((d->flags & (OR_COLLIDE | OR_DOWNWASH)) && n > 1)
         env_pairs(d, state, q0, n, t, contacts, ev, mg, NULL, 0.0);
     }
   }
@@ -918,7 +967,7 @@ int or_rollout(const or_desc* d, const double* params, double* state, const doub
                        actions + ((size_t)c * Q + q) * 4, d->quad_id_offset + (uint32_t)q, t,
                        &ev[q], &mg[q], NULL);
         }
-        if (n > 1 && ((d->flags & OR_COLLIDE) || pen))
+        if (n > 1 && ((d->flags & (OR_COLLIDE | OR_DOWNWASH)) || pen))
           env_pairs(d, state, q0, n, t, NULL, ev, mg, pen, beta);
       }
     }
@@ -940,7 +989,7 @@ int or_rollout_vjp(const or_desc* d, const double* params, const double* state0,
                    double* gstate, const double* gpen, double beta, double* gact,
                    double* gparams) {
   if (check_desc(d) || !params || !state0 || !actions || !gstate || !gact || !gparams ||
-      n_calls < 0 || n_sub < 0)
+      n_calls < 0 || n_sub < 0 || (d->flags & OR_DOWNWASH))
     return -1;
   const int E = d->n_envs, Q = d->env_offsets[E];
   const size_t S = (size_t)n_calls * n_sub;
@@ -970,7 +1019,8 @@ int or_rollout_vjp(const or_desc* d, const double* params, const double* state0,
                      actions + ((size_t)c * Q + q) * 4, d->quad_id_offset + (uint32_t)q,
                      t0 + k, &ev[q], &mg[q], NULL);
       }
-      if ((d->flags & OR_COLLIDE) && n > 1) env_pairs(d, st, q0, n, t0 + k, NULL, ev, mg, NULL, 0.0);
+      if ((d->flags & (OR_COLLIDE | OR_DOWNWASH)) && n > 1)
+        env_pairs(d, st, q0, n, t0 + k, NULL, ev, mg, NULL, 0.0);
     }
   }
   memset(gparams, 0, (size_t)Q * NP * sizeof(double));
@@ -1010,8 +1060,9 @@ int or_rollout_vjp(const or_desc* d, const double* params, const double* state0,
   return 0;
 }
 
-int or_flag_values(uint32_t out[6]) {
+int or_flag_values(uint32_t out[7]) {
   out[0] = OR_ROOM; out[1] = OR_FLOOR; out[2] = OR_COLLIDE;
   out[3] = OR_MOTOR_NOISE; out[4] = OR_APPROACH_ONLY; out[5] = OR_ACT_UNIT;
+  out[6] = OR_DOWNWASH;
   return 0;
 }

@@ -85,7 +85,13 @@ int check_desc(const qs_desc* d) {
       d->col_noise_v < 0.f || d->col_noise_w < 0.f)
     return QS_ERR_INVALID;
   if (d->k_neighbors < 0 || d->k_neighbors >= QS_MAX_SWARM) return QS_ERR_INVALID;
-  if (d->flags & ~63u) return QS_ERR_INVALID;
+  if (d->flags & ~127u) return QS_ERR_INVALID;
+  const float dwv[] = {d->dw_k1, d->dw_k2, d->dw_b1, d->dw_radius, d->dw_height, d->dw_noise_a,
+                       d->dw_noise_w};
+  for (float v : dwv)
+    if (!finite(v)) return QS_ERR_INVALID;
+  if (d->dw_radius < 0.f || d->dw_height < 0.f || d->dw_noise_a < 0.f || d->dw_noise_w < 0.f)
+    return QS_ERR_INVALID;
   return QS_OK;
 }
 
@@ -472,6 +478,13 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   c.key1 = (uint32_t)(desc->seed >> 32);
   c.K = h->K;
   c.obs_dim = h->OD;
+  c.dw_k1 = desc->dw_k1;
+  c.dw_k2 = desc->dw_k2;
+  c.dw_b1 = desc->dw_b1;
+  c.dw_r2 = (float)((double)desc->dw_radius * (double)desc->dw_radius);
+  c.dw_h = desc->dw_height;
+  c.dw_na = desc->dw_noise_a;
+  c.dw_nw = desc->dw_noise_w;
 
   // environment -> workgroup partition (environments are never split)
   h->env_start.resize(E);
@@ -829,6 +842,7 @@ int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
                         float beta, float* d_gactions, float* d_gparams, void* stream) {
   if (!h || !d_actions || !d_ckpt || !d_gstate || !d_gactions || !d_gparams) return QS_ERR_NULL;
   if (n_calls < 0 || n_substeps < 0 || ckpt_every < 1) return QS_ERR_INVALID;
+  if (h->c.flags & qs::F_DOWNWASH) return QS_ERR_UNSUPPORTED;
   if (d_gpenalty && !(beta > 0.f && std::isfinite(beta))) return QS_ERR_INVALID;
   if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_ckpt, 4) ||
       !aligned(d_gstate, 4) || !aligned(d_gparams, 4) || (d_gpenalty && !aligned(d_gpenalty, 4)))
@@ -857,6 +871,7 @@ int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actio
       !d_gparams)
     return QS_ERR_NULL;
   if (n_substeps < 0) return QS_ERR_INVALID;
+  if (h->c.flags & qs::F_DOWNWASH) return QS_ERR_UNSUPPORTED;
   if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_state_in, 4) ||
       !aligned(d_gstate_out, 4) || !aligned(d_gstate_in, 4) || !aligned(d_gparams, 4))
     return QS_ERR_ALIGN;

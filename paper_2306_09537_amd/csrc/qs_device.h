@@ -11,7 +11,8 @@
 namespace qs {
 
 enum : uint32_t {
-  F_ROOM = 1u, F_FLOOR = 2u, F_COLLIDE = 4u, F_NOISE = 8u, F_APPROACH = 16u, F_ACT_UNIT = 32u
+  F_ROOM = 1u, F_FLOOR = 2u, F_COLLIDE = 4u, F_NOISE = 8u, F_APPROACH = 16u, F_ACT_UNIT = 32u,
+  F_DOWNWASH = 64u
 };
 enum : int { NSTATE = 27, NPARAM = 8 };
 // SoA field index of the private state: x3 v3 R9 (row-major) w3 u4 eps4 floor
@@ -19,7 +20,7 @@ enum : int { S_X = 0, S_V = 3, S_R = 6, S_W = 15, S_U = 18, S_E = 22, S_F = 26 }
 // SoA field index of the per-quad parameters (the forward reads the first six)
 enum : int { P_M = 0, P_JX = 1, P_JY = 2, P_JZ = 3, P_FMAX = 4, P_ALAG = 5, P_T2W = 6, P_TAU = 7 };
 // noise streams: fourth Philox counter word = stream << 8 | draw
-enum : uint32_t { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2 };
+enum : uint32_t { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2, STREAM_DOWNWASH = 3 };
 enum : int { ERRBIT_STATE = 1, ERRBIT_ACTION = 2 };
 
 struct Consts {
@@ -31,6 +32,8 @@ struct Consts {
   uint32_t key0, key1;
   int32_t K;
   int32_t obs_dim;
+  // downwash: -k1 (k2 dz + b1) e_z within |dxy|^2 < dw_r2, 0 < dz < dw_h
+  float dw_k1, dw_k2, dw_b1, dw_r2, dw_h, dw_na, dw_nw;
 };
 
 struct Ptrs {
@@ -410,5 +413,80 @@ __device__ __forceinline__ void pair_normal(const float (*tile)[BS], const Quad&
 
 __device__ __forceinline__ float softplusf(float x) { return x > 20.f ? x : log1pf(expf(x)); }
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// In-swarm pass of one live lane after the tile (start positions,
+// displacements, velocities) is written and the workgroup synchronised:
+// §III-B.1 contact detection and Jacobi velocity exchange (every response
+// from the pre-response velocities), the smoothed collision penalty (PEN),
+// and §III-B.4 downwash from the swarm-mates above, applied as a velocity
+// kick after the response.  N > 0 unrolls over the swarm slot; padding
+// partners hold far-away sentinels.  Returns the contact mask.
+template <int BS, int N, bool PEN>
+__device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const float (*tile)[BS],
+                                                        Quad& s, int ls, int n, int me,
+                                                        uint32_t q, unsigned long long t,
+                                                        float& pacc, float beta) {
+  const bool collide = (c.flags & F_COLLIDE) != 0;
+  const bool dw = (c.flags & F_DOWNWASH) != 0 && s.fl == 0.0f;
+  unsigned long long cmask = 0ull;
+  float dv[3] = {0.f, 0.f, 0.f};
+  float adw = 0.f;
+  bool hit = false, dwhit = false;
+  auto pair = [&](int jj) {
+    const int j = ls + jj;
+    float dx, dy, dz, d2;
+    const bool con = pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2);
+    if constexpr (PEN) {
+      if (jj != me) pacc += 0.5f * softplusf(beta * (c.dcol - sqrtf(d2))) / beta;
+    }
+    if (collide && con) {
+      cmask |= 1ull << jj;
+      float nn[3], sp;
+      pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+      if (!(c.flags & F_APPROACH) || sp > 0.f) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dv[k] = fmaf(sp, nn[k], dv[k]);
+        hit = true;
+      }
+    }
+    // downwash: swarm-mate j above (z_j - z_i = -dz) and overlapping in xy
+    if (dw && jj != me && dx * dx + dy * dy < c.dw_r2 && -dz > 0.f && -dz < c.dw_h) {
+      adw -= c.dw_k1 * (c.dw_k2 * -dz + c.dw_b1);
+      dwhit = true;
+    }
+  };
+  if constexpr (N > 0) {
+#pragma unroll
+    for (int jj = 0; jj < N; ++jj) pair(jj);
+  } else {
+    for (int jj = 0; jj < n; ++jj) pair(jj);
+  }
+  if (hit) {
+    float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
+      normal4(c, q, t, STREAM_PAIR, 0, zv);
+      normal4(c, q, t, STREAM_PAIR, 1, zw);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.v[k] = c.col_decay * (s.v[k] + dv[k] + c.col_nv * zv[k]);
+      s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
+    }
+  }
+  if (dwhit) {
+    float za[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c.dw_na > 0.0f || c.dw_nw > 0.0f) {
+      normal4(c, q, t, STREAM_DOWNWASH, 0, za);
+      normal4(c, q, t, STREAM_DOWNWASH, 1, zw);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float a = (k == 2 ? adw : 0.f) + c.dw_na * za[k];
+      s.v[k] = fmaf(c.dt, a, s.v[k]);
+      s.w[k] = fmaf(c.dt, c.dw_nw * zw[k], s.w[k]);
+    }
+  }
+  return cmask;
+}
 
 }  // namespace qs

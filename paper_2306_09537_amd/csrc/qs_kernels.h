@@ -117,7 +117,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
     }
   }
 
-  const bool collide = N != 1 && (c.flags & F_COLLIDE) != 0;
+  const bool collide = N != 1 && (c.flags & (F_COLLIDE | F_DOWNWASH)) != 0;
   unsigned long long cmask = 0ull;
   for (int sub = 0; sub < nsub; ++sub) {
     const unsigned long long t = t0 + (unsigned long long)sub;
@@ -145,41 +145,8 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       __syncthreads();
       cmask = 0ull;
       if (live) {
-        float dvx = 0.f, dvy = 0.f, dvz = 0.f;
-        bool hit = false;
-        auto pair = [&](int jj) {
-          const int j = ls + jj;
-          float dx, dy, dz, d2;
-          if (pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2)) {
-            cmask |= 1ull << jj;
-            float nn[3], sp;
-            pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
-            if (!(c.flags & F_APPROACH) || sp > 0.f) {
-              dvx = fmaf(sp, nn[0], dvx);
-              dvy = fmaf(sp, nn[1], dvy);
-              dvz = fmaf(sp, nn[2], dvz);
-              hit = true;
-            }
-          }
-        };
-        if constexpr (N > 0) {
-#pragma unroll
-          for (int jj = 0; jj < N; ++jj) pair(jj);
-        } else {
-          for (int jj = 0; jj < n; ++jj) pair(jj);
-        }
-        if (hit) {
-          float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
-          if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
-            normal4(c, (uint32_t)q, t, STREAM_PAIR, 0, zv);
-            normal4(c, (uint32_t)q, t, STREAM_PAIR, 1, zw);
-          }
-          s.v[0] = c.col_decay * (s.v[0] + dvx + c.col_nv * zv[0]);
-          s.v[1] = c.col_decay * (s.v[1] + dvy + c.col_nv * zv[1]);
-          s.v[2] = c.col_decay * (s.v[2] + dvz + c.col_nv * zv[2]);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
-        }
+        float unused = 0.f;
+        cmask = pair_pass<BS, N, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
       }
     }
   }

@@ -134,8 +134,7 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Consts c, Ptrs p,
     load_state(p.st, p.Qp, q, s);
     load_params(p, c, q, pp, pa);
   }
-  const bool collide = (c.flags & F_COLLIDE) != 0;
-  const bool pairs = N != 1 && (collide || PEN);
+  const bool pairs = N != 1 && ((c.flags & (F_COLLIDE | F_DOWNWASH)) != 0 || PEN);
   float pacc = 0.f;
   int sidx = 0;
   for (int call = 0; call < ncalls; ++call) {
@@ -158,45 +157,7 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Consts c, Ptrs p,
           }
         }
         __syncthreads();
-        if (live) {
-          float dv[3] = {0.f, 0.f, 0.f};
-          bool hit = false;
-          auto pair = [&](int jj) {
-            const int j = ls + jj;
-            float dx, dy, dz, d2;
-            const bool con = pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2);
-            if constexpr (PEN) {
-              if (jj != me) pacc += 0.5f * softplusf(beta * (c.dcol - sqrtf(d2))) / beta;
-            }
-            if (collide && con) {
-              float nn[3], sp;
-              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
-              if (!(c.flags & F_APPROACH) || sp > 0.f) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) dv[k] = fmaf(sp, nn[k], dv[k]);
-                hit = true;
-              }
-            }
-          };
-          if constexpr (N > 0) {
-#pragma unroll
-            for (int jj = 0; jj < N; ++jj) pair(jj);
-          } else {
-            for (int jj = 0; jj < n; ++jj) pair(jj);
-          }
-          if (hit) {
-            float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
-            if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
-              normal4(c, (uint32_t)q, t, STREAM_PAIR, 0, zv);
-              normal4(c, (uint32_t)q, t, STREAM_PAIR, 1, zw);
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              s.v[k] = c.col_decay * (s.v[k] + dv[k] + c.col_nv * zv[k]);
-              s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
-            }
-          }
-        }
+        if (live) pair_pass<BS, N, PEN>(c, tile, s, ls, n, me, (uint32_t)q, t, pacc, beta);
       }
     }
   }
@@ -277,41 +238,8 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(Consts c, Ptrs p,
           }
         }
         __syncthreads();
-        if (live) {
-          float dv[3] = {0.f, 0.f, 0.f};
-          bool hit = false;
-          auto pair = [&](int jj) {
-            const int j = ls + jj;
-            float dx, dy, dz, d2;
-            if (pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2)) {
-              float nn[3], sp;
-              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
-              if (!(c.flags & F_APPROACH) || sp > 0.f) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) dv[k] = fmaf(sp, nn[k], dv[k]);
-                hit = true;
-              }
-            }
-          };
-          if constexpr (N > 0) {
-#pragma unroll
-            for (int jj = 0; jj < N; ++jj) pair(jj);
-          } else {
-            for (int jj = 0; jj < n; ++jj) pair(jj);
-          }
-          if (hit) {
-            float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
-            if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
-              normal4(c, (uint32_t)q, t, STREAM_PAIR, 0, zv);
-              normal4(c, (uint32_t)q, t, STREAM_PAIR, 1, zw);
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              s.v[k] = c.col_decay * (s.v[k] + dv[k] + c.col_nv * zv[k]);
-              s.w[k] = fmaf(c.col_nw, zw[k], s.w[k]);
-            }
-          }
-        }
+        float unused = 0.f;
+        if (live) pair_pass<BS, N, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
       }
     }
   }

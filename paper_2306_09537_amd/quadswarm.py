@@ -47,6 +47,9 @@ class qs_desc(C.Structure):
         ("col_dist", C.c_float), ("col_decay", C.c_float),
         ("col_noise_v", C.c_float), ("col_noise_w", C.c_float),
         ("k_neighbors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64),
+        ("dw_k1", C.c_float), ("dw_k2", C.c_float), ("dw_b1", C.c_float),
+        ("dw_radius", C.c_float), ("dw_height", C.c_float),
+        ("dw_noise_a", C.c_float), ("dw_noise_w", C.c_float),
     ]
 
 
@@ -109,6 +112,8 @@ def make_desc(env_offsets: np.ndarray, consts: dict, k_neighbors: int, flags: in
     d.k_neighbors = int(k_neighbors)
     d.flags = int(flags)
     d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    for k in ("dw_k1", "dw_k2", "dw_b1", "dw_radius", "dw_height", "dw_noise_a", "dw_noise_w"):
+        setattr(d, k, float(consts.get(k, 0.0)))
     return d
 
 

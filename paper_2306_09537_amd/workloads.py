@@ -38,6 +38,7 @@ QS_COLLIDE = 4         # in-env pairwise collision detection and response
 QS_MOTOR_NOISE = 8     # AR(1) motor-noise process
 QS_APPROACH_ONLY = 16  # pair response only while the pair is approaching
 QS_ACT_UNIT = 32       # action read as normalised thrust in [0,1] (else [-1,1])
+QS_DOWNWASH = 64       # downwash of upper quads on lower ones (§III-B.4)
 
 STATE_DIM = 27         # x3 v3 R9 (row-major) w3 u4 eps4 floor1
 PARAM_DIM = 6          # mass, ixx, iyy, izz, thrust_to_weight, motor_tau
@@ -60,6 +61,10 @@ BASE_CONSTS = dict(
     room_min=(-5.0, -5.0, 0.0), room_max=(5.0, 5.0, 10.0),
     wall_restitution=1.0, col_dist=0.1, col_decay=1.0,
     col_noise_v=0.0, col_noise_w=0.0,
+    # downwash: -k1 (k2 dz + b1) e_z, i.e. 2 m/s^2 decaying linearly to zero
+    # at 0.5 m of vertical separation, within 0.1 m of horizontal offset
+    dw_k1=2.0, dw_k2=-2.0, dw_b1=1.0, dw_radius=0.1, dw_height=0.5,
+    dw_noise_a=0.0, dw_noise_w=0.0,
 )
 
 SWARM_FLAGS = QS_ROOM | QS_FLOOR | QS_COLLIDE | QS_MOTOR_NOISE | QS_APPROACH_ONLY

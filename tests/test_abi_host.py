@@ -37,6 +37,7 @@ def test_header_constants_match_interface():
     assert val["QS_MOTOR_NOISE"] == W.QS_MOTOR_NOISE
     assert val["QS_APPROACH_ONLY"] == W.QS_APPROACH_ONLY
     assert val["QS_ACT_UNIT"] == W.QS_ACT_UNIT
+    assert val["QS_DOWNWASH"] == W.QS_DOWNWASH == O.flag_values()[6]
     assert val["QS_STATE_DIM"] == W.STATE_DIM and val["QS_PARAM_DIM"] == W.PARAM_DIM
     for code, name in QS.ERRORS.items():
         assert val[name] == code
@@ -104,7 +105,10 @@ def test_create_rejects_bad_arguments_before_any_hip_call():
     assert _create(w, consts=c)[0] == -2
     assert _create(w, k=-1)[0] == -2
     assert _create(w, k=64)[0] == -2
-    assert _create(w, flags=64)[0] == -2
+    assert _create(w, flags=128)[0] == -2
+    c = dict(w.consts)
+    c["dw_radius"] = -1.0
+    assert _create(w, consts=c)[0] == -2
     p = w.params.copy()
     p[3, 0] = 0.0
     assert _create(w, params=p)[0] == -2

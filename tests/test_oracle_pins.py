@@ -556,7 +556,68 @@ def test_multi_substep_call_equals_single_calls():
 
 def test_flag_values_agree_with_interface():
     assert O.flag_values() == [W.QS_ROOM, W.QS_FLOOR, W.QS_COLLIDE, W.QS_MOTOR_NOISE,
-                               W.QS_APPROACH_ONLY, W.QS_ACT_UNIT]
+                               W.QS_APPROACH_ONLY, W.QS_ACT_UNIT, W.QS_DOWNWASH]
+
+
+# ---------------------------------------------------------------- downwash
+def _stack(offsets_xyz, v=None):
+    n = len(offsets_xyz)
+    s = blank_state(n, z=0.0)
+    s[:, 0:3] = np.array(offsets_xyz) + [0.0, 0.0, 5.0]
+    if v is not None:
+        s[:, W.SV:W.SV + 3] = v
+    s[:, W.SU:W.SU + 4] = 0.0
+    return s
+
+
+def test_downwash_closed_form_on_the_lower_quad():
+    """Quad 1 sits dz above quad 0 inside the window: after one substep the
+    lower quad's v_z differs from the run without downwash by exactly
+    -dt k1 (k2 dz1 + b1), dz1 the separation after the motion; the upper
+    quad is untouched."""
+    dz = 0.3
+    s = _stack([[0, 0, 0], [0.02, -0.03, dz]], v=[[0.1, 0, 0.2], [0.1, 0, 0.2]])
+    a = -np.ones((2, 4))
+    on, _, ev = make(2, flags=W.QS_DOWNWASH, env_sizes=[2]).step(s, a, 1, 0)
+    off, _, _ = make(2, flags=0, env_sizes=[2]).step(s, a, 1, 0)
+    k1, k2, b1 = 2.0, -2.0, 1.0
+    dz1 = off[1, 2] - off[0, 2]
+    assert on[0, W.SV + 2] - off[0, W.SV + 2] == pytest.approx(-DT * k1 * (k2 * dz1 + b1), rel=1e-12)
+    assert np.array_equal(on[1], off[1]) and np.array_equal(on[0, 0:3], off[0, 0:3])
+    assert ev[0] & O.EV_DOWNWASH and not ev[1] & O.EV_DOWNWASH
+
+
+def test_downwash_zero_outside_the_window():
+    a = -np.ones((2, 4))
+    for pos in ([[0, 0, 0], [0.15, 0, 0.2]],   # no xy overlap
+                [[0, 0, 0], [0, 0, 0.6]],      # too far above
+                [[0, 0, 0.2], [0, 0, 0]]):     # quad 1 is below: quad 1 is the one affected
+        s = _stack(pos)
+        on, _, _ = make(2, flags=W.QS_DOWNWASH, env_sizes=[2]).step(s, a, 1, 0)
+        off, _, _ = make(2, flags=0, env_sizes=[2]).step(s, a, 1, 0)
+        if pos[0][2] > pos[1][2]:
+            assert np.array_equal(on[0], off[0]) and not np.array_equal(on[1], off[1])
+        else:
+            assert np.array_equal(on, off)
+
+
+def test_downwash_sums_over_upper_quads_and_spares_resting_quads():
+    a = -np.ones((3, 4))
+    s = _stack([[0, 0, 0], [0, 0.01, 0.1], [0.01, 0, 0.25]])
+    on, _, _ = make(3, flags=W.QS_DOWNWASH, env_sizes=[3]).step(s, a, 1, 0)
+    off, _, _ = make(3, flags=0, env_sizes=[3]).step(s, a, 1, 0)
+    z = off[:, 2]
+    expect0 = -DT * 2.0 * ((-2.0 * (z[1] - z[0]) + 1.0) + (-2.0 * (z[2] - z[0]) + 1.0))
+    expect1 = -DT * 2.0 * (-2.0 * (z[2] - z[1]) + 1.0)
+    assert on[0, W.SV + 2] - off[0, W.SV + 2] == pytest.approx(expect0, rel=1e-12)
+    assert on[1, W.SV + 2] - off[1, W.SV + 2] == pytest.approx(expect1, rel=1e-12)
+    assert np.array_equal(on[2], off[2])
+    # a quad resting on the floor feels no downwash
+    r = _stack([[0, 0, -5.0], [0, 0, -4.8]])
+    r[0, W.SF] = 1.0
+    on, _, _ = make(2, flags=W.QS_DOWNWASH | W.QS_FLOOR, env_sizes=[2]).step(r, a[:2], 1, 0)
+    off, _, _ = make(2, flags=W.QS_FLOOR, env_sizes=[2]).step(r, a[:2], 1, 0)
+    assert np.array_equal(on, off)
 
 
 def test_rejects_bad_arguments():
