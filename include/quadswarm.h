@@ -68,6 +68,7 @@ extern "C" {
 #define QS_APPROACH_ONLY 16u  /* pair response only while the pair approaches */
 #define QS_ACT_UNIT 32u       /* f_hat = clip(a,0,1) instead of (clip(a,-1,1)+1)/2 */
 #define QS_DOWNWASH 64u       /* §III-B.4 downwash of upper swarm-mates on lower ones */
+#define QS_SENSOR_NOISE 128u  /* §III-C noise on the own-state part of observations */
 
 #define QS_STATE_DIM 27
 #define QS_PARAM_DIM 6
@@ -103,6 +104,12 @@ typedef struct qs_handle qs_handle;
  *                   (m/s^2), and N(0, dw_noise_w^2) angular acceleration
  *                   (rad/s^2), as a kick of dt times them after the pair
  *                   response.  Not differentiated.
+ *  sn_x, sn_v, sn_w sensor noise (QS_SENSOR_NOISE), all >= 0: each
+ *                   observation row gets U(-sn_x, sn_x) added to every
+ *                   component of x - goal (m), U(-sn_v, sn_v) to v (m/s) and
+ *                   N(0, sn_w^2) to omega (rad/s), drawn at the substep index
+ *                   of the observed state; R and the neighbour slots are
+ *                   exact.
  */
 typedef struct {
   int32_t n_envs;
@@ -115,6 +122,7 @@ typedef struct {
   uint32_t flags;
   uint64_t seed;
   float dw_k1, dw_k2, dw_b1, dw_radius, dw_height, dw_noise_a, dw_noise_w;
+  float sn_x, sn_v, sn_w;
 } qs_desc;
 
 /* Per-quad domain-randomised physical parameters (§I, §III-A). */
@@ -161,6 +169,33 @@ int qs_observe(qs_handle* h, const float* d_goals, float* d_obs, void* stream);
  */
 int qs_step_observe(qs_handle* h, const float* d_actions, int32_t n_substeps,
                     const float* d_goals, float* d_obs, void* stream);
+
+/*
+ * §III-E reward weights of the handle, h_w[15] (host): alpha_pos, alpha_vel,
+ * alpha_ori, alpha_spin, alpha_act, alpha_dact, alpha_rot, alpha_yaw,
+ * alpha_floor_hit, alpha_on_floor, alpha_wall, alpha_ceiling, alpha_quad,
+ * alpha_prox, d_prox.  All finite, d_prox > 0 (QS_ERR_INVALID otherwise).
+ * Applies to calls enqueued after it.  A new handle has all weights 0 and
+ * d_prox = 1.
+ */
+int qs_set_reward_weights(qs_handle* h, const float* h_w);
+
+/*
+ * qs_step_observe that also writes each quad's reward of the call into
+ * d_reward [Q] (n_substeps >= 1):
+ *   r = a_pos |x - goal| + a_vel |v| + a_ori R22 + a_spin |omega|
+ *     + a_act |f| + a_dact |f - f_prev| + a_rot (tr R - 1)/2 + a_yaw R00
+ *     + a_floor_hit [hit the floor] + a_on_floor [resting at the end]
+ *     + a_wall [bounced off a wall] + a_ceiling [bounced off the ceiling]
+ *     + a_quad [received a collision response]
+ *     + a_prox sum over the K neighbour slots of max(1 - |x_j - x_i| / d_prox, 0)
+ * with x, v, R, omega the state after the call, f = f_max u_f^2 + eps the
+ * rotor thrusts after (f) and before (f_prev) the call, and each [event]
+ * 1 if it happened at any substep of the call.  The reward reads the exact
+ * (noise-free) observation; QS_SENSOR_NOISE noise goes into d_obs only.
+ */
+int qs_step_observe_reward(qs_handle* h, const float* d_actions, int32_t n_substeps,
+                           const float* d_goals, float* d_obs, float* d_reward, void* stream);
 
 /*
  * Copy the state into d_state [Q][27] (canonical layout) and return the

@@ -21,7 +21,7 @@ SRC = os.path.join(HERE, "quadswarm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 EV_WALL, EV_FLOOR_HIT, EV_FRICTION, EV_TAKEOFF, EV_PAIR_RESPONSE, EV_CONTACT = 1, 2, 4, 8, 16, 32
-EV_DOWNWASH = 64
+EV_DOWNWASH, EV_CEILING = 64, 128
 
 
 def build(force: bool = False) -> str:
@@ -51,6 +51,7 @@ class _Desc(C.Structure):
         ("dw_k1", C.c_double), ("dw_k2", C.c_double), ("dw_b1", C.c_double),
         ("dw_radius", C.c_double), ("dw_height", C.c_double),
         ("dw_noise_a", C.c_double), ("dw_noise_w", C.c_double),
+        ("sn_x", C.c_double), ("sn_v", C.c_double), ("sn_w", C.c_double),
     ]
 
 
@@ -101,7 +102,8 @@ class Oracle:
         d.flags = int(flags)
         d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         d.quad_id_offset = int(quad_id_offset)
-        for k in ("dw_k1", "dw_k2", "dw_b1", "dw_radius", "dw_height", "dw_noise_a", "dw_noise_w"):
+        for k in ("dw_k1", "dw_k2", "dw_b1", "dw_radius", "dw_height", "dw_noise_a", "dw_noise_w",
+                  "sn_x", "sn_v", "sn_w"):
             setattr(d, k, float(consts.get(k, 0.0)))
         self.desc = d
 
@@ -169,6 +171,29 @@ class Oracle:
             raise ValueError("or_rollout_vjp rejected its arguments")
         return g, gact, gpar
 
+    def observe_noise(self, obs, t: int):
+        """Sensor noise added to a copy of obs (as or_observe returns it)."""
+        o = np.array(obs, dtype=np.float64, order="C", copy=True)
+        if lib().or_observe_noise(C.byref(self.desc), _p(o, C.c_double), C.c_uint64(t)) != 0:
+            raise ValueError("or_observe_noise rejected its arguments")
+        return o
+
+    def reward(self, s0, s1, events, goals, obs, weights):
+        """Per-quad reward of one call (see or_reward)."""
+        a = np.ascontiguousarray(s0, dtype=np.float64)
+        b = np.ascontiguousarray(s1, dtype=np.float64)
+        ev = np.ascontiguousarray(events, dtype=np.uint32)
+        g = np.ascontiguousarray(goals, dtype=np.float64)
+        o = np.ascontiguousarray(obs, dtype=np.float64)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        assert w.shape == (15,)
+        r = np.zeros(self.Q)
+        if lib().or_reward(C.byref(self.desc), _p(self.params, C.c_double), _p(a, C.c_double),
+                           _p(b, C.c_double), _p(ev, C.c_uint32), _p(g, C.c_double),
+                           _p(o, C.c_double), _p(w, C.c_double), _p(r, C.c_double)) != 0:
+            raise ValueError("or_reward rejected its arguments")
+        return r
+
     def with_params(self, params) -> "Oracle":
         """Same environments and constants, other per-quad parameters."""
         o = Oracle.__new__(Oracle)
@@ -210,6 +235,6 @@ def uniform_from_u32(r: int) -> float:
 
 
 def flag_values():
-    o = (C.c_uint32 * 7)()
+    o = (C.c_uint32 * 8)()
     lib().or_flag_values(o)
     return [int(v) for v in o]

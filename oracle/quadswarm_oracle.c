@@ -69,6 +69,7 @@
 #define OR_APPROACH_ONLY 16u
 #define OR_ACT_UNIT 32u
 #define OR_DOWNWASH 64u
+#define OR_SENSOR_NOISE 128u
 
 /* canonical state row: x3 v3 R9 (row-major) w3 u4 eps4 floor1 */
 enum { IX = 0, IV = 3, IR = 6, IW = 15, IU = 18, IE = 22, IF = 26, NS = 27 };
@@ -76,12 +77,12 @@ enum { IX = 0, IV = 3, IR = 6, IW = 15, IU = 18, IE = 22, IF = 26, NS = 27 };
 enum { PM = 0, PJX = 1, PJY = 2, PJZ = 3, PT2W = 4, PTAU = 5, NP = 6 };
 
 /* noise streams (fourth counter word = stream << 8 | draw) */
-enum { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2, STREAM_DOWNWASH = 3 };
+enum { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2, STREAM_DOWNWASH = 3, STREAM_SENSOR = 4 };
 
 /* per-quad event bits reported by or_step (OR over the call's substeps) */
 enum {
   EV_WALL = 1, EV_FLOOR_HIT = 2, EV_FRICTION = 4, EV_TAKEOFF = 8,
-  EV_PAIR_RESPONSE = 16, EV_CONTACT = 32, EV_DOWNWASH = 64
+  EV_PAIR_RESPONSE = 16, EV_CONTACT = 32, EV_DOWNWASH = 64, EV_CEILING = 128
 };
 
 typedef struct {
@@ -98,6 +99,9 @@ typedef struct {
   /* downwash (§III-B.4): a = -k1 (k2 dz + b1) e_z on the lower quad of a pair
    * overlapping in xy (|dxy| < dw_radius) with 0 < dz < dw_height */
   double dw_k1, dw_k2, dw_b1, dw_radius, dw_height, dw_noise_a, dw_noise_w;
+  /* observation sensor noise (§III-C): half-widths of the uniform noise on
+   * x - goal and v, standard deviation of the Gaussian noise on omega */
+  double sn_x, sn_v, sn_w;
 } or_desc;
 
 /* ------------------------------------------------------------------------ */
@@ -363,7 +367,8 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     }
     r->bounced = bounced;
     if (bounced) {
-      *ev |= EV_WALL;
+      if (r->flip[0] || r->flip[1]) *ev |= EV_WALL;
+      if (r->flip[2]) *ev |= EV_CEILING;
       double zv[4] = {0, 0, 0, 0}, zw[4] = {0, 0, 0, 0};
       if (d->col_noise_v > 0.0 || d->col_noise_w > 0.0) {
         or_normal4(d->seed, q, t, STREAM_WALL, 0, zv);
@@ -1060,9 +1065,95 @@ int or_rollout_vjp(const or_desc* d, const double* params, const double* state0,
   return 0;
 }
 
-int or_flag_values(uint32_t out[7]) {
+
+/*
+ * §III-C sensor noise, added in place to obs[Q][18+6K] as produced by
+ * or_observe: uniform U(-sn_x, sn_x) on each component of x - goal,
+ * U(-sn_v, sn_v) on v, N(0, sn_w^2) on omega, from Philox stream SENSOR at
+ * substep index t (draw 0: position, 1: velocity, 2: body rate); the
+ * uniforms come from the same (2k+1) 2^-24 map as the Gaussian draws.
+ */
+int or_observe_noise(const or_desc* d, double* obs, uint64_t t) {
+  if (check_desc(d) || !obs) return -1;
+  const int Q = d->env_offsets[d->n_envs], OD = 18 + 6 * d->k_neighbors;
+  const uint32_t key[2] = {(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
+  for (int q = 0; q < Q; ++q) {
+    double* o = obs + (size_t)q * OD;
+    const uint32_t gq = d->quad_id_offset + (uint32_t)q;
+    for (int draw = 0; draw < 2; ++draw) {
+      uint32_t ctr[4] = {gq, (uint32_t)t, (uint32_t)(t >> 32), (STREAM_SENSOR << 8) | draw};
+      uint32_t r[4];
+      or_philox4x32_10(ctr, key, r);
+      const double a = draw == 0 ? d->sn_x : d->sn_v;
+      for (int k = 0; k < 3; ++k) o[3 * draw + k] += a * (2.0 * or_uniform_from_u32(r[k]) - 1.0);
+    }
+    double z[4];
+    or_normal4(d->seed, gq, t, STREAM_SENSOR, 2, z);
+    for (int k = 0; k < 3; ++k) o[15 + k] += d->sn_w * z[k];
+  }
+  return 0;
+}
+
+/*
+ * §III-E reward of one control call per quad.  w[15]: alpha_pos, _vel, _ori,
+ * _spin, _act, _dact, _rot, _yaw, _floor_hit, _on_floor, _wall, _ceiling,
+ * _quad, _prox, d_prox.  s0/s1: state before/after the call; ev: the call's
+ * event bits (or_step); obs: the noise-free observation after the call
+ * (its neighbour slots give the proximity term).
+ *   r = a_pos |x - goal| + a_vel |v| + a_ori R22 + a_spin |w| + a_act |f|
+ *     + a_dact |f - f_prev| + a_rot (tr R - 1)/2 + a_yaw R00
+ *     + a_floor_hit [hit floor] + a_on_floor [resting] + a_wall [wall bounce]
+ *     + a_ceiling [ceiling bounce] + a_quad [collision response]
+ *     + a_prox sum_k max(1 - |x~_k| / d_prox, 0) over the K neighbour slots
+ * with f = f_max u_f^2 + eps the rotor thrusts after (f) and before (f_prev)
+ * the call.
+ */
+int or_reward(const or_desc* d, const double* params, const double* s0, const double* s1,
+              const uint32_t* ev, const double* goals, const double* obs, const double* w,
+              double* reward) {
+  if (check_desc(d) || !params || !s0 || !s1 || !ev || !goals || !obs || !w || !reward) return -1;
+  const int Q = d->env_offsets[d->n_envs], K = d->k_neighbors, OD = 18 + 6 * K;
+  for (int q = 0; q < Q; ++q) {
+    const double* a = s0 + (size_t)q * NS;
+    const double* b = s1 + (size_t)q * NS;
+    const double f_max = 0.25 * params[(size_t)q * NP + PM] * d->gravity * params[(size_t)q * NP + PT2W];
+    double dx2 = 0, v2 = 0, w2 = 0, f2 = 0, df2 = 0;
+    for (int k = 0; k < 3; ++k) {
+      const double e = b[IX + k] - goals[(size_t)q * 3 + k];
+      dx2 += e * e;
+      v2 += b[IV + k] * b[IV + k];
+      w2 += b[IW + k] * b[IW + k];
+    }
+    for (int i = 0; i < 4; ++i) {
+      const double f1 = f_max * b[IU + i] * b[IU + i] + b[IE + i];
+      const double f0 = f_max * a[IU + i] * a[IU + i] + a[IE + i];
+      f2 += f1 * f1;
+      df2 += (f1 - f0) * (f1 - f0);
+    }
+    double r = w[0] * sqrt(dx2) + w[1] * sqrt(v2) + w[2] * b[IR + 8] + w[3] * sqrt(w2) +
+               w[4] * sqrt(f2) + w[5] * sqrt(df2) +
+               w[6] * (b[IR + 0] + b[IR + 4] + b[IR + 8] - 1.0) / 2.0 + w[7] * b[IR + 0];
+    r += w[8] * ((ev[q] & EV_FLOOR_HIT) ? 1.0 : 0.0) + w[9] * (b[IF] != 0.0 ? 1.0 : 0.0) +
+         w[10] * ((ev[q] & EV_WALL) ? 1.0 : 0.0) + w[11] * ((ev[q] & EV_CEILING) ? 1.0 : 0.0) +
+         w[12] * ((ev[q] & EV_PAIR_RESPONSE) ? 1.0 : 0.0);
+    const double* o = obs + (size_t)q * OD;
+    for (int k = 0; k < K; ++k) {
+      const double* x = o + 18 + 6 * k;
+      const double dd = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      /* zero-padded slots (absent neighbours) contribute nothing */
+      if (x[0] == 0.0 && x[1] == 0.0 && x[2] == 0.0 && x[3] == 0.0 && x[4] == 0.0 && x[5] == 0.0)
+        continue;
+      const double h = 1.0 - dd / w[14];
+      r += w[13] * (h > 0.0 ? h : 0.0);
+    }
+    reward[q] = r;
+  }
+  return 0;
+}
+
+int or_flag_values(uint32_t out[8]) {
   out[0] = OR_ROOM; out[1] = OR_FLOOR; out[2] = OR_COLLIDE;
   out[3] = OR_MOTOR_NOISE; out[4] = OR_APPROACH_ONLY; out[5] = OR_ACT_UNIT;
-  out[6] = OR_DOWNWASH;
+  out[6] = OR_DOWNWASH; out[7] = OR_SENSOR_NOISE;
   return 0;
 }

@@ -85,12 +85,15 @@ int check_desc(const qs_desc* d) {
       d->col_noise_v < 0.f || d->col_noise_w < 0.f)
     return QS_ERR_INVALID;
   if (d->k_neighbors < 0 || d->k_neighbors >= QS_MAX_SWARM) return QS_ERR_INVALID;
-  if (d->flags & ~127u) return QS_ERR_INVALID;
+  if (d->flags & ~255u) return QS_ERR_INVALID;
   const float dwv[] = {d->dw_k1, d->dw_k2, d->dw_b1, d->dw_radius, d->dw_height, d->dw_noise_a,
                        d->dw_noise_w};
   for (float v : dwv)
     if (!finite(v)) return QS_ERR_INVALID;
   if (d->dw_radius < 0.f || d->dw_height < 0.f || d->dw_noise_a < 0.f || d->dw_noise_w < 0.f)
+    return QS_ERR_INVALID;
+  if (!(d->sn_x >= 0.f && d->sn_v >= 0.f && d->sn_w >= 0.f && finite(d->sn_x) &&
+        finite(d->sn_v) && finite(d->sn_w)))
     return QS_ERR_INVALID;
   return QS_OK;
 }
@@ -222,7 +225,7 @@ int build_items(qs_handle* h, int bs) {
 // staging area and the pair tile fit in 64 KiB per workgroup.
 template <int BS, int KT, int N>
 void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
-        hipStream_t s) {
+        hipStream_t s, float* rw) {
   size_t dyn = 0;
   int stage = 0;
   if constexpr (KT >= 0) {
@@ -234,76 +237,76 @@ void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs
   }
   hipLaunchKernelGGL((qs::step_kernel<BS, KT, N>), dim3(h->nblk), dim3(BS), dyn, s, h->c,
                      ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, stage,
-                     h->graph_mode ? h->d_t : nullptr, h->d_done);
+                     h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
 }
 
 template <int BS, int KT>
 void go_items(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
-              hipStream_t s) {
+              hipStream_t s, float* rw) {
   const int grid = h->item_grid > 0 ? std::min(h->item_grid, h->n_items) : h->n_items;
   hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), 0, s, h->c,
                      ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, h->n_items,
-                     h->graph_mode ? h->d_t : nullptr, h->d_done);
+                     h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
 }
 
 template <int BS>
 void launch_items(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
-                  bool with_obs, hipStream_t s) {
+                  bool with_obs, hipStream_t s, float* rw) {
   if (!with_obs)
-    go_items<BS, -2>(h, act, nsub, goals, obs, s);
+    go_items<BS, -2>(h, act, nsub, goals, obs, s, rw);
   else if (h->K == 6)
-    go_items<BS, 6>(h, act, nsub, goals, obs, s);
+    go_items<BS, 6>(h, act, nsub, goals, obs, s, rw);
   else if (h->K == 0)
-    go_items<BS, 0>(h, act, nsub, goals, obs, s);
+    go_items<BS, 0>(h, act, nsub, goals, obs, s, rw);
   else
-    go_items<BS, -1>(h, act, nsub, goals, obs, s);
+    go_items<BS, -1>(h, act, nsub, goals, obs, s, rw);
 }
 
 template <int BS, int KT>
 void go_n(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
-          hipStream_t s) {
+          hipStream_t s, float* rw) {
   switch (h->uniform_n) {
-    case 1: go<BS, KT, 1>(h, act, nsub, goals, obs, s); break;
-    case 2: go<BS, KT, 2>(h, act, nsub, goals, obs, s); break;
-    case 4: go<BS, KT, 4>(h, act, nsub, goals, obs, s); break;
-    case 8: go<BS, KT, 8>(h, act, nsub, goals, obs, s); break;
-    case 16: go<BS, KT, 16>(h, act, nsub, goals, obs, s); break;
-    case 32: go<BS, KT, 32>(h, act, nsub, goals, obs, s); break;
-    case 64: go<BS, KT, 64>(h, act, nsub, goals, obs, s); break;
-    default: go<BS, KT, 0>(h, act, nsub, goals, obs, s); break;
+    case 1: go<BS, KT, 1>(h, act, nsub, goals, obs, s, rw); break;
+    case 2: go<BS, KT, 2>(h, act, nsub, goals, obs, s, rw); break;
+    case 4: go<BS, KT, 4>(h, act, nsub, goals, obs, s, rw); break;
+    case 8: go<BS, KT, 8>(h, act, nsub, goals, obs, s, rw); break;
+    case 16: go<BS, KT, 16>(h, act, nsub, goals, obs, s, rw); break;
+    case 32: go<BS, KT, 32>(h, act, nsub, goals, obs, s, rw); break;
+    case 64: go<BS, KT, 64>(h, act, nsub, goals, obs, s, rw); break;
+    default: go<BS, KT, 0>(h, act, nsub, goals, obs, s, rw); break;
   }
 }
 
 template <int BS>
 int launch_bs(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
-              bool with_obs, hipStream_t s) {
+              bool with_obs, hipStream_t s, float* rw) {
   if (!with_obs)
-    go_n<BS, -2>(h, act, nsub, goals, obs, s);
+    go_n<BS, -2>(h, act, nsub, goals, obs, s, rw);
   else if (h->K == 6)
-    go_n<BS, 6>(h, act, nsub, goals, obs, s);
+    go_n<BS, 6>(h, act, nsub, goals, obs, s, rw);
   else if (h->K == 0 && h->uniform_n == 1)
-    go<BS, 0, 1>(h, act, nsub, goals, obs, s);
+    go<BS, 0, 1>(h, act, nsub, goals, obs, s, rw);
   else if (h->K == 0)
-    go<BS, 0, 0>(h, act, nsub, goals, obs, s);
+    go<BS, 0, 0>(h, act, nsub, goals, obs, s, rw);
   else
-    go<BS, -1, 0>(h, act, nsub, goals, obs, s);
+    go<BS, -1, 0>(h, act, nsub, goals, obs, s, rw);
   return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
 }
 
 int launch(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
-           bool with_obs, hipStream_t s) {
+           bool with_obs, hipStream_t s, float* rw = nullptr) {
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
   int rc;
   if (h->bucketed) {
     if (h->item_bs == 128)
-      launch_items<128>(h, act, nsub, goals, obs, with_obs, s);
+      launch_items<128>(h, act, nsub, goals, obs, with_obs, s, rw);
     else
-      launch_items<64>(h, act, nsub, goals, obs, with_obs, s);
+      launch_items<64>(h, act, nsub, goals, obs, with_obs, s, rw);
     rc = hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
   } else {
     switch (h->bs) {
-      case 128: rc = launch_bs<128>(h, act, nsub, goals, obs, with_obs, s); break;
-      default: rc = launch_bs<64>(h, act, nsub, goals, obs, with_obs, s); break;
+      case 128: rc = launch_bs<128>(h, act, nsub, goals, obs, with_obs, s, rw); break;
+      default: rc = launch_bs<64>(h, act, nsub, goals, obs, with_obs, s, rw); break;
     }
   }
   if (rc == QS_OK) h->t += (uint64_t)nsub;
@@ -485,6 +488,11 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   c.dw_h = desc->dw_height;
   c.dw_na = desc->dw_noise_a;
   c.dw_nw = desc->dw_noise_w;
+  c.sn_x = desc->sn_x;
+  c.sn_v = desc->sn_v;
+  c.sn_w = desc->sn_w;
+  for (int k = 0; k < 15; ++k) c.rw[k] = 0.f;
+  c.rw[14] = 1.f;
 
   // environment -> workgroup partition (environments are never split)
   h->env_start.resize(E);
@@ -749,6 +757,25 @@ int qs_step_observe(qs_handle* h, const float* d_actions, int32_t n_substeps,
   if (n_substeps < 0) return QS_ERR_INVALID;
   if (!aligned(d_actions, 16) || !aligned(d_goals, 4) || !aligned(d_obs, 8)) return QS_ERR_ALIGN;
   return launch(h, d_actions, n_substeps, d_goals, d_obs, true, (hipStream_t)stream);
+}
+
+int qs_set_reward_weights(qs_handle* h, const float* h_w) {
+  if (!h || !h_w) return QS_ERR_NULL;
+  for (int k = 0; k < 15; ++k)
+    if (!finite(h_w[k])) return QS_ERR_INVALID;
+  if (!(h_w[14] > 0.f)) return QS_ERR_INVALID;
+  for (int k = 0; k < 15; ++k) h->c.rw[k] = h_w[k];
+  return QS_OK;
+}
+
+int qs_step_observe_reward(qs_handle* h, const float* d_actions, int32_t n_substeps,
+                           const float* d_goals, float* d_obs, float* d_reward, void* stream) {
+  if (!h || !d_actions || !d_goals || !d_obs || !d_reward) return QS_ERR_NULL;
+  if (n_substeps < 1) return QS_ERR_INVALID;
+  if (!aligned(d_actions, 16) || !aligned(d_goals, 4) || !aligned(d_obs, 8) ||
+      !aligned(d_reward, 4))
+    return QS_ERR_ALIGN;
+  return launch(h, d_actions, n_substeps, d_goals, d_obs, true, (hipStream_t)stream, d_reward);
 }
 
 int qs_get_state(qs_handle* h, float* d_state, uint64_t* substep_index, void* stream) {

@@ -12,7 +12,7 @@ namespace qs {
 
 enum : uint32_t {
   F_ROOM = 1u, F_FLOOR = 2u, F_COLLIDE = 4u, F_NOISE = 8u, F_APPROACH = 16u, F_ACT_UNIT = 32u,
-  F_DOWNWASH = 64u
+  F_DOWNWASH = 64u, F_SENSOR = 128u
 };
 enum : int { NSTATE = 27, NPARAM = 8 };
 // SoA field index of the private state: x3 v3 R9 (row-major) w3 u4 eps4 floor
@@ -20,7 +20,11 @@ enum : int { S_X = 0, S_V = 3, S_R = 6, S_W = 15, S_U = 18, S_E = 22, S_F = 26 }
 // SoA field index of the per-quad parameters (the forward reads the first six)
 enum : int { P_M = 0, P_JX = 1, P_JY = 2, P_JZ = 3, P_FMAX = 4, P_ALAG = 5, P_T2W = 6, P_TAU = 7 };
 // noise streams: fourth Philox counter word = stream << 8 | draw
-enum : uint32_t { STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2, STREAM_DOWNWASH = 3 };
+enum : uint32_t {
+  STREAM_MOTOR = 0, STREAM_WALL = 1, STREAM_PAIR = 2, STREAM_DOWNWASH = 3, STREAM_SENSOR = 4
+};
+// events of a call, for the reward's interaction terms
+enum : uint32_t { EVF_FLOOR_HIT = 1u, EVF_WALL = 2u, EVF_CEILING = 4u, EVF_QUAD = 8u };
 enum : int { ERRBIT_STATE = 1, ERRBIT_ACTION = 2 };
 
 struct Consts {
@@ -34,6 +38,11 @@ struct Consts {
   int32_t obs_dim;
   // downwash: -k1 (k2 dz + b1) e_z within |dxy|^2 < dw_r2, 0 < dz < dw_h
   float dw_k1, dw_k2, dw_b1, dw_r2, dw_h, dw_na, dw_nw;
+  // observation sensor noise: uniform half-widths (x - goal, v), Gaussian std (omega)
+  float sn_x, sn_v, sn_w;
+  // reward weights: pos, vel, ori, spin, act, dact, rot, yaw, floor_hit,
+  // on_floor, wall, ceiling, quad, prox, and the proximity distance
+  float rw[15];
 };
 
 struct Ptrs {
@@ -98,6 +107,7 @@ struct Quad {
   float x[3], v[3], R[9], w[3], u[4], e[4];
   float fl;
   float xo[3], inc[3];
+  uint32_t ev;  // EVF_* bits of the current call
 };
 
 struct QuadPar {
@@ -313,6 +323,7 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
         if (s.v[k] < 0.0f) {
           s.v[k] = -c.e_wall * s.v[k];
           b = true;
+          s.ev |= EVF_WALL;
           if constexpr (REC) r->flip[k] = true;
         }
       }
@@ -323,6 +334,7 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
         if (s.v[k] > 0.0f) {
           s.v[k] = -c.e_wall * s.v[k];
           b = true;
+          s.ev |= k == 2 ? EVF_CEILING : EVF_WALL;
           if constexpr (REC) r->flip[k] = true;
         }
       }
@@ -344,6 +356,7 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
 
   // §III-B.3 floor hit: stop, level the body keeping its heading, rest
   if ((c.flags & F_FLOOR) && s.x[2] < c.rmin2) {
+    s.ev |= EVF_FLOOR_HIT;
     s.x[2] = c.rmin2;
     s.inc[2] = s.x[2] - s.xo[2];
     s.v[0] = s.v[1] = s.v[2] = 0.0f;
@@ -462,6 +475,7 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
     for (int jj = 0; jj < n; ++jj) pair(jj);
   }
   if (hit) {
+    s.ev |= EVF_QUAD;
     float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};
     if (c.col_nv > 0.0f || c.col_nw > 0.0f) {
       normal4(c, q, t, STREAM_PAIR, 0, zv);
@@ -487,6 +501,58 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
     }
   }
   return cmask;
+}
+
+// §III-C sensor noise on the own-state part of an observation row:
+// U(-sn_x, sn_x) on x - goal, U(-sn_v, sn_v) on v, N(0, sn_w^2) on omega,
+// from stream SENSOR at the observation's substep index.
+__device__ __forceinline__ void sensor_noise(const Consts& c, uint32_t q, unsigned long long t,
+                                             float o_x[3], float o_v[3], float o_w[3]) {
+#pragma unroll
+  for (int draw = 0; draw < 2; ++draw) {
+    uint32_t r0 = q, r1 = (uint32_t)t, r2 = (uint32_t)(t >> 32), r3 = (STREAM_SENSOR << 8) | draw;
+    philox4x32_10(r0, r1, r2, r3, c.key0, c.key1);
+    const float a = draw == 0 ? c.sn_x : c.sn_v;
+    float* o = draw == 0 ? o_x : o_v;
+    o[0] = fmaf(a, 2.0f * u01(r0) - 1.0f, o[0]);
+    o[1] = fmaf(a, 2.0f * u01(r1) - 1.0f, o[1]);
+    o[2] = fmaf(a, 2.0f * u01(r2) - 1.0f, o[2]);
+  }
+  float z[4];
+  normal4(c, q, t, STREAM_SENSOR, 2, z);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) o_w[k] = fmaf(c.sn_w, z[k], o_w[k]);
+}
+
+// §III-E reward of a call from the post-call state, the goal offset dx, the
+// rotor thrusts before the call (f0) and the call's events; the proximity
+// term is added by the caller per neighbour slot (reward_prox).
+__device__ __forceinline__ float reward_state(const Consts& c, const Quad& s, float f_max,
+                                              const float dx[3], const float f0[4]) {
+  float f2 = 0.f, df2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float f1 = fmaf(f_max * s.u[i], s.u[i], s.e[i]);
+    f2 = fmaf(f1, f1, f2);
+    df2 = fmaf(f1 - f0[i], f1 - f0[i], df2);
+  }
+  const float* w = c.rw;
+  float r = w[0] * sqrtf(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+  r += w[1] * sqrtf(s.v[0] * s.v[0] + s.v[1] * s.v[1] + s.v[2] * s.v[2]);
+  r += w[2] * s.R[8];
+  r += w[3] * sqrtf(s.w[0] * s.w[0] + s.w[1] * s.w[1] + s.w[2] * s.w[2]);
+  r += w[4] * sqrtf(f2) + w[5] * sqrtf(df2);
+  r += w[6] * (s.R[0] + s.R[4] + s.R[8] - 1.0f) * 0.5f + w[7] * s.R[0];
+  r += (s.ev & EVF_FLOOR_HIT) ? w[8] : 0.f;
+  r += s.fl != 0.f ? w[9] : 0.f;
+  r += (s.ev & EVF_WALL) ? w[10] : 0.f;
+  r += (s.ev & EVF_CEILING) ? w[11] : 0.f;
+  r += (s.ev & EVF_QUAD) ? w[12] : 0.f;
+  return r;
+}
+
+__device__ __forceinline__ float reward_prox(const Consts& c, float rx, float ry, float rz) {
+  return c.rw[13] * fmaxf(1.0f - sqrtf(rx * rx + ry * ry + rz * rz) / c.rw[14], 0.f);
 }
 
 }  // namespace qs

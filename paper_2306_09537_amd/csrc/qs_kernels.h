@@ -34,7 +34,8 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
                                           unsigned long long t0,
                                           const float* __restrict__ goals,
                                           float* __restrict__ obs, int stage_obs,
-                                          float (*sxv)[9][BS], float* st_obs, int item) {
+                                          float (*sxv)[9][BS], float* st_obs, int item,
+                                          float* __restrict__ reward) {
   static_assert(N == 0 || BS % N == 0, "workgroups hold whole swarms");
   static_assert(MAP != MAP_TABLE || N == 0, "the table mapping has runtime sizes");
   constexpr bool OBS = KT != -2;
@@ -78,8 +79,10 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   const float* __restrict__ S = p.st;
 
   Quad s;
+  s.ev = 0u;
   QuadPar pp;
   float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+  float f0[4] = {0.f, 0.f, 0.f, 0.f};  // rotor thrusts before the call (reward)
   if (live) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) s.x[k] = S[(S_X + k) * Qp + q];
@@ -106,6 +109,10 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       pp.ijy = 1.0f / pp.jy;
       pp.ijz = 1.0f / pp.jz;
       pp.a_ns = c.ns_scale * pp.f_max;
+      if (reward) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f0[i] = fmaf(pp.f_max * s.u[i], s.u[i], s.e[i]);
+      }
       const float4 a4 = reinterpret_cast<const float4*>(act)[q];
       const bool unit = (c.flags & F_ACT_UNIT) != 0;
       uhat[0] = rotor_cmd(a4.x, unit);
@@ -245,7 +252,17 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           ov[18 + 6 * k + 4] = have ? tile[7][j] - s.v[1] : 0.f;
           ov[18 + 6 * k + 5] = have ? tile[8][j] - s.v[2] : 0.f;
         }
+        if (reward && live) {
+          float rp = 0.f;
+#pragma unroll
+          for (int k = 0; k < KT; ++k)
+            if (bj[k] >= 0) rp += reward_prox(c, ov[18 + 6 * k], ov[19 + 6 * k], ov[20 + 6 * k]);
+          reward[q] = reward_state(c, s, pp.f_max, ov, f0) + rp;
+        }
+      } else {
+        if (reward && live) reward[q] = reward_state(c, s, pp.f_max, ov, f0);
       }
+      if (c.flags & F_SENSOR) sensor_noise(c, (uint32_t)q, t0 + nsub, &ov[0], &ov[3], &ov[15]);
       if (stage_obs) {
         if (live) {
           float2* r2 = reinterpret_cast<float2*>(st_obs + tid * OD);
@@ -282,15 +299,18 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       const int K = c.K, OD = c.obs_dim;
       if (live) {
         float* row = obs + (size_t)q * OD;
-        row[0] = s.x[0] - g0;
-        row[1] = s.x[1] - g1;
-        row[2] = s.x[2] - g2;
+        float ox[3] = {s.x[0] - g0, s.x[1] - g1, s.x[2] - g2};
+        float ovl[3] = {s.v[0], s.v[1], s.v[2]}, ow[3] = {s.w[0], s.w[1], s.w[2]};
+        float rwd = reward ? reward_state(c, s, pp.f_max, ox, f0) : 0.f;
+        if (c.flags & F_SENSOR) sensor_noise(c, (uint32_t)q, t0 + nsub, ox, ovl, ow);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) row[3 + k] = s.v[k];
+        for (int k = 0; k < 3; ++k) {
+          row[k] = ox[k];
+          row[3 + k] = ovl[k];
+          row[15 + k] = ow[k];
+        }
 #pragma unroll
         for (int k = 0; k < 9; ++k) row[6 + k] = s.R[k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) row[15 + k] = s.w[k];
         float pd = -1.0f;
         int pj = -1;
         for (int k = 0; k < K; ++k) {
@@ -314,6 +334,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
             o[3] = tile[6][j] - s.v[0];
             o[4] = tile[7][j] - s.v[1];
             o[5] = tile[8][j] - s.v[2];
+            if (reward) rwd += reward_prox(c, o[0], o[1], o[2]);
             pd = bd;
             pj = bj;
           } else {
@@ -322,6 +343,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
             pj = 1 << 30;
           }
         }
+        if (reward) reward[q] = rwd;
       }
     }
   }
@@ -351,13 +373,14 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
                                                   unsigned long long t0,
                                                   const float* __restrict__ goals,
                                                   float* __restrict__ obs, int stage_obs,
-                                                  unsigned long long* tdev, unsigned int* done) {
+                                                  unsigned long long* tdev, unsigned int* done,
+                                                  float* __restrict__ reward) {
   __shared__ float sxv[2][9][BS];
   extern __shared__ float4 st_obs4[];
   if (tdev) t0 = *tdev;
   constexpr int MAP = (N > 0) ? MAP_DENSE : MAP_TABLE;
   step_body<BS, KT, N, MAP>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
-                            reinterpret_cast<float*>(st_obs4), 0);
+                            reinterpret_cast<float*>(st_obs4), 0, reward);
   if (tdev) advance_counter(tdev, done, nsub);
 }
 
@@ -371,20 +394,21 @@ __global__ __launch_bounds__(BS) void bucket_kernel(Consts c, Ptrs p,
                                                     const float* __restrict__ goals,
                                                     float* __restrict__ obs, int n_items,
                                                     unsigned long long* tdev,
-                                                    unsigned int* done) {
+                                                    unsigned int* done,
+                                                    float* __restrict__ reward) {
   __shared__ float sxv[2][9][BS];
   if (tdev) t0 = *tdev;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int N = p.items[it].x;
     __syncthreads();  // the previous item's readers of the tile are done
     switch (N) {
-      case 1: step_body<BS, KT, 1, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
-      case 2: step_body<BS, KT, 2, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
-      case 4: step_body<BS, KT, 4, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
-      case 8: step_body<BS, KT, 8, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
-      case 16: step_body<BS, KT, 16, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
-      case 32: step_body<BS, KT, 32, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
-      default: step_body<BS, KT, 64, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it); break;
+      case 1: step_body<BS, KT, 1, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 2: step_body<BS, KT, 2, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 4: step_body<BS, KT, 4, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 8: step_body<BS, KT, 8, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 16: step_body<BS, KT, 16, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 32: step_body<BS, KT, 32, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      default: step_body<BS, KT, 64, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
     }
   }
   if (tdev) advance_counter(tdev, done, nsub);

@@ -44,6 +44,7 @@ __device__ __forceinline__ void load_state(const float* __restrict__ S, long lon
 #pragma unroll
   for (int k = 0; k < 4; ++k) s.e[k] = S[(S_E + k) * ld + q];
   s.fl = S[S_F * ld + q];
+  s.ev = 0u;
 }
 
 __device__ __forceinline__ void store_state(float* __restrict__ S, long long ld, int q,

@@ -26,7 +26,7 @@ EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_substep_index", "qs_step",
            "qs_step_observe", "qs_get_state", "qs_set_state", "qs_record_contacts",
            "qs_debug_contacts", "qs_sync", "qs_rollout", "qs_rollout_backward",
            "qs_step_backward", "qs_set_graph_mode", "qs_set_launch", "qs_autotune",
-           "qs_error_string")
+           "qs_set_reward_weights", "qs_step_observe_reward", "qs_error_string")
 
 
 class QuadSwarmError(RuntimeError):
@@ -50,6 +50,7 @@ class qs_desc(C.Structure):
         ("dw_k1", C.c_float), ("dw_k2", C.c_float), ("dw_b1", C.c_float),
         ("dw_radius", C.c_float), ("dw_height", C.c_float),
         ("dw_noise_a", C.c_float), ("dw_noise_w", C.c_float),
+        ("sn_x", C.c_float), ("sn_v", C.c_float), ("sn_w", C.c_float),
     ]
 
 
@@ -71,6 +72,8 @@ def lib() -> C.CDLL:
         L.qs_step.argtypes = [vp, vp, i32, vp]
         L.qs_observe.argtypes = [vp, vp, vp, vp]
         L.qs_step_observe.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.qs_step_observe_reward.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.qs_set_reward_weights.argtypes = [vp, vp]
         L.qs_get_state.argtypes = [vp, vp, C.POINTER(u64), vp]
         L.qs_set_state.argtypes = [vp, vp, u64, vp, vp]
         L.qs_record_contacts.argtypes = [vp, i32]
@@ -112,7 +115,8 @@ def make_desc(env_offsets: np.ndarray, consts: dict, k_neighbors: int, flags: in
     d.k_neighbors = int(k_neighbors)
     d.flags = int(flags)
     d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
-    for k in ("dw_k1", "dw_k2", "dw_b1", "dw_radius", "dw_height", "dw_noise_a", "dw_noise_w"):
+    for k in ("dw_k1", "dw_k2", "dw_b1", "dw_radius", "dw_height", "dw_noise_a", "dw_noise_w",
+              "sn_x", "sn_v", "sn_w"):
         setattr(d, k, float(consts.get(k, 0.0)))
     return d
 
@@ -183,6 +187,27 @@ class QuadSwarm:
         _check(lib().qs_step_observe(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
                                      _stream()), "qs_step_observe")
         return o
+
+    def set_reward_weights(self, weights) -> None:
+        """The 15 reward weights (alpha_pos ... alpha_prox, d_prox)."""
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        if w.shape != (15,):
+            raise ValueError("reward weights: expected 15 values")
+        _check(lib().qs_set_reward_weights(self._h, w.ctypes.data), "qs_set_reward_weights")
+
+    def step_observe_reward(self, actions, n_substeps: int, goals, out=None, reward=None):
+        """step_observe that also returns each quad's reward of the call."""
+        import torch
+        a = self._dev(actions, (self.n_quads, 4))
+        g = self._dev(goals, (self.n_quads, 3))
+        o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
+                                                    device=self.device)
+        r = reward if reward is not None else torch.empty(self.n_quads, device=self.device)
+        self._dev(o, (self.n_quads, self.obs_dim))
+        self._dev(r, (self.n_quads,))
+        _check(lib().qs_step_observe_reward(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
+                                            _ptr(r), _stream()), "qs_step_observe_reward")
+        return o, r
 
     def get_state(self, out=None):
         import torch

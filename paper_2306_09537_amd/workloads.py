@@ -39,6 +39,7 @@ QS_MOTOR_NOISE = 8     # AR(1) motor-noise process
 QS_APPROACH_ONLY = 16  # pair response only while the pair is approaching
 QS_ACT_UNIT = 32       # action read as normalised thrust in [0,1] (else [-1,1])
 QS_DOWNWASH = 64       # downwash of upper quads on lower ones (§III-B.4)
+QS_SENSOR_NOISE = 128  # noise on the observed position, velocity, body rate (§III-C)
 
 STATE_DIM = 27         # x3 v3 R9 (row-major) w3 u4 eps4 floor1
 PARAM_DIM = 6          # mass, ixx, iyy, izz, thrust_to_weight, motor_tau
@@ -65,7 +66,15 @@ BASE_CONSTS = dict(
     # at 0.5 m of vertical separation, within 0.1 m of horizontal offset
     dw_k1=2.0, dw_k2=-2.0, dw_b1=1.0, dw_radius=0.1, dw_height=0.5,
     dw_noise_a=0.0, dw_noise_w=0.0,
+    # observation sensor noise: U(-5e-3, 5e-3) m, U(-1e-2, 1e-2) m/s, N(0, 1.75e-4^2) rad/s
+    sn_x=5e-3, sn_v=1e-2, sn_w=1.75e-4,
 )
+
+# Reward weights (alpha_pos, _vel, _ori, _spin, _act, _dact, _rot, _yaw,
+# _floor_hit, _on_floor, _wall, _ceiling, _quad, _prox, d_prox); the paper
+# names the terms but not their weights.
+REWARD_WEIGHTS = (-1.0, -0.1, 0.2, -0.05, -0.05, -0.1, 0.0, 0.0,
+                  -5.0, -1.0, -2.0, -2.0, -5.0, -1.0, 0.5)
 
 SWARM_FLAGS = QS_ROOM | QS_FLOOR | QS_COLLIDE | QS_MOTOR_NOISE | QS_APPROACH_ONLY
 

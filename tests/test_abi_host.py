@@ -38,6 +38,7 @@ def test_header_constants_match_interface():
     assert val["QS_APPROACH_ONLY"] == W.QS_APPROACH_ONLY
     assert val["QS_ACT_UNIT"] == W.QS_ACT_UNIT
     assert val["QS_DOWNWASH"] == W.QS_DOWNWASH == O.flag_values()[6]
+    assert val["QS_SENSOR_NOISE"] == W.QS_SENSOR_NOISE == O.flag_values()[7]
     assert val["QS_STATE_DIM"] == W.STATE_DIM and val["QS_PARAM_DIM"] == W.PARAM_DIM
     for code, name in QS.ERRORS.items():
         assert val[name] == code
@@ -105,10 +106,11 @@ def test_create_rejects_bad_arguments_before_any_hip_call():
     assert _create(w, consts=c)[0] == -2
     assert _create(w, k=-1)[0] == -2
     assert _create(w, k=64)[0] == -2
-    assert _create(w, flags=128)[0] == -2
-    c = dict(w.consts)
-    c["dw_radius"] = -1.0
-    assert _create(w, consts=c)[0] == -2
+    assert _create(w, flags=256)[0] == -2
+    for key, bad in (("dw_radius", -1.0), ("sn_x", -1e-3), ("sn_w", float("inf"))):
+        c = dict(w.consts)
+        c[key] = bad
+        assert _create(w, consts=c)[0] == -2, key
     p = w.params.copy()
     p[3, 0] = 0.0
     assert _create(w, params=p)[0] == -2
@@ -128,4 +130,7 @@ def test_calls_on_null_handle():
     assert L.qs_record_contacts(None, 1) == -1
     assert L.qs_sync(None, None) == -1
     assert L.qs_sizes(None, None, None, None) == -1
+    assert L.qs_step_observe_reward(None, None, 1, None, None, None, None) == -1
+    w = np.zeros(15, np.float32)
+    assert L.qs_set_reward_weights(None, w.ctypes.data) == -1
     assert L.qs_destroy(None) == 0

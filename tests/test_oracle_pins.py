@@ -309,7 +309,8 @@ def test_wall_and_ceiling_bounce(axis, side):
     np.testing.assert_allclose(out[0, W.SV:W.SV + 3], vr, rtol=1e-15)
     assert math.isclose(np.linalg.norm(out[0, W.SV:W.SV + 3]), np.linalg.norm(v), rel_tol=1e-15)
     assert out[1, W.SV + axis] == -side * 1.0   # clamped, not reflected
-    assert ev[0] & O.EV_WALL and not ev[1] & O.EV_WALL
+    bit = O.EV_CEILING if axis == 2 else O.EV_WALL
+    assert ev[0] & bit and not ev[1] & (O.EV_WALL | O.EV_CEILING)
 
 
 def test_floor_hit_resets_and_keeps_yaw():
@@ -556,7 +557,8 @@ def test_multi_substep_call_equals_single_calls():
 
 def test_flag_values_agree_with_interface():
     assert O.flag_values() == [W.QS_ROOM, W.QS_FLOOR, W.QS_COLLIDE, W.QS_MOTOR_NOISE,
-                               W.QS_APPROACH_ONLY, W.QS_ACT_UNIT, W.QS_DOWNWASH]
+                               W.QS_APPROACH_ONLY, W.QS_ACT_UNIT, W.QS_DOWNWASH,
+                               W.QS_SENSOR_NOISE]
 
 
 # ---------------------------------------------------------------- downwash
@@ -643,3 +645,66 @@ def test_env_range_oracle_matches_full_run():
         s, c, _ = full.step(s, a, 1, t)
         sp, cp, _ = part.step(sp, a[q0:q1], 1, t)
     assert np.array_equal(s[q0:q1], sp) and np.array_equal(c[q0:q1], cp)
+
+
+
+# ------------------------------------------------------- sensor noise, reward
+def test_sensor_noise_statistics_and_fields():
+    """Uniform on (-a, a) (variance a^2/3) for position and velocity, Gaussian
+    for body rate, nothing else touched, independent of the call's substep."""
+    q = 4096
+    s = blank_state(q)
+    orc = make(q, k=2, env_sizes=[4] * (q // 4), sn_x=5e-3, sn_v=1e-2, sn_w=1.75e-4)
+    obs, _ = orc.observe(s, np.zeros((q, 3)))
+    noisy = orc.observe_noise(obs, 123)
+    d = noisy - obs
+    assert np.all(d[:, 6:15] == 0) and np.all(d[:, 18:] == 0)
+    for sl, a in ((slice(0, 3), 5e-3), (slice(3, 6), 1e-2)):
+        x = d[:, sl].reshape(-1)
+        assert np.abs(x).max() < a and abs(x.mean()) < 4 * a / np.sqrt(3 * x.size)
+        assert abs(x.var() / (a * a / 3) - 1) < 0.05
+    z = d[:, 15:18].reshape(-1) / 1.75e-4
+    assert abs(z.mean()) < 0.05 and abs(z.std() - 1) < 0.05
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert not np.allclose(orc.observe_noise(obs, 124), noisy)
+
+
+def test_reward_terms_on_constructed_states():
+    """Each term against a hand-computed value on a known state."""
+    q = 2
+    s0 = blank_state(q)
+    s1 = blank_state(q)
+    R = rot_z(0.3) @ rot_x(0.2)
+    s1[0, W.SR:W.SR + 9] = R.reshape(9)
+    s1[0, 0:3] = [1.0, 2.0, 3.0]
+    s1[0, W.SV:W.SV + 3] = [0.3, 0.4, 0.0]
+    s1[0, W.SW:W.SW + 3] = [0.0, 1.2, 0.5]
+    s0[0, W.SU:W.SU + 4] = [0.5, 0.5, 0.5, 0.5]
+    s1[0, W.SU:W.SU + 4] = [0.6, 0.5, 0.4, 0.5]
+    s1[1, W.SF] = 1.0
+    goals = np.array([[1.0, 2.0, 2.0], [0.0, 0.0, 5.0]])
+    orc = make(q, k=1, env_sizes=[2])
+    obs, _ = orc.observe(s1, goals)
+    ev = np.array([O.EV_FLOOR_HIT | O.EV_PAIR_RESPONSE, O.EV_WALL | O.EV_CEILING], np.uint32)
+    fmax = 0.25 * M * G * 2.0
+    f1 = fmax * np.array([0.6, 0.5, 0.4, 0.5]) ** 2
+    f0 = fmax * np.full(4, 0.25)
+    dist = np.linalg.norm(s1[1, 0:3] - s1[0, 0:3])
+    expect0 = {0: 1.0, 1: 0.5, 2: R[2, 2], 3: 1.3, 4: np.linalg.norm(f1),
+               5: np.linalg.norm(f1 - f0), 6: (np.trace(R) - 1) / 2, 7: R[0, 0],
+               8: 1.0, 9: 0.0, 10: 0.0, 11: 0.0, 12: 1.0, 13: max(1 - dist / 2.5, 0)}
+    for k, v in expect0.items():
+        w = np.zeros(15)
+        w[k] = 1.0
+        w[14] = 2.5
+        r = orc.reward(s0, s1, ev, goals, obs, w)
+        assert r[0] == pytest.approx(v, rel=1e-12, abs=1e-15), k
+    w = np.zeros(15)
+    w[9], w[10], w[11], w[14] = 1.0, 10.0, 100.0, 2.5
+    assert orc.reward(s0, s1, ev, goals, obs, w)[1] == 111.0
+    # a swarm of one has only zero-padded neighbour slots: no proximity term
+    solo = make(1, k=3)
+    o1, _ = solo.observe(s1[:1], goals[:1])
+    w = np.zeros(15)
+    w[13], w[14] = 1.0, 2.5
+    assert solo.reward(s0[:1], s1[:1], ev[:1], goals[:1], o1, w)[0] == 0.0
