@@ -175,8 +175,9 @@ int qs_step_observe(qs_handle* h, const float* d_actions, int32_t n_substeps,
  * alpha_ori, alpha_spin, alpha_act, alpha_dact, alpha_rot, alpha_yaw,
  * alpha_floor_hit, alpha_on_floor, alpha_wall, alpha_ceiling, alpha_quad,
  * alpha_prox, d_prox.  All finite, d_prox > 0 (QS_ERR_INVALID otherwise).
- * Applies to calls enqueued after it.  A new handle has all weights 0 and
- * d_prox = 1.
+ * Synchronises the device (work already enqueued keeps the old weights),
+ * then applies to calls enqueued after it.  A new handle has all weights 0
+ * and d_prox = 1.  Not to be called during stream capture.
  */
 int qs_set_reward_weights(qs_handle* h, const float* h_w);
 

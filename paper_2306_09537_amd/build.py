@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libquadswarm.so")
 SOURCES = [os.path.join(CSRC, "qs_abi.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("qs_device.h", "qs_kernels.h")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("qs_device.h", "qs_kernels.h", "qs_adjoint.h",
+                                                  "qs_rollout.h")] + [
     os.path.join(INCLUDE, "quadswarm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -26,6 +27,10 @@ FLAGS = [
     "-ffp-contract=on",
     # no packed-FP32 instructions: plain float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # leading kernel arguments arrive in SGPRs instead of through a scalar
+    # load of the argument segment (a fallback prologue loads them where the
+    # firmware does not preload)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
     "-I", INCLUDE, "-I", CSRC,
 ]

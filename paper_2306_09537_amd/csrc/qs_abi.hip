@@ -23,6 +23,7 @@ struct qs_handle {
   int bs = 64, nblk = 0;
   int uniform_n = 0;  // every swarm holds this many quads (power of two), else 0
   Consts c{};
+  Consts* d_c = nullptr;  // device copy of c, read by every kernel
   float* d_st = nullptr;
   float* d_par = nullptr;
   uint32_t* d_sw = nullptr;
@@ -133,6 +134,7 @@ void free_all(qs_handle* h) {
   (void)hipFree(h->d_item_envs);
   (void)hipFree(h->d_t);
   (void)hipFree(h->d_done);
+  (void)hipFree(h->d_c);
   if (h->h_err) (void)hipHostFree(h->h_err);
 }
 
@@ -235,18 +237,20 @@ void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs
       stage = 1;
     }
   }
-  hipLaunchKernelGGL((qs::step_kernel<BS, KT, N>), dim3(h->nblk), dim3(BS), dyn, s, h->c,
-                     ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, stage,
-                     h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
+  hipLaunchKernelGGL((qs::step_kernel<BS, KT, N>), dim3(h->nblk), dim3(BS), dyn, s, h->d_st,
+                     h->d_par, act, goals, h->d_c, h->Qp, h->Q, nsub, (unsigned long long)h->t,
+                     ptrs(h), obs, stage, h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
 }
 
 template <int BS, int KT>
 void go_items(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
               hipStream_t s, float* rw) {
   const int grid = h->item_grid > 0 ? std::min(h->item_grid, h->n_items) : h->n_items;
-  hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), 0, s, h->c,
-                     ptrs(h), act, nsub, (unsigned long long)h->t, goals, obs, h->n_items,
-                     h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
+  hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), 0, s,
+                     h->d_st, h->d_par, act, goals, h->d_c, h->Qp, h->Q, nsub,
+                     (unsigned long long)h->t, ptrs(h), obs, h->n_items,
+                     h->graph_mode ? h->d_t : nullptr,
+                     h->d_done, rw);
 }
 
 template <int BS>
@@ -317,14 +321,14 @@ int launch(qs_handle* h, const float* act, int nsub, const float* goals, float* 
 template <int BS, int N, bool PEN>
 void go_roll(qs_handle* h, const float* act, int ncalls, int nsub, float* ckpt, int ce, float* pen,
              float beta, hipStream_t s) {
-  hipLaunchKernelGGL((qs::rollout_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->c, ptrs(h),
+  hipLaunchKernelGGL((qs::rollout_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->d_c, ptrs(h),
                      act, ncalls, nsub, (unsigned long long)h->t, ckpt, ce, pen, beta);
 }
 
 template <int BS, int N, bool PEN>
 void go_adj(qs_handle* h, const float* ckpt, const float* act, int ncalls, int nsub, uint64_t t0,
             const float* gpen, float beta, float* gact, hipStream_t s) {
-  hipLaunchKernelGGL((qs::adjoint_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->c,
+  hipLaunchKernelGGL((qs::adjoint_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->d_c,
                      ptrs(h), ckpt, act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam,
                      gpen, beta, gact, h->d_gpar);
 }
@@ -543,6 +547,7 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
     rc = QS_ERR_NOMEM;
   if (rc == QS_OK && hipMalloc((void**)&h->d_done, sizeof(unsigned int)) != hipSuccess)
     rc = QS_ERR_NOMEM;
+  if (rc == QS_OK && hipMalloc((void**)&h->d_c, sizeof(Consts)) != hipSuccess) rc = QS_ERR_NOMEM;
   if (rc == QS_OK && h->uniform_n == 0) {
     const char* ev = std::getenv("QS_BUCKETED");
     h->bucketed = !(ev && ev[0] == '0');
@@ -561,6 +566,7 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
     ok = ok && hipMemset(h->d_err, 0, sizeof(int)) == hipSuccess;
     ok = ok && hipMemset(h->d_t, 0, sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMemset(h->d_done, 0, sizeof(unsigned int)) == hipSuccess;
+    ok = ok && hipMemcpy(h->d_c, &h->c, sizeof(Consts), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (!ok) rc = QS_ERR_HIP;
   }
@@ -764,7 +770,12 @@ int qs_set_reward_weights(qs_handle* h, const float* h_w) {
   for (int k = 0; k < 15; ++k)
     if (!finite(h_w[k])) return QS_ERR_INVALID;
   if (!(h_w[14] > 0.f)) return QS_ERR_INVALID;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  // enqueued calls still read the previous weights from the device copy
+  if (hipDeviceSynchronize() != hipSuccess) return QS_ERR_HIP;
   for (int k = 0; k < 15; ++k) h->c.rw[k] = h_w[k];
+  if (hipMemcpy(h->d_c, &h->c, sizeof(Consts), hipMemcpyHostToDevice) != hipSuccess)
+    return QS_ERR_HIP;
   return QS_OK;
 }
 

@@ -15,6 +15,9 @@ enum : uint32_t {
   F_DOWNWASH = 64u, F_SENSOR = 128u
 };
 enum : int { NSTATE = 27, NPARAM = 8 };
+// clang vector types, for the non-temporal store builtin
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 // SoA field index of the private state: x3 v3 R9 (row-major) w3 u4 eps4 floor
 enum : int { S_X = 0, S_V = 3, S_R = 6, S_W = 15, S_U = 18, S_E = 22, S_F = 26 };
 // SoA field index of the per-quad parameters (the forward reads the first six)
@@ -396,15 +399,23 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
 // Returns true when the pair is in contact; then n is the unit normal from
 // j to i and sp = (v_j - v_i).n.  Shared by the forward pass and the
 // adjoint's recomputation so both take identical decisions.
+// pj: partner j's start position (0-2) and displacement (3-5).
+__device__ __forceinline__ bool pair_geom_v(const Consts& c, const float pj[6], const Quad& s,
+                                            int jj, int me, float& dx, float& dy, float& dz,
+                                            float& d2) {
+  dx = (s.xo[0] - pj[0]) + (s.inc[0] - pj[3]);
+  dy = (s.xo[1] - pj[1]) + (s.inc[1] - pj[4]);
+  dz = (s.xo[2] - pj[2]) + (s.inc[2] - pj[5]);
+  d2 = dx * dx + dy * dy + dz * dz;
+  return d2 < c.dcol2 && jj != me;
+}
+
 template <int BS>
 __device__ __forceinline__ bool pair_geom(const Consts& c, const float (*tile)[BS], const Quad& s,
                                           int j, int jj, int me, float& dx, float& dy,
                                           float& dz, float& d2) {
-  dx = (s.xo[0] - tile[0][j]) + (s.inc[0] - tile[3][j]);
-  dy = (s.xo[1] - tile[1][j]) + (s.inc[1] - tile[4][j]);
-  dz = (s.xo[2] - tile[2][j]) + (s.inc[2] - tile[5][j]);
-  d2 = dx * dx + dy * dy + dz * dz;
-  return d2 < c.dcol2 && jj != me;
+  const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
+  return pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
 }
 
 template <int BS>
@@ -445,10 +456,10 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   float dv[3] = {0.f, 0.f, 0.f};
   float adw = 0.f;
   bool hit = false, dwhit = false;
-  auto pair = [&](int jj) {
+  auto pair = [&](int jj, const float pj[6]) {
     const int j = ls + jj;
     float dx, dy, dz, d2;
-    const bool con = pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2);
+    const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
     if constexpr (PEN) {
       if (jj != me) pacc += 0.5f * softplusf(beta * (c.dcol - sqrtf(d2))) / beta;
     }
@@ -469,10 +480,25 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
     }
   };
   if constexpr (N > 0) {
+    // partners' geometry read from LDS a chunk at a time, ahead of the
+    // per-pair branches, so the reads overlap instead of waiting one by one
+    constexpr int CH = N < 8 ? N : 8;
 #pragma unroll
-    for (int jj = 0; jj < N; ++jj) pair(jj);
+    for (int j0 = 0; j0 < N; j0 += CH) {
+      float pj[CH][6];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+#pragma unroll
+        for (int r = 0; r < 6; ++r) pj[u][r] = tile[r][ls + j0 + u];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) pair(j0 + u, pj[u]);
+    }
   } else {
-    for (int jj = 0; jj < n; ++jj) pair(jj);
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = ls + jj;
+      const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
+      pair(jj, pj);
+    }
   }
   if (hit) {
     s.ev |= EVF_QUAD;

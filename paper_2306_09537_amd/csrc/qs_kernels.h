@@ -35,7 +35,8 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
                                           const float* __restrict__ goals,
                                           float* __restrict__ obs, int stage_obs,
                                           float (*sxv)[9][BS], float* st_obs, int item,
-                                          float* __restrict__ reward) {
+                                          float* __restrict__ reward,
+                                          const unsigned long long* tdev = nullptr) {
   static_assert(N == 0 || BS % N == 0, "workgroups hold whole swarms");
   static_assert(MAP != MAP_TABLE || N == 0, "the table mapping has runtime sizes");
   constexpr bool OBS = KT != -2;
@@ -83,6 +84,14 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   QuadPar pp;
   float uhat[4] = {0.f, 0.f, 0.f, 0.f};
   float f0[4] = {0.f, 0.f, 0.f, 0.f};  // rotor thrusts before the call (reward)
+  // the goal is loaded with the state: a load issued after the state stores
+  // would wait for their completion (one in-order counter for both)
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  if (OBS && live) {
+    g0 = goals[3 * q];
+    g1 = goals[3 * q + 1];
+    g2 = goals[3 * q + 2];
+  }
   if (live) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) s.x[k] = S[(S_X + k) * Qp + q];
@@ -123,6 +132,9 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
         __hip_atomic_fetch_or(p.err, ERRBIT_ACTION, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  // graph mode: the substep index comes from the device counter (read after
+  // the state loads are in flight)
+  if (tdev) t0 = *tdev;
 
   const bool collide = N != 1 && (c.flags & (F_COLLIDE | F_DOWNWASH)) != 0;
   unsigned long long cmask = 0ull;
@@ -158,6 +170,11 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
     }
   }
 
+  // Every load of the call has been consumed once a substep has run; the
+  // explicit wait says so to the compiler, whose conservative merge with the
+  // no-substep path would otherwise make the observation wait for the state
+  // stores (loads and stores share one in-order counter).
+  __builtin_amdgcn_s_waitcnt(0);
   if (live && nsub > 0) {
     float* St = p.st;
     float chk = 0.f;
@@ -197,12 +214,6 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       }
     }
     __syncthreads();
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    if (live) {
-      g0 = goals[3 * q];
-      g1 = goals[3 * q + 1];
-      g2 = goals[3 * q + 2];
-    }
     if constexpr (KT >= 0) {
       constexpr int OD = 18 + 6 * KT;
       float ov[OD];
@@ -221,9 +232,8 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
         int bj[KT];
 #pragma unroll
         for (int k = 0; k < KT; ++k) { bd[k] = INFINITY; bj[k] = -1; }
-        auto cand = [&](int jj) {
-          const int j = ls + jj;
-          const float rx = tile[0][j] - s.x[0], ry = tile[1][j] - s.x[1], rz = tile[2][j] - s.x[2];
+        auto cand = [&](int jj, float xj, float yj, float zj) {
+          const float rx = xj - s.x[0], ry = yj - s.x[1], rz = zj - s.x[2];
           const float d2 = jj == me ? INFINITY : rx * rx + ry * ry + rz * rz;
 #pragma unroll
           for (int k = KT - 1; k > 0; --k) {
@@ -235,22 +245,45 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           if (bd[0] > d2) { bd[0] = d2; bj[0] = jj; }
         };
         if constexpr (N > 1) {
+          constexpr int CH = N < 8 ? N : 8;
 #pragma unroll
-          for (int jj = 0; jj < N; ++jj) cand(jj);
+          for (int j0 = 0; j0 < N; j0 += CH) {
+            float px[CH][3];
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+#pragma unroll
+              for (int r = 0; r < 3; ++r) px[u][r] = tile[r][ls + j0 + u];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) cand(j0 + u, px[u][0], px[u][1], px[u][2]);
+          }
         } else if constexpr (N == 0) {
           if (live)
-            for (int jj = 0; jj < n; ++jj) cand(jj);
+            for (int jj = 0; jj < n; ++jj)
+              cand(jj, tile[0][ls + jj], tile[1][ls + jj], tile[2][ls + jj]);
+        }
+        // the slots' rows are read unconditionally (j is always a valid
+        // column) and selected afterwards, so all reads are in flight at
+        // once instead of one guarded read and wait per value
+        float nb[KT][6];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+          const int j = ls + (bj[k] >= 0 ? bj[k] : 0);
+          nb[k][0] = tile[0][j];
+          nb[k][1] = tile[1][j];
+          nb[k][2] = tile[2][j];
+          nb[k][3] = tile[6][j];
+          nb[k][4] = tile[7][j];
+          nb[k][5] = tile[8][j];
         }
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
           const bool have = bj[k] >= 0;
-          const int j = ls + (have ? bj[k] : 0);
-          ov[18 + 6 * k + 0] = have ? tile[0][j] - s.x[0] : 0.f;
-          ov[18 + 6 * k + 1] = have ? tile[1][j] - s.x[1] : 0.f;
-          ov[18 + 6 * k + 2] = have ? tile[2][j] - s.x[2] : 0.f;
-          ov[18 + 6 * k + 3] = have ? tile[6][j] - s.v[0] : 0.f;
-          ov[18 + 6 * k + 4] = have ? tile[7][j] - s.v[1] : 0.f;
-          ov[18 + 6 * k + 5] = have ? tile[8][j] - s.v[2] : 0.f;
+          ov[18 + 6 * k + 0] = have ? nb[k][0] - s.x[0] : 0.f;
+          ov[18 + 6 * k + 1] = have ? nb[k][1] - s.x[1] : 0.f;
+          ov[18 + 6 * k + 2] = have ? nb[k][2] - s.x[2] : 0.f;
+          ov[18 + 6 * k + 3] = have ? nb[k][3] - s.v[0] : 0.f;
+          ov[18 + 6 * k + 4] = have ? nb[k][4] - s.v[1] : 0.f;
+          ov[18 + 6 * k + 5] = have ? nb[k][5] - s.v[2] : 0.f;
         }
         if (reward && live) {
           float rp = 0.f;
@@ -271,22 +304,26 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
         }
         __syncthreads();
         // contiguous copy of the workgroup's rows: 16-byte stores when the
-        // destination allows, else 8-byte stores
+        // destination allows, else 8-byte stores; non-temporal, since the
+        // rows go to their consumer and this kernel never reads them back
+        // (fewer dirty L2 lines left to write back when the kernel ends)
         const int total = cnt * OD;
         float* dst = obs + (size_t)qb * OD;
         if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
           const int n4 = total >> 2;
-          float4* d4 = reinterpret_cast<float4*>(dst);
+          v4f* d4 = reinterpret_cast<v4f*>(dst);
+          const v4f* s4 = reinterpret_cast<const v4f*>(st_obs4);
 #pragma unroll 4
-          for (int i = tid; i < n4; i += BS) d4[i] = st_obs4[i];
+          for (int i = tid; i < n4; i += BS) __builtin_nontemporal_store(s4[i], d4 + i);
           if ((total & 3) && tid == 0)
-            reinterpret_cast<float2*>(dst)[2 * n4] = reinterpret_cast<float2*>(st_obs)[2 * n4];
+            __builtin_nontemporal_store(reinterpret_cast<const v2f*>(st_obs)[2 * n4],
+                                        reinterpret_cast<v2f*>(dst) + 2 * n4);
         } else {
           const int n2 = total >> 1;
-          float2* d2p = reinterpret_cast<float2*>(dst);
-          const float2* s2p = reinterpret_cast<const float2*>(st_obs);
+          v2f* d2p = reinterpret_cast<v2f*>(dst);
+          const v2f* s2p = reinterpret_cast<const v2f*>(st_obs);
 #pragma unroll 4
-          for (int i = tid; i < n2; i += BS) d2p[i] = s2p[i];
+          for (int i = tid; i < n2; i += BS) __builtin_nontemporal_store(s2p[i], d2p + i);
         }
       } else if (live) {
         float2* r2 = reinterpret_cast<float2*>(obs + (size_t)q * OD);
@@ -366,21 +403,32 @@ __device__ __forceinline__ void advance_counter(unsigned long long* tdev, unsign
   }
 }
 
+// Kernel arguments: the leading ones (state, parameters, actions, goals,
+// constants, sizes) are what the dense mapping needs before its first load
+// and fit the fourteen SGPRs the hardware can preload where the firmware
+// supports it; the constants live in device memory written at creation.
+
 // One workgroup per block of quads (dense or table mapping).
 template <int BS, int KT, int N>
-__global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
-                                                  const float* __restrict__ act, int nsub,
-                                                  unsigned long long t0,
+__global__ __launch_bounds__(BS) void step_kernel(float* __restrict__ st,
+                                                  const float* __restrict__ par,
+                                                  const float* __restrict__ act,
                                                   const float* __restrict__ goals,
+                                                  const Consts* __restrict__ cp, int Qp, int Q,
+                                                  int nsub, unsigned long long t0, Ptrs p,
                                                   float* __restrict__ obs, int stage_obs,
                                                   unsigned long long* tdev, unsigned int* done,
                                                   float* __restrict__ reward) {
   __shared__ float sxv[2][9][BS];
   extern __shared__ float4 st_obs4[];
-  if (tdev) t0 = *tdev;
+  p.st = st;
+  p.par = par;
+  p.Qp = Qp;
+  p.Q = Q;
+  const Consts& c = *cp;
   constexpr int MAP = (N > 0) ? MAP_DENSE : MAP_TABLE;
   step_body<BS, KT, N, MAP>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
-                            reinterpret_cast<float*>(st_obs4), 0, reward);
+                            reinterpret_cast<float*>(st_obs4), 0, reward, tdev);
   if (tdev) advance_counter(tdev, done, nsub);
 }
 
@@ -388,15 +436,22 @@ __global__ __launch_bounds__(BS) void step_kernel(Consts c, Ptrs p,
 // same slot size N run the body specialised for N (unrolled in-swarm loops);
 // workgroups stride over the item list.
 template <int BS, int KT>
-__global__ __launch_bounds__(BS) void bucket_kernel(Consts c, Ptrs p,
-                                                    const float* __restrict__ act, int nsub,
-                                                    unsigned long long t0,
+__global__ __launch_bounds__(BS) void bucket_kernel(float* __restrict__ st,
+                                                    const float* __restrict__ par,
+                                                    const float* __restrict__ act,
                                                     const float* __restrict__ goals,
+                                                    const Consts* __restrict__ cp, int Qp, int Q,
+                                                    int nsub, unsigned long long t0, Ptrs p,
                                                     float* __restrict__ obs, int n_items,
                                                     unsigned long long* tdev,
                                                     unsigned int* done,
                                                     float* __restrict__ reward) {
   __shared__ float sxv[2][9][BS];
+  p.st = st;
+  p.par = par;
+  p.Qp = Qp;
+  p.Q = Q;
+  const Consts& c = *cp;
   if (tdev) t0 = *tdev;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int N = p.items[it].x;

@@ -114,12 +114,13 @@ __device__ __forceinline__ float duhat_da(const Consts& c, float a, float uhat) 
 // sum over substeps and env-mates of softplus(beta (d_col - d))/(2 beta).
 // ---------------------------------------------------------------------------
 template <int BS, int N, bool PEN>
-__global__ __launch_bounds__(BS) void rollout_kernel(Consts c, Ptrs p,
+__global__ __launch_bounds__(BS) void rollout_kernel(const Consts* __restrict__ cp, Ptrs p,
                                                      const float* __restrict__ act, int ncalls,
                                                      int nsub, unsigned long long t0,
                                                      float* __restrict__ ckpt, int ckpt_every,
                                                      float* __restrict__ pen, float beta) {
   __shared__ float sxv[2][9][BS];
+  const Consts& c = *cp;
   const int tid = threadIdx.x;
   int qb, cnt, ls, n;
   block_map<BS, N>(p, tid, qb, cnt, ls, n);
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Consts c, Ptrs p,
 //  (PEN); gpar: [6][Q] dL/d(m, ixx, iyy, izz, t2w, tau), accumulated.
 // ---------------------------------------------------------------------------
 template <int BS, int N, bool PEN>
-__global__ __launch_bounds__(BS) void adjoint_kernel(Consts c, Ptrs p,
+__global__ __launch_bounds__(BS) void adjoint_kernel(const Consts* __restrict__ cp, Ptrs p,
                                                      const float* __restrict__ ckpt,
                                                      const float* __restrict__ act, int ncalls,
                                                      int nsub, unsigned long long t0,
@@ -195,6 +196,7 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(Consts c, Ptrs p,
   // rows 0-8 as in the forward tile; 9-11: adjoint of the collision
   // velocity change; 12: penalty weight dL/d pen
   __shared__ float tl[13][BS];
+  const Consts& c = *cp;
   const int tid = threadIdx.x;
   int qb, cnt, ls, n;
   block_map<BS, N>(p, tid, qb, cnt, ls, n);
