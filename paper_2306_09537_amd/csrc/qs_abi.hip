@@ -34,8 +34,9 @@ struct qs_handle {
   int* h_err = nullptr;  // pinned
   uint64_t t = 0;
   bool record = false;
-  // adjoint scratch, grown on demand: tape [S][27][Q], adjoint [27][Q],
-  // parameter gradient [6][Q], one checkpoint [27][Q]
+  // adjoint scratch, grown on demand: tape [S][27][Q] (S substeps of the
+  // chunk of segments in flight), adjoint [27][Q], parameter gradient [6][Q],
+  // one checkpoint [27][Q]
   // uneven swarm sizes: work items of the persistent bucketed launch
   std::vector<int> env_start, env_n;  // host copy of the environments
   int4* d_items = nullptr;
@@ -326,11 +327,19 @@ void go_roll(qs_handle* h, const float* act, int ncalls, int nsub, float* ckpt, 
 }
 
 template <int BS, int N, bool PEN>
-void go_adj(qs_handle* h, const float* ckpt, const float* act, int ncalls, int nsub, uint64_t t0,
-            const float* gpen, float beta, float* gact, hipStream_t s) {
-  hipLaunchKernelGGL((qs::adjoint_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->d_c,
-                     ptrs(h), ckpt, act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam,
-                     gpen, beta, gact, h->d_gpar);
+void go_recompute(qs_handle* h, const float* ckpt, const float* act, int ncalls, int ce, int nsub,
+                  uint64_t t0, hipStream_t s) {
+  const int nseg = (ncalls + ce - 1) / ce;
+  hipLaunchKernelGGL((qs::recompute_kernel<BS, N>), dim3(h->nblk, nseg), dim3(BS), 0, s, h->d_c,
+                     ptrs(h), ckpt, act, ncalls, ce, nsub, (unsigned long long)t0, h->d_tape);
+}
+
+template <int BS, int N, bool PEN>
+void go_reverse(qs_handle* h, const float* act, int ncalls, int nsub, uint64_t t0,
+                const float* gpen, float beta, float* gact, hipStream_t s) {
+  hipLaunchKernelGGL((qs::reverse_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->d_c,
+                     ptrs(h), act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam, gpen,
+                     beta, gact, h->d_gpar);
 }
 
 // Dispatch on (block size, uniform swarm size) for a launcher template F.
@@ -362,10 +371,18 @@ struct RollF {
 };
 
 template <int BS, int N, bool PEN>
-struct AdjF {
-  static void run(qs_handle* h, const float* ckpt, const float* act, int ncalls, int nsub,
-                  uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
-    go_adj<BS, N, PEN>(h, ckpt, act, ncalls, nsub, t0, gpen, beta, gact, s);
+struct RecF {
+  static void run(qs_handle* h, const float* ckpt, const float* act, int ncalls, int ce, int nsub,
+                  uint64_t t0, hipStream_t s) {
+    go_recompute<BS, N, PEN>(h, ckpt, act, ncalls, ce, nsub, t0, s);
+  }
+};
+
+template <int BS, int N, bool PEN>
+struct RevF {
+  static void run(qs_handle* h, const float* act, int ncalls, int nsub, uint64_t t0,
+                  const float* gpen, float beta, float* gact, hipStream_t s) {
+    go_reverse<BS, N, PEN>(h, act, ncalls, nsub, t0, gpen, beta, gact, s);
   }
 };
 
@@ -382,13 +399,23 @@ int grow(float** p, size_t* cap, size_t need) {
   return QS_OK;
 }
 
-int ensure_adjoint_scratch(qs_handle* h, size_t tape_floats) {
+int ensure_adjoint_scratch(qs_handle* h) {
   size_t cap_lam = h->d_lam ? 1 : 0, cap_g = h->d_gpar ? 1 : 0, cap_c = h->d_ck1 ? 1 : 0;
-  int rc = grow(&h->d_tape, &h->tape_cap, tape_floats);
-  if (rc == QS_OK && !h->d_lam) rc = grow(&h->d_lam, &cap_lam, (size_t)qs::NSTATE * h->Q);
+  int rc = QS_OK;
+  if (!h->d_lam) rc = grow(&h->d_lam, &cap_lam, (size_t)qs::NSTATE * h->Q);
   if (rc == QS_OK && !h->d_gpar) rc = grow(&h->d_gpar, &cap_g, (size_t)6 * h->Q);
   if (rc == QS_OK && !h->d_ck1) rc = grow(&h->d_ck1, &cap_c, (size_t)qs::NSTATE * h->Q);
   return rc;
+}
+
+// Bytes of tape the backward pass may hold at once (QS_TAPE_BYTES overrides);
+// at least one segment is always taped.
+size_t tape_budget() {
+  if (const char* e = std::getenv("QS_TAPE_BYTES")) {
+    const long long b = std::atoll(e);
+    if (b > 0) return (size_t)b;
+  }
+  return (size_t)8 << 30;
 }
 
 void convert(const float* src, float* dst, int Q, int rows, bool to_row_major, bool acc,
@@ -401,22 +428,32 @@ void convert(const float* src, float* dst, int Q, int rows, bool to_row_major, b
     hipLaunchKernelGGL(qs::rm_to_fm_kernel, grid, block, 0, s, src, dst, Q, rows);
 }
 
-// Reverse sweep over n_calls calls in segments of ce calls, from the
-// checkpoints ckpt ([27][Q] each); lam and gpar scratch already hold the
-// incoming adjoint and zeros.
+// Backward pass over n_calls calls with checkpoints every ce calls (ckpt:
+// [27][Q] each); lam and gpar scratch already hold the incoming adjoint and
+// zeros.  Segments are taken in chunks whose tape fits the budget, last
+// chunk first: one launch recomputes every segment of the chunk in
+// parallel, one launch sweeps the chunk in reverse.
 int run_adjoint(qs_handle* h, const float* act, int n_calls, int nsub, int ce, const float* ckpt,
                 uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
   const int nseg = (n_calls + ce - 1) / ce;
-  for (int seg = nseg - 1; seg >= 0; --seg) {
-    const int c0 = seg * ce, nc = std::min(ce, n_calls - c0);
-    const float* ck = ckpt + (size_t)seg * qs::NSTATE * h->Q;
+  const size_t seg_floats = (size_t)std::min(ce, n_calls) * nsub * qs::NSTATE * h->Q;
+  const size_t fit = tape_budget() / (seg_floats * sizeof(float));
+  // segments per chunk (also the recompute grid's y extent, at most 65535)
+  const int G = (int)std::max<size_t>(1, std::min<size_t>({(size_t)nseg, fit, (size_t)65535}));
+  int rc = grow(&h->d_tape, &h->tape_cap, (size_t)G * seg_floats);
+  if (rc != QS_OK) return rc;
+  for (int hi = nseg; hi > 0; hi -= G) {
+    const int g0 = std::max(0, hi - G);
+    const int c0 = g0 * ce, nc = std::min(n_calls, hi * ce) - c0;
+    const float* ck = ckpt + (size_t)g0 * qs::NSTATE * h->Q;
     const float* a = act + (size_t)c0 * h->Q * 4;
     float* ga = gact + (size_t)c0 * h->Q * 4;
     const uint64_t ts = t0 + (uint64_t)c0 * nsub;
+    dispatch<RecF, false>(h, ck, a, nc, ce, nsub, ts, s);
     if (gpen)
-      dispatch<AdjF, true>(h, ck, a, nc, nsub, ts, gpen, beta, ga, s);
+      dispatch<RevF, true>(h, a, nc, nsub, ts, gpen, beta, ga, s);
     else
-      dispatch<AdjF, false>(h, ck, a, nc, nsub, ts, gpen, beta, ga, s);
+      dispatch<RevF, false>(h, a, nc, nsub, ts, gpen, beta, ga, s);
     if (hipGetLastError() != hipSuccess) return QS_ERR_HIP;
   }
   return QS_OK;
@@ -887,8 +924,7 @@ int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
     return QS_ERR_ALIGN;
   if (n_calls == 0 || n_substeps == 0) return QS_OK;
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
-  const size_t tape = (size_t)std::min<int32_t>(ckpt_every, n_calls) * n_substeps * qs::NSTATE * h->Q;
-  int rc = ensure_adjoint_scratch(h, tape);
+  int rc = ensure_adjoint_scratch(h);
   if (rc != QS_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   convert(d_gstate, h->d_lam, h->Q, qs::NSTATE, false, false, s);
@@ -914,7 +950,7 @@ int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actio
       !aligned(d_gstate_out, 4) || !aligned(d_gstate_in, 4) || !aligned(d_gparams, 4))
     return QS_ERR_ALIGN;
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
-  int rc = ensure_adjoint_scratch(h, (size_t)std::max(n_substeps, 1) * qs::NSTATE * h->Q);
+  int rc = ensure_adjoint_scratch(h);
   if (rc != QS_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   convert(d_state_in, h->d_ck1, h->Q, qs::NSTATE, false, false, s);

@@ -394,12 +394,12 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
   }
 }
 
-// Geometry of the pair (i, j) for the in-env pass, from the tile of start
-// positions (rows 0-2), displacements (rows 3-5) and velocities (rows 6-8).
-// Returns true when the pair is in contact; then n is the unit normal from
-// j to i and sp = (v_j - v_i).n.  Shared by the forward pass and the
-// adjoint's recomputation so both take identical decisions.
-// pj: partner j's start position (0-2) and displacement (3-5).
+// Geometry of the pair (i, j) for the in-env pass, from partner j's start
+// position pj[0..2] and displacement pj[3..5] (rows 0-5 of the tile; rows
+// 6-8 hold the velocities).  Returns true when the pair is in contact; then
+// pair_normal gives the unit normal from j to i and sp = (v_j - v_i).n.
+// Shared by the forward pass and the adjoint's recomputation so both take
+// identical decisions.
 __device__ __forceinline__ bool pair_geom_v(const Consts& c, const float pj[6], const Quad& s,
                                             int jj, int me, float& dx, float& dy, float& dz,
                                             float& d2) {
@@ -408,14 +408,6 @@ __device__ __forceinline__ bool pair_geom_v(const Consts& c, const float pj[6], 
   dz = (s.xo[2] - pj[2]) + (s.inc[2] - pj[5]);
   d2 = dx * dx + dy * dy + dz * dz;
   return d2 < c.dcol2 && jj != me;
-}
-
-template <int BS>
-__device__ __forceinline__ bool pair_geom(const Consts& c, const float (*tile)[BS], const Quad& s,
-                                          int j, int jj, int me, float& dx, float& dy,
-                                          float& dz, float& d2) {
-  const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
-  return pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
 }
 
 template <int BS>
@@ -435,8 +427,50 @@ __device__ __forceinline__ void pair_normal(const float (*tile)[BS], const Quad&
   sp = (tile[6][j] - s.v[0]) * n[0] + (tile[7][j] - s.v[1]) * n[1] + (tile[8][j] - s.v[2]) * n[2];
 }
 
-__device__ __forceinline__ float softplusf(float x) { return x > 20.f ? x : log1pf(expf(x)); }
-__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+// Smoothed collision penalty: softplus(x) = max(x, 0) + ln(1 + e^-|x|) and
+// its derivative, the logistic sigmoid, from the hardware base-2 exponential,
+// logarithm and reciprocal (about 1 ulp each); ln(1 + e) for e < 1e-4 from
+// its series, where 1 + e would round away most of e.
+__device__ __forceinline__ float softplus_hw(float x) {
+  const float e = __builtin_amdgcn_exp2f(-fabsf(x) * 1.4426950408889634f);
+  const float l = e < 1e-4f ? e * fmaf(-0.5f, e, 1.0f)
+                            : 0.6931471805599453f * __builtin_amdgcn_logf(1.0f + e);
+  return fmaxf(x, 0.f) + l;
+}
+__device__ __forceinline__ float sigmoid_hw(float x) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-x * 1.4426950408889634f));
+}
+
+// Calls f(jj, pj) for every swarm-mate jj of the lane's swarm (itself
+// included), pj[0..5] being its start position and displacement from rows
+// 0-5 of the tile and pj[6] row XR (XR < 0: none).  For a compile-time swarm
+// size the reads go out a chunk of eight partners at a time, ahead of the
+// per-pair branches, so they overlap instead of waiting one by one.
+template <int BS, int N, int XR = -1, typename T, typename F>
+__device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
+  if constexpr (N > 0) {
+    constexpr int CH = N < 8 ? N : 8;
+#pragma unroll
+    for (int j0 = 0; j0 < N; j0 += CH) {
+      float pj[CH][7];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) pj[u][r] = tile[r][ls + j0 + u];
+        pj[u][6] = XR >= 0 ? tile[XR < 0 ? 0 : XR][ls + j0 + u] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) f(j0 + u, pj[u]);
+    }
+  } else {
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = ls + jj;
+      const float pj[7] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j],
+                           tile[5][j], XR >= 0 ? tile[XR < 0 ? 0 : XR][j] : 0.f};
+      f(jj, pj);
+    }
+  }
+}
 
 // In-swarm pass of one live lane after the tile (start positions,
 // displacements, velocities) is written and the workgroup synchronised:
@@ -456,12 +490,13 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   float dv[3] = {0.f, 0.f, 0.f};
   float adw = 0.f;
   bool hit = false, dwhit = false;
-  auto pair = [&](int jj, const float pj[6]) {
+  const float hb = PEN ? 0.5f / beta : 0.f;  // each quad of a pair carries half
+  auto pair = [&](int jj, const float* pj) {
     const int j = ls + jj;
     float dx, dy, dz, d2;
     const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
     if constexpr (PEN) {
-      if (jj != me) pacc += 0.5f * softplusf(beta * (c.dcol - sqrtf(d2))) / beta;
+      if (jj != me) pacc += hb * softplus_hw(beta * (c.dcol - __builtin_amdgcn_sqrtf(d2)));
     }
     if (collide && con) {
       cmask |= 1ull << jj;
@@ -479,27 +514,7 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
       dwhit = true;
     }
   };
-  if constexpr (N > 0) {
-    // partners' geometry read from LDS a chunk at a time, ahead of the
-    // per-pair branches, so the reads overlap instead of waiting one by one
-    constexpr int CH = N < 8 ? N : 8;
-#pragma unroll
-    for (int j0 = 0; j0 < N; j0 += CH) {
-      float pj[CH][6];
-#pragma unroll
-      for (int u = 0; u < CH; ++u)
-#pragma unroll
-        for (int r = 0; r < 6; ++r) pj[u][r] = tile[r][ls + j0 + u];
-#pragma unroll
-      for (int u = 0; u < CH; ++u) pair(j0 + u, pj[u]);
-    }
-  } else {
-    for (int jj = 0; jj < n; ++jj) {
-      const int j = ls + jj;
-      const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
-      pair(jj, pj);
-    }
-  }
+  for_partners<BS, N>(tile, ls, n, pair);
   if (hit) {
     s.ev |= EVF_QUAD;
     float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};

@@ -1,7 +1,8 @@
 // Differentiable rollouts: a multi-call forward kernel (a fresh action per
 // call, checkpoints of the state, the smoothed collision penalty) and the
-// segment adjoint kernel that recomputes a segment from its checkpoint,
-// keeps the per-substep states in a tape, and sweeps it in reverse.
+// backward pass: a kernel that recomputes checkpoint segments in parallel,
+// taping the per-substep states, and a kernel that sweeps the tape in
+// reverse.
 //
 // Layouts: checkpoints, tape and adjoint scratch are field-major [27][Q]
 // (coalesced per field); actions and their gradients are [call][Q][4].
@@ -177,18 +178,86 @@ __global__ __launch_bounds__(BS) void rollout_kernel(const Consts* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of one segment of ncalls calls x nsub substeps.
-//  ckpt: state at the segment start ([27][Q]); act/gact: the segment's
-//  first call; tape: scratch [ncalls nsub][27][Q]; lam: [27][Q] adjoint of
-//  the state, dL/d(segment end) in, dL/d(segment start) out; gpen: dL/d pen
-//  (PEN); gpar: [6][Q] dL/d(m, ixx, iyy, izz, t2w, tau), accumulated.
+// Backward pass of a rollout, two launches per chunk of checkpoint segments
+// (a segment: ce calls from one checkpoint).
+//
+// recompute_kernel, grid (workgroups, segments of the chunk): workgroup
+// (b, g) re-runs segment g of the chunk from its checkpoint ckpt + g 27 Q
+// and tapes the state at the start of every substep, tape[k][27][Q] for the
+// chunk's k-th substep.  Given the checkpoints the segments are independent,
+// so a chunk is recomputed in one parallel launch.
+//  act: the chunk's first call; ncalls: calls in the chunk; t0: substep
+//  index of the chunk's first substep.
+// ---------------------------------------------------------------------------
+template <int BS, int N>
+__global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict__ cp, Ptrs p,
+                                                       const float* __restrict__ ckpt,
+                                                       const float* __restrict__ act, int ncalls,
+                                                       int ce, int nsub, unsigned long long t0,
+                                                       float* __restrict__ tape) {
+  __shared__ float sxv[2][9][BS];
+  const Consts& c = *cp;
+  const int tid = threadIdx.x;
+  int qb, cnt, ls, n;
+  block_map<BS, N>(p, tid, qb, cnt, ls, n);
+  const bool live = tid < cnt;
+  const int q = qb + (live ? tid : 0);
+  const int me = tid - ls;
+  const long long Q = p.Q;
+  const int c0 = blockIdx.y * ce;
+  const int nc = min(ce, ncalls - c0);
+  const bool pairs = N != 1 && (c.flags & (F_COLLIDE | F_DOWNWASH)) != 0;
+
+  Quad s;
+  QuadPar pp;
+  ParAdj pa;
+  if (live) {
+    load_state(ckpt + (long long)blockIdx.y * NSTATE * Q, Q, q, s);
+    load_params(p, c, q, pp, pa);
+  }
+  int sidx = c0 * nsub;
+  for (int call = c0; call < c0 + nc; ++call) {
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a4;
+    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
+    for (int sub = 0; sub < nsub; ++sub, ++sidx) {
+      const unsigned long long t = t0 + (unsigned long long)sidx;
+      if (live) {
+        store_state(tape + (long long)sidx * NSTATE * Q, Q, q, s);
+        quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+      }
+      if (pairs) {
+        float(*tile)[BS] = sxv[sidx & 1];
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            tile[k][tid] = s.xo[k];
+            tile[3 + k][tid] = s.inc[k];
+            tile[6 + k][tid] = s.v[k];
+          }
+        }
+        __syncthreads();
+        float unused = 0.f;
+        if (live) pair_pass<BS, N, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reverse_kernel: the reverse sweep over the chunk's ncalls nsub substeps,
+// last to first, from the tape; the adjoint of the state stays in
+// registers for the whole chunk and the tape row of the next substep to
+// process is loaded while the current one is differentiated.
+//  lam: [27][Q] dL/d(chunk end) in, dL/d(chunk start) out; gpen: dL/d pen
+//  (PEN); act/gact: the chunk's first call; gpar: [6][Q]
+//  dL/d(m, ixx, iyy, izz, t2w, tau), accumulated.
 // ---------------------------------------------------------------------------
 template <int BS, int N, bool PEN>
-__global__ __launch_bounds__(BS) void adjoint_kernel(const Consts* __restrict__ cp, Ptrs p,
-                                                     const float* __restrict__ ckpt,
+__global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ cp, Ptrs p,
                                                      const float* __restrict__ act, int ncalls,
                                                      int nsub, unsigned long long t0,
-                                                     float* __restrict__ tape,
+                                                     const float* __restrict__ tape,
                                                      float* __restrict__ lam,
                                                      const float* __restrict__ gpen, float beta,
                                                      float* __restrict__ gact,
@@ -208,43 +277,16 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(const Consts* __restrict__ 
   const bool pairs = N != 1 && (collide || PEN);
   float(*tile)[BS] = tl;
 
-  Quad s;
+  Quad s, sn;
   QuadPar pp;
   ParAdj pa;
+  const int n_steps = ncalls * nsub;
   if (live) {
-    load_state(ckpt, Q, q, s);
     load_params(p, c, q, pp, pa);
+    load_state(tape + (long long)(n_steps - 1) * NSTATE * Q, Q, q, sn);
   }
   if constexpr (PEN) {
     tl[12][tid] = live ? gpen[q] : 0.f;
-  }
-  // ---- recompute the segment, taping the state at each substep's start
-  int sidx = 0;
-  for (int call = 0; call < ncalls; ++call) {
-    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
-    float4 a4;
-    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
-    for (int sub = 0; sub < nsub; ++sub, ++sidx) {
-      const unsigned long long t = t0 + (unsigned long long)sidx;
-      if (live) {
-        store_state(tape + (long long)sidx * NSTATE * Q, Q, q, s);
-        quad_substep(c, pp, s, uhat, (uint32_t)q, t);
-      }
-      if (collide && N != 1) {
-        __syncthreads();  // previous readers of the tile are done
-        if (live) {
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            tile[k][tid] = s.xo[k];
-            tile[3 + k][tid] = s.inc[k];
-            tile[6 + k][tid] = s.v[k];
-          }
-        }
-        __syncthreads();
-        float unused = 0.f;
-        if (live) pair_pass<BS, N, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
-      }
-    }
   }
 
   // ---- reverse sweep
@@ -274,7 +316,8 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(const Consts* __restrict__ 
       const unsigned long long t = t0 + (unsigned long long)k_s;
       Rec r;
       if (live) {
-        load_state(tape + (long long)k_s * NSTATE * Q, Q, q, s);
+        s = sn;
+        if (k_s > 0) load_state(tape + (long long)(k_s - 1) * NSTATE * Q, Q, q, sn);
         quad_substep<true>(c, pp, s, uhat, (uint32_t)q, t, &r);
       }
       if (pairs) {
@@ -291,21 +334,16 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(const Consts* __restrict__ 
         // which quads responded, and the adjoint of their velocity change
         bool hit = false;
         if (live && collide) {
-          auto mark = [&](int jj) {
+          auto mark = [&](int jj, const float* pj) {
             const int j = ls + jj;
             float dx, dy, dz, d2;
-            if (pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2)) {
+            if (pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2)) {
               float nn[3], sp;
               pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
               if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
             }
           };
-          if constexpr (N > 0) {
-#pragma unroll
-            for (int jj = 0; jj < N; ++jj) mark(jj);
-          } else {
-            for (int jj = 0; jj < n; ++jj) mark(jj);
-          }
+          for_partners<BS, N>(tile, ls, n, mark);
         }
         float ldv[3] = {0.f, 0.f, 0.f};
         if (live && hit) {
@@ -321,15 +359,17 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(const Consts* __restrict__ 
         }
         __syncthreads();
         if (live) {
-          auto pvjp = [&](int jj) {
+          const float g_me = PEN ? tile[12][tid] : 0.f;
+          auto pvjp = [&](int jj, const float* pj) {
             const int j = ls + jj;
             float dx, dy, dz, d2;
-            const bool con = pair_geom<BS>(c, tile, s, j, jj, me, dx, dy, dz, d2);
+            const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
             if constexpr (PEN) {
               if (jj != me && d2 > 0.f) {
-                const float dd = sqrtf(d2);
-                const float coef = -0.5f * (tile[12][tid] + tile[12][j]) *
-                                   sigmoidf(beta * (c.dcol - dd)) / dd;
+                // d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d
+                const float rd = __builtin_amdgcn_rsqf(d2);
+                const float coef = -0.5f * (g_me + pj[6]) *
+                                   sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd;
                 l.x[0] = fmaf(coef, dx, l.x[0]);
                 l.x[1] = fmaf(coef, dy, l.x[1]);
                 l.x[2] = fmaf(coef, dz, l.x[2]);
@@ -358,12 +398,7 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(const Consts* __restrict__ 
               }
             }
           };
-          if constexpr (N > 0) {
-#pragma unroll
-            for (int jj = 0; jj < N; ++jj) pvjp(jj);
-          } else {
-            for (int jj = 0; jj < n; ++jj) pvjp(jj);
-          }
+          for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, pvjp);
         }
       }
       if (live) quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
