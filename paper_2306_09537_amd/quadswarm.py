@@ -125,9 +125,14 @@ def _ptr(t) -> int:
     return int(t.data_ptr())
 
 
-def _stream():
+def _stream(device_index=None):
+    """The current HIP stream of the device, as the C ABI's void*."""
     import torch
-    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    idx = torch.cuda.current_device() if device_index is None else device_index
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:  # no Stream object: a few microseconds less per call
+        return raw(idx)
+    return torch.cuda.current_stream(idx).cuda_stream
 
 
 class QuadSwarm:
@@ -148,6 +153,7 @@ class QuadSwarm:
         _check(lib().qs_sizes(h, C.byref(q), C.byref(e), C.byref(od)), "qs_sizes")
         self.n_quads, self.n_envs, self.obs_dim = q.value, e.value, od.value
         self.device = torch.device("cuda", torch.cuda.current_device())
+        self._di = self.device.index
 
     @classmethod
     def from_workload(cls, w: "W.Workload") -> "QuadSwarm":
@@ -166,7 +172,7 @@ class QuadSwarm:
     # -- API ---------------------------------------------------------------
     def step(self, actions, n_substeps: int = 1) -> None:
         a = self._dev(actions, (self.n_quads, 4))
-        _check(lib().qs_step(self._h, _ptr(a), int(n_substeps), _stream()), "qs_step")
+        _check(lib().qs_step(self._h, _ptr(a), int(n_substeps), _stream(self._di)), "qs_step")
 
     def observe(self, goals, out=None):
         import torch
@@ -174,7 +180,7 @@ class QuadSwarm:
         o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
                                                     device=self.device)
         self._dev(o, (self.n_quads, self.obs_dim))
-        _check(lib().qs_observe(self._h, _ptr(g), _ptr(o), _stream()), "qs_observe")
+        _check(lib().qs_observe(self._h, _ptr(g), _ptr(o), _stream(self._di)), "qs_observe")
         return o
 
     def step_observe(self, actions, n_substeps: int, goals, out=None):
@@ -185,7 +191,7 @@ class QuadSwarm:
                                                     device=self.device)
         self._dev(o, (self.n_quads, self.obs_dim))
         _check(lib().qs_step_observe(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
-                                     _stream()), "qs_step_observe")
+                                     _stream(self._di)), "qs_step_observe")
         return o
 
     def set_reward_weights(self, weights) -> None:
@@ -206,7 +212,7 @@ class QuadSwarm:
         self._dev(o, (self.n_quads, self.obs_dim))
         self._dev(r, (self.n_quads,))
         _check(lib().qs_step_observe_reward(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
-                                            _ptr(r), _stream()), "qs_step_observe_reward")
+                                            _ptr(r), _stream(self._di)), "qs_step_observe_reward")
         return o, r
 
     def get_state(self, out=None):
@@ -214,7 +220,7 @@ class QuadSwarm:
         o = out if out is not None else torch.empty((self.n_quads, 27), device=self.device)
         self._dev(o, (self.n_quads, 27))
         t = C.c_uint64()
-        _check(lib().qs_get_state(self._h, _ptr(o), C.byref(t), _stream()), "qs_get_state")
+        _check(lib().qs_get_state(self._h, _ptr(o), C.byref(t), _stream(self._di)), "qs_get_state")
         return o, int(t.value)
 
     def set_state(self, state, substep: int, env_mask=None) -> None:
@@ -224,7 +230,7 @@ class QuadSwarm:
         if env_mask is not None:
             m = self._dev(env_mask, (self.n_envs,), torch.uint8)
         _check(lib().qs_set_state(self._h, _ptr(s), C.c_uint64(int(substep)),
-                                  None if m is None else _ptr(m), _stream()), "qs_set_state")
+                                  None if m is None else _ptr(m), _stream(self._di)), "qs_set_state")
 
     def record_contacts(self, enable: bool = True) -> None:
         _check(lib().qs_record_contacts(self._h, 1 if enable else 0), "qs_record_contacts")
@@ -232,7 +238,7 @@ class QuadSwarm:
     def debug_contacts(self):
         import torch
         o = torch.empty(self.n_quads, dtype=torch.int64, device=self.device)
-        _check(lib().qs_debug_contacts(self._h, _ptr(o), _stream()), "qs_debug_contacts")
+        _check(lib().qs_debug_contacts(self._h, _ptr(o), _stream(self._di)), "qs_debug_contacts")
         return o
 
     @property
@@ -255,7 +261,7 @@ class QuadSwarm:
         _check(lib().qs_rollout(self._h, _ptr(a), n_calls, int(n_substeps), int(ckpt_every),
                                 None if ckpt is None else _ptr(ckpt),
                                 None if penalty is None else _ptr(penalty), float(beta),
-                                _stream()), "qs_rollout")
+                                _stream(self._di)), "qs_rollout")
 
     def rollout_backward(self, actions, n_substeps: int, ckpt_every: int, ckpt,
                          substep_index0: int, gstate, gpenalty, beta: float, gactions,
@@ -272,7 +278,7 @@ class QuadSwarm:
             self._h, _ptr(actions), n_calls, int(n_substeps), int(ckpt_every), _ptr(ckpt),
             C.c_uint64(int(substep_index0)), _ptr(gstate),
             None if gpenalty is None else _ptr(gpenalty), float(beta), _ptr(gactions),
-            _ptr(gparams), _stream()), "qs_rollout_backward")
+            _ptr(gparams), _stream(self._di)), "qs_rollout_backward")
 
     def step_backward(self, state_in, actions, n_substeps: int, substep_index: int,
                       gstate_out, gstate_in, gactions, gparams) -> None:
@@ -283,10 +289,10 @@ class QuadSwarm:
         _check(lib().qs_step_backward(self._h, _ptr(state_in), _ptr(actions), int(n_substeps),
                                       C.c_uint64(int(substep_index)), _ptr(gstate_out),
                                       _ptr(gstate_in), _ptr(gactions), _ptr(gparams),
-                                      _stream()), "qs_step_backward")
+                                      _stream(self._di)), "qs_step_backward")
 
     def set_graph_mode(self, enable: bool = True) -> None:
-        _check(lib().qs_set_graph_mode(self._h, 1 if enable else 0, _stream()),
+        _check(lib().qs_set_graph_mode(self._h, 1 if enable else 0, _stream(self._di)),
                "qs_set_graph_mode")
 
     def set_launch(self, block: int, grid: int = 0) -> None:
@@ -298,12 +304,12 @@ class QuadSwarm:
         ch = (C.c_int32 * 3)()
         _check(lib().qs_autotune(self._h, _ptr(actions), int(n_substeps),
                                  None if goals is None else _ptr(goals),
-                                 None if out is None else _ptr(out), ch, _stream()),
+                                 None if out is None else _ptr(out), ch, _stream(self._di)),
                "qs_autotune")
         return {"block": ch[0], "grid": ch[1], "bucketed": bool(ch[2])}
 
     def sync(self) -> None:
-        _check(lib().qs_sync(self._h, _stream()), "qs_sync")
+        _check(lib().qs_sync(self._h, _stream(self._di)), "qs_sync")
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
