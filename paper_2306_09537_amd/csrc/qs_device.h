@@ -85,20 +85,26 @@ __device__ __forceinline__ float u01(uint32_t r) {
   return (float)(((r >> 9) << 1) | 1u) * 5.9604644775390625e-8f;
 }
 
-// Four N(0,1) draws by Box-Muller for (quad, substep, stream, draw).
+// Four N(0,1) draws by Box-Muller for (quad, substep, stream, draw):
+// radius sqrt(-2 ln u0) = sqrt(-2 ln2 log2 u0), angle 2 pi u1.  The hardware
+// log2, sqrt and the sine/cosine of an angle given in revolutions are used
+// directly: on every u = (2m + 1) 2^-24 their errors are about one ulp
+// (sin/cos 1.3e-7 absolute, log2 1.2e-7 relative, near u = 1 included),
+// giving draws within 6e-7 of the exact ones, at a fraction of the library
+// functions' instruction count.
 __device__ __forceinline__ void normal4(const Consts& c, uint32_t q, uint64_t t,
                                         uint32_t stream, uint32_t draw, float z[4]) {
   uint32_t r0 = q, r1 = (uint32_t)t, r2 = (uint32_t)(t >> 32), r3 = (stream << 8) | draw;
   philox4x32_10(r0, r1, r2, r3, c.key0, c.key1);
-  float s, co;
-  float rad = sqrtf(-2.0f * logf(u01(r0)));
-  sincospif(2.0f * u01(r1), &s, &co);
-  z[0] = rad * co;
-  z[1] = rad * s;
-  rad = sqrtf(-2.0f * logf(u01(r2)));
-  sincospif(2.0f * u01(r3), &s, &co);
-  z[2] = rad * co;
-  z[3] = rad * s;
+  constexpr float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+  float rad = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01(r0)));
+  float a = u01(r1);
+  z[0] = rad * __builtin_amdgcn_cosf(a);
+  z[1] = rad * __builtin_amdgcn_sinf(a);
+  rad = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01(r2)));
+  a = u01(r3);
+  z[2] = rad * __builtin_amdgcn_cosf(a);
+  z[3] = rad * __builtin_amdgcn_sinf(a);
 }
 
 // Per-quad registers.  xo/inc are the substep's start position and
