@@ -27,6 +27,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
+# 4 cycles (16 lanes per cycle) at 2.4 GHz = 614.4 G wave instructions/s,
+# i.e. 39.3 T lane operations/s; FP32 vector FLOP peak (packed FMA) 157.3 TF
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3
+# committed counter summaries of the ten-substep form, per workload
+VALU_PROFILES = {"swarm8": ("step_kernel_swarm4096x8_fused10.md", ""),
+                 "scale32": ("scale_workloads.md", "scale32_")}
 KERNEL_SOURCES = ("paper_2306_09537_amd/csrc/qs_device.h", "paper_2306_09537_amd/csrc/qs_kernels.h")
 STATE_B, PARAM_B, ACT_B, GOAL_B = 108, 24, 16, 12
 
@@ -49,9 +57,10 @@ def kernel_source_hash() -> str:
     return m.hexdigest()[:16]
 
 
-def measured_traffic(profile: str):
-    """HBM bytes per launch from the committed counter summary, or None if
-    the kernel source changed since the counters were taken."""
+def measured_counter(profile: str, key: str):
+    """A per-launch counter value ("key: value" line) from a committed
+    rocprofv3 summary, or None if the kernel source changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(path).read()
@@ -60,9 +69,34 @@ def measured_traffic(profile: str):
     if kernel_source_hash() not in text:
         return None
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch:"):
+        if line.startswith(key + ":"):
             return int(line.split(":")[1])
     return None
+
+
+def measured_traffic(profile: str):
+    """HBM bytes per launch from the committed counter summary."""
+    return measured_counter(profile, "traffic_bytes_per_launch")
+
+
+def valu_roofline(workload: str, nsub: int, ms: float):
+    """ALU roofline of a fused launch from the committed counters: VALU lane
+    operations per second against the issue peak, plus FP32 FLOP/s against
+    the vector peak.  None without counters for this workload and form."""
+    if nsub != 10 or workload not in VALU_PROFILES:
+        return None
+    prof, pre = VALU_PROFILES[workload]
+    insts = measured_counter(prof, pre + "valu_lane_ops_per_launch")
+    flops = measured_counter(prof, pre + "fp32_flops_per_launch")
+    if insts is None or flops is None:
+        return None
+    tops = insts / (ms * 1e-3) / 1e12
+    tflops = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS,
+            "unit": "Tops/s (VALU lane instructions)", "frac": tops / VALU_PEAK_TOPS,
+            "fp32_tflops": tflops, "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS,
+            "valu_lane_ops_per_launch": insts, "fp32_flops_per_launch": flops,
+            "profile": prof}
 
 
 def parse():
@@ -327,6 +361,9 @@ def main():
         extra[f"fused_nsub{ns}"] = dict(
             value=Q * ns / (m2 * 1e-3), ms_per_call=m2,
             speedup_vs_plain=(Q * ns / (m2 * 1e-3)) / value)
+        rl = valu_roofline(args.workload, ns, m2)
+        if rl is not None:
+            extra[f"fused_nsub{ns}"]["roofline"] = rl
 
     line = {
         "metric": "quad-steps/s fwd at 1 MI355X (% of HBM roofline)",

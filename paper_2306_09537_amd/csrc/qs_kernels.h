@@ -23,6 +23,17 @@ namespace qs {
 //              lanes past a swarm's size are padding.
 enum : int { MAP_DENSE = 0, MAP_TABLE = 1, MAP_ITEM = 2 };
 
+// Graph-safe substep counter: every workgroup reads the base substep index
+// from device memory at its start; the last workgroup to finish advances it
+// by nsub.  No ordering beyond atomicity is needed: the last workgroup
+// finishes after every other one has read the counter (each increments
+// `done` after its reads), and the next launch reads the new value after the
+// kernel boundary.  (A release here would write back the XCD's L2 from
+// every workgroup.)
+__device__ __forceinline__ unsigned long long read_counter(const unsigned long long* tdev) {
+  return __hip_atomic_load(tdev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Body of one step (+ observation) over one workgroup's quads.
 // KT: -2 step only; -1 observation with runtime K (selection); >= 0 observation
 // with compile-time K (register insertion network).
@@ -134,7 +145,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   }
   // graph mode: the substep index comes from the device counter (read after
   // the state loads are in flight)
-  if (tdev) t0 = *tdev;
+  if (tdev) t0 = read_counter(tdev);
 
   const bool collide = N != 1 && (c.flags & (F_COLLIDE | F_DOWNWASH)) != 0;
   unsigned long long cmask = 0ull;
@@ -386,19 +397,17 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   }
 }
 
-// Graph-safe substep counter: every workgroup reads the base substep index
-// from device memory; the last workgroup to finish advances it by nsub.
+// The last workgroup to finish advances the graph-mode counter by nsub.
 __device__ __forceinline__ void advance_counter(unsigned long long* tdev, unsigned int* done,
                                                 int nsub) {
-  __syncthreads();
+  __syncthreads();  // every thread of the workgroup has read the counter
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned int prev =
-        __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == gridDim.x - 1) {
       __hip_atomic_fetch_add(tdev, (unsigned long long)nsub, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_exchange(done, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -452,7 +461,7 @@ __global__ __launch_bounds__(BS) void bucket_kernel(float* __restrict__ st,
   p.Qp = Qp;
   p.Q = Q;
   const Consts& c = *cp;
-  if (tdev) t0 = *tdev;
+  if (tdev) t0 = read_counter(tdev);
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int N = p.items[it].x;
     __syncthreads();  // the previous item's readers of the tile are done
