@@ -38,8 +38,10 @@ __device__ __forceinline__ unsigned long long read_counter(const unsigned long l
 // KT: -2 step only; -1 observation with runtime K (selection); >= 0 observation
 // with compile-time K (register insertion network).
 // N: swarm (slot) size known at compile time (MAP_DENSE, MAP_ITEM), or 0.
+// NU: partner count the in-swarm loops are unrolled for (N, or 0 for loops
+// over the swarm's runtime size: fewer registers for large slots).
 // sxv: LDS tile [2][9][BS]; st_obs: LDS staging of observation rows.
-template <int BS, int KT, int N, int MAP>
+template <int BS, int KT, int N, int MAP, int NU = N>
 __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
                                           const float* __restrict__ act, int nsub,
                                           unsigned long long t0,
@@ -176,7 +178,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       cmask = 0ull;
       if (live) {
         float unused = 0.f;
-        cmask = pair_pass<BS, N, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
+        cmask = pair_pass<BS, NU, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
       }
     }
   }
@@ -255,10 +257,10 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           }
           if (bd[0] > d2) { bd[0] = d2; bj[0] = jj; }
         };
-        if constexpr (N > 1) {
-          constexpr int CH = N < 8 ? N : 8;
+        if constexpr (NU > 1) {
+          constexpr int CH = NU < 8 ? NU : 8;
 #pragma unroll
-          for (int j0 = 0; j0 < N; j0 += CH) {
+          for (int j0 = 0; j0 < NU; j0 += CH) {
             float px[CH][3];
 #pragma unroll
             for (int u = 0; u < CH; ++u)
@@ -267,7 +269,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 #pragma unroll
             for (int u = 0; u < CH; ++u) cand(j0 + u, px[u][0], px[u][1], px[u][2]);
           }
-        } else if constexpr (N == 0) {
+        } else if constexpr (NU == 0) {
           if (live)
             for (int jj = 0; jj < n; ++jj)
               cand(jj, tile[0][ls + jj], tile[1][ls + jj], tile[2][ls + jj]);
@@ -465,14 +467,18 @@ __global__ __launch_bounds__(BS) void bucket_kernel(float* __restrict__ st,
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int N = p.items[it].x;
     __syncthreads();  // the previous item's readers of the tile are done
+    // slots of 4 and more loop over the swarm at run time: unrolled, their
+    // bodies would set the whole kernel's register count (one kernel holds
+    // every slot size), and with it the occupancy (135 VGPRs instead of 381:
+    // 3 waves per SIMD instead of 1)
     switch (N) {
       case 1: step_body<BS, KT, 1, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
       case 2: step_body<BS, KT, 2, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 4: step_body<BS, KT, 4, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 8: step_body<BS, KT, 8, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 16: step_body<BS, KT, 16, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 32: step_body<BS, KT, 32, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      default: step_body<BS, KT, 64, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 4: step_body<BS, KT, 4, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 8: step_body<BS, KT, 8, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 16: step_body<BS, KT, 16, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      case 32: step_body<BS, KT, 32, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+      default: step_body<BS, KT, 64, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
     }
   }
   if (tdev) advance_counter(tdev, done, nsub);
