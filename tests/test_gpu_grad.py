@@ -126,6 +126,24 @@ def test_adjoint_matches_oracle(seed, T, nsub, ce):
         assert e <= b
 
 
+def test_adjoint_large_swarms_match_oracle():
+    """Swarms of 32 (in-swarm loops at run time in the differentiation
+    kernels): penalty and gradients against the oracle."""
+    w, acts, Wt, gpen = problem(6, 16, n_envs=3, n=32, spread=0.6)
+    nsub, ce = 1, 5
+    g_ref = oracle_grads(w, acts, nsub, Wt, gpen)
+    tol = bound(w, acts, nsub, Wt, gpen, g_ref, 6)
+    gs, gact, gpar, sT, pen, *_ = gpu_grads(w, acts, nsub, Wt, gpen, ce)
+    _, pen_o = O.Oracle.from_workload(w).rollout(w.state0.astype(np.float64),
+                                                 acts.astype(np.float64), nsub, 0, beta=BETA)
+    assert pen_o.max() > 1e-3
+    np.testing.assert_allclose(pen, pen_o, rtol=2e-4, atol=1e-7)
+    errs = [relerr(gs, g_ref[0]), relerr(gact, g_ref[1]), relerr(gpar, g_ref[2])]
+    print("n = 32 adjoint rel err:", errs, "bounds:", tol)
+    for e, b in zip(errs, tol):
+        assert e <= b
+
+
 def test_step_backward_matches_oracle():
     w, acts, Wt, gpen = problem(5, 1)
     nsub = 3
