@@ -115,6 +115,9 @@ def parse():
     ap.add_argument("--fwdbwd", default="diff", help="workload of the fwd+bwd leg ('' to skip)")
     ap.add_argument("--fwdbwd-horizon", type=int, default=200)
     ap.add_argument("--batched", default="uneven", help="workload of the batched leg ('' to skip)")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the FP64 oracle on samples of every configuration "
+                         "(host cores, no GPU) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of "
                          "known traffic for scaling HBM counters) and exit")
@@ -311,8 +314,61 @@ def cpu_baseline(w, target_s: float):
                        f"substep), FP64, {dt:.1f} s")
 
 
+def cpu_table(seconds: float = 3.0) -> dict:
+    """The FP64 oracle on the host cores for every configuration, each on a
+    bounded sample (the first envs of the workload, a few substeps):
+    quad-steps/s forward (step + K-NN observe per substep) and, for the
+    differentiation workloads, forward + backward (the oracle's reverse mode
+    re-runs its forward, so its whole time counts)."""
+    from oracle import oracle as O
+    from paper_2306_09537_amd import workloads as W
+
+    def fwd(w, e1, max_sub):
+        orc = O.Oracle.from_workload(w, 0, e1)
+        q = int(w.env_offsets[e1])
+        s = w.state0[:q].astype(np.float64)
+        g = w.goals[:q].astype(np.float64)
+        acts = [np.ascontiguousarray(w.actions(i)[:q], dtype=np.float64) for i in range(16)]
+        t0 = time.perf_counter()
+        n = 0
+        while n < max_sub and (n == 0 or time.perf_counter() - t0 < seconds):
+            s, _, _ = orc.step(s, acts[n % 16], 1, n)
+            orc.observe(s, g)
+            n += 1
+        dt = time.perf_counter() - t0
+        return dict(value=q * n / dt, sample=f"{e1} envs ({q} quads) x {n} substeps, {dt:.2f} s")
+
+    def fwd_bwd(w, e1, T):
+        orc = O.Oracle.from_workload(w, 0, e1)
+        q = int(w.env_offsets[e1])
+        rng = np.random.default_rng(0)
+        acts = rng.uniform(0.05, 0.95, size=(T, q, 4))
+        wt = rng.normal(size=(q, 27))
+        gp = np.ones(q)
+        t0 = time.perf_counter()
+        orc.rollout_vjp(w.state0[:q].astype(np.float64), acts, 1, 0, wt, gp, 100.0)
+        dt = time.perf_counter() - t0
+        return dict(value=q * T / dt, sample=f"{e1} envs ({q} quads) x {T} substeps, {dt:.2f} s")
+
+    rows = {
+        "plain_64x1": fwd(W.plain(seed=0), 64, 20000),
+        "swarm_4096x8": fwd(W.swarm8(seed=0), 4096, 1000),
+        "uneven_16384": fwd(W.uneven(seed=0), 16384, 1000),
+        "scale_1048576x1": fwd(W.scale1(seed=0), 1048576, 1000),
+        "scale_32768x32": fwd(W.scale32(seed=0), 4096, 1000),
+        "diff_1024x8 fwd+bwd": fwd_bwd(W.diff(seed=0), 1024, 200),
+        "scale_32768x32 fwd+bwd": fwd_bwd(W.scale32(seed=0), 512, 100),
+    }
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"cpu_table": rows, "unit": "quad-steps/s", "cores": cores, "kind": "oracle",
+            "precision": "f64"}
+
+
 def main():
     args = parse()
+    if args.cpu_table:
+        print(json.dumps(cpu_table()), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the swarm step has no cross-GPU exchange "
               "(environments are independent); run one process per GPU on disjoint "
