@@ -456,8 +456,7 @@ template <int BS, int N, int XR = -1, typename T, typename F>
 __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
   if constexpr (N > 0) {
     constexpr int CH = N < 8 ? N : 8;
-#pragma unroll
-    for (int j0 = 0; j0 < N; j0 += CH) {
+    auto chunk = [&](int j0) {
       float pj[CH][7];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -467,6 +466,15 @@ __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) f(j0 + u, pj[u]);
+    };
+    if constexpr (N > 16) {
+      // large swarms: a run-time loop over the chunks keeps the registers
+      // of an eight-partner body
+#pragma unroll 1
+      for (int j0 = 0; j0 < N; j0 += CH) chunk(j0);
+    } else {
+#pragma unroll
+      for (int j0 = 0; j0 < N; j0 += CH) chunk(j0);
     }
   } else {
     for (int jj = 0; jj < n; ++jj) {

@@ -259,8 +259,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
         };
         if constexpr (NU > 1) {
           constexpr int CH = NU < 8 ? NU : 8;
-#pragma unroll
-          for (int j0 = 0; j0 < NU; j0 += CH) {
+          auto chunk = [&](int j0) {
             float px[CH][3];
 #pragma unroll
             for (int u = 0; u < CH; ++u)
@@ -268,6 +267,13 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
               for (int r = 0; r < 3; ++r) px[u][r] = tile[r][ls + j0 + u];
 #pragma unroll
             for (int u = 0; u < CH; ++u) cand(j0 + u, px[u][0], px[u][1], px[u][2]);
+          };
+          if constexpr (NU > 16) {
+#pragma unroll 1
+            for (int j0 = 0; j0 < NU; j0 += CH) chunk(j0);
+          } else {
+#pragma unroll
+            for (int j0 = 0; j0 < NU; j0 += CH) chunk(j0);
           }
         } else if constexpr (NU == 0) {
           if (live)

@@ -11,11 +11,12 @@
 
 namespace qs {
 
-// Partner count the in-swarm loops of the differentiation kernels are
-// unrolled for: swarms of 16 and more loop at run time.  Their register
-// counts (the adjoint's intermediates, the penalty) otherwise limit the
-// occupancy: at 32768 x 32 run-time loops made forward and backward 1.5x
-// faster, while the step kernel is faster unrolled.
+// Partner count the forward rollout's in-swarm loop is unrolled for:
+// swarms of 16 and more loop one partner at a time at run time (its
+// penalty terms otherwise set a register count that limits the occupancy;
+// 6.4 -> 4.2 ms at 32768 x 32).  The backward kernels use chunks of eight
+// partners in a run-time loop for large swarms (for_partners), which
+// measured faster there (14.6 -> 13.0 ms).
 template <int N>
 constexpr int kUnroll = N < 16 ? N : 0;
 
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
         }
         __syncthreads();
         float unused = 0.f;
-        if (live) pair_pass<BS, kUnroll<N>, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
+        if (live) pair_pass<BS, N, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
       }
     }
   }
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
               if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
             }
           };
-          for_partners<BS, kUnroll<N>>(tile, ls, n, mark);
+          for_partners<BS, N>(tile, ls, n, mark);
         }
         float ldv[3] = {0.f, 0.f, 0.f};
         if (live && hit) {
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
               }
             }
           };
-          for_partners<BS, kUnroll<N>, PEN ? 12 : -1>(tile, ls, n, pvjp);
+          for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, pvjp);
         }
       }
       if (live) quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
