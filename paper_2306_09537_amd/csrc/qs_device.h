@@ -447,6 +447,10 @@ __device__ __forceinline__ float sigmoid_hw(float x) {
   return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-x * 1.4426950408889634f));
 }
 
+// compile-time booleans for generic lambdas
+struct TrueT { static constexpr bool value = true; };
+struct FalseT { static constexpr bool value = false; };
+
 // Calls f(jj, pj) for every swarm-mate jj of the lane's swarm (itself
 // included), pj[0..5] being its start position and displacement from rows
 // 0-5 of the tile and pj[6] row XR (XR < 0: none).  For a compile-time swarm
@@ -505,30 +509,46 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   float adw = 0.f;
   bool hit = false, dwhit = false;
   const float hb = PEN ? 0.5f / beta : 0.f;  // each quad of a pair carries half
-  auto pair = [&](int jj, const float* pj) {
-    const int j = ls + jj;
+  // Every partner's geometry, branch-free (contacts are rare; a branch per
+  // partner would end the scheduling region and serialise the partners'
+  // arithmetic): the contact set, the penalty and, when it is on (a uniform
+  // choice between two loops), downwash.
+  const float dw_r2 = c.dw_r2, dw_h = c.dw_h, dw_k1 = c.dw_k1, dw_k2 = c.dw_k2, dw_b1 = c.dw_b1;
+  auto pair = [&](int jj, const float* pj, auto with_dw) {
     float dx, dy, dz, d2;
     const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
     if constexpr (PEN) {
-      if (jj != me) pacc += hb * softplus_hw(beta * (c.dcol - __builtin_amdgcn_sqrtf(d2)));
+      const float sp = hb * softplus_hw(beta * (c.dcol - __builtin_amdgcn_sqrtf(d2)));
+      pacc = jj != me ? pacc + sp : pacc;
     }
-    if (collide && con) {
-      cmask |= 1ull << jj;
-      float nn[3], sp;
-      pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
-      if (!(c.flags & F_APPROACH) || sp > 0.f) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) dv[k] = fmaf(sp, nn[k], dv[k]);
-        hit = true;
-      }
-    }
-    // downwash: swarm-mate j above (z_j - z_i = -dz) and overlapping in xy
-    if (dw && jj != me && dx * dx + dy * dy < c.dw_r2 && -dz > 0.f && -dz < c.dw_h) {
-      adw -= c.dw_k1 * (c.dw_k2 * -dz + c.dw_b1);
-      dwhit = true;
+    cmask |= con ? 1ull << jj : 0ull;
+    if constexpr (decltype(with_dw)::value) {
+      // swarm-mate j above (z_j - z_i = -dz) and overlapping in xy
+      const bool dwc = dw & (jj != me) & (dx * dx + dy * dy < dw_r2) & (-dz > 0.f) &
+                       (-dz < dw_h);
+      adw = dwc ? adw - dw_k1 * (dw_k2 * -dz + dw_b1) : adw;
+      dwhit = dwhit | dwc;
     }
   };
-  for_partners<BS, N>(tile, ls, n, pair);
+  if (c.flags & F_DOWNWASH)
+    for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, TrueT{}); });
+  else
+    for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, FalseT{}); });
+  if (!collide) cmask = 0ull;
+  // The responses, for the partners in contact only, in partner order.
+  for (unsigned long long m = cmask; m != 0ull; m &= m - 1ull) {
+    const int jj = __builtin_ctzll(m);
+    const int j = ls + jj;
+    const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
+    float dx, dy, dz, d2, nn[3], sp;
+    pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+    pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+    if (!(c.flags & F_APPROACH) || sp > 0.f) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dv[k] = fmaf(sp, nn[k], dv[k]);
+      hit = true;
+    }
+  }
   if (hit) {
     s.ev |= EVF_QUAD;
     float zv[4] = {0.f, 0.f, 0.f, 0.f}, zw[4] = {0.f, 0.f, 0.f, 0.f};

@@ -342,17 +342,25 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
         __syncthreads();
         // which quads responded, and the adjoint of their velocity change
         bool hit = false;
+        unsigned long long cm = 0ull;  // contact set of this substep
         if (live && collide) {
+          // contact set branch-free over all partners, the approach test
+          // for the (rare) contacts only
           auto mark = [&](int jj, const float* pj) {
-            const int j = ls + jj;
             float dx, dy, dz, d2;
-            if (pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2)) {
-              float nn[3], sp;
-              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
-              if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
-            }
+            cm |= pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2) ? 1ull << jj : 0ull;
           };
           for_partners<BS, N>(tile, ls, n, mark);
+          for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
+            const int jj = __builtin_ctzll(m);
+            const int j = ls + jj;
+            const float pj[6] = {tile[0][j], tile[1][j], tile[2][j],
+                                 tile[3][j], tile[4][j], tile[5][j]};
+            float dx, dy, dz, d2, nn[3], sp;
+            pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+            pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+            if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
+          }
         }
         float ldv[3] = {0.f, 0.f, 0.f};
         if (live && hit) {
@@ -368,24 +376,33 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
         }
         __syncthreads();
         if (live) {
-          const float g_me = PEN ? tile[12][tid] : 0.f;
-          auto pvjp = [&](int jj, const float* pj) {
+          if constexpr (PEN) {
+            // d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d,
+            // branch-free over all partners
+            const float g_me = tile[12][tid];
+            auto pvjp = [&](int jj, const float* pj) {
+              float dx, dy, dz, d2;
+              pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+              const float rd = __builtin_amdgcn_rsqf(d2);
+              const float coef = (jj != me && d2 > 0.f)
+                                     ? -0.5f * (g_me + pj[6]) *
+                                           sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
+                                     : 0.f;
+              l.x[0] = fmaf(coef, dx, l.x[0]);
+              l.x[1] = fmaf(coef, dy, l.x[1]);
+              l.x[2] = fmaf(coef, dz, l.x[2]);
+            };
+            for_partners<BS, N, 12>(tile, ls, n, pvjp);
+          }
+          // adjoint of the responses, for the partners in contact
+          for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
+            const int jj = __builtin_ctzll(m);
             const int j = ls + jj;
-            float dx, dy, dz, d2;
-            const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
-            if constexpr (PEN) {
-              if (jj != me && d2 > 0.f) {
-                // d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d
-                const float rd = __builtin_amdgcn_rsqf(d2);
-                const float coef = -0.5f * (g_me + pj[6]) *
-                                   sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd;
-                l.x[0] = fmaf(coef, dx, l.x[0]);
-                l.x[1] = fmaf(coef, dy, l.x[1]);
-                l.x[2] = fmaf(coef, dz, l.x[2]);
-              }
-            }
-            if (collide && con) {
-              float nn[3], sp;
+            const float pj[6] = {tile[0][j], tile[1][j], tile[2][j],
+                                 tile[3][j], tile[4][j], tile[5][j]};
+            {
+              float dx, dy, dz, d2, nn[3], sp;
+              pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
               pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
               if (!(c.flags & F_APPROACH) || sp > 0.f) {
                 const float mu[3] = {ldv[0] - tile[9][j], ldv[1] - tile[10][j],
@@ -406,8 +423,7 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
                 }
               }
             }
-          };
-          for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, pvjp);
+          }
         }
       }
       if (live) quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
