@@ -205,7 +205,14 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     r->F[2] = Fz;
     r->rest = rest;
   }
-  if (!rest) {
+  // Free flight is computed for every lane (one scheduling region); the
+  // rare resting lane then redoes the substep from the saved start values.
+  const float v0r[2] = {s.v[0], s.v[1]};
+  float R0r[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R0r[k] = s.R[k];
+  const float fl0 = s.fl;
+  {
     s.fl = 0.0f;
     const float dm = c.drag * p.inv_m;
     const float ax = fmaf(Fx, p.inv_m, -dm * s.v[0]);
@@ -273,12 +280,18 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     s.R[2] = c0[1] * c1[2] - c0[2] * c1[1];
     s.R[5] = c0[2] * c1[0] - c0[0] * c1[2];
     s.R[8] = c0[0] * c1[1] - c0[1] * c1[0];
-  } else {
+  }
+  if (rest) {
     // §III-B.3 resting on the floor: friction in xy, no vertical motion,
     // no rotation; static friction when still, kinetic when sliding.
+    s.fl = fl0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s.R[k] = R0r[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.x[k] = s.xo[k];  // the substep's start position
     const float mu_n = c.mu * (p.m * c.g - Fz);
     float fbx, fby;
-    const float vx0 = s.v[0], vy0 = s.v[1];
+    const float vx0 = v0r[0], vy0 = v0r[1];
     if (vx0 == 0.0f && vy0 == 0.0f) {
       const float nf = sqrtf(Fx * Fx + Fy * Fy);
       const float mag = fmaxf(nf - mu_n, 0.0f);
@@ -325,27 +338,31 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     const float hi[3] = {c.rmax0, c.rmax1, c.rmax2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      if (k < 2 && s.x[k] < lo[k]) {
-        s.x[k] = lo[k];
-        s.inc[k] = s.x[k] - s.xo[k];
-        if constexpr (REC) r->clamp[k] = true;
-        if (s.v[k] < 0.0f) {
-          s.v[k] = -c.e_wall * s.v[k];
-          b = true;
-          s.ev |= EVF_WALL;
-          if constexpr (REC) r->flip[k] = true;
+      // selects, not branches: hits are rare and the rest of the substep
+      // stays one scheduling region
+      if (k < 2) {
+        const bool out = s.x[k] < lo[k];
+        const bool flip = out && s.v[k] < 0.0f;
+        s.x[k] = out ? lo[k] : s.x[k];
+        s.inc[k] = out ? s.x[k] - s.xo[k] : s.inc[k];
+        s.v[k] = flip ? -c.e_wall * s.v[k] : s.v[k];
+        b = b | flip;
+        s.ev |= flip ? (uint32_t)EVF_WALL : 0u;
+        if constexpr (REC) {
+          r->clamp[k] = r->clamp[k] | out;
+          r->flip[k] = r->flip[k] | flip;
         }
       }
-      if (s.x[k] > hi[k]) {
-        s.x[k] = hi[k];
-        s.inc[k] = s.x[k] - s.xo[k];
-        if constexpr (REC) r->clamp[k] = true;
-        if (s.v[k] > 0.0f) {
-          s.v[k] = -c.e_wall * s.v[k];
-          b = true;
-          s.ev |= k == 2 ? EVF_CEILING : EVF_WALL;
-          if constexpr (REC) r->flip[k] = true;
-        }
+      const bool out = s.x[k] > hi[k];
+      const bool flip = out && s.v[k] > 0.0f;
+      s.x[k] = out ? hi[k] : s.x[k];
+      s.inc[k] = out ? s.x[k] - s.xo[k] : s.inc[k];
+      s.v[k] = flip ? -c.e_wall * s.v[k] : s.v[k];
+      b = b | flip;
+      s.ev |= flip ? (uint32_t)(k == 2 ? EVF_CEILING : EVF_WALL) : 0u;
+      if constexpr (REC) {
+        r->clamp[k] = r->clamp[k] | out;
+        r->flip[k] = r->flip[k] | flip;
       }
     }
     if constexpr (REC) r->bounced = b;
