@@ -60,22 +60,21 @@ __device__ __forceinline__ void quad_vjp(const Consts& c, const QuadPar& p, cons
     l.R[3] = g3;
     l.R[4] = g4;
   }
-  // walls: decay once, then per-axis mirror and clamp
-  if (r.bounced) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) l.v[k] *= c.col_decay;
-  }
+  // walls: decay once, then per-axis mirror and clamp (selects: rare events
+  // must not split the scheduling region)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (r.flip[k]) l.v[k] *= -c.e_wall;
-    if (r.clamp[k]) l.x[k] = 0.f;
+    l.v[k] = r.bounced ? l.v[k] * c.col_decay : l.v[k];
+    l.v[k] = r.flip[k] ? l.v[k] * -c.e_wall : l.v[k];
+    l.x[k] = r.clamp[k] ? 0.f : l.x[k];
   }
 
   float lT = 0.f, lF[3] = {0.f, 0.f, 0.f}, lt[3] = {0.f, 0.f, 0.f};
   float lm = 0.f, lJ[3] = {0.f, 0.f, 0.f};
   float lP[9], lv0[3], lw0[3];
   const float J[3] = {pa.jx, pa.jy, pa.jz};
-  if (!r.rest) {
+  // free flight for every lane; a resting lane (rare) redoes this part below
+  {
     // R = Gram-Schmidt(A): c2 = c0 x c1, c1 = b/|b|, b = A1 - (c0.A1) c0, c0 = A0/|A0|
     float lc0[3] = {l.R[0], l.R[3], l.R[6]}, lc1[3] = {l.R[1], l.R[4], l.R[7]};
     const float lc2[3] = {l.R[2], l.R[5], l.R[8]};
@@ -144,8 +143,12 @@ __device__ __forceinline__ void quad_vjp(const Consts& c, const QuadPar& p, cons
       lF[k] = lacc * p.inv_m;
       lm -= (r.F[k] - c.drag * r.v0[k]) * lacc * p.inv_m * p.inv_m;
     }
-  } else {
+  }
+  if (r.rest) {
     // resting: R held, omega zeroed, v_z zeroed, x_z unchanged
+    lm = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lF[k] = lt[k] = lJ[k] = 0.f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) lP[k] = l.R[k];
 #pragma unroll
@@ -191,6 +194,7 @@ __device__ __forceinline__ void quad_vjp(const Consts& c, const QuadPar& p, cons
   const float sx[4] = {-1.f, -1.f, 1.f, 1.f}, sy[4] = {-1.f, 1.f, 1.f, -1.f},
               sz[4] = {1.f, -1.f, 1.f, -1.f};
   float lfmax = 0.f, lalag = 0.f;
+  const bool noise = (c.flags & F_NOISE) != 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float lf = lT + c.arm_d * (sx[i] * lt[0] + sy[i] * lt[1]) + c.k_tau * sz[i] * lt[2];
@@ -198,12 +202,8 @@ __device__ __forceinline__ void quad_vjp(const Consts& c, const QuadPar& p, cons
     const float le1 = l.e[i] + lf;
     lfmax = fmaf(r.u1[i] * r.u1[i], lf, lfmax);
     // motor noise e1 = a_nd e0 + ns_scale f_max z
-    if (c.flags & F_NOISE) {
-      l.e[i] = c.a_nd * le1;
-      lfmax = fmaf(c.ns_scale * r.z[i], le1, lfmax);
-    } else {
-      l.e[i] = le1;
-    }
+    l.e[i] = noise ? c.a_nd * le1 : le1;
+    lfmax = noise ? fmaf(c.ns_scale * r.z[i], le1, lfmax) : lfmax;
     // motor lag u1 = u0 + a_lag (uhat - u0)
     l.u[i] = (1.0f - p.a_lag) * lu1;
     gu[i] = fmaf(p.a_lag, lu1, gu[i]);
