@@ -27,15 +27,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
-# 4 cycles (16 lanes per cycle) at 2.4 GHz = 614.4 G wave instructions/s,
-# i.e. 39.3 T lane operations/s; FP32 vector FLOP peak (packed FMA) 157.3 TF
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-FP32_PEAK_TFLOPS = 157.3
+# VALU roofline: 256 CUs x 4 SIMDs at 2.4 GHz = 2457.6 G SIMD-cycles/s.  A
+# kernel's VALU busy cycles come from its rocprofv3 counters with per-kind
+# issue costs measured on the chip (calib/valu_probe): a wave64 FP32 add,
+# multiply or FMA occupies a SIMD for 4 cycles, a transcendental for 8,
+# integer and bitwise instructions for 2.  Lower bound: 4 x (ADD + MUL + FMA)
+# + 8 x TRANS + 2 x every other VALU instruction; upper bound: 4 x
+# SQ_ACTIVE_INST_VALU (which counts one quad-cycle per instruction, two per
+# transcendental).  The lower bound is reported as the fraction.
+SIMD_GCYCLES_PER_S = 256 * 4 * 2.4
+FP32_PEAK_TFLOPS = 157.3       # FP32 vector peak (packed FMA)
 # committed counter summaries of the ten-substep form, per workload
 VALU_PROFILES = {"swarm8": ("step_kernel_swarm4096x8_fused10.md", ""),
                  "scale32": ("scale_workloads.md", "scale32_")}
-KERNEL_SOURCES = ("paper_2306_09537_amd/csrc/qs_device.h", "paper_2306_09537_amd/csrc/qs_kernels.h")
+# ... and of the differentiable rollout and its backward pass
+FWDBWD_PROFILES = {"diff_1024x8": ("rollout_reverse_diff1024x8.md", ""),
+                   "scale_32768x32": ("scale_workloads.md", "scale32_")}
+KERNEL_SOURCES = tuple(f"paper_2306_09537_amd/csrc/{f}" for f in
+                       ("qs_device.h", "qs_kernels.h", "qs_rollout.h", "qs_adjoint.h"))
 STATE_B, PARAM_B, ACT_B, GOAL_B = 108, 24, 16, 12
 
 
@@ -79,24 +88,32 @@ def measured_traffic(profile: str):
     return measured_counter(profile, "traffic_bytes_per_launch")
 
 
+def alu_roofline(prof: str, key: str, ms: float):
+    """ALU roofline of a kernel (or kernel sequence) from the committed
+    counters under ``key``: VALU busy SIMD-cycles per second (lower bound)
+    against the chip's SIMD-cycles per second, the upper-bound fraction,
+    and FP32 FLOP/s against the vector peak.  None without counters."""
+    lo = measured_counter(prof, key + "valu_busy_lo_cycles")
+    hi = measured_counter(prof, key + "valu_busy_hi_cycles")
+    flops = measured_counter(prof, key + "fp32_flops")
+    if lo is None or hi is None or flops is None:
+        return None
+    s = ms * 1e-3
+    ach = lo / s / 1e9
+    tflops = flops / s / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": SIMD_GCYCLES_PER_S,
+            "unit": "G SIMD-cycles/s (VALU busy, lower bound)", "frac": ach / SIMD_GCYCLES_PER_S,
+            "frac_upper": hi / s / 1e9 / SIMD_GCYCLES_PER_S, "traffic": None,
+            "fp32_tflops": tflops, "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS,
+            "valu_busy_cycles": [lo, hi], "fp32_flops": flops, "profile": prof}
+
+
 def valu_roofline(workload: str, nsub: int, ms: float):
-    """ALU roofline of a fused launch from the committed counters: VALU lane
-    operations per second against the issue peak, plus FP32 FLOP/s against
-    the vector peak.  None without counters for this workload and form."""
+    """ALU roofline of the ten-substep launch of a workload."""
     if nsub != 10 or workload not in VALU_PROFILES:
         return None
     prof, pre = VALU_PROFILES[workload]
-    insts = measured_counter(prof, pre + "valu_lane_ops_per_launch")
-    flops = measured_counter(prof, pre + "fp32_flops_per_launch")
-    if insts is None or flops is None:
-        return None
-    tops = insts / (ms * 1e-3) / 1e12
-    tflops = flops / (ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS,
-            "unit": "Tops/s (VALU lane instructions)", "frac": tops / VALU_PEAK_TOPS,
-            "fp32_tflops": tflops, "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS,
-            "valu_lane_ops_per_launch": insts, "fp32_flops_per_launch": flops,
-            "profile": prof}
+    return alu_roofline(prof, pre + "fused10_", ms)
 
 
 def parse():
@@ -225,7 +242,20 @@ def time_fwd_bwd(w, torch, horizon: int, nsub: int, ckpt_every: int, reps: int, 
                 bwd_roofline={"bound": "hbm", "achieved": bwd_bytes / (b * 1e-3) / 1e9,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": bwd_bytes / (b * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "bytes": bwd_bytes, "segment_substeps": seg})
+                              "bytes": bwd_bytes, "segment_substeps": seg},
+                fwd_alu=fwdbwd_alu(w.name, horizon, "rollout_", f),
+                bwd_alu=fwdbwd_alu(w.name, horizon, "backward_", b))
+
+
+def fwdbwd_alu(name: str, horizon: int, part: str, ms: float):
+    """ALU roofline of the rollout or of the backward pass (recompute and
+    reverse sweeps together) at the horizon the counters were taken at."""
+    if name not in FWDBWD_PROFILES:
+        return None
+    prof, pre = FWDBWD_PROFILES[name]
+    if measured_counter(prof, pre + "fwdbwd_horizon") != horizon:
+        return None
+    return alu_roofline(prof, pre + part, ms)
 
 
 def sticky_nonfinite(sim, torch) -> int:

@@ -291,26 +291,32 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     for (int k = 0; k < 3; ++k) s.x[k] = s.xo[k];  // the substep's start position
     const float mu_n = c.mu * (p.m * c.g - Fz);
     float fbx, fby;
+    // the record's fields are written once after the branch: stores to
+    // different fields on the two sides get merged into one store through a
+    // selected address, which keeps the record out of registers
+    float rnf = 0.0f, rmag = 0.0f, rnv = 0.0f;
     const float vx0 = v0r[0], vy0 = v0r[1];
-    if (vx0 == 0.0f && vy0 == 0.0f) {
+    const bool still = vx0 == 0.0f && vy0 == 0.0f;
+    if (still) {
       const float nf = sqrtf(Fx * Fx + Fy * Fy);
       const float mag = fmaxf(nf - mu_n, 0.0f);
       const float sc = nf > 0.0f ? mag / nf : 0.0f;
       fbx = sc * Fx;
       fby = sc * Fy;
-      if constexpr (REC) {
-        r->statik = true;
-        r->nf = nf;
-        r->mag = nf > 0.0f ? mag : 0.0f;
-      }
+      rnf = nf;
+      rmag = nf > 0.0f ? mag : 0.0f;
     } else {
       const float nv = sqrtf(vx0 * vx0 + vy0 * vy0);
       const float iv = mu_n / nv;
       fbx = Fx - iv * vx0;
       fby = Fy - iv * vy0;
-      if constexpr (REC) r->nv = nv;
+      rnv = nv;
     }
     if constexpr (REC) {
+      r->statik = still;
+      r->nf = rnf;
+      r->mag = rmag;
+      r->nv = rnv;
       r->mu_n = mu_n;
       r->fb[0] = fbx;
       r->fb[1] = fby;
