@@ -24,6 +24,11 @@
  *  - All device arithmetic is IEEE float32.
  *  - Device pointers: d_actions 16-byte aligned, d_obs and d_mask 8-byte
  *    aligned, others 4-byte aligned (QS_ERR_ALIGN otherwise).
+ *  - The buffers a call writes must not overlap the buffers it reads or
+ *    each other (the result is undefined otherwise; it is not detected),
+ *    except where a call names one buffer as both input and output
+ *    (d_gstate of qs_rollout_backward) or allows it (qs_step_backward:
+ *    d_gstate_in may be d_gstate_out).
  *
  * Canonical layouts (row-major, float32):
  *  state  [Q][27] = x(3) v(3) R(9, row-major, body->world) omega(3, body)
@@ -275,7 +280,9 @@ int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
  * state before the call), d_actions [Q][4], n_substeps and the call's first
  * substep index, map d_gstate_out [Q][27] = dL/d(state after) to
  * d_gstate_in [Q][27] = dL/d(state before) and d_gactions [Q][4], and ADD
- * dL/d(params) into d_gparams [Q][6].  No penalty term.
+ * dL/d(params) into d_gparams [Q][6].  No penalty term.  d_gstate_in may
+ * be the same buffer as d_gstate_out (both are staged through the handle's
+ * scratch).
  */
 int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actions,
                      int32_t n_substeps, uint64_t substep_index, const float* d_gstate_out,

@@ -167,7 +167,23 @@ class QuadSwarm:
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype
                 and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
             raise ValueError(f"expected a contiguous CUDA {dtype} tensor of shape {shape}")
+        if self._di is not None and t.device.index != self._di:
+            raise ValueError(f"tensor on {t.device}, handle on cuda:{self._di}")
         return t
+
+    @staticmethod
+    def _disjoint(writes, reads=()):
+        """The C ABI leaves overlapping output/input buffers undefined: refuse
+        them here (byte ranges of the tensors' storage)."""
+        def span(t):
+            a = t.data_ptr()
+            return a, a + t.numel() * t.element_size()
+        ws = [span(t) for t in writes if t is not None]
+        rs = [span(t) for t in reads if t is not None]
+        for i, (a0, a1) in enumerate(ws):
+            for b0, b1 in ws[i + 1:] + rs:
+                if a0 < b1 and b0 < a1:
+                    raise ValueError("an output buffer overlaps another buffer of the call")
 
     # -- API ---------------------------------------------------------------
     def step(self, actions, n_substeps: int = 1) -> None:
@@ -180,6 +196,7 @@ class QuadSwarm:
         o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
                                                     device=self.device)
         self._dev(o, (self.n_quads, self.obs_dim))
+        self._disjoint([o], [g])
         _check(lib().qs_observe(self._h, _ptr(g), _ptr(o), _stream(self._di)), "qs_observe")
         return o
 
@@ -190,6 +207,7 @@ class QuadSwarm:
         o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
                                                     device=self.device)
         self._dev(o, (self.n_quads, self.obs_dim))
+        self._disjoint([o], [a, g])
         _check(lib().qs_step_observe(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
                                      _stream(self._di)), "qs_step_observe")
         return o
@@ -211,6 +229,7 @@ class QuadSwarm:
         r = reward if reward is not None else torch.empty(self.n_quads, device=self.device)
         self._dev(o, (self.n_quads, self.obs_dim))
         self._dev(r, (self.n_quads,))
+        self._disjoint([o, r], [a, g])
         _check(lib().qs_step_observe_reward(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
                                             _ptr(r), _stream(self._di)), "qs_step_observe_reward")
         return o, r
@@ -254,10 +273,13 @@ class QuadSwarm:
         n_calls = a.shape[0]
         self._dev(a, (n_calls, self.n_quads, 4))
         if ckpt is not None:
+            if ckpt_every <= 0:
+                raise ValueError("checkpoints need ckpt_every >= 1")
             n_ck = (n_calls + ckpt_every - 1) // ckpt_every
             self._dev(ckpt, (n_ck, 27, self.n_quads))
         if penalty is not None:
             self._dev(penalty, (self.n_quads,))
+        self._disjoint([ckpt, penalty], [a])
         _check(lib().qs_rollout(self._h, _ptr(a), n_calls, int(n_substeps), int(ckpt_every),
                                 None if ckpt is None else _ptr(ckpt),
                                 None if penalty is None else _ptr(penalty), float(beta),
@@ -268,12 +290,17 @@ class QuadSwarm:
                          gparams) -> None:
         """qs_rollout_backward (gstate is overwritten with dL/d initial state)."""
         n_calls = actions.shape[0]
+        if ckpt_every <= 0:
+            raise ValueError("the backward pass needs ckpt_every >= 1")
+        n_ck = (n_calls + ckpt_every - 1) // ckpt_every
         self._dev(actions, (n_calls, self.n_quads, 4))
+        self._dev(ckpt, (n_ck, 27, self.n_quads))
         self._dev(gactions, (n_calls, self.n_quads, 4))
         self._dev(gstate, (self.n_quads, 27))
         self._dev(gparams, (self.n_quads, 6))
         if gpenalty is not None:
             self._dev(gpenalty, (self.n_quads,))
+        self._disjoint([gactions, gstate, gparams], [actions, ckpt, gpenalty])
         _check(lib().qs_rollout_backward(
             self._h, _ptr(actions), n_calls, int(n_substeps), int(ckpt_every), _ptr(ckpt),
             C.c_uint64(int(substep_index0)), _ptr(gstate),
@@ -286,6 +313,10 @@ class QuadSwarm:
         for tns, shp in ((state_in, (Q, 27)), (actions, (Q, 4)), (gstate_out, (Q, 27)),
                          (gstate_in, (Q, 27)), (gactions, (Q, 4)), (gparams, (Q, 6))):
             self._dev(tns, shp)
+        # d_gstate_in may be d_gstate_out (staged through the handle's scratch)
+        reads = [state_in, actions] + ([] if gstate_in.data_ptr() == gstate_out.data_ptr()
+                                       else [gstate_out])
+        self._disjoint([gstate_in, gactions, gparams], reads)
         _check(lib().qs_step_backward(self._h, _ptr(state_in), _ptr(actions), int(n_substeps),
                                       C.c_uint64(int(substep_index)), _ptr(gstate_out),
                                       _ptr(gstate_in), _ptr(gactions), _ptr(gparams),
