@@ -343,14 +343,29 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
         // which quads responded, and the adjoint of their velocity change
         bool hit = false;
         unsigned long long cm = 0ull;  // contact set of this substep
-        if (live && collide) {
-          // contact set branch-free over all partners, the approach test
-          // for the (rare) contacts only
+        if (live) {
+          // one branch-free pass over all partners: the contact set and, with
+          // the penalty, its adjoint into lambda_x,
+          //   d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d
+          // (the penalty weights, row 12, were written before the sweep); the
+          // approach test then runs for the (rare) contacts only
+          const float g_me = PEN ? tile[12][tid] : 0.f;
           auto mark = [&](int jj, const float* pj) {
             float dx, dy, dz, d2;
-            cm |= pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2) ? 1ull << jj : 0ull;
+            const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+            cm |= (collide & con) ? 1ull << jj : 0ull;
+            if constexpr (PEN) {
+              const float rd = __builtin_amdgcn_rsqf(d2);
+              const float coef = (jj != me && d2 > 0.f)
+                                     ? -0.5f * (g_me + pj[6]) *
+                                           sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
+                                     : 0.f;
+              l.x[0] = fmaf(coef, dx, l.x[0]);
+              l.x[1] = fmaf(coef, dy, l.x[1]);
+              l.x[2] = fmaf(coef, dz, l.x[2]);
+            }
           };
-          for_partners<BS, N>(tile, ls, n, mark);
+          for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, mark);
           for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
             const int jj = __builtin_ctzll(m);
             const int j = ls + jj;
@@ -376,24 +391,6 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
         }
         __syncthreads();
         if (live) {
-          if constexpr (PEN) {
-            // d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d,
-            // branch-free over all partners
-            const float g_me = tile[12][tid];
-            auto pvjp = [&](int jj, const float* pj) {
-              float dx, dy, dz, d2;
-              pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
-              const float rd = __builtin_amdgcn_rsqf(d2);
-              const float coef = (jj != me && d2 > 0.f)
-                                     ? -0.5f * (g_me + pj[6]) *
-                                           sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
-                                     : 0.f;
-              l.x[0] = fmaf(coef, dx, l.x[0]);
-              l.x[1] = fmaf(coef, dy, l.x[1]);
-              l.x[2] = fmaf(coef, dz, l.x[2]);
-            };
-            for_partners<BS, N, 12>(tile, ls, n, pvjp);
-          }
           // adjoint of the responses, for the partners in contact
           for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
             const int jj = __builtin_ctzll(m);
