@@ -229,13 +229,14 @@ def time_fwd_bwd(w, torch, horizon: int, nsub: int, ckpt_every: int, reps: int, 
     f, b = float(np.median(fwd)), float(np.median(bwd))
     steps = Q * horizon * nsub
     # algorithmic bytes of the backward pass per quad-substep: tape write and
-    # read (2 x 108), actions read twice (2 x 16), action gradient (16); per
+    # read (2 x 124: the state and the motor-noise draws), actions read twice
+    # (2 x 16), action gradient (16); per
     # segment: its checkpoint and the parameters, read by the recompute
     # (108 + 24); once: adjoint in/out (216), parameters and their gradient
     # in the reverse sweep (32 + 48)
     seg = ckpt_every * nsub
     n_seg = (horizon + ckpt_every - 1) // ckpt_every
-    bwd_bytes = Q * horizon * nsub * (216 + 32 + 16) + Q * n_seg * (108 + 24) + Q * (216 + 80)
+    bwd_bytes = Q * horizon * nsub * (248 + 32 + 16) + Q * n_seg * (108 + 24) + Q * (216 + 80)
     return dict(workload=w.name, quads=Q, horizon_substeps=horizon * nsub, ckpt_every=ckpt_every,
                 value=steps / ((f + b) * 1e-3), unit="quad-steps/s (fwd+bwd)",
                 fwd_ms=f, bwd_ms=b, fwd_value=steps / (f * 1e-3),

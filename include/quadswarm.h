@@ -78,12 +78,14 @@ extern "C" {
 #define QS_STATE_DIM 27
 #define QS_PARAM_DIM 6
 #define QS_MAX_SWARM 64
+#define QS_MAX_QUADS (1 << 26) /* quads per handle (67,108,864: 7.2 GB of state) */
 
 typedef struct qs_handle qs_handle;
 
 /*
  * Global constants of one handle.  env_offsets is a host array of n_envs+1
- * non-decreasing int32 (CSR), env_offsets[0] == 0, every swarm 1..64 quads.
+ * non-decreasing int32 (CSR), env_offsets[0] == 0, every swarm 1..64 quads,
+ * at most QS_MAX_QUADS quads in all (QS_ERR_INVALID beyond).
  *  dt               substep length (s), > 0 (200 Hz simulation: 0.005)
  *  gravity          g (m/s^2), acts along -z
  *  arm_length       rotor distance from the centre (m); X layout
@@ -267,7 +269,9 @@ int qs_rollout(qs_handle* h, const float* d_actions, int32_t n_calls, int32_t n_
  * [n_calls][Q][4] and ADDS dL/d(mass, ixx, iyy, izz, thrust_to_weight,
  * motor_tau) into d_gparams [Q][6].  Each segment of ckpt_every calls is
  * recomputed from its checkpoint into a tape of ckpt_every*n_substeps
- * states (device scratch owned by the handle, grown on first use).  Does not
+ * states and motor-noise draws (31 floats per quad and substep; device
+ * scratch owned by the handle, grown on first use, at most the tape budget:
+ * environment QS_TAPE_BYTES, default 8 GiB, and one segment).  Does not
  * change the handle's state.
  */
 int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,

@@ -67,9 +67,12 @@ int check_desc(const qs_desc* d) {
   if (d->n_envs < 1) return QS_ERR_INVALID;
   if (d->env_offsets[0] != 0) return QS_ERR_ENV_SIZE;
   for (int e = 0; e < d->n_envs; ++e) {
-    const int n = d->env_offsets[e + 1] - d->env_offsets[e];
+    const long long n = (long long)d->env_offsets[e + 1] - d->env_offsets[e];
     if (n < 1 || n > QS_MAX_SWARM) return QS_ERR_ENV_SIZE;
   }
+  // field offsets (field * Qp + q) stay within int32 and byte offsets of a
+  // quad within a field within 32 bits
+  if (d->env_offsets[d->n_envs] > QS_MAX_QUADS) return QS_ERR_INVALID;
   const float vals[] = {d->dt, d->gravity, d->arm_length, d->k_tau, d->drag_coef, d->floor_mu,
                         d->motor_noise_decay, d->motor_noise_std, d->room_min[0], d->room_min[1],
                         d->room_min[2], d->room_max[0], d->room_max[1], d->room_max[2],
@@ -436,7 +439,7 @@ void convert(const float* src, float* dst, int Q, int rows, bool to_row_major, b
 int run_adjoint(qs_handle* h, const float* act, int n_calls, int nsub, int ce, const float* ckpt,
                 uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
   const int nseg = (n_calls + ce - 1) / ce;
-  const size_t seg_floats = (size_t)std::min(ce, n_calls) * nsub * qs::NSTATE * h->Q;
+  const size_t seg_floats = (size_t)std::min(ce, n_calls) * nsub * qs::NTAPE * h->Q;
   const size_t fit = tape_budget() / (seg_floats * sizeof(float));
   // segments per chunk (also the recompute grid's y extent, at most 65535)
   const int G = (int)std::max<size_t>(1, std::min<size_t>({(size_t)nseg, fit, (size_t)65535}));

@@ -22,7 +22,8 @@ __device__ __forceinline__ float dot3f(const float a[3], const float b[3]) {
 
 // Physical parameters the adjoint differentiates with respect to.
 struct ParAdj {
-  float m, jx, jy, jz, t2w, tau;
+  float m, jx, jy, jz, t2w;
+  float dlag_dtau;  // d a_lag / d tau = -(1 - a_lag) dt / tau^2
 };
 
 // l: dL/d(state after the floor step) on entry, dL/d(state at the start of
@@ -87,7 +88,7 @@ __device__ __forceinline__ void quad_vjp(const Consts& c, const QuadPar& p, cons
     for (int k = 0; k < 3; ++k) lc1[k] += tmp[k];
     float dd = dot3f(lc1, r.c1);
     float lb[3];
-    const float in1 = 1.0f / r.n1;
+    const float in1 = r.i1;
 #pragma unroll
     for (int k = 0; k < 3; ++k) lb[k] = (lc1[k] - dd * r.c1[k]) * in1;
     const float ldp = -dot3f(lb, r.c0);
@@ -99,7 +100,7 @@ __device__ __forceinline__ void quad_vjp(const Consts& c, const QuadPar& p, cons
     }
     dd = dot3f(lc0, r.c0);
     float lA0[3];
-    const float in0 = 1.0f / r.n0;
+    const float in0 = r.i0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) lA0[k] = (lc0[k] - dd * r.c0[k]) * in0;
     // A0 = P0 + dt (P1 w1z - P2 w1y), A1 = P1 + dt (P2 w1x - P0 w1z) (columns)
@@ -216,7 +217,7 @@ __device__ __forceinline__ void quad_vjp(const Consts& c, const QuadPar& p, cons
   gp[2] += lJ[1];
   gp[3] += lJ[2];
   gp[4] += 0.25f * pa.m * c.g * lfmax;
-  gp[5] += lalag * (-(1.0f - p.a_lag) * dt / (pa.tau * pa.tau));
+  gp[5] = fmaf(lalag, pa.dlag_dtau, gp[5]);
 #pragma unroll
   for (int k = 0; k < 9; ++k) l.R[k] = lP[k];
 #pragma unroll

@@ -136,21 +136,27 @@ __device__ __forceinline__ float rotor_cmd(float a, bool unit) {
 // Intermediates of one substep kept for the reverse sweep (adjoint).
 struct Rec {
   float z[4], u0[4], u1[4], P[9], w0[3], v0[3], T, F[3];
-  float wdot[3], w1[3], A1[3], n0, c0[3], dp, n1, c1[3];
+  float wdot[3], w1[3], A1[3], i0, c0[3], dp, i1, c1[3];  // i0, i1: inverse column norms
   float mu_n, fb[2], nv, nf, mag;
   float hx, hy, nh, kx, ky, nk;
   bool rest, statik, guard, bounced, hit, fallback;
   bool clamp[3], flip[3];
 };
 
+// Where the motor-noise draws of a substep come from: generated (Z_DRAW),
+// generated and also written to zio[4] (Z_EXPORT), or read from zio[4]
+// (Z_IMPORT: the draws an earlier Z_EXPORT run saved for this quad and
+// substep).
+enum ZMode { Z_DRAW, Z_EXPORT, Z_IMPORT };
+
 // One substep of one quad up to (not including) the in-env pair pass:
 // motor lag and noise, thrust and torque mix, floor-rest or free-flight
 // dynamics with semi-implicit Euler and Gram-Schmidt, walls and floor.
 // REC: also record the intermediates the adjoint needs into *r.
-template <bool REC = false>
+template <bool REC = false, ZMode ZM = Z_DRAW>
 __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, Quad& s,
                                              const float uhat[4], uint32_t q, uint64_t t,
-                                             Rec* r = nullptr) {
+                                             Rec* r = nullptr, float* zio = nullptr) {
   if constexpr (REC) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -176,7 +182,16 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
   // §III-A.2 motor noise, AR(1)
   if (c.flags & F_NOISE) {
     float z[4];
-    normal4(c, q, t, STREAM_MOTOR, 0, z);
+    if constexpr (ZM == Z_IMPORT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z[i] = zio[i];
+    } else {
+      normal4(c, q, t, STREAM_MOTOR, 0, z);
+    }
+    if constexpr (ZM == Z_EXPORT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zio[i] = z[i];
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) s.e[i] = fmaf(c.a_nd, s.e[i], p.a_ns * z[i]);
     if constexpr (REC) {
@@ -266,8 +281,8 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
 #pragma unroll
     for (int k = 0; k < 3; ++k) c1[k] *= i1;
     if constexpr (REC) {
-      r->n0 = 1.0f / i0;
-      r->n1 = 1.0f / i1;
+      r->i0 = i0;
+      r->i1 = i1;
       r->dp = dp;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {

@@ -74,6 +74,18 @@ __device__ __forceinline__ void store_state(float* __restrict__ S, long long ld,
   S[S_F * ld + q] = s.fl;
 }
 
+// A tape row: the state at the start of a substep (27 fields) and the
+// motor-noise draws of that substep (4 fields), field-major over Q quads.
+constexpr int NTAPE = NSTATE + 4;
+
+__device__ __forceinline__ void load_draws(const Consts& c, const float* __restrict__ row,
+                                           long long ld, int q, float z[4]) {
+  if (c.flags & F_NOISE) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = row[(NSTATE + i) * ld + q];
+  }
+}
+
 __device__ __forceinline__ void load_params(const Ptrs& p, const Consts& c, int q, QuadPar& pp,
                                             ParAdj& pa) {
   const int Qp = p.Qp;
@@ -93,7 +105,8 @@ __device__ __forceinline__ void load_params(const Ptrs& p, const Consts& c, int 
   pa.jy = pp.jy;
   pa.jz = pp.jz;
   pa.t2w = p.par[P_T2W * Qp + q];
-  pa.tau = p.par[P_TAU * Qp + q];
+  const float tau = p.par[P_TAU * Qp + q];
+  pa.dlag_dtau = -(1.0f - pp.a_lag) * c.dt / (tau * tau);
 }
 
 __device__ __forceinline__ void load_uhat(const Consts& c, const Ptrs& p, const float* act, int q,
@@ -192,9 +205,10 @@ __global__ __launch_bounds__(BS) void rollout_kernel(const Consts* __restrict__ 
 //
 // recompute_kernel, grid (workgroups, segments of the chunk): workgroup
 // (b, g) re-runs segment g of the chunk from its checkpoint ckpt + g 27 Q
-// and tapes the state at the start of every substep, tape[k][27][Q] for the
-// chunk's k-th substep.  Given the checkpoints the segments are independent,
-// so a chunk is recomputed in one parallel launch.
+// and tapes, for the chunk's k-th substep, the state at its start and its
+// motor-noise draws, tape[k][31][Q] (the reverse sweep then re-runs the
+// substep without regenerating the draws).  Given the checkpoints the
+// segments are independent, so a chunk is recomputed in one parallel launch.
 //  act: the chunk's first call; ncalls: calls in the chunk; t0: substep
 //  index of the chunk's first substep.
 // ---------------------------------------------------------------------------
@@ -232,8 +246,14 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
     for (int sub = 0; sub < nsub; ++sub, ++sidx) {
       const unsigned long long t = t0 + (unsigned long long)sidx;
       if (live) {
-        store_state(tape + (long long)sidx * NSTATE * Q, Q, q, s);
-        quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+        float* row = tape + (long long)sidx * NTAPE * Q;
+        store_state(row, Q, q, s);
+        float z[4];
+        quad_substep<false, Z_EXPORT>(c, pp, s, uhat, (uint32_t)q, t, nullptr, z);
+        if (c.flags & F_NOISE) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) row[(NSTATE + i) * Q + q] = z[i];
+        }
       }
       if (pairs) {
         float(*tile)[BS] = sxv[sidx & 1];
@@ -287,12 +307,14 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
   float(*tile)[BS] = tl;
 
   Quad s, sn;
+  float z[4], zn[4] = {0.f, 0.f, 0.f, 0.f};  // motor-noise draws of s and sn
   QuadPar pp;
   ParAdj pa;
   const int n_steps = ncalls * nsub;
   if (live) {
     load_params(p, c, q, pp, pa);
-    load_state(tape + (long long)(n_steps - 1) * NSTATE * Q, Q, q, sn);
+    load_state(tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, sn);
+    load_draws(c, tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, zn);
   }
   if constexpr (PEN) {
     tl[12][tid] = live ? gpen[q] : 0.f;
@@ -326,8 +348,14 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
       Rec r;
       if (live) {
         s = sn;
-        if (k_s > 0) load_state(tape + (long long)(k_s - 1) * NSTATE * Q, Q, q, sn);
-        quad_substep<true>(c, pp, s, uhat, (uint32_t)q, t, &r);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[i] = zn[i];
+        if (k_s > 0) {
+          const float* row = tape + (long long)(k_s - 1) * NTAPE * Q;
+          load_state(row, Q, q, sn);
+          load_draws(c, row, Q, q, zn);
+        }
+        quad_substep<true, Z_IMPORT>(c, pp, s, uhat, (uint32_t)q, t, &r, z);
       }
       if (pairs) {
         __syncthreads();  // previous readers of the tile are done

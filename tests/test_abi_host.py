@@ -117,6 +117,14 @@ def test_create_rejects_bad_arguments_before_any_hip_call():
     s = w.state0.copy()
     s[5, 7] = np.inf
     assert _create(w, state0=s)[0] == -2
+    # more than QS_MAX_QUADS quads in all (refused before parameters or
+    # states are read, so the small arrays of w are never indexed past)
+    limit = {m.group(1): m.group(2) for m in
+             re.finditer(r"#define (QS_MAX_QUADS) \(1 << (\d+)\)", header_text())}
+    n_max = 1 << int(limit["QS_MAX_QUADS"])
+    big = np.arange(0, n_max // 64 + 2, dtype=np.int64) * 64
+    assert big[-1] > n_max
+    assert _create(w, offs=big.astype(np.int32))[0] == -2
 
 
 def test_calls_on_null_handle():
