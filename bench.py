@@ -311,12 +311,19 @@ def time_batched(w, torch, calls: int = 100, nsub: int = 10, reps: int = 3):
     plain_ms, _ = time_calls(sim, w, acts, goals, obs[0], 1, 500, 20, torch, w.substeps)
     plain = Q / (plain_ms * 1e-3)
     sim.close()
-    return dict(workload=w.name, quads=Q, envs=w.n_envs, calls=calls, substeps_per_call=nsub,
-                value=value, unit="quad-steps/s", ms_per_rollout=ms, autotune=choice,
-                nonfinite_quads=nonfinite,
-                form="persistent bucketed launch, 10 substeps per call, 100-call rollout "
-                     "replayed as one captured graph",
-                plain_value=plain, speedup_vs_plain=value / plain)
+    out = dict(workload=w.name, quads=Q, envs=w.n_envs, calls=calls, substeps_per_call=nsub,
+               value=value, unit="quad-steps/s", ms_per_rollout=ms, autotune=choice,
+               nonfinite_quads=nonfinite,
+               form="persistent bucketed launch, 10 substeps per call, 100-call rollout "
+                    "replayed as one captured graph",
+               plain_value=plain, speedup_vs_plain=value / plain)
+    # ALU roofline of one 10-substep call (counters of the autotuned launch)
+    if (w.name, calls, nsub) == ("uneven_16384", 100, 10):
+        rl = alu_roofline("bucket_kernel_uneven16384.md",
+                          f"batched_b{choice['block']}_", ms / calls)
+        if rl is not None:
+            out["roofline"] = rl
+    return out
 
 
 def cpu_baseline(w, target_s: float):

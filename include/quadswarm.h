@@ -24,11 +24,10 @@
  *  - All device arithmetic is IEEE float32.
  *  - Device pointers: d_actions 16-byte aligned, d_obs and d_mask 8-byte
  *    aligned, others 4-byte aligned (QS_ERR_ALIGN otherwise).
- *  - The buffers a call writes must not overlap the buffers it reads or
- *    each other (the result is undefined otherwise; it is not detected),
- *    except where a call names one buffer as both input and output
- *    (d_gstate of qs_rollout_backward) or allows it (qs_step_backward:
- *    d_gstate_in may be d_gstate_out).
+ *  - The device buffers a call writes must not overlap the buffers it
+ *    reads or each other (QS_ERR_INVALID), except where a call names one
+ *    buffer as both input and output (d_gstate of qs_rollout_backward) or
+ *    allows it (qs_step_backward: d_gstate_in may be d_gstate_out).
  *
  * Canonical layouts (row-major, float32):
  *  state  [Q][27] = x(3) v(3) R(9, row-major, body->world) omega(3, body)

@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/quadswarm.h: argument checks,
 // the handle, the environment-to-workgroup partition and the launches.
+#include <initializer_list>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -61,6 +62,29 @@ namespace {
 bool finite(float v) { return std::isfinite(v); }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Byte range [p, p + n) of a caller buffer; a null pointer takes no part.
+struct Span {
+  const void* p;
+  size_t n;
+};
+
+bool overlap(const Span& a, const Span& b) {
+  if (!a.p || !b.p || !a.n || !b.n) return false;
+  const uintptr_t x = (uintptr_t)a.p, y = (uintptr_t)b.p;
+  return x < y + b.n && y < x + a.n;
+}
+
+// Does an output buffer share a byte with another output or with an input?
+bool outputs_overlap(std::initializer_list<Span> outs, std::initializer_list<Span> ins) {
+  for (auto o = outs.begin(); o != outs.end(); ++o) {
+    for (auto o2 = o + 1; o2 != outs.end(); ++o2)
+      if (overlap(*o, *o2)) return true;
+    for (const Span& i : ins)
+      if (overlap(*o, i)) return true;
+  }
+  return false;
+}
 
 int check_desc(const qs_desc* d) {
   if (!d || !d->env_offsets) return QS_ERR_NULL;
@@ -802,6 +826,8 @@ int qs_step(qs_handle* h, const float* d_actions, int32_t n_substeps, void* stre
 int qs_observe(qs_handle* h, const float* d_goals, float* d_obs, void* stream) {
   if (!h || !d_goals || !d_obs) return QS_ERR_NULL;
   if (!aligned(d_goals, 4) || !aligned(d_obs, 8)) return QS_ERR_ALIGN;
+  const size_t Q = (size_t)h->Q;
+  if (outputs_overlap({{d_obs, Q * h->OD * 4}}, {{d_goals, Q * 12}})) return QS_ERR_INVALID;
   return launch(h, nullptr, 0, d_goals, d_obs, true, (hipStream_t)stream);
 }
 
@@ -810,6 +836,9 @@ int qs_step_observe(qs_handle* h, const float* d_actions, int32_t n_substeps,
   if (!h || !d_actions || !d_goals || !d_obs) return QS_ERR_NULL;
   if (n_substeps < 0) return QS_ERR_INVALID;
   if (!aligned(d_actions, 16) || !aligned(d_goals, 4) || !aligned(d_obs, 8)) return QS_ERR_ALIGN;
+  const size_t Q = (size_t)h->Q;
+  if (outputs_overlap({{d_obs, Q * h->OD * 4}}, {{d_actions, Q * 16}, {d_goals, Q * 12}}))
+    return QS_ERR_INVALID;
   return launch(h, d_actions, n_substeps, d_goals, d_obs, true, (hipStream_t)stream);
 }
 
@@ -834,6 +863,10 @@ int qs_step_observe_reward(qs_handle* h, const float* d_actions, int32_t n_subst
   if (!aligned(d_actions, 16) || !aligned(d_goals, 4) || !aligned(d_obs, 8) ||
       !aligned(d_reward, 4))
     return QS_ERR_ALIGN;
+  const size_t Q = (size_t)h->Q;
+  if (outputs_overlap({{d_obs, Q * h->OD * 4}, {d_reward, Q * 4}},
+                      {{d_actions, Q * 16}, {d_goals, Q * 12}}))
+    return QS_ERR_INVALID;
   return launch(h, d_actions, n_substeps, d_goals, d_obs, true, (hipStream_t)stream, d_reward);
 }
 
@@ -909,6 +942,12 @@ int qs_rollout(qs_handle* h, const float* d_actions, int32_t n_calls, int32_t n_
       (d_penalty && !aligned(d_penalty, 4)))
     return QS_ERR_ALIGN;
   if (n_calls == 0 || n_substeps == 0) return QS_OK;
+  {
+    const size_t Q = (size_t)h->Q, n_ck = d_ckpt ? (n_calls + ckpt_every - 1) / ckpt_every : 0;
+    if (outputs_overlap({{d_ckpt, n_ck * qs::NSTATE * Q * 4}, {d_penalty, Q * 4}},
+                        {{d_actions, (size_t)n_calls * Q * 16}}))
+      return QS_ERR_INVALID;
+  }
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
   hipStream_t s = (hipStream_t)stream;
   if (d_penalty)
@@ -933,6 +972,14 @@ int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
   if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_ckpt, 4) ||
       !aligned(d_gstate, 4) || !aligned(d_gparams, 4) || (d_gpenalty && !aligned(d_gpenalty, 4)))
     return QS_ERR_ALIGN;
+  {
+    const size_t Q = (size_t)h->Q, nc = (size_t)std::max(n_calls, 0);
+    const size_t n_ck = (nc + ckpt_every - 1) / ckpt_every;
+    if (outputs_overlap({{d_gactions, nc * Q * 16}, {d_gparams, Q * 24}, {d_gstate, Q * 108}},
+                        {{d_actions, nc * Q * 16}, {d_ckpt, n_ck * qs::NSTATE * Q * 4},
+                         {d_gpenalty, Q * 4}}))
+      return QS_ERR_INVALID;
+  }
   if (n_calls == 0 || n_substeps == 0) return QS_OK;
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
   int rc = ensure_adjoint_scratch(h);
@@ -960,6 +1007,15 @@ int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actio
   if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_state_in, 4) ||
       !aligned(d_gstate_out, 4) || !aligned(d_gstate_in, 4) || !aligned(d_gparams, 4))
     return QS_ERR_ALIGN;
+  {
+    // d_gstate_in may be d_gstate_out itself (both are staged), not a part of it
+    const size_t Q = (size_t)h->Q;
+    const bool same = d_gstate_in == d_gstate_out;
+    if (outputs_overlap({{d_gstate_in, Q * 108}, {d_gactions, Q * 16}, {d_gparams, Q * 24}},
+                        {{d_state_in, Q * 108}, {d_actions, Q * 16},
+                         {same ? nullptr : d_gstate_out, Q * 108}}))
+      return QS_ERR_INVALID;
+  }
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
   int rc = ensure_adjoint_scratch(h);
   if (rc != QS_OK) return rc;

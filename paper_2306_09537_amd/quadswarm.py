@@ -57,6 +57,17 @@ class qs_desc(C.Structure):
 _lib = None
 
 
+_F32 = None
+
+
+def _f32():
+    global _F32
+    if _F32 is None:
+        import torch
+        _F32 = torch.float32
+    return _F32
+
+
 def lib() -> C.CDLL:
     """Load libquadswarm.so (raises if it has not been built)."""
     global _lib
@@ -125,14 +136,22 @@ def _ptr(t) -> int:
     return int(t.data_ptr())
 
 
+_RAW_STREAM = None
+
+
 def _stream(device_index=None):
     """The current HIP stream of the device, as the C ABI's void*."""
-    import torch
-    idx = torch.cuda.current_device() if device_index is None else device_index
-    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
-    if raw is not None:  # no Stream object: a few microseconds less per call
-        return raw(idx)
-    return torch.cuda.current_stream(idx).cuda_stream
+    global _RAW_STREAM
+    if _RAW_STREAM is None:
+        import torch
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        # the raw getter builds no Stream object: a few microseconds less per call
+        _RAW_STREAM = raw if raw is not None else (
+            lambda i: torch.cuda.current_stream(i).cuda_stream)
+    if device_index is None:
+        import torch
+        device_index = torch.cuda.current_device()
+    return _RAW_STREAM(device_index)
 
 
 class QuadSwarm:
@@ -154,6 +173,13 @@ class QuadSwarm:
         self.n_quads, self.n_envs, self.obs_dim = q.value, e.value, od.value
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._di = self.device.index
+        # per-call constants of the stepping calls (their host time has to
+        # stay below the kernel's)
+        L = lib()
+        self._f_step, self._f_observe = L.qs_step, L.qs_observe
+        self._f_step_observe, self._f_step_observe_reward = L.qs_step_observe, L.qs_step_observe_reward
+        Q = self.n_quads
+        self._s_act, self._s_goal, self._s_obs, self._s_q = (Q, 4), (Q, 3), (Q, self.obs_dim), (Q,)
 
     @classmethod
     def from_workload(cls, w: "W.Workload") -> "QuadSwarm":
@@ -162,54 +188,46 @@ class QuadSwarm:
 
     # -- helpers -----------------------------------------------------------
     def _dev(self, t, shape, dtype=None):
-        import torch
-        dtype = dtype or torch.float32
-        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype
-                and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
-            raise ValueError(f"expected a contiguous CUDA {dtype} tensor of shape {shape}")
-        if self._di is not None and t.device.index != self._di:
-            raise ValueError(f"tensor on {t.device}, handle on cuda:{self._di}")
+        """t must be a contiguous tensor of this shape and dtype (float32 by
+        default) on the handle's GPU.  Kept cheap: it runs on every call,
+        and the host time of a call must stay below the kernel's.  (Buffer
+        overlaps are refused by the library itself.)"""
+        try:
+            ok = (t.get_device() == self._di and t.dtype is (dtype or _f32())
+                  and t.size() == shape and t.is_contiguous())
+        except AttributeError:
+            ok = False
+        if not ok:
+            raise ValueError(f"expected a contiguous {dtype or _f32()} tensor of shape "
+                             f"{tuple(shape)} on cuda:{self._di}")
         return t
-
-    @staticmethod
-    def _disjoint(writes, reads=()):
-        """The C ABI leaves overlapping output/input buffers undefined: refuse
-        them here (byte ranges of the tensors' storage)."""
-        def span(t):
-            a = t.data_ptr()
-            return a, a + t.numel() * t.element_size()
-        ws = [span(t) for t in writes if t is not None]
-        rs = [span(t) for t in reads if t is not None]
-        for i, (a0, a1) in enumerate(ws):
-            for b0, b1 in ws[i + 1:] + rs:
-                if a0 < b1 and b0 < a1:
-                    raise ValueError("an output buffer overlaps another buffer of the call")
 
     # -- API ---------------------------------------------------------------
     def step(self, actions, n_substeps: int = 1) -> None:
-        a = self._dev(actions, (self.n_quads, 4))
-        _check(lib().qs_step(self._h, _ptr(a), int(n_substeps), _stream(self._di)), "qs_step")
+        self._dev(actions, self._s_act)
+        _check(self._f_step(self._h, actions.data_ptr(), int(n_substeps), _stream(self._di)),
+               "qs_step")
+
+    def _out_obs(self, out):
+        if out is None:
+            import torch
+            out = torch.empty(self._s_obs, device=self.device)
+        return self._dev(out, self._s_obs)
 
     def observe(self, goals, out=None):
-        import torch
-        g = self._dev(goals, (self.n_quads, 3))
-        o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
-                                                    device=self.device)
-        self._dev(o, (self.n_quads, self.obs_dim))
-        self._disjoint([o], [g])
-        _check(lib().qs_observe(self._h, _ptr(g), _ptr(o), _stream(self._di)), "qs_observe")
+        self._dev(goals, self._s_goal)
+        o = self._out_obs(out)
+        _check(self._f_observe(self._h, goals.data_ptr(), o.data_ptr(), _stream(self._di)),
+               "qs_observe")
         return o
 
     def step_observe(self, actions, n_substeps: int, goals, out=None):
-        import torch
-        a = self._dev(actions, (self.n_quads, 4))
-        g = self._dev(goals, (self.n_quads, 3))
-        o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
-                                                    device=self.device)
-        self._dev(o, (self.n_quads, self.obs_dim))
-        self._disjoint([o], [a, g])
-        _check(lib().qs_step_observe(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
-                                     _stream(self._di)), "qs_step_observe")
+        self._dev(actions, self._s_act)
+        self._dev(goals, self._s_goal)
+        o = self._out_obs(out)
+        _check(self._f_step_observe(self._h, actions.data_ptr(), int(n_substeps),
+                                    goals.data_ptr(), o.data_ptr(), _stream(self._di)),
+               "qs_step_observe")
         return o
 
     def set_reward_weights(self, weights) -> None:
@@ -221,18 +239,17 @@ class QuadSwarm:
 
     def step_observe_reward(self, actions, n_substeps: int, goals, out=None, reward=None):
         """step_observe that also returns each quad's reward of the call."""
-        import torch
-        a = self._dev(actions, (self.n_quads, 4))
-        g = self._dev(goals, (self.n_quads, 3))
-        o = out if out is not None else torch.empty((self.n_quads, self.obs_dim),
-                                                    device=self.device)
-        r = reward if reward is not None else torch.empty(self.n_quads, device=self.device)
-        self._dev(o, (self.n_quads, self.obs_dim))
-        self._dev(r, (self.n_quads,))
-        self._disjoint([o, r], [a, g])
-        _check(lib().qs_step_observe_reward(self._h, _ptr(a), int(n_substeps), _ptr(g), _ptr(o),
-                                            _ptr(r), _stream(self._di)), "qs_step_observe_reward")
-        return o, r
+        self._dev(actions, self._s_act)
+        self._dev(goals, self._s_goal)
+        o = self._out_obs(out)
+        if reward is None:
+            import torch
+            reward = torch.empty(self._s_q, device=self.device)
+        self._dev(reward, self._s_q)
+        _check(self._f_step_observe_reward(self._h, actions.data_ptr(), int(n_substeps),
+                                           goals.data_ptr(), o.data_ptr(), reward.data_ptr(),
+                                           _stream(self._di)), "qs_step_observe_reward")
+        return o, reward
 
     def get_state(self, out=None):
         import torch
@@ -279,7 +296,6 @@ class QuadSwarm:
             self._dev(ckpt, (n_ck, 27, self.n_quads))
         if penalty is not None:
             self._dev(penalty, (self.n_quads,))
-        self._disjoint([ckpt, penalty], [a])
         _check(lib().qs_rollout(self._h, _ptr(a), n_calls, int(n_substeps), int(ckpt_every),
                                 None if ckpt is None else _ptr(ckpt),
                                 None if penalty is None else _ptr(penalty), float(beta),
@@ -300,7 +316,6 @@ class QuadSwarm:
         self._dev(gparams, (self.n_quads, 6))
         if gpenalty is not None:
             self._dev(gpenalty, (self.n_quads,))
-        self._disjoint([gactions, gstate, gparams], [actions, ckpt, gpenalty])
         _check(lib().qs_rollout_backward(
             self._h, _ptr(actions), n_calls, int(n_substeps), int(ckpt_every), _ptr(ckpt),
             C.c_uint64(int(substep_index0)), _ptr(gstate),
@@ -313,10 +328,6 @@ class QuadSwarm:
         for tns, shp in ((state_in, (Q, 27)), (actions, (Q, 4)), (gstate_out, (Q, 27)),
                          (gstate_in, (Q, 27)), (gactions, (Q, 4)), (gparams, (Q, 6))):
             self._dev(tns, shp)
-        # d_gstate_in may be d_gstate_out (staged through the handle's scratch)
-        reads = [state_in, actions] + ([] if gstate_in.data_ptr() == gstate_out.data_ptr()
-                                       else [gstate_out])
-        self._disjoint([gstate_in, gactions, gparams], reads)
         _check(lib().qs_step_backward(self._h, _ptr(state_in), _ptr(actions), int(n_substeps),
                                       C.c_uint64(int(substep_index)), _ptr(gstate_out),
                                       _ptr(gstate_in), _ptr(gactions), _ptr(gparams),
