@@ -35,8 +35,9 @@ struct qs_handle {
   int* h_err = nullptr;  // pinned
   uint64_t t = 0;
   bool record = false;
-  // adjoint scratch, grown on demand: tape [S][27][Q] (S substeps of the
-  // chunk of segments in flight), adjoint [27][Q], parameter gradient [6][Q],
+  // adjoint scratch, grown on demand: tape [S][31][Q] (state and motor-noise
+  // draws of the S substeps of the chunk of segments in flight), adjoint
+  // [27][Q], parameter gradient [6][Q],
   // one checkpoint [27][Q]
   // uneven swarm sizes: work items of the persistent bucketed launch
   std::vector<int> env_start, env_n;  // host copy of the environments

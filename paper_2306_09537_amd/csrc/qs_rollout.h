@@ -1,11 +1,12 @@
 // Differentiable rollouts: a multi-call forward kernel (a fresh action per
 // call, checkpoints of the state, the smoothed collision penalty) and the
 // backward pass: a kernel that recomputes checkpoint segments in parallel,
-// taping the per-substep states, and a kernel that sweeps the tape in
-// reverse.
+// taping the per-substep states and motor-noise draws, and a kernel that
+// sweeps the tape in reverse.
 //
-// Layouts: checkpoints, tape and adjoint scratch are field-major [27][Q]
-// (coalesced per field); actions and their gradients are [call][Q][4].
+// Layouts: checkpoints and adjoint scratch are field-major [27][Q], tape
+// rows [31][Q] (state and draws; coalesced per field); actions and their
+// gradients are [call][Q][4].
 #pragma once
 #include "qs_adjoint.h"
 
