@@ -126,10 +126,13 @@ def test_adjoint_matches_oracle(seed, T, nsub, ce):
         assert e <= b
 
 
-def test_adjoint_large_swarms_match_oracle():
+@pytest.mark.parametrize("block", ["64", "128"])
+def test_adjoint_large_swarms_match_oracle(block, monkeypatch):
     """Swarms of 32 (in-swarm loops at run time in the differentiation
-    kernels): penalty and gradients against the oracle."""
-    w, acts, Wt, gpen = problem(6, 16, n_envs=3, n=32, spread=0.6)
+    kernels), in workgroups of one and of two wavefronts (the latter with
+    workgroup barriers): penalty and gradients against the oracle."""
+    monkeypatch.setenv("QS_BLOCK_SIZE", block)
+    w, acts, Wt, gpen = problem(6, 16, n_envs=5, n=32, spread=0.6)
     nsub, ce = 1, 5
     g_ref = oracle_grads(w, acts, nsub, Wt, gpen)
     tol = bound(w, acts, nsub, Wt, gpen, g_ref, 6)
@@ -139,7 +142,7 @@ def test_adjoint_large_swarms_match_oracle():
     assert pen_o.max() > 1e-3
     np.testing.assert_allclose(pen, pen_o, rtol=2e-4, atol=1e-7)
     errs = [relerr(gs, g_ref[0]), relerr(gact, g_ref[1]), relerr(gpar, g_ref[2])]
-    print("n = 32 adjoint rel err:", errs, "bounds:", tol)
+    print("n = 32 adjoint, block", block, "rel err:", errs, "bounds:", tol)
     for e, b in zip(errs, tol):
         assert e <= b
 
