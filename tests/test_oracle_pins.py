@@ -77,7 +77,7 @@ def test_box_muller_is_standard_normal():
 # ------------------------------------------------------------- motors and mix
 @pytest.mark.parametrize("unit", [False, True])
 def test_hover_equilibrium(unit):
-    """Each rotor at m g / 4 gives zero net acceleration (spec pin)."""
+    """Each rotor at m g / 4 gives zero net acceleration (hover equilibrium)."""
     q = 3
     s = blank_state(q)
     s[:, W.SU:W.SU + 4] = math.sqrt(0.5)  # hover command at thrust-to-weight 2
