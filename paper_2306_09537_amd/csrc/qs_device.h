@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace qs {
 
 enum : uint32_t {
@@ -444,14 +446,17 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
 // pair_normal gives the unit normal from j to i and sp = (v_j - v_i).n.
 // Shared by the forward pass and the adjoint's recomputation so both take
 // identical decisions.
+// Separation from partner pj after the substep's motion and the contact
+// test d^2 < d_col^2.  For the quad itself d = 0 exactly and the test is
+// true: callers clear their own bit once after the partner loop instead of
+// testing every partner's index.
 __device__ __forceinline__ bool pair_geom_v(const Consts& c, const float pj[6], const Quad& s,
-                                            int jj, int me, float& dx, float& dy, float& dz,
-                                            float& d2) {
+                                            float& dx, float& dy, float& dz, float& d2) {
   dx = (s.xo[0] - pj[0]) + (s.inc[0] - pj[3]);
   dy = (s.xo[1] - pj[1]) + (s.inc[1] - pj[4]);
   dz = (s.xo[2] - pj[2]) + (s.inc[2] - pj[5]);
   d2 = dx * dx + dy * dy + dz * dz;
-  return d2 < c.dcol2 && jj != me;
+  return d2 < c.dcol2;
 }
 
 template <int BS>
@@ -488,6 +493,12 @@ __device__ __forceinline__ float sigmoid_hw(float x) {
 // compile-time booleans for generic lambdas
 struct TrueT { static constexpr bool value = true; };
 struct FalseT { static constexpr bool value = false; };
+
+// Contact mask of a swarm slot of N quads: 32 bits suffice up to 32 (one
+// select and one OR per partner instead of two of each).
+template <int N>
+using PairMask = typename std::conditional<(N > 0 && N <= 32), uint32_t,
+                                           unsigned long long>::type;
 
 // Calls f(jj, pj) for every swarm-mate jj of the lane's swarm (itself
 // included), pj[0..5] being its start position and displacement from rows
@@ -542,7 +553,8 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
                                                         float& pacc, float beta) {
   const bool collide = (c.flags & F_COLLIDE) != 0;
   const bool dw = (c.flags & F_DOWNWASH) != 0 && s.fl == 0.0f;
-  unsigned long long cmask = 0ull;
+  using M = PairMask<N>;
+  M cm = 0;
   float dv[3] = {0.f, 0.f, 0.f};
   float adw = 0.f;
   bool hit = false, dwhit = false;
@@ -554,16 +566,16 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   const float dw_r2 = c.dw_r2, dw_h = c.dw_h, dw_k1 = c.dw_k1, dw_k2 = c.dw_k2, dw_b1 = c.dw_b1;
   auto pair = [&](int jj, const float* pj, auto with_dw) {
     float dx, dy, dz, d2;
-    const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+    const bool con = pair_geom_v(c, pj, s, dx, dy, dz, d2);
     if constexpr (PEN) {
       const float sp = hb * softplus_hw(beta * (c.dcol - __builtin_amdgcn_sqrtf(d2)));
       pacc = jj != me ? pacc + sp : pacc;
     }
-    cmask |= con ? 1ull << jj : 0ull;
+    cm |= con ? (M)1 << jj : (M)0;
     if constexpr (decltype(with_dw)::value) {
-      // swarm-mate j above (z_j - z_i = -dz) and overlapping in xy
-      const bool dwc = dw & (jj != me) & (dx * dx + dy * dy < dw_r2) & (-dz > 0.f) &
-                       (-dz < dw_h);
+      // swarm-mate j above (z_j - z_i = -dz) and overlapping in xy (never
+      // the quad itself: dz = 0 there)
+      const bool dwc = dw & (dx * dx + dy * dy < dw_r2) & (-dz > 0.f) & (-dz < dw_h);
       adw = dwc ? adw - dw_k1 * (dw_k2 * -dz + dw_b1) : adw;
       dwhit = dwhit | dwc;
     }
@@ -572,14 +584,14 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
     for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, TrueT{}); });
   else
     for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, FalseT{}); });
-  if (!collide) cmask = 0ull;
+  const unsigned long long cmask = collide ? (unsigned long long)(cm & ~((M)1 << me)) : 0ull;
   // The responses, for the partners in contact only, in partner order.
   for (unsigned long long m = cmask; m != 0ull; m &= m - 1ull) {
     const int jj = __builtin_ctzll(m);
     const int j = ls + jj;
     const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
     float dx, dy, dz, d2, nn[3], sp;
-    pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+    pair_geom_v(c, pj, s, dx, dy, dz, d2);
     pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
     if (!(c.flags & F_APPROACH) || sp > 0.f) {
 #pragma unroll

@@ -379,10 +379,11 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
           // (the penalty weights, row 12, were written before the sweep); the
           // approach test then runs for the (rare) contacts only
           const float g_me = PEN ? tile[12][tid] : 0.f;
+          PairMask<N> cm32 = 0;
           auto mark = [&](int jj, const float* pj) {
             float dx, dy, dz, d2;
-            const bool con = pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
-            cm |= (collide & con) ? 1ull << jj : 0ull;
+            const bool con = pair_geom_v(c, pj, s, dx, dy, dz, d2);
+            cm32 |= (collide & con) ? (PairMask<N>)1 << jj : (PairMask<N>)0;
             if constexpr (PEN) {
               const float rd = __builtin_amdgcn_rsqf(d2);
               const float coef = (jj != me && d2 > 0.f)
@@ -395,13 +396,14 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
             }
           };
           for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, mark);
+          cm = (unsigned long long)(cm32 & ~((PairMask<N>)1 << me));  // not the quad itself
           for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
             const int jj = __builtin_ctzll(m);
             const int j = ls + jj;
             const float pj[6] = {tile[0][j], tile[1][j], tile[2][j],
                                  tile[3][j], tile[4][j], tile[5][j]};
             float dx, dy, dz, d2, nn[3], sp;
-            pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+            pair_geom_v(c, pj, s, dx, dy, dz, d2);
             pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
             if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
           }
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
                                  tile[3][j], tile[4][j], tile[5][j]};
             {
               float dx, dy, dz, d2, nn[3], sp;
-              pair_geom_v(c, pj, s, jj, me, dx, dy, dz, d2);
+              pair_geom_v(c, pj, s, dx, dy, dz, d2);
               pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
               if (!(c.flags & F_APPROACH) || sp > 0.f) {
                 const float mu[3] = {ldv[0] - tile[9][j], ldv[1] - tile[10][j],
