@@ -110,9 +110,17 @@ __device__ __forceinline__ void load_params(const Ptrs& p, const Consts& c, int 
   pa.dlag_dtau = -(1.0f - pp.a_lag) * c.dt / (tau * tau);
 }
 
-__device__ __forceinline__ void load_uhat(const Consts& c, const Ptrs& p, const float* act, int q,
-                                          float uhat[4], float4& a4) {
-  a4 = reinterpret_cast<const float4*>(act)[q];
+// The action row of quad q for one call.  The multi-call kernels load it a
+// call ahead, so the load's latency overlaps the previous call's substeps
+// instead of stalling every call.
+__device__ __forceinline__ float4 load_act(const float* act, int q) {
+  return reinterpret_cast<const float4*>(act)[q];
+}
+
+// Rotor commands of an action row; a non-finite action sets the sticky
+// error bit.
+__device__ __forceinline__ void act_uhat(const Consts& c, const Ptrs& p, const float4& a4,
+                                         float uhat[4]) {
   const bool unit = (c.flags & F_ACT_UNIT) != 0;
   uhat[0] = rotor_cmd(a4.x, unit);
   uhat[1] = rotor_cmd(a4.y, unit);
@@ -163,12 +171,15 @@ __global__ __launch_bounds__(BS) void rollout_kernel(const Consts* __restrict__ 
   const bool pairs = N != 1 && ((c.flags & (F_COLLIDE | F_DOWNWASH)) != 0 || PEN);
   float pacc = 0.f;
   int sidx = 0;
+  float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (live && ncalls > 0) a_nx = load_act(act, q);
   for (int call = 0; call < ncalls; ++call) {
+    const float4 a4 = a_nx;
+    if (live && call + 1 < ncalls) a_nx = load_act(act + (long long)(call + 1) * Q * 4, q);
     if (ckpt && call % ckpt_every == 0 && live)
       store_state(ckpt + (long long)(call / ckpt_every) * NSTATE * Q, Q, q, s);
     float uhat[4] = {0.f, 0.f, 0.f, 0.f};
-    float4 a4;
-    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
+    if (live) act_uhat(c, p, a4, uhat);
     for (int sub = 0; sub < nsub; ++sub, ++sidx) {
       const unsigned long long t = t0 + (unsigned long long)sidx;
       if (live) quad_substep(c, pp, s, uhat, (uint32_t)q, t);
@@ -240,10 +251,13 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
     load_params(p, c, q, pp, pa);
   }
   int sidx = c0 * nsub;
+  float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (live && nc > 0) a_nx = load_act(act + (long long)c0 * Q * 4, q);
   for (int call = c0; call < c0 + nc; ++call) {
+    const float4 a4 = a_nx;
+    if (live && call + 1 < c0 + nc) a_nx = load_act(act + (long long)(call + 1) * Q * 4, q);
     float uhat[4] = {0.f, 0.f, 0.f, 0.f};
-    float4 a4;
-    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
+    if (live) act_uhat(c, p, a4, uhat);
     for (int sub = 0; sub < nsub; ++sub, ++sidx) {
       const unsigned long long t = t0 + (unsigned long long)sidx;
       if (live) {
@@ -339,10 +353,13 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
       l.e[k] = lam[(S_E + k) * Q + q];
     }
   }
+  float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (live && ncalls > 0) a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
   for (int call = ncalls - 1; call >= 0; --call) {
     float uhat[4] = {0.f, 0.f, 0.f, 0.f}, gu[4] = {0.f, 0.f, 0.f, 0.f};
-    float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (live) load_uhat(c, p, act + (long long)call * Q * 4, q, uhat, a4);
+    const float4 a4 = a_nx;
+    if (live && call > 0) a_nx = load_act(act + (long long)(call - 1) * Q * 4, q);
+    if (live) act_uhat(c, p, a4, uhat);
     for (int sub = nsub - 1; sub >= 0; --sub) {
       const int k_s = call * nsub + sub;
       const unsigned long long t = t0 + (unsigned long long)k_s;
