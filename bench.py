@@ -30,11 +30,12 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # VALU roofline: 256 CUs x 4 SIMDs at 2.4 GHz = 2457.6 G SIMD-cycles/s.  A
 # kernel's VALU busy cycles come from its rocprofv3 counters with per-kind
 # issue costs measured on the chip (calib/valu_probe): a wave64 FP32 add,
-# multiply or FMA occupies a SIMD for 4 cycles, a transcendental for 8,
-# integer and bitwise instructions for 2.  Lower bound: 4 x (ADD + MUL + FMA)
-# + 8 x TRANS + 2 x every other VALU instruction; upper bound: 4 x
-# SQ_ACTIVE_INST_VALU (which counts one quad-cycle per instruction, two per
-# transcendental).  The lower bound is reported as the fraction.
+# multiply or FMA occupies a SIMD for 4 cycles, integer and bitwise
+# instructions for 2 to 4, a transcendental 8 alone but it can overlap other
+# VALU work.  Lower bound: 4 x (ADD + MUL + FMA) + 2 x every other
+# non-transcendental VALU instruction; upper bound: 4 x SQ_ACTIVE_INST_VALU
+# (one quad-cycle per instruction, two per transcendental).  The lower bound
+# is reported as the fraction.
 SIMD_GCYCLES_PER_S = 256 * 4 * 2.4
 FP32_PEAK_TFLOPS = 157.3       # FP32 vector peak (packed FMA)
 # committed counter summaries of the ten-substep form, per workload
