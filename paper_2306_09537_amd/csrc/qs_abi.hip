@@ -367,9 +367,30 @@ void go_recompute(qs_handle* h, const float* ckpt, const float* act, int ncalls,
                      ptrs(h), ckpt, act, ncalls, ce, nsub, (unsigned long long)t0, h->d_tape);
 }
 
+// The two-wavefront reverse sweep pays where the batch leaves SIMDs idle:
+// up to 1024 workgroups of 64 quads (QS_REVERSE_PIPE=0/1 forces it off/on).
+bool use_reverse_pipe(const qs_handle* h) {
+  if (const char* e = std::getenv("QS_REVERSE_PIPE")) return e[0] == '1';
+  return h->nblk <= 1024;
+}
+
+template <int N, bool PEN>
+void go_reverse_pipe(qs_handle* h, const float* act, int ncalls, int nsub, uint64_t t0,
+                     const float* gpen, float beta, float* gact, hipStream_t s) {
+  hipLaunchKernelGGL((qs::reverse_pipe_kernel<N, PEN>), dim3(h->nblk), dim3(128), 0, s, h->d_c,
+                     ptrs(h), act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam, gpen,
+                     beta, gact, h->d_gpar);
+}
+
 template <int BS, int N, bool PEN>
 void go_reverse(qs_handle* h, const float* act, int ncalls, int nsub, uint64_t t0,
                 const float* gpen, float beta, float* gact, hipStream_t s) {
+  if constexpr (BS == 64 && (N == 1 || N == 8)) {
+    if (use_reverse_pipe(h)) {
+      go_reverse_pipe<N, PEN>(h, act, ncalls, nsub, t0, gpen, beta, gact, s);
+      return;
+    }
+  }
   hipLaunchKernelGGL((qs::reverse_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->d_c,
                      ptrs(h), act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam, gpen,
                      beta, gact, h->d_gpar);

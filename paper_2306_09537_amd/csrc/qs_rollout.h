@@ -288,6 +288,88 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
   }
 }
 
+// One branch-free pass over the partners of a substep in the reverse sweep:
+// the contact set (the quad itself excluded) and, with the penalty, its
+// adjoint w.r.t. the quad's position,
+//   d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d,
+// summed over the partners in partner order into pen3 (added to lambda_x by
+// the caller).  g_me: the quad's penalty weight; row 12 of the tile holds
+// the partners' weights.
+template <int BS, int N, bool PEN, typename T>
+__device__ __forceinline__ unsigned long long mark_contacts(const Consts& c, T tile, const Quad& s,
+                                                            int ls, int n, int me, float beta,
+                                                            float g_me, float pen3[3]) {
+  const bool collide = (c.flags & F_COLLIDE) != 0;
+  PairMask<N> cm32 = 0;
+  auto mark = [&](int jj, const float* pj) {
+    float dx, dy, dz, d2;
+    const bool con = pair_geom_v(c, pj, s, dx, dy, dz, d2);
+    cm32 |= (collide & con) ? (PairMask<N>)1 << jj : (PairMask<N>)0;
+    if constexpr (PEN) {
+      const float rd = __builtin_amdgcn_rsqf(d2);
+      const float coef = (jj != me && d2 > 0.f)
+                             ? -0.5f * (g_me + pj[6]) * sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
+                             : 0.f;
+      pen3[0] = fmaf(coef, dx, pen3[0]);
+      pen3[1] = fmaf(coef, dy, pen3[1]);
+      pen3[2] = fmaf(coef, dz, pen3[2]);
+    }
+  };
+  for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, mark);
+  return (unsigned long long)(cm32 & ~((PairMask<N>)1 << me));  // not the quad itself
+}
+
+// Approach test of the contact set: does the quad receive a response?
+template <int BS>
+__device__ __forceinline__ bool any_response(const Consts& c, const float (*tile)[BS],
+                                             const Quad& s, int ls, int me,
+                                             unsigned long long cm) {
+  bool hit = false;
+  for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
+    const int jj = __builtin_ctzll(m);
+    const int j = ls + jj;
+    const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
+    float dx, dy, dz, d2, nn[3], sp;
+    pair_geom_v(c, pj, s, dx, dy, dz, d2);
+    pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+    if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
+  }
+  return hit;
+}
+
+// Adjoint of the collision responses of one quad (the partners in contact):
+// ldv (rows 9-11 for the partners): adjoint of each quad's velocity change.
+template <int BS>
+__device__ __forceinline__ void response_vjp(const Consts& c, const float (*tile)[BS],
+                                             const float (*ldvt)[BS], const Quad& s, int ls,
+                                             int me, unsigned long long cm, const float ldv[3],
+                                             Adj& l) {
+  for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
+    const int jj = __builtin_ctzll(m);
+    const int j = ls + jj;
+    const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
+    float dx, dy, dz, d2, nn[3], sp;
+    pair_geom_v(c, pj, s, dx, dy, dz, d2);
+    pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
+    if (!(c.flags & F_APPROACH) || sp > 0.f) {
+      const float mu[3] = {ldv[0] - ldvt[0][j], ldv[1] - ldvt[1][j], ldv[2] - ldvt[2][j]};
+      const float mn = dot3f(mu, nn);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) l.v[k] = fmaf(-mn, nn[k], l.v[k]);
+      if (!(d2 < 1e-12f)) {
+        const float wv[3] = {tile[6][j] - s.v[0], tile[7][j] - s.v[1], tile[8][j] - s.v[2]};
+        float gn[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gn[k] = fmaf(sp, mu[k], mn * wv[k]);
+        const float gnn = dot3f(gn, nn);
+        const float id = rsqrtf(d2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) l.x[k] = fmaf(gn[k] - gnn * nn[k], id, l.x[k]);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // reverse_kernel: the reverse sweep over the chunk's ncalls nsub substeps,
 // last to first, from the tape; the adjoint of the state stays in
@@ -386,44 +468,20 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
           }
         }
         __syncthreads();
-        // which quads responded, and the adjoint of their velocity change
+        // which quads responded, and the adjoint of their velocity change:
+        // one branch-free pass over the partners gives the contact set and
+        // the penalty's adjoint (penalty weights in row 12, written before the
+        // sweep); the approach test runs for the (rare) contacts only
         bool hit = false;
         unsigned long long cm = 0ull;  // contact set of this substep
         if (live) {
-          // one branch-free pass over all partners: the contact set and, with
-          // the penalty, its adjoint into lambda_x,
-          //   d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d
-          // (the penalty weights, row 12, were written before the sweep); the
-          // approach test then runs for the (rare) contacts only
-          const float g_me = PEN ? tile[12][tid] : 0.f;
-          PairMask<N> cm32 = 0;
-          auto mark = [&](int jj, const float* pj) {
-            float dx, dy, dz, d2;
-            const bool con = pair_geom_v(c, pj, s, dx, dy, dz, d2);
-            cm32 |= (collide & con) ? (PairMask<N>)1 << jj : (PairMask<N>)0;
-            if constexpr (PEN) {
-              const float rd = __builtin_amdgcn_rsqf(d2);
-              const float coef = (jj != me && d2 > 0.f)
-                                     ? -0.5f * (g_me + pj[6]) *
-                                           sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
-                                     : 0.f;
-              l.x[0] = fmaf(coef, dx, l.x[0]);
-              l.x[1] = fmaf(coef, dy, l.x[1]);
-              l.x[2] = fmaf(coef, dz, l.x[2]);
-            }
-          };
-          for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, mark);
-          cm = (unsigned long long)(cm32 & ~((PairMask<N>)1 << me));  // not the quad itself
-          for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
-            const int jj = __builtin_ctzll(m);
-            const int j = ls + jj;
-            const float pj[6] = {tile[0][j], tile[1][j], tile[2][j],
-                                 tile[3][j], tile[4][j], tile[5][j]};
-            float dx, dy, dz, d2, nn[3], sp;
-            pair_geom_v(c, pj, s, dx, dy, dz, d2);
-            pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
-            if (!(c.flags & F_APPROACH) || sp > 0.f) hit = true;
+          float pen3[3] = {0.f, 0.f, 0.f};
+          cm = mark_contacts<BS, N, PEN>(c, tile, s, ls, n, me, beta, tile[12][tid], pen3);
+          if constexpr (PEN) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) l.x[k] += pen3[k];
           }
+          hit = any_response<BS>(c, tile, s, ls, me, cm);
         }
         float ldv[3] = {0.f, 0.f, 0.f};
         if (live && hit) {
@@ -438,38 +496,7 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
           for (int k = 0; k < 3; ++k) tile[9 + k][tid] = ldv[k];
         }
         __syncthreads();
-        if (live) {
-          // adjoint of the responses, for the partners in contact
-          for (unsigned long long m = cm; m != 0ull; m &= m - 1ull) {
-            const int jj = __builtin_ctzll(m);
-            const int j = ls + jj;
-            const float pj[6] = {tile[0][j], tile[1][j], tile[2][j],
-                                 tile[3][j], tile[4][j], tile[5][j]};
-            {
-              float dx, dy, dz, d2, nn[3], sp;
-              pair_geom_v(c, pj, s, dx, dy, dz, d2);
-              pair_normal<BS>(tile, s, j, jj, me, dx, dy, dz, d2, nn, sp);
-              if (!(c.flags & F_APPROACH) || sp > 0.f) {
-                const float mu[3] = {ldv[0] - tile[9][j], ldv[1] - tile[10][j],
-                                     ldv[2] - tile[11][j]};
-                const float mn = dot3f(mu, nn);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) l.v[k] = fmaf(-mn, nn[k], l.v[k]);
-                if (!(d2 < 1e-12f)) {
-                  const float wv[3] = {tile[6][j] - s.v[0], tile[7][j] - s.v[1],
-                                       tile[8][j] - s.v[2]};
-                  float gn[3];
-#pragma unroll
-                  for (int k = 0; k < 3; ++k) gn[k] = fmaf(sp, mu[k], mn * wv[k]);
-                  const float gnn = dot3f(gn, nn);
-                  const float id = rsqrtf(d2);
-#pragma unroll
-                  for (int k = 0; k < 3; ++k) l.x[k] = fmaf(gn[k] - gnn * nn[k], id, l.x[k]);
-                }
-              }
-            }
-          }
-        }
+        if (live) response_vjp<BS>(c, tile, tile + 9, s, ls, me, cm, ldv, l);
       }
       if (live) quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
     }
@@ -499,6 +526,293 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
     lam[S_F * Q + q] = 0.f;
 #pragma unroll
     for (int k = 0; k < 6; ++k) gpar[k * Q + q] += gp[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reverse_pipe_kernel: the reverse sweep of reverse_kernel for small batches
+// (one wavefront per SIMD or fewer), split over two wavefronts per
+// workgroup of 64 quads.  Wavefront 0 re-runs the substeps from the tape
+// (quad_substep with its record, the post-motion exchange, the contact set,
+// the penalty's adjoint) one substep ahead and passes each quad's record
+// through a two-slot LDS ring; wavefront 1 differentiates the substep whose
+// record is ready (response adjoint, quad_vjp) and holds the adjoint state.
+// The two halves of a substep are independent across consecutive substeps,
+// so they run side by side on two SIMDs; one workgroup barrier per substep
+// hands a slot over.  Same arithmetic in the same order as reverse_kernel,
+// so the results are identical.
+// ---------------------------------------------------------------------------
+constexpr int REC_FLOATS = 61;  // the float fields of Rec
+// ring words of one quad and substep: Rec floats, Rec flags and the
+// response flag, contact set, penalty adjoint
+constexpr int RING_WORDS = REC_FLOATS + 1 + 1 + 3;
+
+template <typename R, typename F>
+__device__ __forceinline__ void rec_floats(R& r, F&& f) {
+  int w = 0;
+  auto g = [&](auto& v) { f(w++, v); };
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g(r.z[k]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g(r.u0[k]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g(r.u1[k]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) g(r.P[k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { g(r.w0[k]); g(r.v0[k]); g(r.F[k]); g(r.wdot[k]); g(r.w1[k]); }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { g(r.A1[k]); g(r.c0[k]); g(r.c1[k]); }
+  g(r.T); g(r.i0); g(r.dp); g(r.i1);
+  g(r.mu_n); g(r.fb[0]); g(r.fb[1]); g(r.nv); g(r.nf); g(r.mag);
+  g(r.hx); g(r.hy); g(r.nh); g(r.kx); g(r.ky); g(r.nk);
+}
+
+__device__ __forceinline__ uint32_t rec_flags(const Rec& r, bool pair_hit) {
+  uint32_t b = (uint32_t)r.rest | (uint32_t)r.statik << 1 | (uint32_t)r.guard << 2 |
+               (uint32_t)r.bounced << 3 | (uint32_t)r.hit << 4 | (uint32_t)r.fallback << 5 |
+               (uint32_t)pair_hit << 12;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) b |= (uint32_t)r.clamp[k] << (6 + k) | (uint32_t)r.flip[k] << (9 + k);
+  return b;
+}
+
+__device__ __forceinline__ bool rec_unflag(Rec& r, uint32_t b) {
+  r.rest = b & 1u;
+  r.statik = (b >> 1) & 1u;
+  r.guard = (b >> 2) & 1u;
+  r.bounced = (b >> 3) & 1u;
+  r.hit = (b >> 4) & 1u;
+  r.fallback = (b >> 5) & 1u;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.clamp[k] = (b >> (6 + k)) & 1u;
+    r.flip[k] = (b >> (9 + k)) & 1u;
+  }
+  return (b >> 12) & 1u;
+}
+
+// workgroup barrier with the LDS fences around it (the two wavefronts run
+// different code, each reaching it once per substep)
+__device__ __forceinline__ void wg_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// LDS written by some lanes of a wavefront, then read by others of the same
+// wavefront
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, bool PEN>
+__global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
+                                                           const float* __restrict__ act,
+                                                           int ncalls, int nsub,
+                                                           unsigned long long t0,
+                                                           const float* __restrict__ tape,
+                                                           float* __restrict__ lam,
+                                                           const float* __restrict__ gpen,
+                                                           float beta, float* __restrict__ gact,
+                                                           float* __restrict__ gpar) {
+  constexpr int BS = 64;
+  static_assert(N == 1 || N == 8, "pipelined reverse sweep for swarms of 1 or 8");
+  // tile slots as in reverse_kernel: rows 0-8 post-motion start position,
+  // displacement, velocity (wavefront 0); 9-11 adjoint of the collision
+  // velocity change (wavefront 1); 12 penalty weights (both slots)
+  __shared__ float tl[2][13][BS];
+  __shared__ float ring[2][RING_WORDS][BS];
+  const Consts& c = *cp;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tid = threadIdx.x & 63;
+  int qb, cnt, ls, n;
+  block_map<BS, N>(p, tid, qb, cnt, ls, n);
+  const bool live = tid < cnt;
+  const int q = qb + (live ? tid : 0);
+  const int me = tid - ls;
+  const long long Q = p.Q;
+  const bool collide = (c.flags & F_COLLIDE) != 0;
+  const bool pairs = N != 1 && (collide || PEN);
+  const int n_steps = ncalls * nsub;
+
+  QuadPar pp;
+  ParAdj pa;
+  if (live) load_params(p, c, q, pp, pa);
+  if (PEN && wave == 1) {
+    const float g = live ? gpen[q] : 0.f;
+    tl[0][12][tid] = g;
+    tl[1][12][tid] = g;
+  }
+  wg_sync();
+
+  if (wave == 0) {
+    // ---- re-run: substep k = n_steps - 1 - i at step i
+    Quad s, sn;
+    float z[4], zn[4] = {0.f, 0.f, 0.f, 0.f};
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live && n_steps > 0) {
+      const float* row = tape + (long long)(n_steps - 1) * NTAPE * Q;
+      load_state(row, Q, q, sn);
+      load_draws(c, row, Q, q, zn);
+      a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
+    }
+    for (int i = 0; i <= n_steps; ++i) {
+      if (i < n_steps) {
+        const int k = n_steps - 1 - i;
+        const int call = k / nsub, sub = k - call * nsub;
+        if (sub == nsub - 1) {  // the call's last substep comes first
+          const float4 a4 = a_nx;
+          if (live && call > 0) a_nx = load_act(act + (long long)(call - 1) * Q * 4, q);
+          if (live) act_uhat(c, p, a4, uhat);
+        }
+        Rec r;
+        if (live) {
+          s = sn;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) z[m] = zn[m];
+          if (k > 0) {
+            const float* row = tape + (long long)(k - 1) * NTAPE * Q;
+            load_state(row, Q, q, sn);
+            load_draws(c, row, Q, q, zn);
+          }
+          quad_substep<true, Z_IMPORT>(c, pp, s, uhat, (uint32_t)q, t0 + (unsigned long long)k,
+                                       &r, z);
+        }
+        unsigned long long cm = 0ull;
+        bool hit = false;
+        float pen3[3] = {0.f, 0.f, 0.f};
+        if (pairs) {
+          float(*tile)[BS] = tl[i & 1];
+          if (live) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+              tile[m][tid] = s.xo[m];
+              tile[3 + m][tid] = s.inc[m];
+              tile[6 + m][tid] = s.v[m];
+            }
+          }
+          wave_sync();
+          if (live) {
+            cm = mark_contacts<BS, N, PEN>(c, tile, s, ls, n, me, beta, tile[12][tid], pen3);
+            hit = any_response<BS>(c, tile, s, ls, me, cm);
+          }
+        }
+        if (live) {
+          float(*slot)[BS] = ring[i & 1];
+          rec_floats(r, [&](int w, const float& v) { slot[w][tid] = v; });
+          slot[REC_FLOATS][tid] = __uint_as_float(rec_flags(r, hit));
+          slot[REC_FLOATS + 1][tid] = __uint_as_float((uint32_t)cm);
+#pragma unroll
+          for (int m = 0; m < 3; ++m) slot[REC_FLOATS + 2 + m][tid] = pen3[m];
+        }
+      }
+      wg_sync();
+    }
+  } else {
+    // ---- differentiate: substep k = n_steps - i at step i >= 1
+    Adj l;
+    float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        l.x[k] = lam[(S_X + k) * Q + q];
+        l.v[k] = lam[(S_V + k) * Q + q];
+        l.w[k] = lam[(S_W + k) * Q + q];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) l.R[k] = lam[(S_R + k) * Q + q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        l.u[k] = lam[(S_U + k) * Q + q];
+        l.e[k] = lam[(S_E + k) * Q + q];
+      }
+    }
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f}, gu[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live && n_steps > 0) a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
+    wg_sync();  // step 0: nothing to differentiate yet
+    for (int i = 1; i <= n_steps; ++i) {
+      const int k = n_steps - i;
+      const int call = k / nsub, sub = k - call * nsub;
+      if (sub == nsub - 1) {
+        a4 = a_nx;
+        if (live && call > 0) a_nx = load_act(act + (long long)(call - 1) * Q * 4, q);
+        if (live) act_uhat(c, p, a4, uhat);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) gu[m] = 0.f;
+      }
+      const int sl = (i - 1) & 1;
+      if (live) {
+        const float(*slot)[BS] = ring[sl];
+        Rec r;
+        rec_floats(r, [&](int w, float& v) { v = slot[w][tid]; });
+        const bool hit = rec_unflag(r, __float_as_uint(slot[REC_FLOATS][tid]));
+        const unsigned long long cm = __float_as_uint(slot[REC_FLOATS + 1][tid]);
+        if constexpr (PEN) {
+#pragma unroll
+          for (int m = 0; m < 3; ++m) l.x[m] += slot[REC_FLOATS + 2 + m][tid];
+        }
+        if (pairs) {
+          float(*tile)[BS] = tl[sl];
+          float ldv[3] = {0.f, 0.f, 0.f};
+          if (hit) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+              ldv[m] = c.col_decay * l.v[m];
+              l.v[m] = ldv[m];
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < 3; ++m) tile[9 + m][tid] = ldv[m];
+          wave_sync();
+          if (cm != 0ull) {
+            Quad so;  // the quad's post-motion position and velocity
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+              so.xo[m] = tile[m][tid];
+              so.inc[m] = tile[3 + m][tid];
+              so.v[m] = tile[6 + m][tid];
+            }
+            response_vjp<BS>(c, tile, tile + 9, so, ls, me, cm, ldv, l);
+          }
+        }
+        quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
+        if (sub == 0) {
+          float4 g;
+          g.x = gu[0] * duhat_da(c, a4.x, uhat[0]);
+          g.y = gu[1] * duhat_da(c, a4.y, uhat[1]);
+          g.z = gu[2] * duhat_da(c, a4.z, uhat[2]);
+          g.w = gu[3] * duhat_da(c, a4.w, uhat[3]);
+          reinterpret_cast<float4*>(gact + (long long)call * Q * 4)[q] = g;
+        }
+      } else if (pairs) {
+        wave_sync();
+      }
+      wg_sync();
+    }
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lam[(S_X + k) * Q + q] = l.x[k];
+        lam[(S_V + k) * Q + q] = l.v[k];
+        lam[(S_W + k) * Q + q] = l.w[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) lam[(S_R + k) * Q + q] = l.R[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        lam[(S_U + k) * Q + q] = l.u[k];
+        lam[(S_E + k) * Q + q] = l.e[k];
+      }
+      lam[S_F * Q + q] = 0.f;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) gpar[k * Q + q] += gp[k];
+    }
   }
 }
 

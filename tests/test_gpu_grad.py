@@ -147,6 +147,34 @@ def test_adjoint_large_swarms_match_oracle(block, monkeypatch):
         assert e <= b
 
 
+@pytest.mark.parametrize("n,pen", [(8, True), (8, False), (1, True)])
+def test_pipelined_reverse_sweep_is_bit_identical(n, pen, monkeypatch):
+    """Small batches differentiate in two wavefronts per workgroup (one
+    re-runs the substeps, the other differentiates them); the result equals
+    the one-wavefront sweep bit for bit."""
+    w, acts, Wt, gpen = problem(7, 12, n_envs=20 if n == 8 else 150, n=n, spread=0.6)
+    gp = gpen if pen else None
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("QS_REVERSE_PIPE", mode)
+        sim = QuadSwarm.from_workload(w)
+        a = dev(acts)
+        ckpt = torch.empty((3, 27, w.n_quads), device="cuda")
+        pen_t = torch.zeros(w.n_quads, device="cuda") if pen else None
+        sim.rollout(a, 2, 5, ckpt, pen_t, BETA if pen else 0.0)
+        gs = dev(Wt).clone()
+        gact = torch.empty_like(a)
+        gpar = torch.zeros((w.n_quads, 6), device="cuda")
+        sim.rollout_backward(a, 2, 5, ckpt, 0, gs, None if gp is None else dev(gp),
+                             BETA if pen else 0.0, gact, gpar)
+        sim.sync()
+        out[mode] = (gs.cpu(), gact.cpu(), gpar.cpu())
+        sim.close()
+    for x, y in zip(out["0"], out["1"]):
+        assert torch.equal(x, y)
+    assert float(out["1"][1].abs().max()) > 0
+
+
 def test_step_backward_matches_oracle():
     w, acts, Wt, gpen = problem(5, 1)
     nsub = 3
