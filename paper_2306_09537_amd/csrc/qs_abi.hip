@@ -352,9 +352,23 @@ int launch(qs_handle* h, const float* act, int nsub, const float* goals, float* 
 }
 
 // ---- differentiable rollouts ------------------------------------------------
+// The two-wavefront rollout (motor part one substep ahead) for small
+// batches, as the reverse sweep (QS_ROLLOUT_PIPE=0/1 forces it off/on).
+bool use_rollout_pipe(const qs_handle* h) {
+  if (const char* e = std::getenv("QS_ROLLOUT_PIPE")) return e[0] == '1';
+  return h->nblk <= 1024;
+}
+
 template <int BS, int N, bool PEN>
 void go_roll(qs_handle* h, const float* act, int ncalls, int nsub, float* ckpt, int ce, float* pen,
              float beta, hipStream_t s) {
+  if constexpr (BS == 64 && (N == 1 || N == 8)) {
+    if (use_rollout_pipe(h)) {
+      hipLaunchKernelGGL((qs::rollout_pipe_kernel<N, PEN>), dim3(h->nblk), dim3(128), 0, s, h->d_c,
+                         ptrs(h), act, ncalls, nsub, (unsigned long long)h->t, ckpt, ce, pen, beta);
+      return;
+    }
+  }
   hipLaunchKernelGGL((qs::rollout_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->d_c, ptrs(h),
                      act, ncalls, nsub, (unsigned long long)h->t, ckpt, ce, pen, beta);
 }

@@ -151,20 +151,57 @@ struct Rec {
 // substep).
 enum ZMode { Z_DRAW, Z_EXPORT, Z_IMPORT };
 
-// One substep of one quad up to (not including) the in-env pair pass:
-// motor lag and noise, thrust and torque mix, floor-rest or free-flight
-// dynamics with semi-implicit Euler and Gram-Schmidt, walls and floor.
-// REC: also record the intermediates the adjoint needs into *r.
-template <bool REC = false, ZMode ZM = Z_DRAW>
-__device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, Quad& s,
-                                             const float uhat[4], uint32_t q, uint64_t t,
-                                             Rec* r = nullptr, float* zio = nullptr) {
-  if constexpr (REC) {
+// Thrust and body torques of one substep: the output of the motor part.
+struct Drive {
+  float T, tx, ty, tz;
+};
+
+// §III-A.1 motor lag, §III-A.2 motor noise (AR(1)) and per-rotor thrust,
+// §III-A X mix: updates the rotor state (u, eps) and returns the thrust and
+// torques.  Depends on the rotor state, the command and the substep's draws
+// only (not on position, velocity or attitude).  z: the draws (zeros
+// without motor noise).
+template <ZMode ZM = Z_DRAW>
+__device__ __forceinline__ Drive motor_step(const Consts& c, const QuadPar& p, float u[4],
+                                            float e[4], const float uhat[4], uint32_t q,
+                                            uint64_t t, float z[4], float* zio = nullptr) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      r->u0[i] = s.u[i];
-      r->z[i] = 0.f;
+  for (int i = 0; i < 4; ++i) u[i] = fmaf(p.a_lag, uhat[i] - u[i], u[i]);
+  if (c.flags & F_NOISE) {
+    if constexpr (ZM == Z_IMPORT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z[i] = zio[i];
+    } else {
+      normal4(c, q, t, STREAM_MOTOR, 0, z);
     }
+    if constexpr (ZM == Z_EXPORT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zio[i] = z[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = fmaf(c.a_nd, e[i], p.a_ns * z[i]);
+  }
+  // X layout FR, BR, BL, FL
+  float f[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f[i] = fmaf(p.f_max * u[i], u[i], e[i]);
+  Drive d;
+  d.T = (f[0] + f[1]) + (f[2] + f[3]);
+  d.tx = c.arm_d * ((f[2] + f[3]) - (f[0] + f[1]));
+  d.ty = c.arm_d * ((f[1] + f[2]) - (f[0] + f[3]));
+  d.tz = c.k_tau * ((f[0] + f[2]) - (f[1] + f[3]));
+  return d;
+}
+
+// The rest of a substep from its thrust and torques: floor-rest or
+// free-flight dynamics with semi-implicit Euler and Gram-Schmidt, walls and
+// floor (not the rotor state).  REC: also record the intermediates the
+// adjoint needs into *r (the rotor fields are the caller's).
+template <bool REC = false>
+__device__ __forceinline__ void body_step(const Consts& c, const QuadPar& p, Quad& s,
+                                          const Drive& d, uint32_t q, uint64_t t,
+                                          Rec* r = nullptr) {
+  if constexpr (REC) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) r->P[k] = s.R[k];
 #pragma unroll
@@ -178,44 +215,12 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) s.xo[k] = s.x[k];
-  // §III-A.1 motor lag
-#pragma unroll
-  for (int i = 0; i < 4; ++i) s.u[i] = fmaf(p.a_lag, uhat[i] - s.u[i], s.u[i]);
-  // §III-A.2 motor noise, AR(1)
-  if (c.flags & F_NOISE) {
-    float z[4];
-    if constexpr (ZM == Z_IMPORT) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) z[i] = zio[i];
-    } else {
-      normal4(c, q, t, STREAM_MOTOR, 0, z);
-    }
-    if constexpr (ZM == Z_EXPORT) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) zio[i] = z[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) s.e[i] = fmaf(c.a_nd, s.e[i], p.a_ns * z[i]);
-    if constexpr (REC) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) r->z[i] = z[i];
-    }
-  }
-  // §III-A.2 per-rotor thrust, §III-A mix (X layout FR, BR, BL, FL)
-  float f[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) f[i] = fmaf(p.f_max * s.u[i], s.u[i], s.e[i]);
-  const float T = (f[0] + f[1]) + (f[2] + f[3]);
-  const float tx = c.arm_d * ((f[2] + f[3]) - (f[0] + f[1]));
-  const float ty = c.arm_d * ((f[1] + f[2]) - (f[0] + f[3]));
-  const float tz = c.k_tau * ((f[0] + f[2]) - (f[1] + f[3]));
+  const float T = d.T, tx = d.tx, ty = d.ty, tz = d.tz;
   // world-frame thrust = T * third column of R
   const float Fx = T * s.R[2], Fy = T * s.R[5], Fz = T * s.R[8];
 
   const bool rest = (c.flags & F_FLOOR) && s.fl != 0.0f && Fz <= p.m * c.g;
   if constexpr (REC) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r->u1[i] = s.u[i];
     r->T = T;
     r->F[0] = Fx;
     r->F[1] = Fy;
@@ -438,6 +443,29 @@ __device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, 
     s.R[3] = ay;  s.R[4] = ax;  s.R[5] = 0.0f;
     s.R[6] = 0.0f; s.R[7] = 0.0f; s.R[8] = 1.0f;
   }
+}
+
+// One substep of one quad up to (not including) the in-env pair pass: the
+// motor part, then the body part.  REC: also record the intermediates the
+// adjoint needs into *r.
+template <bool REC = false, ZMode ZM = Z_DRAW>
+__device__ __forceinline__ void quad_substep(const Consts& c, const QuadPar& p, Quad& s,
+                                             const float uhat[4], uint32_t q, uint64_t t,
+                                             Rec* r = nullptr, float* zio = nullptr) {
+  if constexpr (REC) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r->u0[i] = s.u[i];
+  }
+  float z[4] = {0.f, 0.f, 0.f, 0.f};
+  const Drive d = motor_step<ZM>(c, p, s.u, s.e, uhat, q, t, z, zio);
+  if constexpr (REC) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      r->z[i] = z[i];
+      r->u1[i] = s.u[i];
+    }
+  }
+  body_step<REC>(c, p, s, d, q, t, r);
 }
 
 // Geometry of the pair (i, j) for the in-env pass, from partner j's start

@@ -816,6 +816,160 @@ __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// rollout_pipe_kernel: rollout_kernel for small batches, over two wavefronts
+// per workgroup of 64 quads.  The motor part of a substep (lag, noise,
+// thrust, mix) depends on the rotor state, the action and the substep's
+// draws only, so wavefront 0 runs it one substep ahead and hands the thrust
+// and torques (4 words per quad) to wavefront 1 through a two-slot LDS
+// ring; wavefront 1 runs the body part, the in-swarm pass and the penalty.
+// One workgroup barrier per substep; each wavefront stores its own fields
+// of the checkpoints and of the final state.  Same arithmetic in the same
+// order as rollout_kernel, so the results are identical.
+// ---------------------------------------------------------------------------
+template <int N, bool PEN>
+__global__ __launch_bounds__(128) void rollout_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
+                                                           const float* __restrict__ act,
+                                                           int ncalls, int nsub,
+                                                           unsigned long long t0,
+                                                           float* __restrict__ ckpt,
+                                                           int ckpt_every,
+                                                           float* __restrict__ pen, float beta) {
+  constexpr int BS = 64;
+  static_assert(N == 1 || N == 8, "pipelined rollout for swarms of 1 or 8");
+  __shared__ float sxv[2][9][BS];
+  __shared__ float ring[2][4][BS];
+  const Consts& c = *cp;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tid = threadIdx.x & 63;
+  int qb, cnt, ls, n;
+  block_map<BS, N>(p, tid, qb, cnt, ls, n);
+  const bool live = tid < cnt;
+  const int q = qb + (live ? tid : 0);
+  const int me = tid - ls;
+  const long long Q = p.Q;
+  const int n_steps = ncalls * nsub;
+  QuadPar pp;
+  ParAdj pa;
+  if (live) load_params(p, c, q, pp, pa);
+
+  if (wave == 0) {
+    // ---- motor part of substep i at step i
+    float u[4], e[4];
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        u[k] = p.st[(S_U + k) * p.Qp + q];
+        e[k] = p.st[(S_E + k) * p.Qp + q];
+      }
+    }
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live && ncalls > 0) a_nx = load_act(act, q);
+    for (int i = 0; i <= n_steps; ++i) {
+      if (i < n_steps) {
+        const int call = i / nsub, sub = i - call * nsub;
+        if (sub == 0) {
+          const float4 a4 = a_nx;
+          if (live && call + 1 < ncalls) a_nx = load_act(act + (long long)(call + 1) * Q * 4, q);
+          if (ckpt && call % ckpt_every == 0 && live) {
+            float* ck = ckpt + (long long)(call / ckpt_every) * NSTATE * Q;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              ck[(S_U + k) * Q + q] = u[k];
+              ck[(S_E + k) * Q + q] = e[k];
+            }
+          }
+          if (live) act_uhat(c, p, a4, uhat);
+        }
+        if (live) {
+          float z[4] = {0.f, 0.f, 0.f, 0.f};
+          const Drive d = motor_step(c, pp, u, e, uhat, (uint32_t)q, t0 + (unsigned long long)i, z);
+          float(*slot)[BS] = ring[i & 1];
+          slot[0][tid] = d.T;
+          slot[1][tid] = d.tx;
+          slot[2][tid] = d.ty;
+          slot[3][tid] = d.tz;
+        }
+      }
+      wg_sync();
+    }
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        p.st[(S_U + k) * p.Qp + q] = u[k];
+        p.st[(S_E + k) * p.Qp + q] = e[k];
+      }
+    }
+  } else {
+    // ---- body part, in-swarm pass and penalty of substep i - 1 at step i
+    Quad s;
+    if (live) load_state(p.st, p.Qp, q, s);
+    const bool pairs = N != 1 && ((c.flags & (F_COLLIDE | F_DOWNWASH)) != 0 || PEN);
+    float pacc = 0.f;
+    wg_sync();  // step 0: no thrust yet
+    for (int i = 1; i <= n_steps; ++i) {
+      const int sidx = i - 1;
+      const int call = sidx / nsub, sub = sidx - call * nsub;
+      if (sub == 0 && ckpt && call % ckpt_every == 0 && live) {
+        float* ck = ckpt + (long long)(call / ckpt_every) * NSTATE * Q;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          ck[(S_X + k) * Q + q] = s.x[k];
+          ck[(S_V + k) * Q + q] = s.v[k];
+          ck[(S_W + k) * Q + q] = s.w[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ck[(S_R + k) * Q + q] = s.R[k];
+        ck[S_F * Q + q] = s.fl;
+      }
+      const unsigned long long t = t0 + (unsigned long long)sidx;
+      if (live) {
+        const float(*slot)[BS] = ring[sidx & 1];
+        Drive d;
+        d.T = slot[0][tid];
+        d.tx = slot[1][tid];
+        d.ty = slot[2][tid];
+        d.tz = slot[3][tid];
+        body_step(c, pp, s, d, (uint32_t)q, t);
+      }
+      if (pairs) {
+        float(*tile)[BS] = sxv[sidx & 1];
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            tile[k][tid] = s.xo[k];
+            tile[3 + k][tid] = s.inc[k];
+            tile[6 + k][tid] = s.v[k];
+          }
+        }
+        wave_sync();
+        if (live) pair_pass<BS, kUnroll<N>, PEN>(c, tile, s, ls, n, me, (uint32_t)q, t, pacc, beta);
+      }
+      wg_sync();
+    }
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        p.st[(S_X + k) * p.Qp + q] = s.x[k];
+        p.st[(S_V + k) * p.Qp + q] = s.v[k];
+        p.st[(S_W + k) * p.Qp + q] = s.w[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) p.st[(S_R + k) * p.Qp + q] = s.R[k];
+      p.st[S_F * p.Qp + q] = s.fl;
+      float chk = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) chk += s.x[k] + s.v[k] + s.w[k];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) chk += s.R[k];
+      if (!isfinite(chk))
+        __hip_atomic_fetch_or(p.err, ERRBIT_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if constexpr (PEN) pen[q] += pacc;
+    }
+  }
+}
+
 // [rows][Q] field-major <-> [Q][rows] row-major conversions (optionally
 // adding into the destination).
 __global__ void fm_to_rm_kernel(const float* __restrict__ src, float* __restrict__ dst, int Q,

@@ -175,6 +175,30 @@ def test_pipelined_reverse_sweep_is_bit_identical(n, pen, monkeypatch):
     assert float(out["1"][1].abs().max()) > 0
 
 
+@pytest.mark.parametrize("n,pen", [(8, True), (8, False), (1, False)])
+def test_pipelined_rollout_is_bit_identical(n, pen, monkeypatch):
+    """Small batches run the rollout in two wavefronts per workgroup (the
+    motor part one substep ahead); state, checkpoints and penalty equal the
+    one-wavefront rollout bit for bit."""
+    w, acts, Wt, gpen = problem(8, 13, n_envs=20 if n == 8 else 150, n=n, spread=0.6)
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("QS_ROLLOUT_PIPE", mode)
+        sim = QuadSwarm.from_workload(w)
+        ckpt = torch.empty((3, 27, w.n_quads), device="cuda")
+        pen_t = torch.zeros(w.n_quads, device="cuda") if pen else None
+        sim.rollout(dev(acts), 3, 5, ckpt, pen_t, BETA if pen else 0.0)
+        sT, tT = sim.get_state()
+        sim.sync()
+        out[mode] = (sT.cpu(), ckpt.cpu(), None if pen_t is None else pen_t.cpu(), tT)
+        sim.close()
+    assert out["0"][3] == out["1"][3] == 13 * 3
+    assert torch.equal(out["0"][0], out["1"][0])
+    assert torch.equal(out["0"][1], out["1"][1])
+    if pen:
+        assert torch.equal(out["0"][2], out["1"][2]) and float(out["1"][2].max()) > 0
+
+
 def test_step_backward_matches_oracle():
     w, acts, Wt, gpen = problem(5, 1)
     nsub = 3
