@@ -259,6 +259,13 @@ int build_items(qs_handle* h, int bs) {
 
 // Launch one instantiation.  Observation rows are staged in LDS when the
 // staging area and the pair tile fit in 64 KiB per workgroup.
+// Calls of several substeps on small batches run the motor part one substep
+// ahead in a second wavefront (QS_STEP_PIPE=0/1 forces it off/on).
+bool use_step_pipe(const qs_handle* h) {
+  if (const char* e = std::getenv("QS_STEP_PIPE")) return e[0] == '1';
+  return h->nblk <= 1024;
+}
+
 template <int BS, int KT, int N>
 void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
         hipStream_t s, float* rw) {
@@ -269,6 +276,15 @@ void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs
     if (lds + sizeof(float) * 2 * 9 * BS <= 64 * 1024) {
       dyn = lds;
       stage = 1;
+    }
+  }
+  if constexpr (BS == 64 && N == 8 && (KT == 6 || KT == -2)) {
+    if (nsub >= 2 && use_step_pipe(h)) {
+      hipLaunchKernelGGL((qs::step_pipe_kernel<KT, N>), dim3(h->nblk), dim3(128), dyn, s,
+                         h->d_st, h->d_par, act, goals, h->d_c, h->Qp, h->Q, nsub,
+                         (unsigned long long)h->t, ptrs(h), obs, stage,
+                         h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
+      return;
     }
   }
   hipLaunchKernelGGL((qs::step_kernel<BS, KT, N>), dim3(h->nblk), dim3(BS), dyn, s, h->d_st,

@@ -41,7 +41,12 @@ __device__ __forceinline__ unsigned long long read_counter(const unsigned long l
 // NU: partner count the in-swarm loops are unrolled for (N, or 0 for loops
 // over the swarm's runtime size: fewer registers for large slots).
 // sxv: LDS tile [2][9][BS]; st_obs: LDS staging of observation rows.
-template <int BS, int KT, int N, int MAP, int NU = N>
+// ROLE: -1 one wavefront does everything; in a workgroup of two wavefronts
+// over the same 64 quads (step_pipe_kernel), 0 runs the motor part of every
+// substep one substep ahead and hands thrust and torques through ring, 1
+// runs the rest (body part, in-swarm pass, observation); rx hands the rotor
+// state over for the reward.
+template <int BS, int KT, int N, int MAP, int NU = N, int ROLE = -1>
 __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
                                           const float* __restrict__ act, int nsub,
                                           unsigned long long t0,
@@ -49,13 +54,22 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
                                           float* __restrict__ obs, int stage_obs,
                                           float (*sxv)[9][BS], float* st_obs, int item,
                                           float* __restrict__ reward,
-                                          const unsigned long long* tdev = nullptr) {
+                                          const unsigned long long* tdev = nullptr,
+                                          float (*ring)[4][BS] = nullptr,
+                                          float (*rx)[BS] = nullptr) {
+  static_assert(ROLE < 0 || (MAP == MAP_DENSE && BS == 64), "two roles: dense 64-quad groups");
   static_assert(N == 0 || BS % N == 0, "workgroups hold whole swarms");
   static_assert(MAP != MAP_TABLE || N == 0, "the table mapping has runtime sizes");
   constexpr bool OBS = KT != -2;
   const float4* st_obs4 = reinterpret_cast<const float4*>(st_obs);
 
-  const int tid = threadIdx.x;
+  const int tid = ROLE < 0 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  // the in-swarm exchanges: every wavefront of the workgroup, or (two roles)
+  // the one that runs them
+  auto quad_sync = [&]() {
+    if constexpr (ROLE < 0) __syncthreads();
+    else wave_sync();
+  };
   int qb = 0, cnt = 0, ls = 0, n = 0;
   bool live = false;
   int q = 0;
@@ -100,26 +114,30 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   // the goal is loaded with the state: a load issued after the state stores
   // would wait for their completion (one in-order counter for both)
   float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  if (OBS && live) {
+  if (OBS && ROLE != 0 && live) {
     g0 = goals[3 * q];
     g1 = goals[3 * q + 1];
     g2 = goals[3 * q + 2];
   }
   if (live) {
+    if constexpr (ROLE != 0) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s.x[k] = S[(S_X + k) * Qp + q];
+      for (int k = 0; k < 3; ++k) s.x[k] = S[(S_X + k) * Qp + q];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s.v[k] = S[(S_V + k) * Qp + q];
+      for (int k = 0; k < 3; ++k) s.v[k] = S[(S_V + k) * Qp + q];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) s.R[k] = S[(S_R + k) * Qp + q];
+      for (int k = 0; k < 9; ++k) s.R[k] = S[(S_R + k) * Qp + q];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s.w[k] = S[(S_W + k) * Qp + q];
+      for (int k = 0; k < 3; ++k) s.w[k] = S[(S_W + k) * Qp + q];
+    }
     if (nsub > 0) {
+      if constexpr (ROLE != 1) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) s.u[k] = S[(S_U + k) * Qp + q];
+        for (int k = 0; k < 4; ++k) s.u[k] = S[(S_U + k) * Qp + q];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) s.e[k] = S[(S_E + k) * Qp + q];
-      s.fl = S[S_F * Qp + q];
+        for (int k = 0; k < 4; ++k) s.e[k] = S[(S_E + k) * Qp + q];
+      }
+      if constexpr (ROLE != 0) s.fl = S[S_F * Qp + q];
       pp.m = p.par[P_M * Qp + q];
       pp.jx = p.par[P_JX * Qp + q];
       pp.jy = p.par[P_JY * Qp + q];
@@ -131,18 +149,20 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       pp.ijy = 1.0f / pp.jy;
       pp.ijz = 1.0f / pp.jz;
       pp.a_ns = c.ns_scale * pp.f_max;
-      if (reward) {
+      if constexpr (ROLE != 1) {
+        if (reward) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f0[i] = fmaf(pp.f_max * s.u[i], s.u[i], s.e[i]);
+          for (int i = 0; i < 4; ++i) f0[i] = fmaf(pp.f_max * s.u[i], s.u[i], s.e[i]);
+        }
+        const float4 a4 = reinterpret_cast<const float4*>(act)[q];
+        const bool unit = (c.flags & F_ACT_UNIT) != 0;
+        uhat[0] = rotor_cmd(a4.x, unit);
+        uhat[1] = rotor_cmd(a4.y, unit);
+        uhat[2] = rotor_cmd(a4.z, unit);
+        uhat[3] = rotor_cmd(a4.w, unit);
+        if (!(isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z) && isfinite(a4.w)))
+          __hip_atomic_fetch_or(p.err, ERRBIT_ACTION, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      const float4 a4 = reinterpret_cast<const float4*>(act)[q];
-      const bool unit = (c.flags & F_ACT_UNIT) != 0;
-      uhat[0] = rotor_cmd(a4.x, unit);
-      uhat[1] = rotor_cmd(a4.y, unit);
-      uhat[2] = rotor_cmd(a4.z, unit);
-      uhat[3] = rotor_cmd(a4.w, unit);
-      if (!(isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z) && isfinite(a4.w)))
-        __hip_atomic_fetch_or(p.err, ERRBIT_ACTION, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   // graph mode: the substep index comes from the device counter (read after
@@ -153,7 +173,31 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   unsigned long long cmask = 0ull;
   for (int sub = 0; sub < nsub; ++sub) {
     const unsigned long long t = t0 + (unsigned long long)sub;
-    if (live) quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+    if constexpr (ROLE == 0) {
+      if (live) {
+        float z[4] = {0.f, 0.f, 0.f, 0.f};
+        const Drive d = motor_step(c, pp, s.u, s.e, uhat, (uint32_t)q, t, z);
+        ring[sub & 1][0][tid] = d.T;
+        ring[sub & 1][1][tid] = d.tx;
+        ring[sub & 1][2][tid] = d.ty;
+        ring[sub & 1][3][tid] = d.tz;
+      }
+      wg_sync();
+      continue;
+    }
+    if constexpr (ROLE == 1) {
+      wg_sync();
+      if (live) {
+        Drive d;
+        d.T = ring[sub & 1][0][tid];
+        d.tx = ring[sub & 1][1][tid];
+        d.ty = ring[sub & 1][2][tid];
+        d.tz = ring[sub & 1][3][tid];
+        body_step(c, pp, s, d, (uint32_t)q, t);
+      }
+    } else {
+      if (live) quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+    }
     if (collide) {
       // §III-B.1 in-env pair pass (Jacobi: every response from the
       // pre-response velocities of this substep)
@@ -174,7 +218,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           tile[6 + k][tid] = 0.f;
         }
       }
-      __syncthreads();
+      quad_sync();
       cmask = 0ull;
       if (live) {
         float unused = 0.f;
@@ -191,22 +235,55 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   if (live && nsub > 0) {
     float* St = p.st;
     float chk = 0.f;
+    if constexpr (ROLE != 0) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { St[(S_X + k) * Qp + q] = s.x[k]; chk += s.x[k]; }
+      for (int k = 0; k < 3; ++k) { St[(S_X + k) * Qp + q] = s.x[k]; chk += s.x[k]; }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { St[(S_V + k) * Qp + q] = s.v[k]; chk += s.v[k]; }
+      for (int k = 0; k < 3; ++k) { St[(S_V + k) * Qp + q] = s.v[k]; chk += s.v[k]; }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) { St[(S_R + k) * Qp + q] = s.R[k]; chk += s.R[k]; }
+      for (int k = 0; k < 9; ++k) { St[(S_R + k) * Qp + q] = s.R[k]; chk += s.R[k]; }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { St[(S_W + k) * Qp + q] = s.w[k]; chk += s.w[k]; }
+      for (int k = 0; k < 3; ++k) { St[(S_W + k) * Qp + q] = s.w[k]; chk += s.w[k]; }
+    }
+    if constexpr (ROLE != 1) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { St[(S_U + k) * Qp + q] = s.u[k]; chk += s.u[k]; }
+      for (int k = 0; k < 4; ++k) { St[(S_U + k) * Qp + q] = s.u[k]; chk += s.u[k]; }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { St[(S_E + k) * Qp + q] = s.e[k]; chk += s.e[k]; }
-    St[S_F * Qp + q] = s.fl;
+      for (int k = 0; k < 4; ++k) { St[(S_E + k) * Qp + q] = s.e[k]; chk += s.e[k]; }
+    }
+    if constexpr (ROLE != 0) St[S_F * Qp + q] = s.fl;
     if (!isfinite(chk))
       __hip_atomic_fetch_or(p.err, ERRBIT_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (p.contacts) p.contacts[q] = cmask;
+    if (ROLE != 0 && p.contacts) p.contacts[q] = cmask;
+  }
+  // two roles: the motor wavefront hands the rotor state (start and end of
+  // the call) over for the reward, and is done
+  if constexpr (ROLE == 0) {
+    if (OBS && reward) {
+      if (live) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          rx[i][tid] = f0[i];
+          rx[4 + i][tid] = s.u[i];
+          rx[8 + i][tid] = s.e[i];
+        }
+      }
+      wg_sync();
+    }
+    return;
+  }
+  if constexpr (ROLE == 1) {
+    if (OBS && reward) {
+      wg_sync();
+      if (live) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          f0[i] = rx[i][tid];
+          s.u[i] = rx[4 + i][tid];
+          s.e[i] = rx[8 + i][tid];
+        }
+      }
+    }
   }
 
   if constexpr (OBS) {
@@ -226,7 +303,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
         tile[6 + k][tid] = 0.f;
       }
     }
-    __syncthreads();
+    quad_sync();
     if constexpr (KT >= 0) {
       constexpr int OD = 18 + 6 * KT;
       float ov[OD];
@@ -321,7 +398,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 #pragma unroll
           for (int k = 0; k < OD / 2; ++k) r2[k] = make_float2(ov[2 * k], ov[2 * k + 1]);
         }
-        __syncthreads();
+        quad_sync();
         // contiguous copy of the workgroup's rows: 16-byte stores when the
         // destination allows, else 8-byte stores; non-temporal, since the
         // rows go to their consumer and this kernel never reads them back
@@ -446,6 +523,43 @@ __global__ __launch_bounds__(BS) void step_kernel(float* __restrict__ st,
   constexpr int MAP = (N > 0) ? MAP_DENSE : MAP_TABLE;
   step_body<BS, KT, N, MAP>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
                             reinterpret_cast<float*>(st_obs4), 0, reward, tdev);
+  if (tdev) advance_counter(tdev, done, nsub);
+}
+
+// Several substeps per call for small batches of swarms of 8: two
+// wavefronts per workgroup of 64 quads, the motor part of each substep one
+// substep ahead of the rest (step_body ROLE 0 and 1).  Same arithmetic in
+// the same order as step_kernel, so identical results.
+template <int KT, int N>
+__global__ __launch_bounds__(128) void step_pipe_kernel(float* __restrict__ st,
+                                                        const float* __restrict__ par,
+                                                        const float* __restrict__ act,
+                                                        const float* __restrict__ goals,
+                                                        const Consts* __restrict__ cp, int Qp,
+                                                        int Q, int nsub, unsigned long long t0,
+                                                        Ptrs p, float* __restrict__ obs,
+                                                        int stage_obs, unsigned long long* tdev,
+                                                        unsigned int* done,
+                                                        float* __restrict__ reward) {
+  constexpr int BS = 64;
+  __shared__ float sxv[2][9][BS];
+  __shared__ float ring[2][4][BS];
+  __shared__ float rx[12][BS];
+  extern __shared__ float4 st_obs4[];
+  p.st = st;
+  p.par = par;
+  p.Qp = Qp;
+  p.Q = Q;
+  const Consts& c = *cp;
+  const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (role == 0)
+    step_body<BS, KT, N, MAP_DENSE, N, 0>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
+                                          reinterpret_cast<float*>(st_obs4), 0, reward, tdev,
+                                          ring, rx);
+  else
+    step_body<BS, KT, N, MAP_DENSE, N, 1>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
+                                          reinterpret_cast<float*>(st_obs4), 0, reward, tdev,
+                                          ring, rx);
   if (tdev) advance_counter(tdev, done, nsub);
 }
 

@@ -592,22 +592,6 @@ __device__ __forceinline__ bool rec_unflag(Rec& r, uint32_t b) {
   return (b >> 12) & 1u;
 }
 
-// workgroup barrier with the LDS fences around it (the two wavefronts run
-// different code, each reaching it once per substep)
-__device__ __forceinline__ void wg_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// LDS written by some lanes of a wavefront, then read by others of the same
-// wavefront
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int N, bool PEN>
 __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
                                                            const float* __restrict__ act,
