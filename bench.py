@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 SIMD_GCYCLES_PER_S = 256 * 4 * 2.4
 FP32_PEAK_TFLOPS = 157.3       # FP32 vector peak (packed FMA)
 # committed counter summaries of the ten-substep form, per workload
-VALU_PROFILES = {"swarm8": ("step_kernel_swarm4096x8_fused10.md", ""),
+VALU_PROFILES = {"swarm8": ("step_pipe_kernel_swarm4096x8_fused10.md", ""),
                  "scale32": ("scale_workloads.md", "scale32_")}
 # ... and of the differentiable rollout and its backward pass
 FWDBWD_PROFILES = {"diff_1024x8": ("rollout_reverse_diff1024x8.md", ""),
