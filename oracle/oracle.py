@@ -24,14 +24,19 @@ EV_WALL, EV_FLOOR_HIT, EV_FRICTION, EV_TAKEOFF, EV_PAIR_RESPONSE, EV_CONTACT = 1
 EV_DOWNWASH, EV_CEILING = 64, 128
 
 
+def compile_lib(src: str, out: str) -> None:
+    """gcc build of an oracle source file (IEEE double, no FMA contraction)."""
+    subprocess.check_call([
+        "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+        "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+        "-Wno-unused-parameter", src, "-o", out, "-lm"])
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (IEEE double, no FMA contraction)."""
+    """Compile the oracle into ``liboracle.so`` next to its source."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-            "-Wno-unused-parameter", SRC, "-o", tmp, "-lm"])
+        compile_lib(SRC, tmp)
         os.replace(tmp, LIB)
     return LIB
 
@@ -59,9 +64,12 @@ _lib = None
 
 
 def lib():
+    """The loaded oracle.  ``QS_ORACLE_LIB``, when set, names another build
+    to load instead: the mutation tests run the pins against copies of the
+    source with one planted mistake this way."""
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(os.environ.get("QS_ORACLE_LIB") or build())
         _lib.or_step.restype = C.c_int
         _lib.or_observe.restype = C.c_int
         _lib.or_uniform_from_u32.restype = C.c_double

@@ -1,0 +1,233 @@
+"""Mutation check of the oracle's pins (CPU).
+
+Each case plants one plausible mistake in a copy of the oracle's C source (a
+dropped term, a wrong sign, index or constant, a transposed operand, a
+world/body mix-up), builds the copy, and runs the pin files against it with
+``QS_ORACLE_LIB`` pointing at that build; the case passes when at least one
+pin fails.  An unmodified copy built and run the same way must pass every
+pin, so a failing pin is the planted mistake's doing, not the harness's.
+The mistakes never reach the GPU library or the committed oracle.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_grad.py"]
+
+# (name, passage the original follows, original text, planted text)
+MUTANTS = [
+    # Philox4x32-10 and the draws built on it (§III-A.2 noise)
+    ("philox_multiplier", "Philox4x32-10", "M0 = 0xD2511F53u", "M0 = 0xD2511F57u"),
+    ("philox_key_bump", "Philox4x32-10", "k0 += W0; k1 += W1;", "k0 += W0; k1 += W0;"),
+    ("philox_word_order", "Philox4x32-10",
+     "n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;", "n0 = (uint32_t)(p1 >> 32) ^ c3 ^ k0;"),
+    ("uniform_offset", "uniform map", "(double)(2u * (r >> 9) + 1u)", "(double)(2u * (r >> 9) + 2u)"),
+    ("box_muller_radius", "Box-Muller", "sqrt(-2.0 * log(u1))", "sqrt(-log(u1))"),
+    ("box_muller_angle", "Box-Muller",
+     "const double two_pi = 6.283185307179586476925286766559;",
+     "const double two_pi = 3.141592653589793238462643383279;"),
+    # §III-A.1 action map and motor lag
+    ("action_map_unit_in_default", "§III-A.1",
+     "0.5 * (clampd(act[i], -1.0, 1.0) + 1.0)", "clampd(act[i], 0.0, 1.0)"),
+    ("lag_direction", "§III-A.1",
+     "s[IU + i] = alpha_lag * (uhat[i] - s[IU + i]) + s[IU + i];",
+     "s[IU + i] = alpha_lag * (s[IU + i] - uhat[i]) + s[IU + i];"),
+    ("lag_forward_euler", "§III-A.1",
+     "const double alpha_lag = 1.0 - exp(-dt / p[PTAU]);",
+     "const double alpha_lag = dt / p[PTAU];"),
+    # §III-A.2 motor noise and thrust
+    ("noise_scale_no_sqrt", "§III-A.2",
+     "const double a_ns = d->motor_noise_std * f_max * sqrt(1.0 - a_nd * a_nd);",
+     "const double a_ns = d->motor_noise_std * f_max * (1.0 - a_nd * a_nd);"),
+    ("noise_no_decay", "§III-A.2",
+     "s[IE + i] = a_nd * s[IE + i] + a_ns * z[i];", "s[IE + i] = s[IE + i] + a_ns * z[i];"),
+    ("thrust_not_squared", "§III-A.2",
+     "f[i] = f_max * s[IU + i] * s[IU + i] + s[IE + i];", "f[i] = f_max * s[IU + i] + s[IE + i];"),
+    ("f_max_half_weight", "§III-A.2",
+     "const double f_max = 0.25 * m * g * p[PT2W];", "const double f_max = 0.5 * m * g * p[PT2W];"),
+    # §III-A X mix and rigid body
+    ("roll_mix_rotors", "§III-A mix",
+     "tau[0] = arm_d * ((f[2] + f[3]) - (f[0] + f[1]));",
+     "tau[0] = arm_d * ((f[1] + f[2]) - (f[0] + f[3]));"),
+    ("yaw_reaction_sign", "§III-A mix",
+     "tau[2] = d->k_tau * ((f[0] + f[2]) - (f[1] + f[3]));",
+     "tau[2] = d->k_tau * ((f[1] + f[3]) - (f[0] + f[2]));"),
+    ("arm_not_diagonal", "§III-A mix",
+     "const double arm_d = d->arm_length / sqrt(2.0);\n\n  /* §III-A.1",
+     "const double arm_d = d->arm_length;\n\n  /* §III-A.1"),
+    ("thrust_along_row", "§III-A",
+     "double F[3] = {T * R[2], T * R[5], T * R[8]};", "double F[3] = {T * R[6], T * R[7], T * R[8]};"),
+    ("gravity_sign", "§III-A", "acc[2] -= g;", "acc[2] += g;"),
+    ("drag_dropped", "linear drag",
+     "acc[k] = F[k] / m - d->drag_coef / m * v[k];", "acc[k] = F[k] / m;"),
+    ("gyroscopic_dropped", "§III-A Euler's equation", "(tau[0] - wxJw[0]) / jx", "tau[0] / jx"),
+    ("inertia_index", "§III-A Euler's equation", "(tau[1] - wxJw[1]) / jy", "(tau[1] - wxJw[1]) / jx"),
+    ("explicit_euler", "semi-implicit Euler",
+     "    for (int k = 0; k < 3; ++k) v[k] += dt * acc[k];\n"
+     "    for (int k = 0; k < 3; ++k) x[k] += dt * v[k];",
+     "    for (int k = 0; k < 3; ++k) x[k] += dt * v[k];\n"
+     "    for (int k = 0; k < 3; ++k) v[k] += dt * acc[k];"),
+    ("rotation_world_rate", "§III-A attitude",
+     "acc_rc += R[3 * r + k] * W[3 * k + c];", "acc_rc += W[3 * r + k] * R[3 * k + c];"),
+    ("gram_schmidt_projection", "Gram-Schmidt",
+     "for (int k = 0; k < 3; ++k) c1[k] -= dp * c0[k];",
+     "for (int k = 0; k < 3; ++k) c1[k] -= dp * c1[k];"),
+    ("gram_schmidt_handedness", "Gram-Schmidt",
+     "double c2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2],\n"
+     "                    c0[0] * c1[1] - c0[1] * c1[0]};",
+     "double c2[3] = {c1[1] * c0[2] - c1[2] * c0[1], c1[2] * c0[0] - c1[0] * c0[2],\n"
+     "                    c1[0] * c0[1] - c1[1] * c0[0]};"),
+    # §III-B.2 walls, §III-B.3 floor
+    ("upper_wall_absorbs", "§III-B.2",
+     "if (v[k] > 0.0) { v[k] = -e * v[k]; bounced = 1; r->flip[k] = 1; }",
+     "if (v[k] > 0.0) { v[k] = 0.0 * v[k]; bounced = 1; r->flip[k] = 1; }"),
+    ("lower_wall_no_clamp", "§III-B.2",
+     "x[k] = d->room_min[k];\n        r->clamp[k] = 1;", "r->clamp[k] = 1;"),
+    ("rest_threshold", "§III-B.3",
+     "s[IF] != 0.0 && F[2] <= m * g;", "s[IF] != 0.0 && F[2] <= 0.5 * m * g;"),
+    ("friction_direction", "§III-B.3",
+     "fb[0] = F[0] - mu_n * v[0] / nv;", "fb[0] = F[0] + mu_n * v[0] / nv;"),
+    ("friction_normal_force", "§III-B.3", "double N = m * g - F[2];", "double N = m * g;"),
+    ("floor_level_handedness", "§III-B.3",
+     "c1[0] = -c0[1]; c1[1] = c0[0]; c1[2] = 0.0;", "c1[0] = c0[1]; c1[1] = -c0[0]; c1[2] = 0.0;"),
+    ("floor_hit_keeps_xy_velocity", "§III-B.3",
+     "    v[0] = v[1] = v[2] = 0.0;\n    w[0] = w[1] = w[2] = 0.0;\n    s[IF] = 1.0;",
+     "    v[2] = 0.0;\n    w[0] = w[1] = w[2] = 0.0;\n    s[IF] = 1.0;"),
+    # §III-B.1 pair collisions
+    ("contact_unsquared_distance", "§III-B.1",
+     "if (!(d->flags & OR_COLLIDE) || !(d2 < dc2)) continue;",
+     "if (!(d->flags & OR_COLLIDE) || !(d2 < d->col_dist)) continue;"),
+    ("response_sign", "§III-B.1",
+     "        dv[i][k] += sp * nrm[k];\n        dv[j][k] -= sp * nrm[k];",
+     "        dv[i][k] -= sp * nrm[k];\n        dv[j][k] += sp * nrm[k];"),
+    ("approach_test_sign", "§III-B.1",
+     "if ((d->flags & OR_APPROACH_ONLY) && !(sp > 0.0)) continue;\n"
+     "      for (int k = 0; k < 3; ++k) {\n        dv[i][k]",
+     "if ((d->flags & OR_APPROACH_ONLY) && !(sp < 0.0)) continue;\n"
+     "      for (int k = 0; k < 3; ++k) {\n        dv[i][k]"),
+    # §III-B.4 downwash
+    ("downwash_sign", "§III-B.4",
+     "adw[i] += -d->dw_k1 * (d->dw_k2 * dz + d->dw_b1);",
+     "adw[i] += d->dw_k1 * (d->dw_k2 * dz + d->dw_b1);"),
+    ("downwash_on_upper_quad", "§III-B.4",
+     "dz > 0.0 && dz < d->dw_height", "dz < 0.0 && -dz < d->dw_height"),
+    ("downwash_on_resting_quad", "§III-B.4",
+     "if (si[IF] != 0.0) continue; /* resting on the floor */", "/* resting quads too */"),
+    # §III-C observation and sensor noise
+    ("knn_farthest_first", "§III-C",
+     "if (!used[j] && (best < 0 || dist[j] < dist[best])) best = j;",
+     "if (!used[j] && (best < 0 || dist[j] > dist[best])) best = j;"),
+    ("knn_tie_to_later_index", "§III-C",
+     "if (!used[j] && (best < 0 || dist[j] < dist[best])) best = j;",
+     "if (!used[j] && (best < 0 || dist[j] <= dist[best])) best = j;"),
+    ("knn_relative_sign", "§III-C",
+     "for (int k = 0; k < 3; ++k) os[k] = sj[IX + k] - si[IX + k];",
+     "for (int k = 0; k < 3; ++k) os[k] = si[IX + k] - sj[IX + k];"),
+    ("knn_rate_for_velocity", "§III-C",
+     "os[3 + k] = sj[IV + k] - si[IV + k];", "os[3 + k] = sj[IW + k] - si[IW + k];"),
+    ("obs_goal_sign", "§III-C",
+     "o[k] = si[IX + k] - goals[(size_t)(q0 + i) * 3 + k];",
+     "o[k] = goals[(size_t)(q0 + i) * 3 + k] - si[IX + k];"),
+    ("obs_rotation_transposed", "§III-C",
+     "for (int k = 0; k < 9; ++k) o[6 + k] = si[IR + k];",
+     "for (int k = 0; k < 9; ++k) o[6 + k] = si[IR + 3 * (k % 3) + k / 3];"),
+    ("sensor_noise_one_sided", "§III-C",
+     "o[3 * draw + k] += a * (2.0 * or_uniform_from_u32(r[k]) - 1.0);",
+     "o[3 * draw + k] += a * or_uniform_from_u32(r[k]);"),
+    ("sensor_rate_variance_for_std", "§III-C",
+     "o[15 + k] += d->sn_w * z[k];", "o[15 + k] += d->sn_w * d->sn_w * z[k];"),
+    # §III-E reward
+    ("reward_orientation_entry", "§III-E", "w[2] * b[IR + 8]", "w[2] * b[IR + 6]"),
+    ("reward_yaw_entry", "§III-E", "w[7] * b[IR + 0]", "w[7] * b[IR + 4]"),
+    ("reward_proximity_scale", "§III-E",
+     "const double h = 1.0 - dd / w[14];", "const double h = 1.0 - dd * w[14];"),
+    ("reward_thrust_change", "§III-E",
+     "df2 += (f1 - f0) * (f1 - f0);", "df2 += f1 * f1;"),
+    ("reward_wall_bit", "§III-E",
+     "w[10] * ((ev[q] & EV_WALL) ? 1.0 : 0.0)", "w[10] * ((ev[q] & EV_CEILING) ? 1.0 : 0.0)"),
+    ("reward_floor_hit_bit", "§III-E",
+     "w[8] * ((ev[q] & EV_FLOOR_HIT) ? 1.0 : 0.0)", "w[8] * ((ev[q] & EV_PAIR_RESPONSE) ? 1.0 : 0.0)"),
+    ("reward_on_floor_from_hit", "§III-E",
+     "w[9] * (b[IF] != 0.0 ? 1.0 : 0.0)", "w[9] * ((ev[q] & EV_FLOOR_HIT) ? 1.0 : 0.0)"),
+    ("reward_prox_counts_empty_slots", "§III-E",
+     "      if (x[0] == 0.0 && x[1] == 0.0 && x[2] == 0.0 && x[3] == 0.0 && x[4] == 0.0 && x[5] == 0.0)\n        continue;\n",
+     ""),
+    # reverse mode (§III-E penalty and every row above)
+    ("vjp_lag_factor", "reverse mode, §III-A.1",
+     "lu0[i] = (1.0 - r->alpha_lag) * lu[i];", "lu0[i] = r->alpha_lag * lu[i];"),
+    ("vjp_thrust_square", "reverse mode, §III-A.2",
+     "lu[i] += 2.0 * r->f_max * r->u1[i] * lf[i];", "lu[i] += r->f_max * r->u1[i] * lf[i];"),
+    ("vjp_noise_decay", "reverse mode, §III-A.2",
+     "le0[i] = d->motor_noise_decay * le[i];", "le0[i] = le[i];"),
+    ("vjp_tau_derivative_sign", "reverse mode, §III-A.1",
+     "gp[PTAU] += lalag * (-exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));",
+     "gp[PTAU] += lalag * (exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));"),
+    ("vjp_wall_mirror", "reverse mode, §III-B.2",
+     "if (r->flip[k]) lv[k] *= -d->wall_restitution;",
+     "if (r->flip[k]) lv[k] *= d->wall_restitution;"),
+    ("vjp_gyroscopic_operands", "reverse mode, §III-A", "cross3(r->Jw, lc, tmp);", "cross3(lc, r->Jw, tmp);"),
+    ("vjp_mass_power", "reverse mode, §III-A",
+     "lm += -(r->F[k] - d->drag_coef * r->v0[k]) * lacc[k] / (m * m);",
+     "lm += -(r->F[k] - d->drag_coef * r->v0[k]) * lacc[k] / m;"),
+    ("vjp_friction_normal", "reverse mode, §III-B.3",
+     "lF[2] += -d->floor_mu * lmu;", "lF[2] += d->floor_mu * lmu;"),
+    ("vjp_response_sign", "reverse mode, §III-B.1",
+     "        li[IV + k] += -mn * nrm[k];\n        lj[IV + k] += mn * nrm[k];",
+     "        li[IV + k] += mn * nrm[k];\n        lj[IV + k] += -mn * nrm[k];"),
+    ("vjp_penalty_sign", "reverse mode, §III-E penalty",
+     "double coef = -0.5 * (gpen[q0 + i] + gpen[q0 + j])",
+     "double coef = 0.5 * (gpen[q0 + i] + gpen[q0 + j])"),
+]
+
+CASES = [("unmodified", "", "", "")] + MUTANTS
+
+
+def _run_case(case, work):
+    name, _, orig, planted = case
+    src = open(O.SRC).read()
+    if orig:
+        if src.count(orig) != 1:
+            return ("harness", f"original text found {src.count(orig)} times")
+        src = src.replace(orig, planted)
+    path = os.path.join(work, name + ".c")
+    lib = os.path.join(work, name + ".so")
+    with open(path, "w") as f:
+        f.write(src)
+    try:
+        O.compile_lib(path, lib)
+    except subprocess.CalledProcessError as e:
+        return ("harness", f"build failed: {e}")
+    env = dict(os.environ, QS_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "-m", "not gpu", *PIN_FILES],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    failed = [ln for ln in p.stdout.splitlines() if ln.startswith("FAILED")]
+    return (p.returncode, failed[0] if failed else p.stdout[-600:])
+
+
+@pytest.fixture(scope="module")
+def results(tmp_path_factory):
+    work = str(tmp_path_factory.mktemp("mutants"))
+    workers = max(1, min(8, (os.cpu_count() or 2) - 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        out = list(ex.map(lambda c: _run_case(c, work), CASES))
+    return {c[0]: r for c, r in zip(CASES, out)}
+
+
+def test_unmodified_copy_passes_every_pin(results):
+    rc, detail = results["unmodified"]
+    assert rc == 0, detail
+
+
+@pytest.mark.parametrize("name", [m[0] for m in MUTANTS])
+def test_planted_mistake_fails_a_pin(name, results):
+    rc, detail = results[name]
+    assert rc != "harness", detail
+    # pytest exit code 1: the run completed and at least one pin failed
+    assert rc == 1, f"mutant {name} survived the pins (exit {rc}): {detail}"

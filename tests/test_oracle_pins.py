@@ -527,6 +527,22 @@ def test_knn_matches_full_sort_and_pads():
         q0 += n
 
 
+def test_knn_ties_go_to_the_lower_index():
+    """Equal squared distances (exact here: dyadic coordinates) are ordered by
+    the env-mate's index, reading R20 of the (distance, index) order."""
+    pts = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                    [0, 0, 1], [0, 0, -1], [0.5, 0, 0]], dtype=float)
+    n, K = len(pts), 6
+    s = blank_state(n)
+    s[:, 0:3] = pts + np.array([0.25, -0.5, 2.0])
+    _, nbr = make(n, k=K, env_sizes=[n]).observe(s, np.zeros((n, 3)))
+    assert [int(j) for j in nbr[0]] == [7, 1, 2, 3, 4, 5]
+    for i in range(n):
+        d2 = np.sum((pts - pts[i]) ** 2, axis=1)
+        order = [j for j in np.lexsort((np.arange(n), d2)) if j != i][:K]
+        assert [int(j) for j in nbr[i]] == order
+
+
 def test_obs_layout():
     s = blank_state(1)
     R = rot_z(0.4) @ rot_x(0.7)
@@ -682,6 +698,7 @@ def test_reward_terms_on_constructed_states():
     s0[0, W.SU:W.SU + 4] = [0.5, 0.5, 0.5, 0.5]
     s1[0, W.SU:W.SU + 4] = [0.6, 0.5, 0.4, 0.5]
     s1[1, W.SF] = 1.0
+    s1[1, 0:3] = [1.3, 2.4, 3.0]  # 0.5 m from quad 0: inside d_prox
     goals = np.array([[1.0, 2.0, 2.0], [0.0, 0.0, 5.0]])
     orc = make(q, k=1, env_sizes=[2])
     obs, _ = orc.observe(s1, goals)
@@ -690,6 +707,7 @@ def test_reward_terms_on_constructed_states():
     f1 = fmax * np.array([0.6, 0.5, 0.4, 0.5]) ** 2
     f0 = fmax * np.full(4, 0.25)
     dist = np.linalg.norm(s1[1, 0:3] - s1[0, 0:3])
+    assert dist == pytest.approx(0.5)
     expect0 = {0: 1.0, 1: 0.5, 2: R[2, 2], 3: 1.3, 4: np.linalg.norm(f1),
                5: np.linalg.norm(f1 - f0), 6: (np.trace(R) - 1) / 2, 7: R[0, 0],
                8: 1.0, 9: 0.0, 10: 0.0, 11: 0.0, 12: 1.0, 13: max(1 - dist / 2.5, 0)}
@@ -702,6 +720,13 @@ def test_reward_terms_on_constructed_states():
     w = np.zeros(15)
     w[9], w[10], w[11], w[14] = 1.0, 10.0, 100.0, 2.5
     assert orc.reward(s0, s1, ev, goals, obs, w)[1] == 111.0
+    # each indicator reads its own event bit
+    w = np.zeros(15)
+    w[8], w[10], w[11], w[12], w[14] = 1.0, 10.0, 100.0, 1000.0, 2.5
+    for bits, want in (((O.EV_WALL, O.EV_CEILING), (10.0, 100.0)),
+                       ((O.EV_FLOOR_HIT, O.EV_PAIR_RESPONSE), (1.0, 1000.0))):
+        r = orc.reward(s0, s1, np.array(bits, np.uint32), goals, obs, w)
+        np.testing.assert_array_equal(r, want)
     # a swarm of one has only zero-padded neighbour slots: no proximity term
     solo = make(1, k=3)
     o1, _ = solo.observe(s1[:1], goals[:1])
