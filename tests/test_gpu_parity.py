@@ -369,3 +369,31 @@ def test_gpu_floor_hit_and_rest():
     np.testing.assert_allclose(R[:, 2], [0, 0, 1], atol=0)
     assert math.atan2(R[1, 0], R[0, 0]) == pytest.approx(1.1, abs=2e-6)
     assert np.all(rest[0:3] == hit[0:3]) and rest[W.SF] == 1.0
+
+
+@pytest.mark.parametrize("sizes,k", [([8] * 16, 6), ([8] * 16, 3), ([8, 7, 8, 5, 8], 6)])
+def test_knn_exact_ties_follow_index_order(sizes, k):
+    """Neighbours at exactly equal distances come in index order (reading R20
+    of the (distance, index) order): dyadic positions, velocities and goals
+    make every observed value exact in float32, so the rows must equal the
+    oracle's bit for bit.  Covers the unrolled K = 6 path, the runtime-K
+    selection and the runtime swarm-size loops."""
+    lattice = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                        [0, 0, 1], [0, 0, -1], [0.5, 0, 0]], dtype=float) * 0.25
+    w = W.custom(sizes, seed=11, k=k, flags=W.SWARM_FLAGS, name="ties")
+    st = w.state0.astype(np.float64).copy()
+    for e, n in enumerate(sizes):
+        q0 = int(w.env_offsets[e])
+        st[q0:q0 + n, 0:3] = lattice[:n] + np.array([-3.0 + 0.5 * e, 1.0, 2.0])
+        st[q0:q0 + n, W.SV:W.SV + 3] = np.arange(3 * n).reshape(n, 3) * 0.125 - 1.0
+    goals = np.tile(np.array([0.5, -0.25, 1.5]), (w.n_quads, 1))
+    sim = QuadSwarm.from_workload(w)
+    sim.set_state(dev(st), 0)
+    obs = sim.observe(dev(goals)).cpu().numpy()
+    ref, nbr = O.Oracle.from_workload(w).observe(st.astype(np.float32).astype(np.float64), goals)
+    q0 = 0
+    for n in sizes:
+        if n == 8 and k >= 6:
+            assert [int(j) for j in nbr[q0, :6]] == [7, 1, 2, 3, 4, 5]
+        q0 += n
+    np.testing.assert_array_equal(obs, ref.astype(np.float32))
