@@ -28,6 +28,21 @@
  *    reads or each other (QS_ERR_INVALID), except where a call names one
  *    buffer as both input and output (d_gstate of qs_rollout_backward) or
  *    allows it (qs_step_backward: d_gstate_in may be d_gstate_out).
+ *  - Environment overrides of launch choices (the library picks each by
+ *    itself; results are bit-identical whichever form runs):
+ *      QS_BLOCK_SIZE=64|128  workgroup size, read by qs_create (default 64;
+ *                            128 for >= 262,144 single-quad swarms);
+ *      QS_BUCKETED=0         uneven swarm sizes run one workgroup per packed
+ *                            block instead of the persistent bucketed
+ *                            launch, read by qs_create;
+ *      QS_STEP_PIPE, QS_ROLLOUT_PIPE, QS_REVERSE_PIPE = 0|1
+ *                            force the two-wavefront form of multi-substep
+ *                            step calls (uniform 8-quad swarms), of
+ *                            qs_rollout and of the reverse sweep of
+ *                            qs_rollout_backward (swarms of 1 or 8) off or
+ *                            on; default on up to 1024 workgroups; read on
+ *                            every call;
+ *      QS_TAPE_BYTES         tape budget of qs_rollout_backward (below).
  *
  * Canonical layouts (row-major, float32):
  *  state  [Q][27] = x(3) v(3) R(9, row-major, body->world) omega(3, body)
