@@ -131,8 +131,11 @@ __device__ __forceinline__ float clampf(float a, float lo, float hi) {
 
 // §III-A.1: rotor-speed command from the normalised thrust action.
 __device__ __forceinline__ float rotor_cmd(float a, bool unit) {
-  const float fh = unit ? clampf(a, 0.0f, 1.0f) : 0.5f * (clampf(a, -1.0f, 1.0f) + 1.0f);
-  return sqrtf(fh);
+  // both maps, then a select: a branch on the flag would end the scheduling
+  // region (and wait for the action load) once per rotor
+  const float fu = clampf(a, 0.0f, 1.0f);
+  const float fs = 0.5f * (clampf(a, -1.0f, 1.0f) + 1.0f);
+  return sqrtf(unit ? fu : fs);
 }
 
 // Intermediates of one substep kept for the reverse sweep (adjoint).

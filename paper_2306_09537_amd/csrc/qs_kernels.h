@@ -105,12 +105,20 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   const int me = tid - ls;  // index within the swarm
   const int Qp = p.Qp;
   const float* __restrict__ S = p.st;
+  // field f of quad q: a uniform field base plus the quad's 32-bit byte
+  // offset (one address add per access instead of an index multiply,
+  // sign extension and shift)
+  const uint32_t qo = 4u * (uint32_t)q;
+  auto at = [&](const float* base, int f) -> const float& {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base + (size_t)f * Qp) + qo);
+  };
 
   Quad s;
   s.ev = 0u;
   QuadPar pp;
   float uhat[4] = {0.f, 0.f, 0.f, 0.f};
   float f0[4] = {0.f, 0.f, 0.f, 0.f};  // rotor thrusts before the call (reward)
+  float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);  // the call's action
   // the goal is loaded with the state: a load issued after the state stores
   // would wait for their completion (one in-order counter for both)
   float g0 = 0.f, g1 = 0.f, g2 = 0.f;
@@ -122,47 +130,60 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   if (live) {
     if constexpr (ROLE != 0) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s.x[k] = S[(S_X + k) * Qp + q];
+      for (int k = 0; k < 3; ++k) s.x[k] = at(S, S_X + k);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s.v[k] = S[(S_V + k) * Qp + q];
+      for (int k = 0; k < 3; ++k) s.v[k] = at(S, S_V + k);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) s.R[k] = S[(S_R + k) * Qp + q];
+      for (int k = 0; k < 9; ++k) s.R[k] = at(S, S_R + k);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s.w[k] = S[(S_W + k) * Qp + q];
+      for (int k = 0; k < 3; ++k) s.w[k] = at(S, S_W + k);
     }
     if (nsub > 0) {
       if constexpr (ROLE != 1) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s.u[k] = S[(S_U + k) * Qp + q];
+        for (int k = 0; k < 4; ++k) s.u[k] = at(S, S_U + k);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s.e[k] = S[(S_E + k) * Qp + q];
+        for (int k = 0; k < 4; ++k) s.e[k] = at(S, S_E + k);
       }
-      if constexpr (ROLE != 0) s.fl = S[S_F * Qp + q];
-      pp.m = p.par[P_M * Qp + q];
-      pp.jx = p.par[P_JX * Qp + q];
-      pp.jy = p.par[P_JY * Qp + q];
-      pp.jz = p.par[P_JZ * Qp + q];
-      pp.f_max = p.par[P_FMAX * Qp + q];
-      pp.a_lag = p.par[P_ALAG * Qp + q];
-      pp.inv_m = 1.0f / pp.m;
-      pp.ijx = 1.0f / pp.jx;
-      pp.ijy = 1.0f / pp.jy;
-      pp.ijz = 1.0f / pp.jz;
-      pp.a_ns = c.ns_scale * pp.f_max;
-      if constexpr (ROLE != 1) {
-        if (reward) {
+      if constexpr (ROLE != 0) s.fl = at(S, S_F);
+      pp.m = at(p.par, P_M);
+      pp.jx = at(p.par, P_JX);
+      pp.jy = at(p.par, P_JY);
+      pp.jz = at(p.par, P_JZ);
+      pp.f_max = at(p.par, P_FMAX);
+      pp.a_lag = at(p.par, P_ALAG);
+    }
+  }
+  // the call's action, loaded by every lane without a branch (an idle lane's
+  // q is its workgroup's first quad, and a call without substeps reads a row
+  // of the state instead), so no merge of its value has to wait for it
+  if constexpr (ROLE != 1)
+    a4 = reinterpret_cast<const float4*>(nsub > 0 ? act : p.st)[q];
+  // §III-A.2 motor noise: the draws depend on the quad, the substep index and
+  // the seed only.  With the index known at launch, the first substep's are
+  // drawn here, between issuing the loads above and using what they return.
+  const bool noise = (c.flags & F_NOISE) != 0;
+  const bool early_z = ROLE != 1 && tdev == nullptr && nsub > 0 && noise;
+  float z0[4] = {0.f, 0.f, 0.f, 0.f};
+  if (early_z && live) normal4(c, (uint32_t)q, t0, STREAM_MOTOR, 0, z0);
+  if (live && nsub > 0) {
+    pp.inv_m = 1.0f / pp.m;
+    pp.ijx = 1.0f / pp.jx;
+    pp.ijy = 1.0f / pp.jy;
+    pp.ijz = 1.0f / pp.jz;
+    pp.a_ns = c.ns_scale * pp.f_max;
+    if constexpr (ROLE != 1) {
+      if (reward) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) f0[i] = fmaf(pp.f_max * s.u[i], s.u[i], s.e[i]);
-        }
-        const float4 a4 = reinterpret_cast<const float4*>(act)[q];
-        const bool unit = (c.flags & F_ACT_UNIT) != 0;
-        uhat[0] = rotor_cmd(a4.x, unit);
-        uhat[1] = rotor_cmd(a4.y, unit);
-        uhat[2] = rotor_cmd(a4.z, unit);
-        uhat[3] = rotor_cmd(a4.w, unit);
-        if (!(isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z) && isfinite(a4.w)))
-          __hip_atomic_fetch_or(p.err, ERRBIT_ACTION, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int i = 0; i < 4; ++i) f0[i] = fmaf(pp.f_max * s.u[i], s.u[i], s.e[i]);
       }
+      const bool unit = (c.flags & F_ACT_UNIT) != 0;
+      uhat[0] = rotor_cmd(a4.x, unit);
+      uhat[1] = rotor_cmd(a4.y, unit);
+      uhat[2] = rotor_cmd(a4.z, unit);
+      uhat[3] = rotor_cmd(a4.w, unit);
+      if (!(isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z) && isfinite(a4.w)))
+        __hip_atomic_fetch_or(p.err, ERRBIT_ACTION, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   // graph mode: the substep index comes from the device counter (read after
@@ -173,10 +194,15 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   unsigned long long cmask = 0ull;
   for (int sub = 0; sub < nsub; ++sub) {
     const unsigned long long t = t0 + (unsigned long long)sub;
+    // this substep's motor-noise draws
+    float zs[4] = {z0[0], z0[1], z0[2], z0[3]};
+    if constexpr (ROLE != 1) {
+      if (noise && live && !(sub == 0 && early_z)) normal4(c, (uint32_t)q, t, STREAM_MOTOR, 0, zs);
+    }
     if constexpr (ROLE == 0) {
       if (live) {
         float z[4] = {0.f, 0.f, 0.f, 0.f};
-        const Drive d = motor_step(c, pp, s.u, s.e, uhat, (uint32_t)q, t, z);
+        const Drive d = motor_step<Z_IMPORT>(c, pp, s.u, s.e, uhat, (uint32_t)q, t, z, zs);
         ring[sub & 1][0][tid] = d.T;
         ring[sub & 1][1][tid] = d.tx;
         ring[sub & 1][2][tid] = d.ty;
@@ -196,7 +222,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
         body_step(c, pp, s, d, (uint32_t)q, t);
       }
     } else {
-      if (live) quad_substep(c, pp, s, uhat, (uint32_t)q, t);
+      if (live) quad_substep<false, Z_IMPORT>(c, pp, s, uhat, (uint32_t)q, t, nullptr, zs);
     }
     if (collide) {
       // §III-B.1 in-env pair pass (Jacobi: every response from the
@@ -234,24 +260,27 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   __builtin_amdgcn_s_waitcnt(0);
   if (live && nsub > 0) {
     float* St = p.st;
+    auto to = [&](int f) -> float& {
+      return *reinterpret_cast<float*>(reinterpret_cast<char*>(St + (size_t)f * Qp) + qo);
+    };
     float chk = 0.f;
     if constexpr (ROLE != 0) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) { St[(S_X + k) * Qp + q] = s.x[k]; chk += s.x[k]; }
+      for (int k = 0; k < 3; ++k) { to(S_X + k) = s.x[k]; chk += s.x[k]; }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) { St[(S_V + k) * Qp + q] = s.v[k]; chk += s.v[k]; }
+      for (int k = 0; k < 3; ++k) { to(S_V + k) = s.v[k]; chk += s.v[k]; }
 #pragma unroll
-      for (int k = 0; k < 9; ++k) { St[(S_R + k) * Qp + q] = s.R[k]; chk += s.R[k]; }
+      for (int k = 0; k < 9; ++k) { to(S_R + k) = s.R[k]; chk += s.R[k]; }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) { St[(S_W + k) * Qp + q] = s.w[k]; chk += s.w[k]; }
+      for (int k = 0; k < 3; ++k) { to(S_W + k) = s.w[k]; chk += s.w[k]; }
     }
     if constexpr (ROLE != 1) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) { St[(S_U + k) * Qp + q] = s.u[k]; chk += s.u[k]; }
+      for (int k = 0; k < 4; ++k) { to(S_U + k) = s.u[k]; chk += s.u[k]; }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) { St[(S_E + k) * Qp + q] = s.e[k]; chk += s.e[k]; }
+      for (int k = 0; k < 4; ++k) { to(S_E + k) = s.e[k]; chk += s.e[k]; }
     }
-    if constexpr (ROLE != 0) St[S_F * Qp + q] = s.fl;
+    if constexpr (ROLE != 0) to(S_F) = s.fl;
     if (!isfinite(chk))
       __hip_atomic_fetch_or(p.err, ERRBIT_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ROLE != 0 && p.contacts) p.contacts[q] = cmask;
