@@ -89,6 +89,15 @@ MUTANTS = [
      "if (v[k] > 0.0) { v[k] = 0.0 * v[k]; bounced = 1; r->flip[k] = 1; }"),
     ("lower_wall_no_clamp", "§III-B.2",
      "x[k] = d->room_min[k];\n        r->clamp[k] = 1;", "r->clamp[k] = 1;"),
+    ("wall_decay_dropped", "§III-B.2",
+     "v[k] = d->col_decay * (v[k] + d->col_noise_v * zv[k]);",
+     "v[k] = (v[k] + d->col_noise_v * zv[k]);"),
+    ("wall_decay_per_wall", "§III-B.2",
+     "if (v[k] > 0.0) { v[k] = -e * v[k]; bounced = 1; r->flip[k] = 1; }",
+     "if (v[k] > 0.0) { v[k] = -e * d->col_decay * v[k]; bounced = 1; r->flip[k] = 1; }"),
+    ("pair_decay_dropped", "§III-B.1",
+     "si[IV + k] = d->col_decay * (si[IV + k] + dv[i][k] + d->col_noise_v * zv[k]);",
+     "si[IV + k] = (si[IV + k] + dv[i][k] + d->col_noise_v * zv[k]);"),
     ("rest_threshold", "§III-B.3",
      "s[IF] != 0.0 && F[2] <= m * g;", "s[IF] != 0.0 && F[2] <= 0.5 * m * g;"),
     ("friction_direction", "§III-B.3",

@@ -313,6 +313,24 @@ def test_wall_and_ceiling_bounce(axis, side):
     assert ev[0] & bit and not ev[1] & (O.EV_WALL | O.EV_CEILING)
 
 
+def test_corner_bounce_mirrors_with_restitution_and_decays_once():
+    """§III-B.2 with restitution e < 1 and decay alpha < 1: a quad crossing the
+    x and y walls in one substep has both normal components mirrored and scaled
+    by e, then its whole velocity scaled by alpha once (reading R12), not once
+    per wall.  No thrust and no gravity, so the free velocity is unchanged."""
+    s = blank_state(1, z=5.0)
+    s[0, 0:3] = [4.999, 4.999, 5.0]
+    s[0, W.SU:W.SU + 4] = 0.0
+    s[0, W.SV:W.SV + 3] = [3.0, 2.0, 0.25]
+    e, a = 0.5, 0.8
+    orc = make(1, flags=W.QS_ROOM, gravity=0.0, wall_restitution=e, col_decay=a)
+    out, _, ev = orc.step(s, -np.ones((1, 4)), 1, 0)
+    assert out[0, 0] == 5.0 and out[0, 1] == 5.0
+    np.testing.assert_allclose(out[0, W.SV:W.SV + 3], [a * -e * 3.0, a * -e * 2.0, a * 0.25],
+                               rtol=1e-15)
+    assert ev[0] & O.EV_WALL
+
+
 def test_floor_hit_resets_and_keeps_yaw():
     psi = 1.1
     R0 = rot_z(psi) @ rot_x(0.5)
@@ -434,6 +452,28 @@ def test_head_on_exchange():
     # normal along x: normal components swap, tangential components kept
     np.testing.assert_allclose(out[0, W.SV:W.SV + 3], [-0.5, 0.3, -0.2], atol=1e-15)
     np.testing.assert_allclose(out[1, W.SV:W.SV + 3], [1.0, 0.3, -0.2], atol=1e-15)
+
+
+def test_pair_response_decays_the_responding_quads():
+    """§III-B.1 with decay alpha < 1: v <- alpha (v + dv) for both quads of a
+    responding pair (the head-on exchange above, scaled); a swarm-mate out of
+    contact keeps its velocity."""
+    s = blank_state(3, z=5.0)
+    s[0, 0:3] = [0.0, 0.0, 5.0]
+    s[1, 0:3] = [0.08, 0.0, 5.0]
+    s[2, 0:3] = [2.0, 0.0, 5.0]
+    s[0, W.SV:W.SV + 3] = [1.0, 0.3, -0.2]
+    s[1, W.SV:W.SV + 3] = [-0.5, 0.3, -0.2]
+    s[2, W.SV:W.SV + 3] = [0.1, 0.2, 0.3]
+    s[:, W.SU:W.SU + 4] = 0.0
+    a = 0.8
+    flags = W.QS_COLLIDE | W.QS_APPROACH_ONLY
+    orc = make(3, flags=flags, env_sizes=[3], gravity=0.0, col_decay=a)
+    out, c, _ = orc.step(s, -np.ones((3, 4)), 1, 0)
+    assert c[0] == 2 and c[1] == 1 and c[2] == 0
+    np.testing.assert_allclose(out[0, W.SV:W.SV + 3], a * np.array([-0.5, 0.3, -0.2]), atol=1e-15)
+    np.testing.assert_allclose(out[1, W.SV:W.SV + 3], a * np.array([1.0, 0.3, -0.2]), atol=1e-15)
+    np.testing.assert_array_equal(out[2, W.SV:W.SV + 3], [0.1, 0.2, 0.3])
 
 
 def test_separating_pair_is_left_alone():
