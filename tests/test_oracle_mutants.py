@@ -192,6 +192,51 @@ MUTANTS = [
     ("vjp_penalty_sign", "reverse mode, §III-E penalty",
      "double coef = -0.5 * (gpen[q0 + i] + gpen[q0 + j])",
      "double coef = 0.5 * (gpen[q0 + i] + gpen[q0 + j])"),
+    # further slips in the floor model, contacts, downwash, sensor noise,
+    # reward and reverse mode
+    ("static_friction_sign", "§III-B.3",
+     "double mag = nf - mu_n > 0.0 ? nf - mu_n : 0.0;", "double mag = nf + mu_n > 0.0 ? nf + mu_n : 0.0;"),
+    ("friction_guard_dropped", "§III-B.3",
+     "if (dot < 0.0) { v[0] = 0.0; v[1] = 0.0; r->guard = 1; }",
+     "if (dot < -1e300) { v[0] = 0.0; v[1] = 0.0; r->guard = 1; }"),
+    ("rest_keeps_vz", "§III-B.3",
+     "    v[0] += dt * acc[0];\n    v[1] += dt * acc[1];\n    v[2] = 0.0;",
+     "    v[0] += dt * acc[0];\n    v[1] += dt * acc[1];"),
+    ("rest_keeps_body_rate", "§III-B.3",
+     "    for (int k = 0; k < 3; ++k) x[k] += dt * v[k];\n    w[0] = w[1] = w[2] = 0.0;\n  }",
+     "    for (int k = 0; k < 3; ++k) x[k] += dt * v[k];\n  }"),
+    ("takeoff_keeps_flag", "§III-B.3", "    s[IF] = 0.0;\n", "\n"),
+    ("coincident_normal_along_x", "§III-B.1",
+     "        nrm[0] = 0.0; nrm[1] = 0.0; nrm[2] = 1.0;", "        nrm[0] = 1.0; nrm[1] = 0.0; nrm[2] = 0.0;"),
+    ("downwash_slope_sign", "§III-B.4",
+     "adw[i] += -d->dw_k1 * (d->dw_k2 * dz + d->dw_b1);",
+     "adw[i] += -d->dw_k1 * (-d->dw_k2 * dz + d->dw_b1);"),
+    ("downwash_radius_unsquared", "§III-B.4",
+     "hx * hx + hy * hy < d->dw_radius * d->dw_radius", "hx * hx + hy * hy < d->dw_radius"),
+    ("sensor_widths_swapped", "§III-C",
+     "const double a = draw == 0 ? d->sn_x : d->sn_v;", "const double a = draw == 0 ? d->sn_v : d->sn_x;"),
+    ("observe_padding_nonzero", "§III-C",
+     "          for (int k = 0; k < 6; ++k) os[k] = 0.0;", "          for (int k = 0; k < 6; ++k) os[k] = 1.0;"),
+    ("reward_goal_distance_squared", "§III-E", "w[0] * sqrt(dx2)", "w[0] * dx2"),
+    ("reward_spin_squared", "§III-E", "w[3] * sqrt(w2)", "w[3] * w2"),
+    ("reward_rotation_offset", "§III-E",
+     "w[6] * (b[IR + 0] + b[IR + 4] + b[IR + 8] - 1.0) / 2.0",
+     "w[6] * (b[IR + 0] + b[IR + 4] + b[IR + 8]) / 2.0"),
+    ("penalty_half_dropped", "§III-E penalty",
+     "double h = 0.5 * softplus(beta * (d->col_dist - sqrt(d2))) / beta;",
+     "double h = softplus(beta * (d->col_dist - sqrt(d2))) / beta;"),
+    ("vjp_inertia_sign", "reverse mode, §III-A",
+     "lJ[k] += -lwd[k] * r->wdot[k] / J[k];", "lJ[k] += lwd[k] * r->wdot[k] / J[k];"),
+    ("vjp_gram_schmidt_norm", "reverse mode, Gram-Schmidt",
+     "lb[k] = (lc1[k] - dd * r->c1[k]) / r->n1;", "lb[k] = (lc1[k] - dd * r->c1[k]) / r->n0;"),
+    ("vjp_gram_schmidt_projection", "reverse mode, Gram-Schmidt",
+     "lc0[k] += -r->dp * lb[k] + ldp * r->A1[k];", "lc0[k] += -r->dp * lb[k];"),
+    ("vjp_sqrt_half_dropped", "reverse mode, §III-A.1",
+     "gu[(size_t)q * 4 + i] * 0.5 / uh * dfhat_da(d, a)", "gu[(size_t)q * 4 + i] / uh * dfhat_da(d, a)"),
+    ("vjp_penalty_sigmoid_argument", "reverse mode, §III-E penalty",
+     "sigmoid(beta * (d->col_dist - dd))", "sigmoid(beta * (dd - d->col_dist))"),
+    ("vjp_action_map_slope", "reverse mode, §III-A.1",
+     "return (a > -1.0 && a < 1.0) ? 0.5 : 0.0;", "return (a > -1.0 && a < 1.0) ? 1.0 : 0.0;"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS

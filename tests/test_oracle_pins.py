@@ -367,6 +367,36 @@ def test_floor_static_hold_keeps_position():
         assert st[0, W.SF] == 1.0
 
 
+@pytest.mark.parametrize("theta,fhat,slides", [(5.0, 0.25, False), (30.0, 0.45, True)])
+def test_floor_static_friction_under_tilted_thrust(theta, fhat, slides):
+    """§III-B.3 static regime (v_xy = 0) of a resting quad tilted about body y,
+    thrust below its weight: the horizontal thrust |F_xy| = T sin(theta) is
+    held while below mu N, N = m g - T cos(theta); above it the quad starts
+    to slide with a = (|F_xy| - mu N)/m along F_xy.  Resting zeroes the body
+    rate and holds the attitude either way (reading R13)."""
+    R = rot_y(math.radians(theta))
+    s = blank_state(1, z=0.0)
+    s[0, W.SF] = 1.0
+    s[0, W.SR:W.SR + 9] = R.reshape(9)
+    s[0, W.SW:W.SW + 3] = [0.3, -0.2, 0.1]
+    u = math.sqrt(fhat)
+    s[0, W.SU:W.SU + 4] = u                  # already at the commanded speed
+    out, _, _ = make(1, flags=W.QS_FLOOR).step(s, np.full((1, 4), 2.0 * fhat - 1.0), 1, 0)
+    fmax = 0.25 * M * G * 2.0
+    f = fmax * u * u
+    T = (f + f) + (f + f)
+    F = T * R[:, 2]
+    assert F[2] <= M * G
+    excess = math.hypot(F[0], F[1]) - 0.6 * (M * G - F[2])
+    assert (excess > 0.0) == slides
+    vx = DT * excess / M if slides else 0.0
+    np.testing.assert_allclose(out[0, W.SV:W.SV + 3], [vx, 0.0, 0.0], rtol=1e-12, atol=0.0)
+    np.testing.assert_allclose(out[0, 0:3], [DT * vx, 0.0, 0.0], rtol=1e-12, atol=0.0)
+    assert np.all(out[0, W.SW:W.SW + 3] == 0.0)
+    np.testing.assert_array_equal(out[0, W.SR:W.SR + 9], R.reshape(9))
+    assert out[0, W.SF] == 1.0
+
+
 def test_floor_kinetic_friction_and_stop():
     """Sliding on the floor with no thrust: |v_xy| drops by mu g dt per substep
     along -v_hat and stops at zero without reversing."""
@@ -739,7 +769,7 @@ def test_reward_terms_on_constructed_states():
     s1[0, W.SU:W.SU + 4] = [0.6, 0.5, 0.4, 0.5]
     s1[1, W.SF] = 1.0
     s1[1, 0:3] = [1.3, 2.4, 3.0]  # 0.5 m from quad 0: inside d_prox
-    goals = np.array([[1.0, 2.0, 2.0], [0.0, 0.0, 5.0]])
+    goals = np.array([[1.0, 2.0, 1.5], [0.0, 0.0, 5.0]])
     orc = make(q, k=1, env_sizes=[2])
     obs, _ = orc.observe(s1, goals)
     ev = np.array([O.EV_FLOOR_HIT | O.EV_PAIR_RESPONSE, O.EV_WALL | O.EV_CEILING], np.uint32)
@@ -748,7 +778,7 @@ def test_reward_terms_on_constructed_states():
     f0 = fmax * np.full(4, 0.25)
     dist = np.linalg.norm(s1[1, 0:3] - s1[0, 0:3])
     assert dist == pytest.approx(0.5)
-    expect0 = {0: 1.0, 1: 0.5, 2: R[2, 2], 3: 1.3, 4: np.linalg.norm(f1),
+    expect0 = {0: 1.5, 1: 0.5, 2: R[2, 2], 3: 1.3, 4: np.linalg.norm(f1),
                5: np.linalg.norm(f1 - f0), 6: (np.trace(R) - 1) / 2, 7: R[0, 0],
                8: 1.0, 9: 0.0, 10: 0.0, 11: 0.0, 12: 1.0, 13: max(1 - dist / 2.5, 0)}
     for k, v in expect0.items():
