@@ -21,7 +21,7 @@ from oracle import oracle as O  # noqa: E402
 from paper_2306_09537_amd import workloads as W  # noqa: E402
 from paper_2306_09537_amd.quadswarm import QuadSwarm, QuadSwarmError  # noqa: E402
 from tests import gpu_util as U  # noqa: E402
-from tests.helpers import blank_state, consts, nominal_params, rot_x, rot_z  # noqa: E402
+from tests.helpers import blank_state, consts, nominal_params, rot_x, rot_y, rot_z  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -397,3 +397,33 @@ def test_knn_exact_ties_follow_index_order(sizes, k):
             assert [int(j) for j in nbr[q0, :6]] == [7, 1, 2, 3, 4, 5]
         q0 += n
     np.testing.assert_array_equal(obs, ref.astype(np.float32))
+
+
+def test_gpu_static_friction_under_tilted_thrust():
+    """§III-B.3 static regime on the GPU, against the oracle: a resting quad
+    tilted about body y with thrust below its weight holds while its
+    horizontal thrust is below mu N (5 degrees, half the weight) and starts
+    to slide above it (30 degrees, 0.9 of the weight); both have their body
+    rate zeroed and their attitude held."""
+    s = blank_state(2, z=0.0)
+    s[:, W.SF] = 1.0
+    s[:, W.SW:W.SW + 3] = [0.3, -0.2, 0.1]
+    acts = np.zeros((2, 4))
+    for i, (theta, fhat) in enumerate([(5.0, 0.25), (30.0, 0.45)]):
+        s[i, W.SR:W.SR + 9] = rot_y(math.radians(theta)).reshape(9)
+        s[i, W.SU:W.SU + 4] = math.sqrt(fhat)
+        acts[i] = 2.0 * fhat - 1.0
+    s32 = s.astype(np.float32).astype(np.float64)
+    sim = _custom_sim(s32, flags=W.QS_FLOOR)
+    sim.step(dev(acts), 1)
+    got = sim.get_state()[0].cpu().numpy().astype(np.float64)
+    orc = O.Oracle(np.array([0, 1, 2], np.int32), consts(), nominal_params(2), 0, W.QS_FLOOR, 3)
+    ref, _, _ = orc.step(s32, acts.astype(np.float32).astype(np.float64), 1, 0)
+    # held: no motion at all; sliding: v_x > 0 from rest, matching the oracle
+    assert np.all(got[0, 0:3] == s32[0, 0:3]) and np.all(got[0, W.SV:W.SV + 3] == 0.0)
+    assert ref[1, W.SV] > 0.0
+    np.testing.assert_allclose(got[1, W.SV:W.SV + 3], ref[1, W.SV:W.SV + 3], rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(got[1, 0:3], ref[1, 0:3], rtol=1e-5, atol=1e-9)
+    assert np.all(got[:, W.SW:W.SW + 3] == 0.0)
+    np.testing.assert_array_equal(got[:, W.SR:W.SR + 9], s32[:, W.SR:W.SR + 9])
+    assert np.all(got[:, W.SF] == 1.0)
