@@ -47,10 +47,15 @@ def fd(f, x, h):
     return (f(x + h) - f(x - h)) / (2 * h)
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_action_gradient_matches_central_differences(seed):
+# non-default constants make the drag, wall-restitution and decay terms of
+# the reverse mode count (at the defaults they vanish or are the identity)
+LOSSY = dict(drag_coef=0.05, col_decay=0.9, wall_restitution=0.8)
+
+
+@pytest.mark.parametrize("seed,c", [(0, {}), (1, {}), (2, LOSSY)])
+def test_action_gradient_matches_central_differences(seed, c):
     T, nsub = 30, 2
-    w, s0, orc, acts, Wt, gpen, gs0, gact, gpar = setup(seed, T, nsub)
+    w, s0, orc, acts, Wt, gpen, gs0, gact, gpar = setup(seed, T, nsub, **c)
     rng = np.random.default_rng(seed)
     h = 1e-6
     checked = 0
@@ -114,9 +119,10 @@ def test_contacts_and_penalty_are_exercised():
     assert pen.min() > 0 and pen.max() > 1e-3
 
 
-def test_floor_and_wall_branches():
+@pytest.mark.parametrize("c", [{}, LOSSY])
+def test_floor_and_wall_branches(c):
     """Gradients through the floor rest / friction and the wall mirror."""
-    w, s0 = dense_problem(11, n_envs=2, z=0.0, spread=0.3)
+    w, s0 = dense_problem(11, n_envs=2, z=0.0, spread=0.3, **c)
     s0[:, 2] = 0.0
     s0[:, W.SF] = 1.0                       # resting
     s0[:, W.SR:W.SR + 9] = np.eye(3).reshape(9)

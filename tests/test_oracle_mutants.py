@@ -237,6 +237,30 @@ MUTANTS = [
      "sigmoid(beta * (d->col_dist - dd))", "sigmoid(beta * (dd - d->col_dist))"),
     ("vjp_action_map_slope", "reverse mode, §III-A.1",
      "return (a > -1.0 && a < 1.0) ? 0.5 : 0.0;", "return (a > -1.0 && a < 1.0) ? 1.0 : 0.0;"),
+    ("room_floor_as_wall", "§III-B.2, §III-B.3",
+     "if (k < 2 && x[k] < d->room_min[k]) {", "if (x[k] < d->room_min[k]) {"),
+    ("gyroscopic_operand_order", "§III-A Euler's equation",
+     "double wxJw[3] = {w[1] * Jw[2] - w[2] * Jw[1], w[2] * Jw[0] - w[0] * Jw[2],\n"
+     "                      w[0] * Jw[1] - w[1] * Jw[0]};",
+     "double wxJw[3] = {Jw[1] * w[2] - Jw[2] * w[1], Jw[2] * w[0] - Jw[0] * w[2],\n"
+     "                      Jw[0] * w[1] - Jw[1] * w[0]};"),
+    ("drag_not_per_mass", "linear drag",
+     "acc[k] = F[k] / m - d->drag_coef / m * v[k];", "acc[k] = F[k] / m - d->drag_coef * v[k];"),
+    ("kinetic_friction_index", "§III-B.3",
+     "fb[1] = F[1] - mu_n * v[1] / nv;", "fb[1] = F[1] - mu_n * v[0] / nv;"),
+    ("floor_heading_from_row", "§III-B.3",
+     "double hx = R[0], hy = R[3];", "double hx = R[0], hy = R[1];"),
+    ("knn_self_included", "§III-C", "used[j] = (j == i);", "used[j] = 0;"),
+    ("reward_thrust_without_noise", "§III-E",
+     "const double f1 = f_max * b[IU + i] * b[IU + i] + b[IE + i];",
+     "const double f1 = f_max * b[IU + i] * b[IU + i];"),
+    ("vjp_drag_dropped", "reverse mode, linear drag",
+     "lv0[k] = lv1 - d->drag_coef / m * lacc[k];", "lv0[k] = lv1;"),
+    ("vjp_wall_decay_dropped", "reverse mode, §III-B.2",
+     "for (int k = 0; k < 3; ++k) lv[k] *= d->col_decay;",
+     "for (int k = 0; k < 3; ++k) lv[k] *= 1.0;"),
+    ("vjp_contact_position_sign", "reverse mode, §III-B.1",
+     "          li[IX + k] += gx;", "          li[IX + k] -= gx;"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS

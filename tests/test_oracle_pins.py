@@ -331,7 +331,10 @@ def test_corner_bounce_mirrors_with_restitution_and_decays_once():
     assert ev[0] & O.EV_WALL
 
 
-def test_floor_hit_resets_and_keeps_yaw():
+@pytest.mark.parametrize("flags", [W.QS_FLOOR, W.QS_FLOOR | W.QS_ROOM])
+def test_floor_hit_resets_and_keeps_yaw(flags):
+    """§III-B.3 floor hit, alone and with the room on (the room's lower
+    bounds are walls in x and y only: the floor is the floor model's)."""
     psi = 1.1
     R0 = rot_z(psi) @ rot_x(0.5)
     s = blank_state(1, z=0.002)
@@ -340,10 +343,10 @@ def test_floor_hit_resets_and_keeps_yaw():
     s[0, W.SU:W.SU + 4] = 0.0
     s2 = s.copy()
     s2[0, W.SW:W.SW + 3] = [1.0, 2.0, 3.0]   # spinning when it lands
-    out2, _, _ = make(1, flags=W.QS_FLOOR).step(s2, -np.ones((1, 4)), 1, 0)
+    out2, _, _ = make(1, flags=flags).step(s2, -np.ones((1, 4)), 1, 0)
     assert np.all(out2[0, W.SW:W.SW + 3] == 0.0) and out2[0, W.SF] == 1.0
     # no spin: R is unchanged by the substep, so the yaw to keep is R0's
-    out, _, ev = make(1, flags=W.QS_FLOOR).step(s, -np.ones((1, 4)), 1, 0)
+    out, _, ev = make(1, flags=flags).step(s, -np.ones((1, 4)), 1, 0)
     assert ev[0] & O.EV_FLOOR_HIT
     assert out[0, 2] == 0.0 and out[0, W.SF] == 1.0
     assert np.all(out[0, W.SV:W.SV + 3] == 0.0) and np.all(out[0, W.SW:W.SW + 3] == 0.0)
@@ -767,6 +770,10 @@ def test_reward_terms_on_constructed_states():
     s1[0, W.SW:W.SW + 3] = [0.0, 1.2, 0.5]
     s0[0, W.SU:W.SU + 4] = [0.5, 0.5, 0.5, 0.5]
     s1[0, W.SU:W.SU + 4] = [0.6, 0.5, 0.4, 0.5]
+    e0 = np.array([0.002, -0.001, 0.0, 0.003])   # motor noise (N) in the thrusts
+    e1 = np.array([-0.004, 0.001, 0.002, 0.0])
+    s0[0, W.SE:W.SE + 4] = e0
+    s1[0, W.SE:W.SE + 4] = e1
     s1[1, W.SF] = 1.0
     s1[1, 0:3] = [1.3, 2.4, 3.0]  # 0.5 m from quad 0: inside d_prox
     goals = np.array([[1.0, 2.0, 1.5], [0.0, 0.0, 5.0]])
@@ -774,8 +781,8 @@ def test_reward_terms_on_constructed_states():
     obs, _ = orc.observe(s1, goals)
     ev = np.array([O.EV_FLOOR_HIT | O.EV_PAIR_RESPONSE, O.EV_WALL | O.EV_CEILING], np.uint32)
     fmax = 0.25 * M * G * 2.0
-    f1 = fmax * np.array([0.6, 0.5, 0.4, 0.5]) ** 2
-    f0 = fmax * np.full(4, 0.25)
+    f1 = fmax * np.array([0.6, 0.5, 0.4, 0.5]) ** 2 + e1
+    f0 = fmax * np.full(4, 0.25) + e0
     dist = np.linalg.norm(s1[1, 0:3] - s1[0, 0:3])
     assert dist == pytest.approx(0.5)
     expect0 = {0: 1.5, 1: 0.5, 2: R[2, 2], 3: 1.3, 4: np.linalg.norm(f1),
