@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as O  # noqa: E402
 from paper_2306_09537_amd import workloads as W  # noqa: E402
 from paper_2306_09537_amd.quadswarm import QuadSwarm, rollout  # noqa: E402
-from tests.test_oracle_grad import dense_problem  # noqa: E402
+from tests.test_oracle_grad import LOSSY, dense_problem  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 BETA = 100.0
@@ -114,9 +114,10 @@ def test_rollout_forward_matches_steps_and_oracle_penalty():
     np.testing.assert_allclose(pen.cpu().numpy(), pen_o, rtol=2e-4, atol=1e-7)
 
 
-@pytest.mark.parametrize("seed,T,nsub,ce", [(0, 30, 2, 7), (1, 60, 1, 20), (3, 20, 5, 3)])
-def test_adjoint_matches_oracle(seed, T, nsub, ce):
-    w, acts, Wt, gpen = problem(seed, T)
+@pytest.mark.parametrize("seed,T,nsub,ce,c", [(0, 30, 2, 7, {}), (1, 60, 1, 20, {}), (3, 20, 5, 3, {}),
+                                              (2, 30, 2, 7, LOSSY)])
+def test_adjoint_matches_oracle(seed, T, nsub, ce, c):
+    w, acts, Wt, gpen = problem(seed, T, **c)
     g_ref = oracle_grads(w, acts, nsub, Wt, gpen)
     tol = bound(w, acts, nsub, Wt, gpen, g_ref, seed)
     gs, gact, gpar, *_ = gpu_grads(w, acts, nsub, Wt, gpen, ce)
@@ -264,5 +265,46 @@ def test_diff_workload_full_size_sampled():
     errs = [relerr(gs[q0:q1], g_ref[0]), relerr(gact[:, q0:q1], g_ref[1]),
             relerr(gpar[q0:q1], g_ref[2])]
     print("full-size sampled rel err:", errs, "bounds:", tol)
+    for e, b in zip(errs, tol):
+        assert e <= b
+
+
+def floor_wall_problem(**c):
+    """Eight quads resting (some sliding) on the floor under low thrust and
+    eight flying into the +x wall: the floor-rest, friction and wall-mirror
+    branches of the adjoint (the oracle's own pin of these branches, on the
+    GPU)."""
+    w, s0 = dense_problem(11, n_envs=2, z=0.0, spread=0.3, **c)
+    s0[:, 2] = 0.0
+    s0[:, W.SF] = 1.0
+    s0[:, W.SR:W.SR + 9] = np.eye(3).reshape(9)
+    s0[:8, W.SV:W.SV + 2] = np.random.default_rng(1).normal(0, 0.5, size=(8, 2))
+    s0[8:, 0] = 4.95
+    s0[8:, W.SF] = 0.0
+    s0[8:, 2] = 3.0
+    s0[8:, W.SV] = 2.0
+    w = w.with_(state0=s0.astype(np.float32))
+    rng = np.random.default_rng(5)
+    T = 10
+    acts = np.concatenate([rng.uniform(0.0, 0.2, size=(T, 8, 4)) - 0.8,
+                           rng.uniform(0.2, 0.8, size=(T, 8, 4))], axis=1).astype(np.float32)
+    Wt = rng.normal(size=(w.n_quads, 27)).astype(np.float32)
+    Wt[:, 26] = 0
+    gpen = np.ones(w.n_quads, np.float32)
+    return w, acts, Wt, gpen
+
+
+@pytest.mark.parametrize("c", [{}, LOSSY])
+def test_adjoint_through_floor_and_walls_matches_oracle(c):
+    """Gradients through floor rest and friction and the wall mirror; with
+    non-default constants also through the drag, decay and restitution
+    terms."""
+    w, acts, Wt, gpen = floor_wall_problem(**c)
+    g_ref = oracle_grads(w, acts, 1, Wt, gpen)
+    tol = bound(w, acts, 1, Wt, gpen, g_ref, 11)
+    gs, gact, gpar, sT, *_ = gpu_grads(w, acts, 1, Wt, gpen, 4)
+    assert np.all(sT[:8, W.SF] == 1.0) and np.all(sT[8:, 0] <= 5.0)
+    errs = [relerr(gs, g_ref[0]), relerr(gact, g_ref[1]), relerr(gpar, g_ref[2])]
+    print("floor/wall adjoint rel err (state0, actions, params):", errs, "bounds:", tol)
     for e, b in zip(errs, tol):
         assert e <= b
