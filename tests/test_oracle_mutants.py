@@ -261,6 +261,25 @@ MUTANTS = [
      "for (int k = 0; k < 3; ++k) lv[k] *= 1.0;"),
     ("vjp_contact_position_sign", "reverse mode, §III-B.1",
      "          li[IX + k] += gx;", "          li[IX + k] -= gx;"),
+    ("wall_noise_one_axis", "§III-B.2",
+     "v[k] = d->col_decay * (v[k] + d->col_noise_v * zv[k]);",
+     "v[k] = d->col_decay * (v[k] + d->col_noise_v * zv[0]);"),
+    ("wall_rate_noise_from_velocity_draws", "§III-B.2",
+     "w[k] = w[k] + d->col_noise_w * zw[k];", "w[k] = w[k] + d->col_noise_w * zv[k];"),
+    ("pair_noise_one_axis", "§III-B.1",
+     "si[IV + k] = d->col_decay * (si[IV + k] + dv[i][k] + d->col_noise_v * zv[k]);",
+     "si[IV + k] = d->col_decay * (si[IV + k] + dv[i][k] + d->col_noise_v * zv[0]);"),
+    ("pair_rate_noise_from_velocity_draws", "§III-B.1",
+     "si[IW + k] = si[IW + k] + d->col_noise_w * zw[k];",
+     "si[IW + k] = si[IW + k] + d->col_noise_w * zv[k];"),
+    ("downwash_noise_one_axis", "§III-B.4", "d->dw_noise_a * za[k]", "d->dw_noise_a * za[0]"),
+    ("downwash_rate_noise_from_acceleration_draws", "§III-B.4",
+     "si[IW + k] += d->dt * d->dw_noise_w * zw[k];", "si[IW + k] += d->dt * d->dw_noise_w * za[k];"),
+    ("substep_index_not_advanced", "§III-A.2 noise per substep",
+     "    const uint64_t t = t0 + (uint64_t)sub;\n    if (contacts)",
+     "    const uint64_t t = t0;\n    if (contacts)"),
+    ("penalty_on_one_quad", "§III-E penalty",
+     "        pen[q0 + i] += h;\n        pen[q0 + j] += h;", "        pen[q0 + i] += h + h;"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS

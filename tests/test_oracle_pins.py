@@ -711,6 +711,60 @@ def test_downwash_sums_over_upper_quads_and_spares_resting_quads():
     assert np.array_equal(on, off)
 
 
+def _event_noise_case(model, n):
+    """n independent environments that all take the same event in their first
+    substep: a wall bounce, a head-on pair response, or downwash on the lower
+    quad of a stacked pair.  Returns (flags, sizes, state, the quads that take
+    the event, noise constants, noise-free constants)."""
+    if model == "wall":
+        s = blank_state(n, z=5.0)
+        s[:, 0] = 4.999
+        s[:, W.SV:W.SV + 3] = [3.0, 0.5, 0.2]
+        hit = np.arange(n)
+        return W.QS_ROOM, [1] * n, s, hit, dict(col_noise_v=0.3, col_noise_w=0.7), {}
+    s = blank_state(2 * n, z=5.0)
+    s[:, 0] = np.repeat(np.arange(n) * 1.0, 2)          # environments 1 m apart
+    if model == "pair":
+        s[1::2, 0] += 0.08
+        s[0::2, W.SV:W.SV + 3] = [1.0, 0.3, -0.2]
+        s[1::2, W.SV:W.SV + 3] = [-0.5, 0.3, -0.2]
+        flags = W.QS_COLLIDE | W.QS_APPROACH_ONLY
+        return flags, [2] * n, s, np.arange(2 * n), dict(col_noise_v=0.3, col_noise_w=0.7), {}
+    s[1::2, 2] += 0.3                                   # the upper quad of each pair
+    return W.QS_DOWNWASH, [2] * n, s, np.arange(0, 2 * n, 2), dict(dw_noise_a=3.0, dw_noise_w=5.0), {}
+
+
+@pytest.mark.parametrize("model", ["wall", "pair", "downwash"])
+def test_event_noise_is_independent_per_axis(model):
+    """The noise terms of a wall bounce and a pair response (§III-B.1-2:
+    alpha (v + eps_v), omega + eps_omega) and of downwash (§III-B.4:
+    dt (a + eps_d), dt eps_omega_d) are one independent N(0, sigma^2) draw per
+    axis and per term.  The kick is the difference between a run with the
+    noise scales set and one without (the deterministic parts cancel); over
+    4096 events its components must have mean 0, standard deviation
+    (alpha or dt) sigma, and no correlation between axes or between the
+    velocity and body-rate kicks."""
+    n = 4096
+    flags, sizes, s, hit, noisy, quiet = _event_noise_case(model, n)
+    q = len(s)
+    a = -np.ones((q, 4))
+    out1, _, ev = make(q, flags=flags, env_sizes=sizes, gravity=0.0, seed=21, **noisy).step(s, a, 1, 0)
+    out0, _, _ = make(q, flags=flags, env_sizes=sizes, gravity=0.0, seed=21, **quiet).step(s, a, 1, 0)
+    kv = (out1 - out0)[hit, W.SV:W.SV + 3]
+    kw = (out1 - out0)[hit, W.SW:W.SW + 3]
+    if model == "downwash":
+        sv, sw = DT * noisy["dw_noise_a"], DT * noisy["dw_noise_w"]
+    else:
+        sv, sw = noisy["col_noise_v"], noisy["col_noise_w"]   # decay alpha = 1
+    m = len(hit)
+    for k, sd in ((kv, sv), (kw, sw)):
+        assert np.all(np.abs(k.mean(axis=0)) < 5 * sd / math.sqrt(m))
+        np.testing.assert_allclose(k.std(axis=0), sd, rtol=0.06)
+    c = np.corrcoef(np.hstack([kv, kw]).T)
+    off = c[~np.eye(6, dtype=bool)]
+    assert np.all(np.abs(off) < 0.08), c
+
+
 def test_rejects_bad_arguments():
     with pytest.raises(ValueError):
         O.Oracle(np.array([0, 65], dtype=np.int32), consts(), nominal_params(65), 0, 0, 0).step(
