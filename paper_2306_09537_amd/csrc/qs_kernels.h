@@ -155,8 +155,9 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
     }
   }
   // the call's action, loaded by every lane without a branch (an idle lane's
-  // q is its workgroup's first quad, and a call without substeps reads a row
-  // of the state instead), so no merge of its value has to wait for it
+  // q is still a valid quad: its workgroup's first, or quad 0 in the bucketed
+  // launch; a call without substeps reads a row of the state instead), so no
+  // merge of its value has to wait for it
   if constexpr (ROLE != 1)
     a4 = reinterpret_cast<const float4*>(nsub > 0 ? act : p.st)[q];
   // §III-A.2 motor noise: the draws depend on the quad, the substep index and
