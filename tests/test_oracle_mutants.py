@@ -280,6 +280,23 @@ MUTANTS = [
      "    const uint64_t t = t0;\n    if (contacts)"),
     ("penalty_on_one_quad", "§III-E penalty",
      "        pen[q0 + i] += h;\n        pen[q0 + j] += h;", "        pen[q0 + i] += h + h;"),
+    ("pair_noise_local_index", "§III-B.1 (noise keyed by global quad index)",
+     "or_normal4(d->seed, d->quad_id_offset + (uint32_t)(q0 + i), t, STREAM_PAIR, 0, zv);",
+     "or_normal4(d->seed, (uint32_t)(q0 + i), t, STREAM_PAIR, 0, zv);"),
+    ("downwash_noise_local_index", "§III-B.4 (noise keyed by global quad index)",
+     "or_normal4(d->seed, d->quad_id_offset + (uint32_t)(q0 + i), t, STREAM_DOWNWASH, 0, za);",
+     "or_normal4(d->seed, (uint32_t)(q0 + i), t, STREAM_DOWNWASH, 0, za);"),
+    ("sensor_noise_local_index", "§III-C (noise keyed by global quad index)",
+     "const uint32_t gq = d->quad_id_offset + (uint32_t)q;", "const uint32_t gq = (uint32_t)q;"),
+    ("rollout_first_action_only", "rollout",
+     "actions + ((size_t)c * Q + q) * 4, d->quad_id_offset + (uint32_t)q, t,\n"
+     "                       &ev[q], &mg[q], NULL);",
+     "actions + ((size_t)0 * Q + q) * 4, d->quad_id_offset + (uint32_t)q, t,\n"
+     "                       &ev[q], &mg[q], NULL);"),
+    ("vjp_rerun_wrong_substep", "reverse mode",
+     "t0 + kk, &ev[q], &mg[q], &rec[q]);", "t0 + kk + 1, &ev[q], &mg[q], &rec[q]);"),
+    ("vjp_command_gradient_not_reset", "reverse mode, §III-A.1",
+     "          gu[(size_t)q * 4 + i] = 0.0;", "          (void)0;"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS

@@ -774,20 +774,40 @@ def test_rejects_bad_arguments():
             np.zeros((0, 27)), np.zeros((0, 4)))
 
 
-def test_env_range_oracle_matches_full_run():
+@pytest.mark.parametrize("noisy", [False, True])
+def test_env_range_oracle_matches_full_run(noisy):
     """An oracle over a slice of environments reproduces the full run there
-    (noise keyed by global quad index)."""
-    w = W.swarm8(seed=4, n_envs=12)
+    (noise keyed by global quad index).  The noisy case packs each swarm
+    within +-0.15 m so that pairs respond, and turns on the pair, wall and
+    downwash noise and the sensor noise of the observation."""
+    if noisy:
+        w = W.custom([8] * 12, seed=4, k=6,
+                     flags=W.SWARM_FLAGS | W.QS_DOWNWASH | W.QS_SENSOR_NOISE, name="slice",
+                     col_noise_v=0.1, col_noise_w=0.2, dw_noise_a=1.0, dw_noise_w=1.0)
+        st = w.state0.astype(np.float64).copy()
+        rng = np.random.default_rng(4)
+        for e in range(12):
+            st[8 * e:8 * e + 8, 0:3] = st[8 * e, 0:3] + rng.uniform(-0.15, 0.15, size=(8, 3))
+        w = w.with_(state0=st)
+    else:
+        w = W.swarm8(seed=4, n_envs=12)
     full = O.Oracle.from_workload(w)
     part = O.Oracle.from_workload(w, 5, 9)
     q0, q1 = int(w.env_offsets[5]), int(w.env_offsets[9])
     s = w.state0.astype(np.float64)
     sp = s[q0:q1]
+    events = 0
     for t in range(20):
         a = w.actions(t)
-        s, c, _ = full.step(s, a, 1, t)
+        s, c, ev = full.step(s, a, 1, t)
         sp, cp, _ = part.step(sp, a[q0:q1], 1, t)
+        events |= int(np.bitwise_or.reduce(ev[q0:q1]))
     assert np.array_equal(s[q0:q1], sp) and np.array_equal(c[q0:q1], cp)
+    if noisy:
+        assert events & O.EV_PAIR_RESPONSE
+        o, _ = full.observe(s, w.goals.astype(np.float64))
+        op, _ = part.observe(sp, w.goals[q0:q1].astype(np.float64))
+        np.testing.assert_array_equal(full.observe_noise(o, 20)[q0:q1], part.observe_noise(op, 20))
 
 
 
