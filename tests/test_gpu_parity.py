@@ -211,6 +211,30 @@ def test_collision_and_wall_noise_streams():
     assert st["max_err"] <= U.TOL
 
 
+def test_wall_restitution_decay_and_drag():
+    """Walls and ceiling with restitution 0.6, collision decay 0.85 and drag
+    0.01: swarms placed in the room's top corners flying outward and up,
+    teacher-forced against the oracle (which bounces them off walls and the
+    ceiling in the same calls)."""
+    w = W.swarm8(seed=15, n_envs=64)
+    rng = np.random.default_rng(15)
+    side = rng.choice([-1.0, 1.0], size=(64, 2))
+    centres = np.column_stack([side * 4.8, rng.uniform(9.5, 9.8, 64)])
+    s0 = w.state0.copy()
+    s0[:, 0:3] = np.repeat(centres, 8, axis=0) + rng.uniform(-0.15, 0.15, size=(512, 3))
+    s0[:, W.SV:W.SV + 3] = np.repeat(np.column_stack([side * 2.0, np.full(64, 2.0)]), 8, axis=0)
+    c = dict(w.consts, wall_restitution=0.6, col_decay=0.85, drag_coef=0.01)
+    w = w.with_(consts=c, state0=s0.astype(np.float32))
+    orc = O.Oracle.from_workload(w)
+    s, bits = w.state0.astype(np.float64), 0
+    for call in range(20):
+        s, _, ev = orc.step(s, w.actions(call), 1, call)
+        bits |= int(np.bitwise_or.reduce(ev))
+    assert bits & O.EV_WALL and bits & O.EV_CEILING
+    st = teacher_forced(w, 60)
+    assert st["max_err"] <= U.TOL
+
+
 # ------------------------------------------------------- equivalences
 def test_fused_equals_separate_calls_bitwise():
     w = W.swarm8(seed=9, n_envs=128)
@@ -353,12 +377,13 @@ def test_gpu_momentum_conserved_in_pile_up():
     assert not np.allclose(out[:, W.SV:W.SV + 3], s[:, W.SV:W.SV + 3])
 
 
-def test_gpu_floor_hit_and_rest():
+@pytest.mark.parametrize("flags", [W.QS_FLOOR, W.QS_FLOOR | W.QS_ROOM])
+def test_gpu_floor_hit_and_rest(flags):
     s = blank_state(1, z=0.002)
     s[0, W.SR:W.SR + 9] = (rot_z(1.1) @ rot_x(0.5)).reshape(9)
     s[0, W.SV:W.SV + 3] = [0.5, 0.2, -1.0]
     s[0, W.SU:W.SU + 4] = 0.0
-    sim = _custom_sim(s, flags=W.QS_FLOOR)
+    sim = _custom_sim(s, flags=flags)
     sim.step(dev(-np.ones((1, 4))), 1)
     hit = sim.get_state()[0].cpu().numpy()[0].astype(np.float64)
     for _ in range(50):
