@@ -5,7 +5,8 @@ sampled environments the oracle can follow one by one:
   launch, one 10-substep call captured as a graph and replayed;
 - 32768 x 32 (1,048,576 quads): one-substep and 10-substep launches, and
   the differentiable rollout (100 substeps, checkpoint every 20 calls);
-- 1,048,576 x 1: one-substep and 10-substep launches.
+- 1,048,576 x 1: one-substep and 10-substep launches;
+- 2^26 single-quad swarms, the library's quad limit: one launch.
 
 Teacher-forced as in the other parity tests (the oracle restarts from the
 GPU's float32 state of the sampled environments after every call); bounds
@@ -144,6 +145,25 @@ def test_scale1_full_size_sampled(nsub, calls):
                                    U.TOL * nsub)
     print("scale1 full size", nsub, "worst", worst)
     assert worst <= U.TOL * nsub
+
+
+def test_maximum_size_sampled():
+    """The largest handle the library takes: 2^26 single-quad swarms (its
+    quad limit), 64 tiles of the 1,048,576 x 1 workload's parameters and
+    states (each tile draws its own noise: the noise is keyed by the global
+    quad index).  One step + observation, sampled at the start, the middle
+    and the end of the quad range."""
+    base = W.scale1(seed=5)
+    reps = 64
+    q = base.n_quads * reps
+    assert q == 1 << 26
+    w = base.with_(env_sizes=np.ones(q, np.int32), env_offsets=np.arange(q + 1, dtype=np.int32),
+                   params=np.tile(base.params, (reps, 1)), state0=np.tile(base.state0, (reps, 1)),
+                   goals=np.tile(base.goals, (reps, 1)))
+    worst = sampled_teacher_forced(w, 1, 1, [(0, 2048), (q // 2 - 1024, q // 2 + 1024),
+                                             (q - 2048, q)], U.TOL)
+    print("maximum size worst", worst)
+    assert worst <= U.TOL
 
 
 def test_scale32_fwd_bwd_full_size_sampled():
