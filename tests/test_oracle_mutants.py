@@ -297,6 +297,22 @@ MUTANTS = [
      "t0 + kk, &ev[q], &mg[q], &rec[q]);", "t0 + kk + 1, &ev[q], &mg[q], &rec[q]);"),
     ("vjp_command_gradient_not_reset", "reverse mode, §III-A.1",
      "          gu[(size_t)q * 4 + i] = 0.0;", "          (void)0;"),
+    ("contacts_accumulate_over_substeps", "§III-B.1 (contact mask of the last substep)",
+     "    if (contacts) memset(contacts, 0, (size_t)Q * sizeof(uint64_t));\n#pragma omp",
+     "\n#pragma omp"),
+    ("observe_rate_field", "§III-C",
+     "for (int k = 0; k < 3; ++k) o[15 + k] = si[IW + k];",
+     "for (int k = 0; k < 3; ++k) o[15 + k] = si[IV + k];"),
+    ("reward_speed_from_rate", "§III-E", "w[1] * sqrt(v2)", "w[1] * sqrt(w2)"),
+    ("reward_previous_thrust_from_after", "§III-E",
+     "const double f0 = f_max * a[IU + i] * a[IU + i] + a[IE + i];",
+     "const double f0 = f_max * b[IU + i] * b[IU + i] + b[IE + i];"),
+    ("downwash_rest_check_on_upper_quad", "§III-B.4",
+     "      if (si[IF] != 0.0) continue; /* resting on the floor */\n"
+     "      for (int j = 0; j < n; ++j) {\n        if (j == i) continue;\n"
+     "        const double* sj = S + (size_t)(q0 + j) * NS;",
+     "      for (int j = 0; j < n; ++j) {\n        if (j == i) continue;\n"
+     "        const double* sj = S + (size_t)(q0 + j) * NS;\n        if (sj[IF] != 0.0) continue;"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS

@@ -509,6 +509,28 @@ def test_pair_response_decays_the_responding_quads():
     np.testing.assert_array_equal(out[2, W.SV:W.SV + 3], [0.1, 0.2, 0.3])
 
 
+def test_contact_mask_is_the_last_substeps():
+    """The contact mask a call returns is that of its last substep, while its
+    event bits are the OR over the call: a pair 8.5 cm apart separating at
+    2 m/s is in contact after the first substep (9.5 cm) and not after the
+    second (10.5 cm)."""
+    s = blank_state(2, z=5.0)
+    s[0, 0:3] = [0.0, 0.0, 5.0]
+    s[1, 0:3] = [0.085, 0.0, 5.0]
+    s[0, W.SV] = -1.0
+    s[1, W.SV] = 1.0
+    s[:, W.SU:W.SU + 4] = 0.0
+    orc = make(2, flags=W.QS_COLLIDE | W.QS_APPROACH_ONLY, env_sizes=[2], gravity=0.0)
+    a = -np.ones((2, 4))
+    _, c1, _ = orc.step(s, a, 1, 0)
+    assert c1[0] == 2 and c1[1] == 1
+    out, c2, ev = orc.step(s, a, 2, 0)
+    assert c2[0] == 0 and c2[1] == 0
+    assert ev[0] & O.EV_CONTACT and ev[1] & O.EV_CONTACT
+    assert not ev[0] & O.EV_PAIR_RESPONSE            # separating: no response
+    np.testing.assert_array_equal(out[:, W.SV], [-1.0, 1.0])
+
+
 def test_separating_pair_is_left_alone():
     s = blank_state(2, z=5.0)
     s[1, 0] = 0.05
