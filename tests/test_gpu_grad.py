@@ -308,3 +308,35 @@ def test_adjoint_through_floor_and_walls_matches_oracle(c):
     print("floor/wall adjoint rel err (state0, actions, params):", errs, "bounds:", tol)
     for e, b in zip(errs, tol):
         assert e <= b
+
+
+def test_adjoint_through_floor_hits_matches_oracle():
+    """64 tilted, yawed quads land in the first substep (the attitude levelled
+    keeping the heading) and then rest under low thrust: the floor-hit branch
+    of the adjoint on the GPU against the oracle's."""
+    from tests.helpers import rot_x, rot_z
+    n = 64
+    w = W.custom([1] * n, seed=32, k=0, flags=W.QS_FLOOR | W.QS_MOTOR_NOISE, name="land")
+    rng = np.random.default_rng(32)
+    s0 = w.state0.astype(np.float64).copy()
+    s0[:, 0:2] = rng.uniform(-3, 3, size=(n, 2))
+    s0[:, 2] = rng.uniform(0.001, 0.004, n)
+    s0[:, W.SV:W.SV + 3] = np.column_stack([rng.uniform(-0.3, 0.3, (n, 2)), np.full(n, -1.0)])
+    for q in range(n):
+        s0[q, W.SR:W.SR + 9] = (rot_z(rng.uniform(-3, 3)) @ rot_x(rng.uniform(0.1, 0.5))).reshape(9)
+    s0[:, W.SW:W.SW + 3] = rng.normal(0, 0.4, size=(n, 3))
+    s0[:, W.SF] = 0.0
+    w = w.with_(state0=s0.astype(np.float32))
+    T = 4
+    acts = np.full((T, n, 4), -0.9, np.float32)
+    Wt = rng.normal(size=(n, 27)).astype(np.float32)
+    Wt[:, 26] = 0
+    gpen = np.zeros(n, np.float32)
+    g_ref = oracle_grads(w, acts, 1, Wt, gpen)
+    tol = bound(w, acts, 1, Wt, gpen, g_ref, 32)
+    gs, gact, gpar, sT, *_ = gpu_grads(w, acts, 1, Wt, gpen, 2)
+    assert np.all(sT[:, W.SF] == 1.0)
+    errs = [relerr(gs, g_ref[0]), relerr(gact, g_ref[1]), relerr(gpar, g_ref[2])]
+    print("floor-hit adjoint rel err (state0, actions, params):", errs, "bounds:", tol)
+    for e, b in zip(errs, tol):
+        assert e <= b

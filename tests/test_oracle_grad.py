@@ -162,6 +162,43 @@ def test_floor_and_wall_branches(c):
             assert gpar[q, k] == pytest.approx(fd(f, P[q, k], h), rel=5e-5, abs=1e-6)
 
 
+def test_floor_hit_gradient_through_the_levelled_heading():
+    """Tilted, yawed quads land in the first substep: the attitude is levelled
+    keeping the heading (R = [h, e_z x h, e_z], h the normalised (R00, R10)
+    after the substep's rotation update), so the final attitude depends on
+    the initial one only through that heading.  The adjoint of the levelling
+    (the normalisation's projection included) against central differences."""
+    from tests.helpers import rot_x, rot_z
+    w = W.custom([1, 1], seed=31, k=0, flags=W.QS_FLOOR, name="land")
+    s0 = w.state0.astype(np.float64).copy()
+    for q, (psi, tilt) in enumerate([(0.7, 0.4), (-2.0, 0.25)]):
+        s0[q, 0:3] = [0.0, 0.0, 0.004]
+        s0[q, W.SV:W.SV + 3] = [0.2, -0.1, -1.0]
+        s0[q, W.SR:W.SR + 9] = (rot_z(psi) @ rot_x(tilt)).reshape(9)
+        s0[q, W.SW:W.SW + 3] = [0.3, -0.2, 0.5]
+        s0[q, W.SF] = 0.0
+    orc = O.Oracle.from_workload(w)
+    acts = np.full((2, 2, 4), -1.0)
+    rng = np.random.default_rng(31)
+    Wt = rng.normal(size=(2, 27))
+    Wt[:, 26] = 0.0
+    gpen = np.zeros(2)
+    sT, _ = orc.rollout(s0, acts, 1, 0, beta=BETA)
+    assert np.all(sT[:, W.SF] == 1.0)
+    gs0, _, _ = orc.rollout_vjp(s0, acts, 1, 0, Wt, gpen, BETA)
+    biggest = 0.0
+    for q in range(2):
+        for k in (W.SR + 0, W.SR + 1, W.SR + 3, W.SR + 4, W.SW + 0, W.SW + 2):
+            def f(v):
+                s = s0.copy()
+                s[q, k] = v
+                return loss(orc, s, acts, 1, Wt, gpen)
+            g = fd(f, s0[q, k], 1e-7)
+            biggest = max(biggest, abs(g))
+            assert gs0[q, k] == pytest.approx(g, rel=1e-5, abs=1e-7), (q, k)
+    assert biggest > 0.1          # the heading carries real sensitivity
+
+
 @pytest.mark.slow
 def test_200_step_horizon_action_gradient():
     """The differentiation workload's horizon: 200 substeps, 4 envs x 8 quads."""

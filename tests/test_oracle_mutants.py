@@ -313,6 +313,13 @@ MUTANTS = [
      "        const double* sj = S + (size_t)(q0 + j) * NS;",
      "      for (int j = 0; j < n; ++j) {\n        if (j == i) continue;\n"
      "        const double* sj = S + (size_t)(q0 + j) * NS;\n        if (sj[IF] != 0.0) continue;"),
+    ("vjp_floor_hit_heading_sign", "reverse mode, §III-B.3",
+     "      double gh[2] = {lR[0] + lR[4], lR[3] - lR[1]};",
+     "      double gh[2] = {lR[0] + lR[4], lR[1] - lR[3]};"),
+    ("vjp_floor_hit_projection_dropped", "reverse mode, §III-B.3",
+     "      gr[0] = (gh[0] - dd * h[0]) / r->nh;", "      gr[0] = gh[0] / r->nh;"),
+    ("vjp_floor_hit_height_kept", "reverse mode, §III-B.3",
+     "  if (r->hit) {\n    lx[2] = 0.0;", "  if (r->hit) {\n    (void)0;"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS
