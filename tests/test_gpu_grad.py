@@ -340,3 +340,40 @@ def test_adjoint_through_floor_hits_matches_oracle():
     print("floor-hit adjoint rel err (state0, actions, params):", errs, "bounds:", tol)
     for e, b in zip(errs, tol):
         assert e <= b
+
+
+def test_adjoint_through_static_friction_breakaway_matches_oracle():
+    """64 resting quads tilted 20-35 degrees about body y (random heading),
+    horizontal thrust above mu N: the first substep takes the static branch
+    of the floor friction, the later ones the kinetic branch.  GPU gradients
+    against the oracle's."""
+    import math
+    from tests.helpers import rot_y, rot_z
+    n = 64
+    w = W.custom([1] * n, seed=34, k=0, flags=W.QS_FLOOR, randomise=False, name="slide")
+    rng = np.random.default_rng(34)
+    s0 = w.state0.astype(np.float64).copy()
+    s0[:, 0:2] = rng.uniform(-3, 3, size=(n, 2))
+    s0[:, 2] = 0.0
+    s0[:, W.SV:W.SV + 3] = 0.0
+    s0[:, W.SF] = 1.0
+    for q in range(n):
+        R = rot_z(rng.uniform(-3, 3)) @ rot_y(math.radians(rng.uniform(20, 35)))
+        s0[q, W.SR:W.SR + 9] = R.reshape(9)
+    s0[:, W.SW:W.SW + 3] = 0.0
+    s0[:, W.SU:W.SU + 4] = math.sqrt(0.45)
+    s0[:, W.SE:W.SE + 4] = 0.0
+    w = w.with_(state0=s0.astype(np.float32))
+    T = 4
+    acts = np.full((T, n, 4), -0.1, np.float32)
+    Wt = rng.normal(size=(n, 27)).astype(np.float32)
+    Wt[:, 26] = 0
+    gpen = np.zeros(n, np.float32)
+    g_ref = oracle_grads(w, acts, 1, Wt, gpen)
+    tol = bound(w, acts, 1, Wt, gpen, g_ref, 34)
+    gs, gact, gpar, sT, *_ = gpu_grads(w, acts, 1, Wt, gpen, 2)
+    assert np.all(sT[:, W.SF] == 1.0) and np.all(np.hypot(sT[:, W.SV], sT[:, W.SV + 1]) > 0)
+    errs = [relerr(gs, g_ref[0]), relerr(gact, g_ref[1]), relerr(gpar, g_ref[2])]
+    print("static-friction adjoint rel err (state0, actions, params):", errs, "bounds:", tol)
+    for e, b in zip(errs, tol):
+        assert e <= b

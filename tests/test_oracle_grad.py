@@ -199,6 +199,57 @@ def test_floor_hit_gradient_through_the_levelled_heading():
     assert biggest > 0.1          # the heading carries real sensitivity
 
 
+def test_static_friction_breakaway_gradient():
+    """Resting quads tilted about body y, horizontal thrust above mu N, start
+    to slide from rest: their first substep takes the static branch (force
+    |F_xy| - mu N along F_xy), the later ones the kinetic branch.  Gradients
+    with respect to the attitude's third column, the rotor speed, an action
+    and the parameters against central differences."""
+    import math
+    from tests.helpers import rot_y, rot_z
+    w = W.custom([1, 1], seed=33, k=0, flags=W.QS_FLOOR, randomise=False, name="slide")
+    s0 = w.state0.astype(np.float64).copy()
+    for q, (theta, psi) in enumerate([(30.0, 0.3), (25.0, -1.1)]):
+        s0[q, 0:3] = [0.5 * q, 0.0, 0.0]
+        s0[q, W.SV:W.SV + 3] = 0.0
+        s0[q, W.SF] = 1.0
+        s0[q, W.SR:W.SR + 9] = (rot_z(psi) @ rot_y(math.radians(theta))).reshape(9)
+        s0[q, W.SW:W.SW + 3] = 0.0
+        s0[q, W.SU:W.SU + 4] = math.sqrt(0.45)
+        s0[q, W.SE:W.SE + 4] = 0.0
+    orc = O.Oracle.from_workload(w)
+    acts = np.full((3, 2, 4), -0.1)                 # normalised thrust 0.45
+    rng = np.random.default_rng(33)
+    Wt = rng.normal(size=(2, 27))
+    Wt[:, 26] = 0.0
+    gpen = np.zeros(2)
+    sT, _ = orc.rollout(s0, acts, 1, 0, beta=BETA)
+    assert np.all(sT[:, W.SF] == 1.0) and np.all(np.abs(sT[:, W.SV]) + np.abs(sT[:, W.SV + 1]) > 0)
+    gs0, gact, gpar = orc.rollout_vjp(s0, acts, 1, 0, Wt, gpen, BETA)
+    for q in range(2):
+        for k in (W.SR + 2, W.SR + 5, W.SR + 8, W.SU + 0):
+            def f(v):
+                s = s0.copy()
+                s[q, k] = v
+                return loss(orc, s, acts, 1, Wt, gpen)
+            assert gs0[q, k] == pytest.approx(fd(f, s0[q, k], 1e-7), rel=1e-5, abs=1e-8), (q, k)
+
+        def fa(v):
+            a = acts.copy()
+            a[0, q, 1] = v
+            return loss(orc, s0, a, 1, Wt, gpen)
+        assert gact[0, q, 1] == pytest.approx(fd(fa, acts[0, q, 1], 1e-7), rel=1e-5, abs=1e-8)
+        for k in (0, 4):
+            P = orc.params
+            h = 1e-6 * P[q, k]
+
+            def fp(v):
+                p2 = P.copy()
+                p2[q, k] = v
+                return loss(orc.with_params(p2), s0, acts, 1, Wt, gpen)
+            assert gpar[q, k] == pytest.approx(fd(fp, P[q, k], h), rel=1e-5, abs=1e-8), (q, k)
+
+
 @pytest.mark.slow
 def test_200_step_horizon_action_gradient():
     """The differentiation workload's horizon: 200 substeps, 4 envs x 8 quads."""

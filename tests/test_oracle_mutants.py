@@ -320,6 +320,13 @@ MUTANTS = [
      "      gr[0] = (gh[0] - dd * h[0]) / r->nh;", "      gr[0] = gh[0] / r->nh;"),
     ("vjp_floor_hit_height_kept", "reverse mode, §III-B.3",
      "  if (r->hit) {\n    lx[2] = 0.0;", "  if (r->hit) {\n    (void)0;"),
+    ("vjp_static_friction_projection_dropped", "reverse mode, §III-B.3",
+     "for (int k = 0; k < 2; ++k) lF[k] += lfb[k] - r->mu_n * (lfb[k] - dd * Fh[k]) / r->nf;",
+     "for (int k = 0; k < 2; ++k) lF[k] += lfb[k] - r->mu_n * lfb[k] / r->nf;"),
+    ("vjp_static_friction_normal_force_sign", "reverse mode, §III-B.3",
+     "          lmu = -dd;", "          lmu = dd;"),
+    ("vjp_kinetic_friction_normal_force_sign", "reverse mode, §III-B.3",
+     "        lmu = -(lfb[0] * vh[0] + lfb[1] * vh[1]);", "        lmu = (lfb[0] * vh[0] + lfb[1] * vh[1]);"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS
