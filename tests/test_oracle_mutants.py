@@ -327,6 +327,16 @@ MUTANTS = [
      "          lmu = -dd;", "          lmu = dd;"),
     ("vjp_kinetic_friction_normal_force_sign", "reverse mode, §III-B.3",
      "        lmu = -(lfb[0] * vh[0] + lfb[1] * vh[1]);", "        lmu = (lfb[0] * vh[0] + lfb[1] * vh[1]);"),
+    ("vjp_wall_clamp_position_kept", "reverse mode, §III-B.2",
+     "if (r->clamp[k]) lx[k] = 0.0;", "if (r->clamp[k]) (void)0;"),
+    ("vjp_friction_stop_ignored", "reverse mode, §III-B.3", "    if (!r->guard) {", "    if (1) {"),
+    ("vjp_rest_drag_dropped", "reverse mode, §III-B.3",
+     "lv0[k] = lv1[k] * (1.0 - dt * d->drag_coef / m);", "lv0[k] = lv1[k];"),
+    ("vjp_response_decay_dropped", "reverse mode, §III-B.1",
+     "ldv[i][k] = marked[i] ? d->col_decay * li[IV + k] : 0.0;",
+     "ldv[i][k] = marked[i] ? li[IV + k] : 0.0;"),
+    ("vjp_contact_normal_term_dropped", "reverse mode, §III-B.1",
+     "gn[k] = sp * mu[k] + mn * wv[k];", "gn[k] = sp * mu[k];"),
 ]
 
 CASES = [("unmodified", "", "", "")] + MUTANTS
