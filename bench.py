@@ -244,6 +244,8 @@ def time_fwd_bwd(w, torch, horizon: int, nsub: int, ckpt_every: int, reps: int, 
                 bwd_roofline={"bound": "hbm", "achieved": bwd_bytes / (b * 1e-3) / 1e9,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": bwd_bytes / (b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "traffic": fwdbwd_counter(w.name, horizon,
+                                                        "backward_traffic_bytes"),
                               "bytes": bwd_bytes, "segment_substeps": seg},
                 fwd_alu=fwdbwd_alu(w.name, horizon, "rollout_", f),
                 bwd_alu=fwdbwd_alu(w.name, horizon, "backward_", b))
@@ -258,6 +260,17 @@ def fwdbwd_alu(name: str, horizon: int, part: str, ms: float):
     if measured_counter(prof, pre + "fwdbwd_horizon") != horizon:
         return None
     return alu_roofline(prof, pre + part, ms)
+
+
+def fwdbwd_counter(name: str, horizon: int, key: str):
+    """A committed counter value of the fwd+bwd leg (e.g. the backward pass's
+    HBM bytes), only at the horizon it was taken at."""
+    if name not in FWDBWD_PROFILES:
+        return None
+    prof, pre = FWDBWD_PROFILES[name]
+    if measured_counter(prof, pre + "fwdbwd_horizon") != horizon:
+        return None
+    return measured_counter(prof, pre + key)
 
 
 def sticky_nonfinite(sim, torch) -> int:

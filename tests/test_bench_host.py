@@ -89,3 +89,14 @@ def test_more_than_one_gpu_is_refused():
     assert p.returncode == 2
     assert "one GPU" in p.stderr
     assert p.stdout == ""
+
+
+def test_fwdbwd_counter_needs_matching_horizon(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abcdef0123456789")
+    write_profile(tmp_path, monkeypatch, "`abcdef0123456789`\n"
+                  "fwdbwd_horizon: 200\n"
+                  "backward_traffic_bytes: 496901258\n")
+    monkeypatch.setattr(bench, "FWDBWD_PROFILES", {"w": ("p.md", "")})
+    assert bench.fwdbwd_counter("w", 200, "backward_traffic_bytes") == 496901258
+    assert bench.fwdbwd_counter("w", 100, "backward_traffic_bytes") is None
+    assert bench.fwdbwd_counter("other", 200, "backward_traffic_bytes") is None
