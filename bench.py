@@ -89,6 +89,20 @@ def measured_traffic(profile: str):
     return measured_counter(profile, "traffic_bytes_per_launch")
 
 
+# committed counter summaries of the one-substep launch, per workload
+TRAFFIC_PROFILES = {"swarm8": ("step_kernel_swarm4096x8_plain.md", "traffic_bytes_per_launch"),
+                    "scale32": ("scale_workloads.md", "scale32_traffic_bytes_per_launch"),
+                    "scale1": ("scale_workloads.md", "scale1_traffic_bytes_per_launch")}
+
+
+def launch_traffic(workload: str, nsub: int):
+    """Counter-measured HBM bytes of the timed launch, where committed (one
+    substep per call) and taken on the current kernel sources."""
+    if nsub != 1 or workload not in TRAFFIC_PROFILES:
+        return None
+    return measured_counter(*TRAFFIC_PROFILES[workload])
+
+
 def alu_roofline(prof: str, key: str, ms: float):
     """ALU roofline of a kernel (or kernel sequence) from the committed
     counters under ``key``: VALU busy SIMD-cycles per second (lower bound)
@@ -473,8 +487,7 @@ def main():
         if rl is not None:
             extra[f"fused_nsub{ns}"]["roofline"] = rl
 
-    traffic = (measured_traffic("step_kernel_swarm4096x8_plain.md")
-               if (args.workload, args.nsub) == ("swarm8", 1) else None)
+    traffic = launch_traffic(args.workload, args.nsub)
     line = {
         "metric": "quad-steps/s fwd at 1 MI355X (% of HBM roofline)",
         "value": value,

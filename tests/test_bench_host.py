@@ -100,3 +100,13 @@ def test_fwdbwd_counter_needs_matching_horizon(tmp_path, monkeypatch):
     assert bench.fwdbwd_counter("w", 200, "backward_traffic_bytes") == 496901258
     assert bench.fwdbwd_counter("w", 100, "backward_traffic_bytes") is None
     assert bench.fwdbwd_counter("other", 200, "backward_traffic_bytes") is None
+
+
+def test_launch_traffic_per_workload():
+    # the committed summaries carry the counter bytes of every timed
+    # one-substep workload, on the current kernel sources
+    for wl in ("swarm8", "scale32", "scale1"):
+        t = bench.launch_traffic(wl, 1)
+        assert t is None or t > 0
+    assert bench.launch_traffic("swarm8", 10) is None
+    assert bench.launch_traffic("uneven", 1) is None
