@@ -18,9 +18,9 @@
  *    returns without waiting, except where noted.  A handle is not
  *    thread-safe; calls on one handle must be ordered by the caller.
  *  - Argument errors are detected on the host before anything is enqueued.
- *    Device-side errors (a non-finite value produced in the state, or a
- *    non-finite action) are sticky in the handle and are returned by the
- *    next qs_sync().
+ *    Device-side errors (a non-finite value produced in the state, a
+ *    non-finite action, or a rejected qs_set_params row) are sticky in the
+ *    handle and are returned by the next qs_sync().
  *  - All device arithmetic is IEEE float32.
  *  - Device pointers: d_actions 16-byte aligned, d_obs and d_mask 8-byte
  *    aligned, others 4-byte aligned (QS_ERR_ALIGN otherwise).
@@ -161,13 +161,16 @@ typedef struct {
 int qs_create(const qs_desc* desc, const qs_quad_params* h_params,
               const float* h_state0, qs_handle** out);
 
-/* Free the handle and its device memory (synchronises the device). NULL is OK. */
+/* Free the handle and its device memory (synchronises the device). NULL is OK.
+ * Infrastructure: no passage of the paper; it releases what qs_create took. */
 int qs_destroy(qs_handle* h);
 
-/* Sizes of a handle: number of quads, of environments, and the obs row length. */
+/* Sizes of a handle: number of quads, of environments, and the §III-C
+ * observation row length 18 + 6K.  Infrastructure. */
 int qs_sizes(const qs_handle* h, int32_t* n_quads, int32_t* n_envs, int32_t* obs_dim);
 
-/* Substep counter: number of substeps enqueued so far (keys the noise). */
+/* Substep counter: number of substeps enqueued so far (keys the noise).
+ * Infrastructure. */
 int qs_substep_index(const qs_handle* h, uint64_t* substep_index);
 
 /*
@@ -222,20 +225,38 @@ int qs_step_observe_reward(qs_handle* h, const float* d_actions, int32_t n_subst
 /*
  * Copy the state into d_state [Q][27] (canonical layout) and return the
  * substep counter (number of substeps enqueued so far; host value).
- * substep_index may be NULL.
+ * substep_index may be NULL.  The state is §III-A's rigid body (x, v, R,
+ * omega) with the rotor state of §III-A.1/§III-A.2 (u_f, eps) and the
+ * resting flag of §III-B.3; the layout is the library's own.
  */
 int qs_get_state(qs_handle* h, float* d_state, uint64_t* substep_index, void* stream);
 
 /*
  * Load d_state [Q][27] for the environments whose d_env_mask[e] != 0
  * (d_env_mask NULL: all) and set the substep counter, which keys the noise.
- * Values are taken as given (not validated on the device).
+ * Values are taken as given (not validated on the device).  Same state as
+ * qs_get_state (§III-A, §III-A.1/2, §III-B.3); resetting environments
+ * between episodes is what the training loop of §III-D asks of it.
  */
 int qs_set_state(qs_handle* h, const float* d_state, uint64_t substep_index,
                  const uint8_t* d_env_mask, void* stream);
 
 /*
- * Enable (enable != 0) or disable recording of the contact sets.  While
+ * Replace the per-quad parameters (§I domain randomisation of the §III-A
+ * mass and inertia, §III-A.2 thrust-to-weight, §III-A.1 motor time
+ * constant) of the environments whose d_env_mask[e] != 0 (NULL: all) with
+ * d_params [Q][6] (device memory, qs_quad_params rows, 4-byte aligned), and
+ * re-derive f_max = m g t2w / 4 and alpha_lag = 1 - exp(-dt / tau_m) on the
+ * device, as qs_create does.  Stream-ordered: calls enqueued after it use
+ * the new values.  Every entry of a selected row must be finite and > 0; a
+ * row that is not keeps its old values and makes the next qs_sync return
+ * QS_ERR_INVALID.  Allocates nothing (can be captured in a graph).
+ */
+int qs_set_params(qs_handle* h, const float* d_params, const uint8_t* d_env_mask, void* stream);
+
+/*
+ * Enable (enable != 0) or disable recording of the §III-B.1 contact sets
+ * (centre distance below col_dist within an environment).  While
  * enabled, every qs_step / qs_step_observe writes, for each quad, the mask
  * of swarm-mates it was in contact with (|x_i - x_j| < col_dist) at its last
  * substep; qs_debug_contacts copies it to d_mask [Q] (bit j = the
@@ -246,8 +267,10 @@ int qs_debug_contacts(qs_handle* h, uint64_t* d_mask, void* stream);
 
 /*
  * Wait for the handle's work on `stream` and return the sticky device error
- * (QS_ERR_NONFINITE) if one was raised since the last qs_sync, else QS_OK.
- * Synchronous.  The error is cleared by the call that reports it.
+ * raised since the last qs_sync: QS_ERR_NONFINITE for a non-finite action
+ * or state, else QS_ERR_INVALID for a rejected qs_set_params row; QS_OK if
+ * none.  Synchronous.  The error is cleared by the call that reports it.
+ * Infrastructure (no passage of the paper).
  */
 int qs_sync(qs_handle* h, void* stream);
 
@@ -343,6 +366,26 @@ int qs_set_launch(qs_handle* h, int32_t block, int32_t grid);
  */
 int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const float* d_goals,
                 float* d_obs, int32_t* choice, void* stream);
+
+/* ---- diagnostics -------------------------------------------------------------
+ * The noise of §III-A.2 (motor), §III-B (wall, pair and downwash kicks) and
+ * §III-C (sensor) comes from one counter-based generator, Philox4x32-10
+ * (Salmon et al., SC'11; the paper names no generator): key = seed, counter
+ * = (quad, substep low word, substep high word, noise_stream << 8 | draw),
+ * streams 0 motor, 1 wall, 2 pair, 3 downwash, 4 sensor.
+ *
+ * qs_debug_philox writes, for quads quad0 .. quad0 + n - 1 at substep_index,
+ * the generator's four 32-bit words into d_words [n][4] and, if d_normals
+ * is not NULL, the four N(0,1) draws the library builds from them (uniforms
+ * (2 (r >> 9) + 1) 2^-24, Box-Muller on (w0, w1) and (w2, w3)) into
+ * d_normals [n][4].  Device buffers, 4-byte aligned, not overlapping;
+ * noise_stream < 2^24, draw < 256, quad0 + n <= 2^32 (QS_ERR_INVALID
+ * otherwise).  No handle: it runs on the current device and `stream`.
+ * For tests of the generator against an independent implementation.
+ */
+int qs_debug_philox(uint64_t seed, uint32_t noise_stream, uint32_t draw, uint64_t substep_index,
+                    uint32_t quad0, int32_t n, uint32_t* d_words, float* d_normals,
+                    void* stream);
 
 /* Static description of a return code. */
 const char* qs_error_string(int code);

@@ -238,6 +238,19 @@ def normal4(seed: int, quad: int, t: int, stream: int, draw: int):
     return np.array(list(z))
 
 
+def noise_batch(seed: int, stream: int, draw: int, t: int, quad0: int, n: int):
+    """(words [n][4] uint32, normals [n][4] f64) of the generator for quads
+    quad0 .. quad0 + n - 1 at substep t (see or_noise_batch)."""
+    words = np.zeros((n, 4), dtype=np.uint32)
+    normals = np.zeros((n, 4))
+    rc = lib().or_noise_batch(C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), C.c_uint32(stream),
+                              C.c_uint32(draw), C.c_uint64(t), C.c_uint32(quad0), C.c_int(n),
+                              _p(words, C.c_uint32), _p(normals, C.c_double))
+    if rc != 0:
+        raise ValueError("or_noise_batch rejected its arguments")
+    return words, normals
+
+
 def uniform_from_u32(r: int) -> float:
     return float(lib().or_uniform_from_u32(C.c_uint32(r)))
 

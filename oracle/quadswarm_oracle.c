@@ -1104,7 +1104,8 @@ int or_observe_noise(const or_desc* d, double* obs, uint64_t t) {
  *     + a_dact |f - f_prev| + a_rot (tr R - 1)/2 + a_yaw R00
  *     + a_floor_hit [hit floor] + a_on_floor [resting] + a_wall [wall bounce]
  *     + a_ceiling [ceiling bounce] + a_quad [collision response]
- *     + a_prox sum_k max(1 - |x~_k| / d_prox, 0) over the K neighbour slots
+ *     + a_prox sum_k max(1 - |x~_k| / d_prox, 0) over the min(K, n_e - 1) real
+ *       neighbour slots (padded slots add nothing)
  * with f = f_max u_f^2 + eps the rotor thrusts after (f) and before (f_prev)
  * the call.
  */
@@ -1112,41 +1113,64 @@ int or_reward(const or_desc* d, const double* params, const double* s0, const do
               const uint32_t* ev, const double* goals, const double* obs, const double* w,
               double* reward) {
   if (check_desc(d) || !params || !s0 || !s1 || !ev || !goals || !obs || !w || !reward) return -1;
-  const int Q = d->env_offsets[d->n_envs], K = d->k_neighbors, OD = 18 + 6 * K;
-  for (int q = 0; q < Q; ++q) {
-    const double* a = s0 + (size_t)q * NS;
-    const double* b = s1 + (size_t)q * NS;
-    const double f_max = 0.25 * params[(size_t)q * NP + PM] * d->gravity * params[(size_t)q * NP + PT2W];
-    double dx2 = 0, v2 = 0, w2 = 0, f2 = 0, df2 = 0;
-    for (int k = 0; k < 3; ++k) {
-      const double e = b[IX + k] - goals[(size_t)q * 3 + k];
-      dx2 += e * e;
-      v2 += b[IV + k] * b[IV + k];
-      w2 += b[IW + k] * b[IW + k];
+  const int K = d->k_neighbors, OD = 18 + 6 * K;
+  for (int e = 0; e < d->n_envs; ++e) {
+    const int q0 = d->env_offsets[e], n = d->env_offsets[e + 1] - q0;
+    /* the real neighbour slots are the first min(K, n_e - 1); the rest are
+       padding and add nothing, whatever their values */
+    const int kr = n - 1 < K ? n - 1 : K;
+    for (int q = q0; q < q0 + n; ++q) {
+      const double* a = s0 + (size_t)q * NS;
+      const double* b = s1 + (size_t)q * NS;
+      const double f_max =
+          0.25 * params[(size_t)q * NP + PM] * d->gravity * params[(size_t)q * NP + PT2W];
+      double dx2 = 0, v2 = 0, w2 = 0, f2 = 0, df2 = 0;
+      for (int k = 0; k < 3; ++k) {
+        const double g = b[IX + k] - goals[(size_t)q * 3 + k];
+        dx2 += g * g;
+        v2 += b[IV + k] * b[IV + k];
+        w2 += b[IW + k] * b[IW + k];
+      }
+      for (int i = 0; i < 4; ++i) {
+        const double f1 = f_max * b[IU + i] * b[IU + i] + b[IE + i];
+        const double f0 = f_max * a[IU + i] * a[IU + i] + a[IE + i];
+        f2 += f1 * f1;
+        df2 += (f1 - f0) * (f1 - f0);
+      }
+      double r = w[0] * sqrt(dx2) + w[1] * sqrt(v2) + w[2] * b[IR + 8] + w[3] * sqrt(w2) +
+                 w[4] * sqrt(f2) + w[5] * sqrt(df2) +
+                 w[6] * (b[IR + 0] + b[IR + 4] + b[IR + 8] - 1.0) / 2.0 + w[7] * b[IR + 0];
+      r += w[8] * ((ev[q] & EV_FLOOR_HIT) ? 1.0 : 0.0) + w[9] * (b[IF] != 0.0 ? 1.0 : 0.0) +
+           w[10] * ((ev[q] & EV_WALL) ? 1.0 : 0.0) + w[11] * ((ev[q] & EV_CEILING) ? 1.0 : 0.0) +
+           w[12] * ((ev[q] & EV_PAIR_RESPONSE) ? 1.0 : 0.0);
+      const double* o = obs + (size_t)q * OD;
+      for (int k = 0; k < kr; ++k) {
+        const double* x = o + 18 + 6 * k;
+        const double dd = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        const double h = 1.0 - dd / w[14];
+        r += w[13] * (h > 0.0 ? h : 0.0);
+      }
+      reward[q] = r;
     }
-    for (int i = 0; i < 4; ++i) {
-      const double f1 = f_max * b[IU + i] * b[IU + i] + b[IE + i];
-      const double f0 = f_max * a[IU + i] * a[IU + i] + a[IE + i];
-      f2 += f1 * f1;
-      df2 += (f1 - f0) * (f1 - f0);
-    }
-    double r = w[0] * sqrt(dx2) + w[1] * sqrt(v2) + w[2] * b[IR + 8] + w[3] * sqrt(w2) +
-               w[4] * sqrt(f2) + w[5] * sqrt(df2) +
-               w[6] * (b[IR + 0] + b[IR + 4] + b[IR + 8] - 1.0) / 2.0 + w[7] * b[IR + 0];
-    r += w[8] * ((ev[q] & EV_FLOOR_HIT) ? 1.0 : 0.0) + w[9] * (b[IF] != 0.0 ? 1.0 : 0.0) +
-         w[10] * ((ev[q] & EV_WALL) ? 1.0 : 0.0) + w[11] * ((ev[q] & EV_CEILING) ? 1.0 : 0.0) +
-         w[12] * ((ev[q] & EV_PAIR_RESPONSE) ? 1.0 : 0.0);
-    const double* o = obs + (size_t)q * OD;
-    for (int k = 0; k < K; ++k) {
-      const double* x = o + 18 + 6 * k;
-      const double dd = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-      /* zero-padded slots (absent neighbours) contribute nothing */
-      if (x[0] == 0.0 && x[1] == 0.0 && x[2] == 0.0 && x[3] == 0.0 && x[4] == 0.0 && x[5] == 0.0)
-        continue;
-      const double h = 1.0 - dd / w[14];
-      r += w[13] * (h > 0.0 ? h : 0.0);
-    }
-    reward[q] = r;
+  }
+  return 0;
+}
+
+/*
+ * The generator over a range of quads, for comparisons with another
+ * implementation: words[n][4] = Philox4x32-10 of the counter (quad0 + i,
+ * t_lo, t_hi, stream << 8 | draw) under key seed, and normals[n][4] (may be
+ * NULL) the Box-Muller draws or_normal4 builds from them.
+ */
+int or_noise_batch(uint64_t seed, uint32_t stream, uint32_t draw, uint64_t t, uint32_t quad0,
+                   int n, uint32_t* words, double* normals) {
+  if (n < 0 || !words) return -1;
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int i = 0; i < n; ++i) {
+    const uint32_t q = quad0 + (uint32_t)i;
+    const uint32_t ctr[4] = {q, (uint32_t)t, (uint32_t)(t >> 32), (stream << 8) | draw};
+    or_philox4x32_10(ctr, key, words + 4 * (size_t)i);
+    if (normals) or_normal4(seed, q, t, stream, draw, normals + 4 * (size_t)i);
   }
   return 0;
 }

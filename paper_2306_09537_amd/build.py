@@ -1,8 +1,7 @@
-"""Build the HIP library libquadswarm.so for gfx950 (in-tree), and the
-VALU issue-cost probe used to calibrate the ALU roofline (calib/valu_probe).
+"""Build the HIP library libquadswarm.so for gfx950 (in-tree).
 
 Run as ``python -m paper_2306_09537_amd.build``; ``__graft_entry__.build()``
-calls :func:`build` and :func:`build_probe` as well.
+calls :func:`build`.
 """
 from __future__ import annotations
 
@@ -15,8 +14,6 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libquadswarm.so")
-PROBE_SRC = os.path.join(PKG, "calib", "valu_probe.hip")
-PROBE = os.path.join(PKG, "calib", "valu_probe")
 SOURCES = [os.path.join(CSRC, "qs_abi.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("qs_device.h", "qs_kernels.h", "qs_adjoint.h",
                                                   "qs_rollout.h")] + [
@@ -52,19 +49,5 @@ def build(force: bool = True, verbose: bool = False) -> str:
     return LIB
 
 
-def build_probe(verbose: bool = False) -> str:
-    """The probe is a stand-alone program: plain float code, same target and
-    packed-FP32 setting as the library."""
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-command-line-argument", PROBE_SRC, "-o", PROBE + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(PROBE + ".tmp", PROBE)
-    return PROBE
-
-
 if __name__ == "__main__":
     print(build(force=True, verbose="-v" in sys.argv))
-    print(build_probe(verbose="-v" in sys.argv))

@@ -975,13 +975,43 @@ int qs_sync(qs_handle* h, void* stream) {
   if (hipMemcpyAsync(h->h_err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
     return QS_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return QS_ERR_HIP;
-  if (*h->h_err != 0) {
+  const int bits = *h->h_err;
+  if (bits != 0) {
     *h->h_err = 0;
     if (hipMemsetAsync(h->d_err, 0, sizeof(int), s) != hipSuccess) return QS_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return QS_ERR_HIP;
-    return QS_ERR_NONFINITE;
+    return (bits & (qs::ERRBIT_STATE | qs::ERRBIT_ACTION)) ? QS_ERR_NONFINITE : QS_ERR_INVALID;
   }
   return QS_OK;
+}
+
+int qs_set_params(qs_handle* h, const float* d_params, const uint8_t* d_env_mask, void* stream) {
+  if (!h || !d_params) return QS_ERR_NULL;
+  if (!aligned(d_params, 4)) return QS_ERR_ALIGN;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  const int tb = 256;
+  hipLaunchKernelGGL(qs::set_params_kernel, dim3((unsigned)((h->Q + tb - 1) / tb)), dim3(tb), 0,
+                     (hipStream_t)stream, h->d_par, h->Qp, h->Q, d_params, h->d_qenv, d_env_mask,
+                     h->c.dt, h->c.g, h->d_err);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+}
+
+int qs_debug_philox(uint64_t seed, uint32_t noise_stream, uint32_t draw, uint64_t substep_index,
+                    uint32_t quad0, int32_t n, uint32_t* d_words, float* d_normals,
+                    void* stream) {
+  if (!d_words) return QS_ERR_NULL;
+  if (n < 0 || noise_stream > 0xffffffu || draw > 0xffu ||
+      (uint64_t)quad0 + (uint64_t)n > 0x100000000ull)
+    return QS_ERR_INVALID;
+  if (!aligned(d_words, 4) || (d_normals && !aligned(d_normals, 4))) return QS_ERR_ALIGN;
+  if (d_normals && overlap({d_words, (size_t)n * 16}, {d_normals, (size_t)n * 16}))
+    return QS_ERR_INVALID;
+  if (n == 0) return QS_OK;
+  const int tb = 256;
+  hipLaunchKernelGGL(qs::philox_debug_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0,
+                     (hipStream_t)stream, (uint32_t)seed, (uint32_t)(seed >> 32), noise_stream,
+                     draw, (unsigned long long)substep_index, quad0, (int)n, d_words, d_normals);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
 }
 
 int qs_rollout(qs_handle* h, const float* d_actions, int32_t n_calls, int32_t n_substeps,

@@ -30,7 +30,7 @@ enum : uint32_t {
 };
 // events of a call, for the reward's interaction terms
 enum : uint32_t { EVF_FLOOR_HIT = 1u, EVF_WALL = 2u, EVF_CEILING = 4u, EVF_QUAD = 8u };
-enum : int { ERRBIT_STATE = 1, ERRBIT_ACTION = 2 };
+enum : int { ERRBIT_STATE = 1, ERRBIT_ACTION = 2, ERRBIT_PARAM = 4 };
 
 struct Consts {
   float dt, g, arm_d, k_tau, drag, mu;

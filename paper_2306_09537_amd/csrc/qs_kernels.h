@@ -642,6 +642,67 @@ __global__ void set_counter_kernel(unsigned long long* tdev, unsigned int* done,
   }
 }
 
+// Per-quad parameters [Q][6] (mass, ixx, iyy, izz, thrust-to-weight, tau_m)
+// -> private SoA, for environments selected by env_mask, with f_max and
+// alpha_lag derived in double and rounded once (as at creation).  A row
+// with a non-finite or non-positive entry is left as it was and raises the
+// sticky parameter error bit.
+__global__ void set_params_kernel(float* __restrict__ par, int Qp, int Q,
+                                  const float* __restrict__ src,
+                                  const int32_t* __restrict__ qenv,
+                                  const uint8_t* __restrict__ env_mask, float dt, float g,
+                                  int* err) {
+  const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (q >= Q) return;
+  if (env_mask && env_mask[qenv[q]] == 0) return;
+  float v[6];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    v[k] = src[(size_t)q * 6 + k];
+    ok = ok && isfinite(v[k]) && v[k] > 0.0f;
+  }
+  if (!ok) {
+    __hip_atomic_fetch_or(err, ERRBIT_PARAM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  par[(size_t)P_M * Qp + q] = v[0];
+  par[(size_t)P_JX * Qp + q] = v[1];
+  par[(size_t)P_JY * Qp + q] = v[2];
+  par[(size_t)P_JZ * Qp + q] = v[3];
+  par[(size_t)P_FMAX * Qp + q] = (float)(0.25 * (double)v[0] * (double)g * (double)v[4]);
+  par[(size_t)P_ALAG * Qp + q] = (float)(1.0 - exp(-(double)dt / (double)v[5]));
+  par[(size_t)P_T2W * Qp + q] = v[4];
+  par[(size_t)P_TAU * Qp + q] = v[5];
+}
+
+// The library's counter-based generator, exported for tests: for quads
+// quad0 .. quad0 + n - 1 at substep t, the four Philox4x32-10 words of
+// (stream, draw) into words[n][4] and, when normals is not null, the four
+// N(0,1) draws built from them into normals[n][4].
+__global__ void philox_debug_kernel(uint32_t key0, uint32_t key1, uint32_t stream,
+                                    uint32_t draw, unsigned long long t, uint32_t quad0, int n,
+                                    uint32_t* __restrict__ words, float* __restrict__ normals) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  const uint32_t q = quad0 + (uint32_t)i;
+  uint32_t r0 = q, r1 = (uint32_t)t, r2 = (uint32_t)(t >> 32), r3 = (stream << 8) | draw;
+  philox4x32_10(r0, r1, r2, r3, key0, key1);
+  words[4 * (size_t)i + 0] = r0;
+  words[4 * (size_t)i + 1] = r1;
+  words[4 * (size_t)i + 2] = r2;
+  words[4 * (size_t)i + 3] = r3;
+  if (normals) {
+    Consts c{};
+    c.key0 = key0;
+    c.key1 = key1;
+    float z[4];
+    normal4(c, q, t, stream, draw, z);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) normals[4 * (size_t)i + k] = z[k];
+  }
+}
+
 // Canonical [Q][27] -> private SoA, for environments selected by env_mask.
 __global__ void set_state_kernel(float* __restrict__ st, int Qp, int Q,
                                  const float* __restrict__ src,

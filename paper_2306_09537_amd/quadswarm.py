@@ -26,7 +26,8 @@ EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_substep_index", "qs_step",
            "qs_step_observe", "qs_get_state", "qs_set_state", "qs_record_contacts",
            "qs_debug_contacts", "qs_sync", "qs_rollout", "qs_rollout_backward",
            "qs_step_backward", "qs_set_graph_mode", "qs_set_launch", "qs_autotune",
-           "qs_set_reward_weights", "qs_step_observe_reward", "qs_error_string")
+           "qs_set_reward_weights", "qs_step_observe_reward", "qs_set_params",
+           "qs_debug_philox", "qs_error_string")
 
 
 class QuadSwarmError(RuntimeError):
@@ -87,6 +88,9 @@ def lib() -> C.CDLL:
         L.qs_set_reward_weights.argtypes = [vp, vp]
         L.qs_get_state.argtypes = [vp, vp, C.POINTER(u64), vp]
         L.qs_set_state.argtypes = [vp, vp, u64, vp, vp]
+        L.qs_set_params.argtypes = [vp, vp, vp, vp]
+        u32 = C.c_uint32
+        L.qs_debug_philox.argtypes = [u64, u32, u32, u64, u32, i32, vp, vp, vp]
         L.qs_record_contacts.argtypes = [vp, i32]
         L.qs_debug_contacts.argtypes = [vp, vp, vp]
         L.qs_sync.argtypes = [vp, vp]
@@ -268,6 +272,18 @@ class QuadSwarm:
         _check(lib().qs_set_state(self._h, _ptr(s), C.c_uint64(int(substep)),
                                   None if m is None else _ptr(m), _stream(self._di)), "qs_set_state")
 
+    def set_params(self, params, env_mask=None) -> None:
+        """qs_set_params: per-quad (mass, ixx, iyy, izz, thrust_to_weight,
+        tau_m) [Q][6] on the handle's device; f_max and alpha_lag are
+        re-derived on the device."""
+        import torch
+        p = self._dev(params, (self.n_quads, 6))
+        m = None
+        if env_mask is not None:
+            m = self._dev(env_mask, (self.n_envs,), torch.uint8)
+        _check(lib().qs_set_params(self._h, _ptr(p), None if m is None else _ptr(m),
+                                   _stream(self._di)), "qs_set_params")
+
     def record_contacts(self, enable: bool = True) -> None:
         _check(lib().qs_record_contacts(self._h, 1 if enable else 0), "qs_record_contacts")
 
@@ -371,6 +387,21 @@ class QuadSwarm:
         self.close()
 
 
+def debug_philox(seed: int, noise_stream: int, draw: int, substep_index: int, quad0: int,
+                 n: int, with_normals: bool = True, device=None):
+    """qs_debug_philox: the library's generator words [n][4] (int32 tensor
+    holding the uint32 bits) and, optionally, its N(0,1) draws [n][4]."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    words = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    normals = torch.empty((n, 4), dtype=torch.float32, device=dev) if with_normals else None
+    _check(lib().qs_debug_philox(C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(noise_stream),
+                                 int(draw), C.c_uint64(int(substep_index)), int(quad0), int(n),
+                                 _ptr(words), None if normals is None else _ptr(normals),
+                                 _stream(dev.index)), "qs_debug_philox")
+    return words, normals
+
+
 def _make_rollout_fn():
     import torch
 
@@ -379,16 +410,19 @@ def _make_rollout_fn():
 
         forward(state0 [Q][27], actions [T][Q][4], params [Q][6], sim,
         n_substeps, ckpt_every, beta) -> (final state [Q][27], penalty [Q]).
-        ``params`` must hold the parameters the handle was created with; it is
-        an input only so that autograd can return dL/d params.  The forward
-        keeps ceil(T / ckpt_every) checkpoints; the backward recomputes each
-        segment from its checkpoint.
+        ``params`` (mass, ixx, iyy, izz, thrust_to_weight, tau_m per quad)
+        are loaded into the handle (qs_set_params) before the rollout, so the
+        simulation runs with them and dL/d params belongs to them; the handle
+        keeps them afterwards.  The forward keeps ceil(T / ckpt_every)
+        checkpoints; the backward recomputes each segment from its
+        checkpoint.
         """
 
         @staticmethod
         def forward(ctx, state0, actions, params, sim, n_substeps, ckpt_every, beta):
             T = actions.shape[0]
             t0 = sim.substep
+            sim.set_params(params.detach().contiguous())
             sim.set_state(state0.detach().contiguous(), t0)
             n_ck = (T + ckpt_every - 1) // ckpt_every
             ckpt = torch.empty((n_ck, 27, sim.n_quads), device=state0.device)

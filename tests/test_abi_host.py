@@ -142,3 +142,21 @@ def test_calls_on_null_handle():
     w = np.zeros(15, np.float32)
     assert L.qs_set_reward_weights(None, w.ctypes.data) == -1
     assert L.qs_destroy(None) == 0
+
+
+def test_set_params_and_debug_philox_argument_checks():
+    L = QS.lib()
+    p = np.zeros((4, 6), np.float32)
+    assert L.qs_set_params(None, p.ctypes.data, None, None) == -1
+    words = np.zeros((4, 4), np.uint32)
+    assert L.qs_debug_philox(1, 0, 0, 0, 0, 4, None, None, None) == -1
+    assert L.qs_debug_philox(1, 0, 0, 0, 0, -1, words.ctypes.data, None, None) == -2
+    assert L.qs_debug_philox(1, 1 << 24, 0, 0, 0, 4, words.ctypes.data, None, None) == -2
+    assert L.qs_debug_philox(1, 0, 256, 0, 0, 4, words.ctypes.data, None, None) == -2
+    assert L.qs_debug_philox(1, 0, 0, 0, (1 << 32) - 2, 4, words.ctypes.data, None, None) == -2
+    assert L.qs_debug_philox(1, 0, 0, 0, 0, 4, words.ctypes.data + 1, None, None) == -7
+    # the two outputs may not overlap
+    assert L.qs_debug_philox(1, 0, 0, 0, 0, 4, words.ctypes.data, words.ctypes.data + 16,
+                             None) == -2
+    # nothing to do is no error
+    assert L.qs_debug_philox(1, 0, 0, 0, 0, 0, words.ctypes.data, None, None) == 0

@@ -230,3 +230,43 @@ def test_reward_argument_errors():
         sim.step_observe_reward(dev(w.actions(0)), 0, g)
     assert ei.value.code == -2
     sim.sync()
+
+
+@pytest.mark.parametrize("sizes,k", [([3] * 48, 6), ([3] * 48, 4), ([2] * 64, 6)])
+def test_proximity_reward_counts_coincident_swarm_mates(sizes, k):
+    """Quads 0 and 1 of every swarm start at the same position with the same
+    velocity, nominal parameters, no noise and the same action: they stay
+    bitwise coincident and co-moving, so each sees the other in an all-zero
+    neighbour slot at distance 0 (§III-E: alpha_prox * 1).  The kernel's
+    reward, per quad, against the oracle's, which sums over the real slots
+    by count.  Cases: bucketed launch with K = 6, runtime-K path (K = 4),
+    and two-quad swarms with padded slots (K = 6)."""
+    flags = W.QS_ROOM | W.QS_FLOOR | W.QS_COLLIDE | W.QS_APPROACH_ONLY
+    w = W.custom(sizes, seed=31, k=k, flags=flags, randomise=False, name="coincident")
+    s0 = w.state0.copy()
+    for e in range(w.n_envs):
+        q0 = int(w.env_offsets[e])
+        s0[q0 + 1] = s0[q0]
+    w = w.with_(state0=s0)
+    a = np.repeat(w.actions(0)[:1], w.n_quads, axis=0)
+    weights = np.zeros(15, np.float32)
+    weights[13], weights[14] = 0.75, 0.5
+    sim = QuadSwarm.from_workload(w)
+    sim.set_reward_weights(weights)
+    obs_d, rw_d = sim.step_observe_reward(dev(a), 2, dev(w.goals))
+    s_d, _ = sim.get_state()
+    sim.sync()
+    s_gpu = s_d.cpu().numpy().astype(np.float64)
+    q0s = w.env_offsets[:-1]
+    assert np.array_equal(s_gpu[q0s], s_gpu[q0s + 1])
+    orc = O.Oracle.from_workload(w)
+    goals = w.goals.astype(np.float64)
+    o_exact, nbr = orc.observe(s_gpu, goals)
+    assert np.all(o_exact[q0s, 18:24] == 0.0) and np.all(nbr[q0s, 0] == 1)
+    ev = np.zeros(w.n_quads, np.uint32)
+    r_ref = orc.reward(w.state0.astype(np.float64), s_gpu, ev, goals, o_exact,
+                       weights.astype(np.float64))
+    r_gpu = rw_d.cpu().numpy().astype(np.float64)
+    assert np.all(r_ref[q0s] >= 0.75) and np.all(r_ref[q0s + 1] >= 0.75)
+    np.testing.assert_allclose(r_gpu, r_ref, rtol=1e-6, atol=1e-6)
+    sim.close()

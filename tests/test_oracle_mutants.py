@@ -165,8 +165,14 @@ MUTANTS = [
     ("reward_on_floor_from_hit", "§III-E",
      "w[9] * (b[IF] != 0.0 ? 1.0 : 0.0)", "w[9] * ((ev[q] & EV_FLOOR_HIT) ? 1.0 : 0.0)"),
     ("reward_prox_counts_empty_slots", "§III-E",
-     "      if (x[0] == 0.0 && x[1] == 0.0 && x[2] == 0.0 && x[3] == 0.0 && x[4] == 0.0 && x[5] == 0.0)\n        continue;\n",
-     ""),
+     "const int kr = n - 1 < K ? n - 1 : K;", "const int kr = K;"),
+    # padded slots told apart by their zero values instead of by count: a
+    # coincident, co-moving swarm-mate then adds nothing
+    ("reward_prox_skips_zero_valued_slots", "§III-E",
+     "        const double* x = o + 18 + 6 * k;\n",
+     "        const double* x = o + 18 + 6 * k;\n"
+     "        if (x[0] == 0.0 && x[1] == 0.0 && x[2] == 0.0 && x[3] == 0.0 && x[4] == 0.0 &&\n"
+     "            x[5] == 0.0)\n          continue;\n"),
     # reverse mode (§III-E penalty and every row above)
     ("vjp_lag_factor", "reverse mode, §III-A.1",
      "lu0[i] = (1.0 - r->alpha_lag) * lu[i];", "lu0[i] = r->alpha_lag * lu[i];"),

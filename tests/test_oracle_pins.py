@@ -906,3 +906,23 @@ def test_reward_terms_on_constructed_states():
     w = np.zeros(15)
     w[13], w[14] = 1.0, 2.5
     assert solo.reward(s0[:1], s1[:1], ev[:1], goals[:1], o1, w)[0] == 0.0
+
+
+def test_reward_proximity_counts_real_slots_not_zero_values():
+    """The proximity term sums over the min(K, n_e - 1) real neighbour slots
+    (§III-E): a swarm-mate at exactly the same position with the same
+    velocity has an all-zero slot, yet it is a neighbour at distance 0 and
+    adds alpha_prox * 1; the padded slots beyond n_e - 1 add nothing."""
+    q = 3
+    s1 = blank_state(q)
+    s1[:, 0:3] = [0.5, -1.0, 2.0]          # quads 0 and 1 coincide ...
+    s1[:, W.SV:W.SV + 3] = [0.2, 0.1, -0.3]  # ... and move together
+    s1[2, 0:3] = [0.5, -1.0, 3.0]          # quad 2: 1 m above, beyond d_prox
+    goals = np.zeros((q, 3))
+    orc = make(q, k=4, env_sizes=[3])      # K = 4 > n_e - 1 = 2: two padded slots
+    obs, nbr = orc.observe(s1, goals)
+    assert np.all(obs[0, 18:24] == 0.0) and nbr[0, 0] == 1 and nbr[0, 2] == -1
+    w = np.zeros(15)
+    w[13], w[14] = 0.75, 0.5
+    r = orc.reward(s1, s1, np.zeros(q, np.uint32), goals, obs, w)
+    assert r[0] == 0.75 and r[1] == 0.75 and r[2] == 0.0
