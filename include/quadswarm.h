@@ -78,6 +78,7 @@ extern "C" {
 #define QS_ERR_NOMEM (-6)         /* device or host allocation failed */
 #define QS_ERR_ALIGN (-7)         /* a device pointer is misaligned (see above) */
 #define QS_ERR_UNSUPPORTED (-8)   /* valid request this build does not handle */
+#define QS_ERR_TOO_LARGE (-9)     /* exceeds the fixed scratch of qs_step_backward_noalloc */
 
 /* ---- physics switches (qs_desc.flags) ---- */
 #define QS_ROOM 1u            /* §III-B.2 walls and ceiling bounce the quad */
@@ -93,6 +94,7 @@ extern "C" {
 #define QS_PARAM_DIM 6
 #define QS_MAX_SWARM 64
 #define QS_MAX_QUADS (1 << 26) /* quads per handle (67,108,864: 7.2 GB of state) */
+#define QS_NOALLOC_SCRATCH_BYTES (64 << 20) /* fixed scratch per device, 64 MiB */
 
 typedef struct qs_handle qs_handle;
 
@@ -328,6 +330,29 @@ int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
 int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actions,
                      int32_t n_substeps, uint64_t substep_index, const float* d_gstate_out,
                      float* d_gstate_in, float* d_gactions, float* d_gparams, void* stream);
+
+/*
+ * qs_step_backward for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, checks and results (bit-identical) as
+ * qs_step_backward, same kernels; it calls no hipMalloc, hipFree or other
+ * allocating routine.  Its scratch -- the state before the call and the
+ * state adjoint ([27][Q] each), the parameter gradient ([6][Q]) and the
+ * tape of the call's substeps ([n_substeps][31][Q]), each part rounded up
+ * to 64 floats -- lives in a fixed device array of QS_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every device it runs on until the process
+ * ends.  A request that does not fit returns QS_ERR_TOO_LARGE before
+ * anything is enqueued: (60 + 31 n_substeps) Q floats must stay within
+ * 16,777,216 (e.g. at most 184,000 quads for one substep, 45,000 for ten).
+ * Every call on a device shares that device's array and the array keeps
+ * the last call's contents (each call overwrites what it reads): calls
+ * that overlap in time on one device (several streams, threads or
+ * handles) race, and the caller must order them.
+ */
+int qs_step_backward_noalloc(qs_handle* h, const float* d_state_in, const float* d_actions,
+                             int32_t n_substeps, uint64_t substep_index,
+                             const float* d_gstate_out, float* d_gstate_in, float* d_gactions,
+                             float* d_gparams, void* stream);
 
 /* ---- batching and scheduling ------------------------------------------------
  * Swarms of uneven sizes run in one persistent launch: every swarm gets a

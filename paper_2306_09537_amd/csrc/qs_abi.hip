@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -389,12 +390,21 @@ void go_roll(qs_handle* h, const float* act, int ncalls, int nsub, float* ckpt, 
                      act, ncalls, nsub, (unsigned long long)h->t, ckpt, ce, pen, beta);
 }
 
+// Device scratch of one backward pass: the tape of the chunk of segments in
+// flight ([S][31][Q]), the state adjoint ([27][Q]) and the parameter
+// gradient ([6][Q]).
+struct AdjScratch {
+  float* tape;
+  float* lam;
+  float* gpar;
+};
+
 template <int BS, int N, bool PEN>
-void go_recompute(qs_handle* h, const float* ckpt, const float* act, int ncalls, int ce, int nsub,
-                  uint64_t t0, hipStream_t s) {
+void go_recompute(qs_handle* h, const AdjScratch& sc, const float* ckpt, const float* act,
+                  int ncalls, int ce, int nsub, uint64_t t0, hipStream_t s) {
   const int nseg = (ncalls + ce - 1) / ce;
   hipLaunchKernelGGL((qs::recompute_kernel<BS, N>), dim3(h->nblk, nseg), dim3(BS), 0, s, h->d_c,
-                     ptrs(h), ckpt, act, ncalls, ce, nsub, (unsigned long long)t0, h->d_tape);
+                     ptrs(h), ckpt, act, ncalls, ce, nsub, (unsigned long long)t0, sc.tape);
 }
 
 // The two-wavefront reverse sweep pays where the batch leaves SIMDs idle:
@@ -405,25 +415,25 @@ bool use_reverse_pipe(const qs_handle* h) {
 }
 
 template <int N, bool PEN>
-void go_reverse_pipe(qs_handle* h, const float* act, int ncalls, int nsub, uint64_t t0,
-                     const float* gpen, float beta, float* gact, hipStream_t s) {
+void go_reverse_pipe(qs_handle* h, const AdjScratch& sc, const float* act, int ncalls, int nsub,
+                     uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
   hipLaunchKernelGGL((qs::reverse_pipe_kernel<N, PEN>), dim3(h->nblk), dim3(128), 0, s, h->d_c,
-                     ptrs(h), act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam, gpen,
-                     beta, gact, h->d_gpar);
+                     ptrs(h), act, ncalls, nsub, (unsigned long long)t0, sc.tape, sc.lam, gpen,
+                     beta, gact, sc.gpar);
 }
 
 template <int BS, int N, bool PEN>
-void go_reverse(qs_handle* h, const float* act, int ncalls, int nsub, uint64_t t0,
-                const float* gpen, float beta, float* gact, hipStream_t s) {
+void go_reverse(qs_handle* h, const AdjScratch& sc, const float* act, int ncalls, int nsub,
+                uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
   if constexpr (BS == 64 && (N == 1 || N == 8)) {
     if (use_reverse_pipe(h)) {
-      go_reverse_pipe<N, PEN>(h, act, ncalls, nsub, t0, gpen, beta, gact, s);
+      go_reverse_pipe<N, PEN>(h, sc, act, ncalls, nsub, t0, gpen, beta, gact, s);
       return;
     }
   }
   hipLaunchKernelGGL((qs::reverse_kernel<BS, N, PEN>), dim3(h->nblk), dim3(BS), 0, s, h->d_c,
-                     ptrs(h), act, ncalls, nsub, (unsigned long long)t0, h->d_tape, h->d_lam, gpen,
-                     beta, gact, h->d_gpar);
+                     ptrs(h), act, ncalls, nsub, (unsigned long long)t0, sc.tape, sc.lam, gpen,
+                     beta, gact, sc.gpar);
 }
 
 // Dispatch on (block size, uniform swarm size) for a launcher template F.
@@ -456,17 +466,17 @@ struct RollF {
 
 template <int BS, int N, bool PEN>
 struct RecF {
-  static void run(qs_handle* h, const float* ckpt, const float* act, int ncalls, int ce, int nsub,
-                  uint64_t t0, hipStream_t s) {
-    go_recompute<BS, N, PEN>(h, ckpt, act, ncalls, ce, nsub, t0, s);
+  static void run(qs_handle* h, const AdjScratch* sc, const float* ckpt, const float* act,
+                  int ncalls, int ce, int nsub, uint64_t t0, hipStream_t s) {
+    go_recompute<BS, N, PEN>(h, *sc, ckpt, act, ncalls, ce, nsub, t0, s);
   }
 };
 
 template <int BS, int N, bool PEN>
 struct RevF {
-  static void run(qs_handle* h, const float* act, int ncalls, int nsub, uint64_t t0,
-                  const float* gpen, float beta, float* gact, hipStream_t s) {
-    go_reverse<BS, N, PEN>(h, act, ncalls, nsub, t0, gpen, beta, gact, s);
+  static void run(qs_handle* h, const AdjScratch* sc, const float* act, int ncalls, int nsub,
+                  uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
+    go_reverse<BS, N, PEN>(h, *sc, act, ncalls, nsub, t0, gpen, beta, gact, s);
   }
 };
 
@@ -512,20 +522,20 @@ void convert(const float* src, float* dst, int Q, int rows, bool to_row_major, b
     hipLaunchKernelGGL(qs::rm_to_fm_kernel, grid, block, 0, s, src, dst, Q, rows);
 }
 
+// Floats of tape one checkpoint segment needs.
+size_t segment_tape_floats(const qs_handle* h, int n_calls, int nsub, int ce) {
+  return (size_t)std::min(ce, n_calls) * nsub * qs::NTAPE * h->Q;
+}
+
 // Backward pass over n_calls calls with checkpoints every ce calls (ckpt:
-// [27][Q] each); lam and gpar scratch already hold the incoming adjoint and
-// zeros.  Segments are taken in chunks whose tape fits the budget, last
-// chunk first: one launch recomputes every segment of the chunk in
+// [27][Q] each); sc.lam and sc.gpar already hold the incoming adjoint and
+// zeros, and sc.tape holds G segments.  Segments are taken in chunks of G,
+// last chunk first: one launch recomputes every segment of the chunk in
 // parallel, one launch sweeps the chunk in reverse.
-int run_adjoint(qs_handle* h, const float* act, int n_calls, int nsub, int ce, const float* ckpt,
-                uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
+int run_adjoint(qs_handle* h, const AdjScratch& sc, int G, const float* act, int n_calls,
+                int nsub, int ce, const float* ckpt, uint64_t t0, const float* gpen, float beta,
+                float* gact, hipStream_t s) {
   const int nseg = (n_calls + ce - 1) / ce;
-  const size_t seg_floats = (size_t)std::min(ce, n_calls) * nsub * qs::NTAPE * h->Q;
-  const size_t fit = tape_budget() / (seg_floats * sizeof(float));
-  // segments per chunk (also the recompute grid's y extent, at most 65535)
-  const int G = (int)std::max<size_t>(1, std::min<size_t>({(size_t)nseg, fit, (size_t)65535}));
-  int rc = grow(&h->d_tape, &h->tape_cap, (size_t)G * seg_floats);
-  if (rc != QS_OK) return rc;
   for (int hi = nseg; hi > 0; hi -= G) {
     const int g0 = std::max(0, hi - G);
     const int c0 = g0 * ce, nc = std::min(n_calls, hi * ce) - c0;
@@ -533,13 +543,93 @@ int run_adjoint(qs_handle* h, const float* act, int n_calls, int nsub, int ce, c
     const float* a = act + (size_t)c0 * h->Q * 4;
     float* ga = gact + (size_t)c0 * h->Q * 4;
     const uint64_t ts = t0 + (uint64_t)c0 * nsub;
-    dispatch<RecF, false>(h, ck, a, nc, ce, nsub, ts, s);
+    dispatch<RecF, false>(h, &sc, ck, a, nc, ce, nsub, ts, s);
     if (gpen)
-      dispatch<RevF, true>(h, a, nc, nsub, ts, gpen, beta, ga, s);
+      dispatch<RevF, true>(h, &sc, a, nc, nsub, ts, gpen, beta, ga, s);
     else
-      dispatch<RevF, false>(h, a, nc, nsub, ts, gpen, beta, ga, s);
+      dispatch<RevF, false>(h, &sc, a, nc, nsub, ts, gpen, beta, ga, s);
     if (hipGetLastError() != hipSuccess) return QS_ERR_HIP;
   }
+  return QS_OK;
+}
+
+// Argument checks shared by the two forms of qs_step_backward.
+int check_step_backward(const qs_handle* h, const float* d_state_in, const float* d_actions,
+                        int32_t n_substeps, const float* d_gstate_out, const float* d_gstate_in,
+                        const float* d_gactions, const float* d_gparams) {
+  if (!h || !d_state_in || !d_actions || !d_gstate_out || !d_gstate_in || !d_gactions ||
+      !d_gparams)
+    return QS_ERR_NULL;
+  if (n_substeps < 0) return QS_ERR_INVALID;
+  if (h->c.flags & qs::F_DOWNWASH) return QS_ERR_UNSUPPORTED;
+  if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_state_in, 4) ||
+      !aligned(d_gstate_out, 4) || !aligned(d_gstate_in, 4) || !aligned(d_gparams, 4))
+    return QS_ERR_ALIGN;
+  // d_gstate_in may be d_gstate_out itself (both are staged), not a part of it
+  const size_t Q = (size_t)h->Q;
+  const bool same = d_gstate_in == d_gstate_out;
+  if (outputs_overlap({{d_gstate_in, Q * 108}, {d_gactions, Q * 16}, {d_gparams, Q * 24}},
+                      {{d_state_in, Q * 108}, {d_actions, Q * 16},
+                       {same ? nullptr : d_gstate_out, Q * 108}}))
+    return QS_ERR_INVALID;
+  return QS_OK;
+}
+
+// The launches of one qs_step_backward call on the given scratch: ck1 [27][Q]
+// receives the state before the call, sc.lam the incoming adjoint, sc.gpar
+// zeros (a fill kernel, not a memset, so the sequence can be captured), then
+// the recompute and reverse sweeps of one segment, and the results are
+// converted back to the caller's row-major layouts.
+int step_backward_run(qs_handle* h, const AdjScratch& sc, float* ck1, const float* d_state_in,
+                      const float* d_actions, int32_t n_substeps, uint64_t substep_index,
+                      const float* d_gstate_out, float* d_gstate_in, float* d_gactions,
+                      float* d_gparams, hipStream_t s) {
+  convert(d_state_in, ck1, h->Q, qs::NSTATE, false, false, s);
+  convert(d_gstate_out, sc.lam, h->Q, qs::NSTATE, false, false, s);
+  hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((6LL * h->Q + 255) / 256)), dim3(256), 0, s,
+                     sc.gpar, 6LL * h->Q, 0.0f);
+  if (n_substeps > 0) {
+    const int rc = run_adjoint(h, sc, 1, d_actions, 1, n_substeps, 1, ck1, substep_index, nullptr,
+                               0.f, d_gactions, s);
+    if (rc != QS_OK) return rc;
+  } else {
+    hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((4LL * h->Q + 255) / 256)), dim3(256), 0,
+                       s, d_gactions, 4LL * h->Q, 0.0f);
+  }
+  convert(sc.lam, d_gstate_in, h->Q, qs::NSTATE, true, false, s);
+  convert(sc.gpar, d_gparams, h->Q, 6, true, true, s);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+}
+
+// ---- fixed scratch of the allocation-free entry point -------------------
+// qs_step_backward_noalloc keeps its scratch in this array instead of
+// allocating: 64 MiB, one copy on every device the library runs on, held
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it names a stand-in, not device memory): the device
+// address comes from hipGetSymbolAddress, looked up once per device with
+// that device current, and only that pointer is passed to kernels.
+}  // namespace
+
+constexpr size_t kNoAllocScratchFloats = (size_t)QS_NOALLOC_SCRATCH_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the scratch array on device dev (which must be
+// current), looked up on first use and kept.
+int noalloc_scratch(int dev, float** out) {
+  if (dev < 0 || dev >= kMaxDevices) return QS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return QS_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
   return QS_OK;
 }
 
@@ -700,6 +790,10 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
     return rc;
   }
   *h->h_err = 0;
+  // set-up of the allocation-free entry point's scratch address on this
+  // device (its own first call retries if this lookup failed)
+  float* unused = nullptr;
+  (void)noalloc_scratch(h->dev, &unused);
   *out = h;
   return QS_OK;
 }
@@ -1070,7 +1164,16 @@ int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
   convert(d_gstate, h->d_lam, h->Q, qs::NSTATE, false, false, s);
   hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((6LL * h->Q + 255) / 256)), dim3(256), 0, s,
                      h->d_gpar, 6LL * h->Q, 0.0f);
-  rc = run_adjoint(h, d_actions, n_calls, n_substeps, ckpt_every, d_ckpt, substep_index0,
+  // segments per chunk: as many as fit the tape budget (also the recompute
+  // grid's y extent, at most 65535), at least one
+  const int nseg = (n_calls + ckpt_every - 1) / ckpt_every;
+  const size_t seg = segment_tape_floats(h, n_calls, n_substeps, ckpt_every);
+  const size_t fit = tape_budget() / (seg * sizeof(float));
+  const int G = (int)std::max<size_t>(1, std::min<size_t>({(size_t)nseg, fit, (size_t)65535}));
+  rc = grow(&h->d_tape, &h->tape_cap, (size_t)G * seg);
+  if (rc != QS_OK) return rc;
+  const AdjScratch sc{h->d_tape, h->d_lam, h->d_gpar};
+  rc = run_adjoint(h, sc, G, d_actions, n_calls, n_substeps, ckpt_every, d_ckpt, substep_index0,
                    d_gpenalty, beta, d_gactions, s);
   if (rc != QS_OK) return rc;
   convert(h->d_lam, d_gstate, h->Q, qs::NSTATE, true, false, s);
@@ -1081,42 +1184,39 @@ int qs_rollout_backward(qs_handle* h, const float* d_actions, int32_t n_calls,
 int qs_step_backward(qs_handle* h, const float* d_state_in, const float* d_actions,
                      int32_t n_substeps, uint64_t substep_index, const float* d_gstate_out,
                      float* d_gstate_in, float* d_gactions, float* d_gparams, void* stream) {
-  if (!h || !d_state_in || !d_actions || !d_gstate_out || !d_gstate_in || !d_gactions ||
-      !d_gparams)
-    return QS_ERR_NULL;
-  if (n_substeps < 0) return QS_ERR_INVALID;
-  if (h->c.flags & qs::F_DOWNWASH) return QS_ERR_UNSUPPORTED;
-  if (!aligned(d_actions, 16) || !aligned(d_gactions, 16) || !aligned(d_state_in, 4) ||
-      !aligned(d_gstate_out, 4) || !aligned(d_gstate_in, 4) || !aligned(d_gparams, 4))
-    return QS_ERR_ALIGN;
-  {
-    // d_gstate_in may be d_gstate_out itself (both are staged), not a part of it
-    const size_t Q = (size_t)h->Q;
-    const bool same = d_gstate_in == d_gstate_out;
-    if (outputs_overlap({{d_gstate_in, Q * 108}, {d_gactions, Q * 16}, {d_gparams, Q * 24}},
-                        {{d_state_in, Q * 108}, {d_actions, Q * 16},
-                         {same ? nullptr : d_gstate_out, Q * 108}}))
-      return QS_ERR_INVALID;
-  }
-  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
-  int rc = ensure_adjoint_scratch(h);
+  int rc = check_step_backward(h, d_state_in, d_actions, n_substeps, d_gstate_out, d_gstate_in,
+                               d_gactions, d_gparams);
   if (rc != QS_OK) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  convert(d_state_in, h->d_ck1, h->Q, qs::NSTATE, false, false, s);
-  convert(d_gstate_out, h->d_lam, h->Q, qs::NSTATE, false, false, s);
-  hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((6LL * h->Q + 255) / 256)), dim3(256), 0, s,
-                     h->d_gpar, 6LL * h->Q, 0.0f);
-  if (n_substeps > 0) {
-    rc = run_adjoint(h, d_actions, 1, n_substeps, 1, h->d_ck1, substep_index, nullptr, 0.f,
-                     d_gactions, s);
-    if (rc != QS_OK) return rc;
-  } else {
-    hipLaunchKernelGGL(qs::fill_kernel, dim3((unsigned)((4LL * h->Q + 255) / 256)), dim3(256), 0,
-                       s, d_gactions, 4LL * h->Q, 0.0f);
-  }
-  convert(h->d_lam, d_gstate_in, h->Q, qs::NSTATE, true, false, s);
-  convert(h->d_gpar, d_gparams, h->Q, 6, true, true, s);
-  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  rc = ensure_adjoint_scratch(h);
+  if (rc == QS_OK && n_substeps > 0)
+    rc = grow(&h->d_tape, &h->tape_cap, segment_tape_floats(h, 1, n_substeps, 1));
+  if (rc != QS_OK) return rc;
+  const AdjScratch sc{h->d_tape, h->d_lam, h->d_gpar};
+  return step_backward_run(h, sc, h->d_ck1, d_state_in, d_actions, n_substeps, substep_index,
+                           d_gstate_out, d_gstate_in, d_gactions, d_gparams, (hipStream_t)stream);
+}
+
+int qs_step_backward_noalloc(qs_handle* h, const float* d_state_in, const float* d_actions,
+                             int32_t n_substeps, uint64_t substep_index,
+                             const float* d_gstate_out, float* d_gstate_in, float* d_gactions,
+                             float* d_gparams, void* stream) {
+  int rc = check_step_backward(h, d_state_in, d_actions, n_substeps, d_gstate_out, d_gstate_in,
+                               d_gactions, d_gparams);
+  if (rc != QS_OK) return rc;
+  // parts of the fixed scratch, each rounded up to 64 floats (256 bytes)
+  auto part = [](size_t n) { return (n + 63) / 64 * 64; };
+  const size_t Q = (size_t)h->Q;
+  const size_t n_ck = part(qs::NSTATE * Q), n_lam = part(qs::NSTATE * Q), n_g = part(6 * Q);
+  const size_t n_tape = n_substeps > 0 ? part(segment_tape_floats(h, 1, n_substeps, 1)) : 0;
+  if (n_ck + n_lam + n_g + n_tape > kNoAllocScratchFloats) return QS_ERR_TOO_LARGE;
+  if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
+  float* base = nullptr;
+  rc = noalloc_scratch(h->dev, &base);
+  if (rc != QS_OK) return rc;
+  const AdjScratch sc{base + n_ck + n_lam + n_g, base + n_ck, base + n_ck + n_lam};
+  return step_backward_run(h, sc, base, d_state_in, d_actions, n_substeps, substep_index,
+                           d_gstate_out, d_gstate_in, d_gactions, d_gparams, (hipStream_t)stream);
 }
 
 const char* qs_error_string(int code) {
@@ -1130,6 +1230,8 @@ const char* qs_error_string(int code) {
     case QS_ERR_NOMEM: return "allocation failed";
     case QS_ERR_ALIGN: return "a device pointer is misaligned";
     case QS_ERR_UNSUPPORTED: return "request not supported by this build";
+    case QS_ERR_TOO_LARGE:
+      return "request exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown error code";
   }
 }

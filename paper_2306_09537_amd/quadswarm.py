@@ -19,14 +19,15 @@ LIB_PATH = os.path.join(HERE, "libquadswarm.so")
 
 QS_OK = 0
 ERRORS = {-1: "QS_ERR_NULL", -2: "QS_ERR_INVALID", -3: "QS_ERR_ENV_SIZE", -4: "QS_ERR_HIP",
-          -5: "QS_ERR_NONFINITE", -6: "QS_ERR_NOMEM", -7: "QS_ERR_ALIGN", -8: "QS_ERR_UNSUPPORTED"}
+          -5: "QS_ERR_NONFINITE", -6: "QS_ERR_NOMEM", -7: "QS_ERR_ALIGN", -8: "QS_ERR_UNSUPPORTED",
+          -9: "QS_ERR_TOO_LARGE"}
 
 # every entry point of include/quadswarm.h
 EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_substep_index", "qs_step", "qs_observe",
            "qs_step_observe", "qs_get_state", "qs_set_state", "qs_record_contacts",
            "qs_debug_contacts", "qs_sync", "qs_rollout", "qs_rollout_backward",
-           "qs_step_backward", "qs_set_graph_mode", "qs_set_launch", "qs_autotune",
-           "qs_set_reward_weights", "qs_step_observe_reward", "qs_set_params",
+           "qs_step_backward", "qs_step_backward_noalloc", "qs_set_graph_mode", "qs_set_launch",
+           "qs_autotune", "qs_set_reward_weights", "qs_step_observe_reward", "qs_set_params",
            "qs_debug_philox", "qs_error_string")
 
 
@@ -99,6 +100,7 @@ def lib() -> C.CDLL:
         L.qs_rollout.argtypes = [vp, vp, i32, i32, i32, vp, vp, f32, vp]
         L.qs_rollout_backward.argtypes = [vp, vp, i32, i32, i32, vp, u64, vp, vp, f32, vp, vp, vp]
         L.qs_step_backward.argtypes = [vp, vp, vp, i32, u64, vp, vp, vp, vp, vp]
+        L.qs_step_backward_noalloc.argtypes = [vp, vp, vp, i32, u64, vp, vp, vp, vp, vp]
         L.qs_set_graph_mode.argtypes = [vp, i32, vp]
         L.qs_autotune.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.qs_set_launch.argtypes = [vp, i32, i32]
@@ -348,6 +350,19 @@ class QuadSwarm:
                                       C.c_uint64(int(substep_index)), _ptr(gstate_out),
                                       _ptr(gstate_in), _ptr(gactions), _ptr(gparams),
                                       _stream(self._di)), "qs_step_backward")
+
+    def step_backward_noalloc(self, state_in, actions, n_substeps: int, substep_index: int,
+                              gstate_out, gstate_in, gactions, gparams) -> None:
+        """qs_step_backward_noalloc: as step_backward, with the library's
+        fixed per-device scratch instead of any device allocation."""
+        Q = self.n_quads
+        for tns, shp in ((state_in, (Q, 27)), (actions, (Q, 4)), (gstate_out, (Q, 27)),
+                         (gstate_in, (Q, 27)), (gactions, (Q, 4)), (gparams, (Q, 6))):
+            self._dev(tns, shp)
+        _check(lib().qs_step_backward_noalloc(
+            self._h, _ptr(state_in), _ptr(actions), int(n_substeps),
+            C.c_uint64(int(substep_index)), _ptr(gstate_out), _ptr(gstate_in), _ptr(gactions),
+            _ptr(gparams), _stream(self._di)), "qs_step_backward_noalloc")
 
     def set_graph_mode(self, enable: bool = True) -> None:
         _check(lib().qs_set_graph_mode(self._h, 1 if enable else 0, _stream(self._di)),
