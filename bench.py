@@ -1,16 +1,35 @@
 """Throughput benchmark of the batched quadrotor-swarm step on one MI355X.
 
-Default workload: 4096 environments x 8 quadrotors (32,768 quads), full
-physics (motor lag and noise, walls, floor, in-env collisions) and the K = 6
-nearest-neighbour observation, dt = 5 ms.  One timed "step" is one call of
-the whole hot path over the batch: ``qs_step_observe`` with ``--nsub``
-substeps (default 1: every row of the path, including the observation, runs
-once per substep), on inputs already resident in HBM.  Rollouts are the
-workload's 1000-substep episodes with a fresh action set per call; the
-state is reset to the initial state between episodes outside the timed
-region.
+Headline: 32768 environments x 32 quadrotors (1,048,576 quads), full physics
+(motor lag and noise, walls, floor, in-env collisions) and the K = 6
+nearest-neighbour observation, dt = 5 ms, domain randomisation -- the
+largest single-GPU configuration.  One timed "step" is one call of the whole
+hot path over the batch: ``qs_step_observe`` with one substep (every row of
+the path, including the observation, runs once per substep), on inputs
+already resident in HBM.  value = quad-steps/s (quads x substeps / s).
 
-Prints one JSON line.  value = quad-steps/s (quads x substeps / s).
+The same JSON line carries the other forms and workloads:
+  fused     the headline workload with 2 and 10 substeps per call;
+  fwd_bwd   the headline workload's differentiable rollout (100 substeps,
+            checkpoint every 20 calls, collision penalty) and its reverse pass;
+  scale1    1,048,576 single-quad environments (K = 0), 1 and 10 substeps;
+  swarm8    4096 x 8 (K = 6), 1 and 10 substeps;
+  batched   16384 environments of uneven sizes 1..32, a 100-call rollout of
+            10-substep calls replayed from a captured graph;
+  diff      1024 x 8 differentiable rollout of 200 substeps;
+  cpu_baseline  the FP64 oracle on the host cores, on a sample of the
+            headline workload (median of 3, all cores and one core).
+
+Rooflines: a one-substep launch moves ~340-484 B per quad for ~250-670
+arithmetic operations, so it is bound by HBM (8 TB/s); its ``achieved`` is
+algorithmic bytes per launch over the event-timed launch duration.  The
+multi-substep forms re-use the state in registers and are bound by the
+vector ALUs; their ``achieved`` is the algorithmic FP operations of the
+method per second -- counted by the op-counting build of the FP64 oracle
+(profiles/alg_flops.md) -- against the FP32 vector peak of 157.3 TFLOP/s.
+Counter-measured HBM bytes and VALU instruction counts come from the
+committed rocprofv3 summaries and are reported only while the kernel
+sources still hash to the value they were taken at.
 """
 from __future__ import annotations
 
@@ -27,35 +46,43 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# VALU roofline: 256 CUs x 4 SIMDs at 2.4 GHz = 2457.6 G SIMD-cycles/s.  A
-# kernel's VALU busy cycles come from its rocprofv3 counters with per-kind
-# issue costs measured on the chip (calib/valu_probe): a wave64 FP32 add,
-# multiply or FMA occupies a SIMD for 4 cycles, integer and bitwise
-# instructions for 2 to 4, a transcendental 8 alone but it can overlap other
-# VALU work.  Lower bound: 4 x (ADD + MUL + FMA) + 2 x every other
-# non-transcendental VALU instruction; upper bound: 4 x SQ_ACTIVE_INST_VALU
-# (one quad-cycle per instruction, two per transcendental).  The lower bound
-# is reported as the fraction.
-SIMD_GCYCLES_PER_S = 256 * 4 * 2.4
-FP32_PEAK_TFLOPS = 157.3       # FP32 vector peak (packed FMA)
-# committed counter summaries of the ten-substep form, per workload
-VALU_PROFILES = {"swarm8": ("step_pipe_kernel_swarm4096x8_fused10.md", ""),
-                 "scale32": ("scale_workloads.md", "scale32_")}
-# ... and of the differentiable rollout and its backward pass
-FWDBWD_PROFILES = {"diff_1024x8": ("rollout_reverse_diff1024x8.md", ""),
-                   "scale_32768x32": ("scale_workloads.md", "scale32_")}
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector peak (256 CUs x 128 lanes x 2 x 2.4 GHz)
+SIMD_GCYCLES_PER_S = 256 * 4 * 2.4   # VALU issue slots: 1024 SIMDs at 2.4 GHz
+METRIC = "quad-steps/s fwd and fwd+bwd at 1 MI355X; % of HBM/VALU roofline"
 KERNEL_SOURCES = tuple(f"paper_2306_09537_amd/csrc/{f}" for f in
                        ("qs_device.h", "qs_kernels.h", "qs_rollout.h", "qs_adjoint.h"))
 STATE_B, PARAM_B, ACT_B, GOAL_B = 108, 24, 16, 12
+ALG_FLOPS = "alg_flops.md"
+# committed rocprofv3 summary per workload (kernel trace, HBM and VALU counters)
+PROFILES = {"scale32": "step_kernel_scale32768x32.md",
+            "scale1": "step_kernel_scale1048576x1.md",
+            "swarm8": "step_kernel_swarm4096x8.md",
+            "uneven": "bucket_kernel_uneven16384.md",
+            "scale32_fwdbwd": "rollout_reverse_scale32768x32.md",
+            "diff_fwdbwd": "rollout_reverse_diff1024x8.md"}
+WORKLOAD_KEYS = {"plain_64x1": "plain", "swarm_4096x8": "swarm8", "uneven_16384": "uneven",
+                 "diff_1024x8": "diff", "scale_32768x32": "scale32",
+                 "scale_1048576x1": "scale1"}
 
 
 def algorithmic_bytes_per_quad(k: int, nsub: int, with_obs: bool = True) -> int:
     """Bytes one call must move per quad: state in and out, parameters,
-    action, and (with the observation) goal and obs row."""
+    action, and (with the observation) goal and obs row.  Independent of
+    the number of substeps: the state stays in registers between them."""
     b = 2 * STATE_B + PARAM_B + ACT_B
     if with_obs:
         b += GOAL_B + 4 * (18 + 6 * k)
     return b
+
+
+def backward_bytes(Q: int, horizon: int, nsub: int, ckpt_every: int) -> int:
+    """Algorithmic bytes of one reverse pass: per quad-substep the tape
+    written and read (2 x 124: state and motor-noise draws), the actions read
+    twice (recompute and sweep) and the action gradient written; per segment
+    its checkpoint and the parameters (read by the recompute); once the
+    state adjoint in and out and the parameters and their gradient."""
+    n_seg = (horizon + ckpt_every - 1) // ckpt_every
+    return Q * horizon * nsub * (248 + 32 + 16) + Q * n_seg * (108 + 24) + Q * (216 + 80)
 
 
 def kernel_source_hash() -> str:
@@ -67,86 +94,98 @@ def kernel_source_hash() -> str:
     return m.hexdigest()[:16]
 
 
-def measured_counter(profile: str, key: str):
-    """A per-launch counter value ("key: value" line) from a committed
-    rocprofv3 summary, or None if the kernel source changed since the
-    counters were taken."""
-    path = os.path.join(ROOT, "profiles", profile)
+def profile_value(profile: str, key: str, need_hash: bool = True):
+    """A "key: value" number from a committed summary under profiles/, or
+    None (missing, or -- for counters -- taken on other kernel sources)."""
     try:
-        text = open(path).read()
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
     except OSError:
         return None
-    if kernel_source_hash() not in text:
+    if need_hash and kernel_source_hash() not in text:
         return None
     for line in text.splitlines():
+        line = line.strip()
         if line.startswith(key + ":"):
-            return int(line.split(":")[1])
+            v = line.split(":", 1)[1].strip()
+            return float(v) if any(c in v for c in ".eE") else int(v)
     return None
 
 
-def measured_traffic(profile: str):
-    """HBM bytes per launch from the committed counter summary."""
-    return measured_counter(profile, "traffic_bytes_per_launch")
-
-
-# committed counter summaries of the one-substep launch, per workload
-TRAFFIC_PROFILES = {"swarm8": ("step_kernel_swarm4096x8_plain.md", "traffic_bytes_per_launch"),
-                    "scale32": ("scale_workloads.md", "scale32_traffic_bytes_per_launch"),
-                    "scale1": ("scale_workloads.md", "scale1_traffic_bytes_per_launch")}
-
-
-def launch_traffic(workload: str, nsub: int):
-    """Counter-measured HBM bytes of the timed launch, where committed (one
-    substep per call) and taken on the current kernel sources."""
-    if nsub != 1 or workload not in TRAFFIC_PROFILES:
+def alg_flops(workload_name: str, what: str):
+    """Algorithmic FP operations per unit (per quad-substep for step,
+    rollout and fwdbwd; per quad for observe) from the op-counting oracle."""
+    key = WORKLOAD_KEYS.get(workload_name)
+    if key is None:
         return None
-    return measured_counter(*TRAFFIC_PROFILES[workload])
+    return profile_value(ALG_FLOPS, f"{key}_{what}_flops", need_hash=False)
 
 
-def alu_roofline(prof: str, key: str, ms: float):
-    """ALU roofline of a kernel (or kernel sequence) from the committed
-    counters under ``key``: VALU busy SIMD-cycles per second (lower bound)
-    against the chip's SIMD-cycles per second, the upper-bound fraction,
-    and FP32 FLOP/s against the vector peak.  None without counters."""
-    lo = measured_counter(prof, key + "valu_busy_lo_cycles")
-    hi = measured_counter(prof, key + "valu_busy_hi_cycles")
-    flops = measured_counter(prof, key + "fp32_flops")
-    if lo is None or hi is None or flops is None:
+def call_flops(w, nsub: int, with_obs: bool = True):
+    """Algorithmic FP operations of one call over the whole batch."""
+    st = alg_flops(w.name, "step")
+    ob = alg_flops(w.name, "observe") if with_obs else 0.0
+    if st is None or ob is None:
+        return None
+    return w.n_quads * (nsub * st + ob)
+
+
+def hbm_roofline(bytes_per_launch: int, ms: float, traffic=None, **extra) -> dict:
+    ach = bytes_per_launch / (ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+           "traffic_achieved": traffic / (ms * 1e-3) / 1e9 if traffic else None,
+           "traffic_frac": traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+           "bytes_per_launch": bytes_per_launch}
+    out.update(extra)
+    return out
+
+
+def alu_roofline(flops, ms: float, profile=None, prefix: str = "", **extra):
+    """Algorithmic FLOP/s against the FP32 vector peak; with the committed
+    VALU counters of the same launch (if current), the kernel's instruction
+    mix per algorithmic operation and its VALU issue utilisation as
+    diagnostics."""
+    if flops is None:
         return None
     s = ms * 1e-3
-    ach = lo / s / 1e9
-    tflops = flops / s / 1e12
-    return {"bound": "alu", "achieved": ach, "peak": SIMD_GCYCLES_PER_S,
-            "unit": "G SIMD-cycles/s (VALU busy, lower bound)", "frac": ach / SIMD_GCYCLES_PER_S,
-            "frac_upper": hi / s / 1e9 / SIMD_GCYCLES_PER_S, "traffic": None,
-            "fp32_tflops": tflops, "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS,
-            "valu_busy_cycles": [lo, hi], "fp32_flops": flops, "profile": prof}
-
-
-def valu_roofline(workload: str, nsub: int, ms: float):
-    """ALU roofline of the ten-substep launch of a workload."""
-    if nsub != 10 or workload not in VALU_PROFILES:
-        return None
-    prof, pre = VALU_PROFILES[workload]
-    return alu_roofline(prof, pre + "fused10_", ms)
+    tf = flops / s / 1e12
+    out = {"bound": "alu", "achieved": tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": tf / FP32_PEAK_TFLOPS, "traffic": None, "alg_flops_per_call": flops}
+    if profile:
+        valu = profile_value(profile, prefix + "valu_insts")
+        fp32 = profile_value(profile, prefix + "fp32_valu_insts")
+        act = profile_value(profile, prefix + "active_inst_valu")
+        traffic = profile_value(profile, prefix + "traffic_bytes")
+        if traffic:
+            out["traffic"] = traffic
+        if valu:
+            # wave64 instructions: 64 lane operations each
+            out["valu_lane_ops_per_alg_flop"] = valu * 64 / flops
+            out["fp32_lane_ops_per_alg_flop"] = (fp32 or 0) * 64 / flops
+        if act:
+            # SQ_ACTIVE_INST_VALU counts 4 cycles per instruction issued
+            out["valu_issue_util"] = act * 4 / (s * SIMD_GCYCLES_PER_S * 1e9)
+    out.update(extra)
+    return out
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="swarm8",
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="scale32",
                     choices=["swarm8", "plain", "uneven", "diff", "scale32", "scale1"])
     ap.add_argument("--nsub", type=int, default=1, help="substeps per call")
     ap.add_argument("--extra-nsub", default="2,10",
                     help="also time these fused substep counts (comma list, '' for none)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target length of the oracle CPU-baseline sample")
+    ap.add_argument("--legs", default="fwd_bwd,scale1,swarm8,batched,diff",
+                    help="extra legs (comma list of fwd_bwd, scale1, swarm8, batched, diff; "
+                         "'' for none)")
+    ap.add_argument("--fwdbwd-horizon", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=3.0,
+                    help="length of each oracle CPU-baseline run")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--fwdbwd", default="diff", help="workload of the fwd+bwd leg ('' to skip)")
-    ap.add_argument("--fwdbwd-horizon", type=int, default=200)
-    ap.add_argument("--batched", default="uneven", help="workload of the batched leg ('' to skip)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the FP64 oracle on samples of every configuration "
                          "(host cores, no GPU) and exit")
@@ -204,6 +243,43 @@ def time_calls(sim, w, acts, goals, obs, nsub, steps, warmup, torch, episode=100
     return total_ms / steps, wall * 1e3 / steps
 
 
+def step_leg(w, torch, nsubs, steps: int, warmup: int, plain_value=None):
+    """One workload at several substep counts per call: value, ms per call,
+    and the roofline of each form (HBM for one substep, ALU otherwise)."""
+    from paper_2306_09537_amd.quadswarm import QuadSwarm
+    key = WORKLOAD_KEYS.get(w.name)
+    prof = PROFILES.get(key)
+    Q = w.n_quads
+    goals = torch.from_numpy(w.goals).cuda()
+    obs = torch.empty((Q, w.obs_dim), device="cuda")
+    out = {}
+    for ns in nsubs:
+        n_steps = max(steps // ns, 10) if ns > 1 else steps
+        n_warm = max(warmup // ns, 3) if ns > 1 else warmup
+        acts = torch.from_numpy(w.action_sequence(min(n_steps + n_warm, 64))).cuda()
+        sim = QuadSwarm.from_workload(w)
+        ms, wall = time_calls(sim, w, acts, goals, obs, ns, n_steps, n_warm, torch, w.substeps)
+        sim.close()
+        del acts
+        v = Q * ns / (ms * 1e-3)
+        r = {"value": v, "ms_per_call": ms, "host_ms_per_call": wall, "substeps_per_call": ns}
+        flops = call_flops(w, ns)
+        if ns == 1:
+            plain_value = v
+            bpq = algorithmic_bytes_per_quad(w.k_neighbors, ns)
+            r["roofline"] = hbm_roofline(
+                bpq * Q, ms, profile_value(prof, "plain_traffic_bytes") if prof else None,
+                kernel="step_kernel (fused step + observe)", kernel_ms=ms, bytes_per_quad=bpq,
+                alg_flops_per_call=flops,
+                alg_tflops=flops / (ms * 1e-3) / 1e12 if flops else None)
+        else:
+            r["roofline"] = alu_roofline(flops, ms, prof, f"fused{ns}_")
+            if plain_value:
+                r["speedup_vs_plain"] = v / plain_value
+        out[f"nsub{ns}"] = r
+    return out
+
+
 def time_fwd_bwd(w, torch, horizon: int, nsub: int, ckpt_every: int, reps: int, beta=100.0):
     """Differentiable rollout of ``horizon`` calls (checkpoints every
     ``ckpt_every`` calls, smoothed collision penalty) and its reverse pass,
@@ -241,50 +317,28 @@ def time_fwd_bwd(w, torch, horizon: int, nsub: int, ckpt_every: int, reps: int, 
             bwd.append(e[1].elapsed_time(e[2]))
     sim.sync()
     sim.close()
+    del acts, gact, ckpt
     f, b = float(np.median(fwd)), float(np.median(bwd))
     steps = Q * horizon * nsub
-    # algorithmic bytes of the backward pass per quad-substep: tape write and
-    # read (2 x 124: the state and the motor-noise draws), actions read twice
-    # (2 x 16), action gradient (16); per
-    # segment: its checkpoint and the parameters, read by the recompute
-    # (108 + 24); once: adjoint in/out (216), parameters and their gradient
-    # in the reverse sweep (32 + 48)
-    seg = ckpt_every * nsub
-    n_seg = (horizon + ckpt_every - 1) // ckpt_every
-    bwd_bytes = Q * horizon * nsub * (248 + 32 + 16) + Q * n_seg * (108 + 24) + Q * (216 + 80)
-    return dict(workload=w.name, quads=Q, horizon_substeps=horizon * nsub, ckpt_every=ckpt_every,
-                value=steps / ((f + b) * 1e-3), unit="quad-steps/s (fwd+bwd)",
-                fwd_ms=f, bwd_ms=b, fwd_value=steps / (f * 1e-3),
-                bwd_roofline={"bound": "hbm", "achieved": bwd_bytes / (b * 1e-3) / 1e9,
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": bwd_bytes / (b * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "traffic": fwdbwd_counter(w.name, horizon,
-                                                        "backward_traffic_bytes"),
-                              "bytes": bwd_bytes, "segment_substeps": seg},
-                fwd_alu=fwdbwd_alu(w.name, horizon, "rollout_", f),
-                bwd_alu=fwdbwd_alu(w.name, horizon, "backward_", b))
-
-
-def fwdbwd_alu(name: str, horizon: int, part: str, ms: float):
-    """ALU roofline of the rollout or of the backward pass (recompute and
-    reverse sweeps together) at the horizon the counters were taken at."""
-    if name not in FWDBWD_PROFILES:
-        return None
-    prof, pre = FWDBWD_PROFILES[name]
-    if measured_counter(prof, pre + "fwdbwd_horizon") != horizon:
-        return None
-    return alu_roofline(prof, pre + part, ms)
-
-
-def fwdbwd_counter(name: str, horizon: int, key: str):
-    """A committed counter value of the fwd+bwd leg (e.g. the backward pass's
-    HBM bytes), only at the horizon it was taken at."""
-    if name not in FWDBWD_PROFILES:
-        return None
-    prof, pre = FWDBWD_PROFILES[name]
-    if measured_counter(prof, pre + "fwdbwd_horizon") != horizon:
-        return None
-    return measured_counter(prof, pre + key)
+    key = WORKLOAD_KEYS.get(w.name)
+    prof = PROFILES.get(f"{key}_fwdbwd")
+    fb = alg_flops(w.name, "fwdbwd")
+    ro = alg_flops(w.name, "rollout")
+    bb = backward_bytes(Q, horizon, nsub, ckpt_every)
+    h_ok = prof is not None and profile_value(prof, "fwdbwd_horizon") == horizon
+    return dict(
+        workload=w.name, quads=Q, horizon_substeps=horizon * nsub, ckpt_every=ckpt_every,
+        value=steps / ((f + b) * 1e-3), unit="quad-steps/s (fwd+bwd)",
+        fwd_ms=f, bwd_ms=b, fwd_value=steps / (f * 1e-3),
+        roofline=alu_roofline(fb * steps if fb else None, f + b,
+                              prof if h_ok else None, "fwdbwd_",
+                              note="algorithmic operations of the forward and its "
+                                   "derivative over forward + backward time"),
+        fwd_roofline=alu_roofline(ro * steps if ro else None, f, prof if h_ok else None,
+                                  "rollout_"),
+        bwd_roofline=hbm_roofline(
+            bb, b, profile_value(prof, "backward_traffic_bytes") if h_ok else None,
+            segment_substeps=ckpt_every * nsub))
 
 
 def sticky_nonfinite(sim, torch) -> int:
@@ -339,45 +393,88 @@ def time_batched(w, torch, calls: int = 100, nsub: int = 10, reps: int = 3):
     plain_ms, _ = time_calls(sim, w, acts, goals, obs[0], 1, 500, 20, torch, w.substeps)
     plain = Q / (plain_ms * 1e-3)
     sim.close()
-    out = dict(workload=w.name, quads=Q, envs=w.n_envs, calls=calls, substeps_per_call=nsub,
-               value=value, unit="quad-steps/s", ms_per_rollout=ms, autotune=choice,
-               nonfinite_quads=nonfinite,
-               form="persistent bucketed launch, 10 substeps per call, 100-call rollout "
-                    "replayed as one captured graph",
-               plain_value=plain, speedup_vs_plain=value / plain)
-    # ALU roofline of one 10-substep call (counters of the autotuned launch)
-    if (w.name, calls, nsub) == ("uneven_16384", 100, 10):
-        rl = alu_roofline("bucket_kernel_uneven16384.md",
-                          f"batched_b{choice['block']}_", ms / calls)
-        if rl is not None:
-            out["roofline"] = rl
-    return out
+    key = WORKLOAD_KEYS.get(w.name)
+    return dict(workload=w.name, quads=Q, envs=w.n_envs, calls=calls, substeps_per_call=nsub,
+                value=value, unit="quad-steps/s", ms_per_rollout=ms, autotune=choice,
+                nonfinite_quads=nonfinite,
+                form="persistent bucketed launch, 10 substeps per call, 100-call rollout "
+                     "replayed as one captured graph",
+                plain_value=plain, speedup_vs_plain=value / plain,
+                plain_roofline=hbm_roofline(algorithmic_bytes_per_quad(w.k_neighbors, 1) * Q,
+                                            plain_ms),
+                roofline=alu_roofline(call_flops(w, nsub), ms / calls, PROFILES.get(key),
+                                      "fused10_"))
 
 
-def cpu_baseline(w, target_s: float):
-    """The FP64 oracle on the host cores: step + observe per substep over a
-    bounded number of substeps of the same workload."""
+def _omp():
+    """The OpenMP runtime the oracle links (thread count control)."""
+    import ctypes
     from oracle import oracle as O
-    orc = O.Oracle.from_workload(w)
-    s0 = w.state0.astype(np.float64)
-    s = s0
-    g = w.goals.astype(np.float64)
-    acts = [w.actions(i).astype(np.float64) for i in range(100)]
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        if n and n % 1000 == 0:
-            s = s0  # episode reset, as on the GPU
-        s, _, _ = orc.step(s, acts[n % 100], 1, n)
-        orc.observe(s, g)
-        n += 1
-        if time.perf_counter() - t0 >= target_s:
-            break
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=w.n_quads * n / dt, unit="quad-steps/s", cores=cores, kind="oracle",
-                sample=f"{w.name}: {n} substeps x {w.n_quads} quads (step + K-NN observe per "
-                       f"substep), FP64, {dt:.1f} s")
+    O.lib()  # loads libgomp with the oracle
+    try:
+        return ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, seconds: float, n_envs: int = 4096, runs: int = 3):
+    """The FP64 oracle on the host cores: step + K-NN observe per substep
+    on the first ``n_envs`` environments of the workload, each run bounded
+    to ``seconds``; median of ``runs`` runs with every host core the
+    process may use and with one core."""
+    from oracle import oracle as O
+    e1 = min(n_envs, w.n_envs)
+    orc = O.Oracle.from_workload(w, 0, e1)
+    q = int(w.env_offsets[e1])
+    s0 = w.state0[:q].astype(np.float64)
+    g = w.goals[:q].astype(np.float64)
+    acts = [np.ascontiguousarray(w.actions(i)[:q], dtype=np.float64) for i in range(10)]
+
+    def one_run():
+        s = s0
+        n = 0
+        t0 = time.perf_counter()
+        while n == 0 or time.perf_counter() - t0 < seconds:
+            if n and n % w.substeps == 0:
+                s = s0  # episode reset, as on the GPU
+            s, _, _ = orc.step(s, acts[n % 10], 1, n)
+            orc.observe(s, g)
+            n += 1
+        dt = time.perf_counter() - t0
+        return q * n / dt, n, dt
+
+    omp = _omp()
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    all_threads = omp.omp_get_max_threads() if omp else avail
+    res = {}
+    for label, nthr in (("all", all_threads), ("one", 1)):
+        if omp:
+            omp.omp_set_num_threads(int(nthr))
+        rr = [one_run() for _ in range(runs)]
+        res[label] = (float(np.median([r[0] for r in rr])), [r[0] for r in rr],
+                      int(np.median([r[1] for r in rr])))
+    if omp:
+        omp.omp_set_num_threads(int(all_threads))
+    v, vals, n = res["all"]
+    v1, vals1, n1 = res["one"]
+    return dict(value=v, unit="quad-steps/s", cores=int(all_threads), kind="oracle",
+                sample=f"{w.name}: first {e1} envs ({q} quads), step + K-NN observe per substep, "
+                       f"FP64, {runs} runs of {seconds:.0f} s each (median; ~{n} substeps per run "
+                       f"on all cores, ~{n1} on one)",
+                runs=vals, per_core=v / max(1, all_threads),
+                one_core={"value": v1, "runs": vals1, "cores": 1},
+                cpu_model=cpu_model(), host_cpus_available=avail,
+                omp_proc_bind=os.environ.get("OMP_PROC_BIND", ""))
 
 
 def cpu_table(seconds: float = 3.0) -> dict:
@@ -425,9 +522,10 @@ def cpu_table(seconds: float = 3.0) -> dict:
         "diff_1024x8 fwd+bwd": fwd_bwd(W.diff(seed=0), 1024, 200),
         "scale_32768x32 fwd+bwd": fwd_bwd(W.scale32(seed=0), 512, 100),
     }
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    omp = _omp()
+    cores = omp.omp_get_max_threads() if omp else (os.cpu_count() or 1)
     return {"cpu_table": rows, "unit": "quad-steps/s", "cores": cores, "kind": "oracle",
-            "precision": "f64"}
+            "precision": "f64", "cpu_model": cpu_model()}
 
 
 def main():
@@ -453,44 +551,22 @@ def main():
         return
 
     from paper_2306_09537_amd import workloads as W
-    from paper_2306_09537_amd.quadswarm import QuadSwarm
 
     torch.cuda.set_device(0)
     w = W.WORKLOADS[args.workload](seed=0)
-    sim = QuadSwarm.from_workload(w)
-    n_act = args.steps + args.warmup
-    acts = torch.from_numpy(w.action_sequence(n_act)).cuda()  # a fresh action set per call
-    goals = torch.from_numpy(w.goals).cuda()
-    obs = torch.empty((w.n_quads, w.obs_dim), device="cuda")
-
-    ms, wall_ms = time_calls(sim, w, acts, goals, obs, args.nsub, args.steps,
-                             args.warmup, torch, w.substeps)
-    kern_ms = ms
+    extra = [int(x) for x in args.extra_nsub.split(",") if x.strip() and int(x) != args.nsub]
+    head = step_leg(w, torch, [args.nsub], args.steps, args.warmup)[f"nsub{args.nsub}"]
+    fused = step_leg(w, torch, extra, args.steps, args.warmup, plain_value=head["value"]) \
+        if extra else {}
     Q = w.n_quads
-    value = Q * args.nsub / (ms * 1e-3)
-    bpq = algorithmic_bytes_per_quad(w.k_neighbors, args.nsub)
-    launch_bytes = bpq * Q
-    achieved = launch_bytes / (kern_ms * 1e-3) / 1e9
-
-    extra = {}
-    for ns in [int(x) for x in args.extra_nsub.split(",") if x.strip()]:
-        if ns == args.nsub:
-            continue
-        sim2 = QuadSwarm.from_workload(w)
-        m2, _ = time_calls(sim2, w, acts, goals, obs, ns, max(args.steps // ns, 20),
-                           max(args.warmup // ns, 5), torch, w.substeps)
-        sim2.close()
-        extra[f"fused_nsub{ns}"] = dict(
-            value=Q * ns / (m2 * 1e-3), ms_per_call=m2,
-            speedup_vs_plain=(Q * ns / (m2 * 1e-3)) / value)
-        rl = valu_roofline(args.workload, ns, m2)
-        if rl is not None:
-            extra[f"fused_nsub{ns}"]["roofline"] = rl
-
-    traffic = launch_traffic(args.workload, args.nsub)
+    ms = head["ms_per_call"]
+    roof = head["roofline"]
+    if args.nsub != 1:  # a multi-substep headline is priced on the ALUs
+        roof = alu_roofline(call_flops(w, args.nsub), ms, PROFILES.get(WORKLOAD_KEYS[w.name]),
+                            f"fused{args.nsub}_")
     line = {
-        "metric": "quad-steps/s fwd at 1 MI355X (% of HBM roofline)",
-        "value": value,
+        "metric": METRIC,
+        "value": head["value"],
         "unit": "quad-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -500,32 +576,34 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded: domain-randomised params, random initial states, U[0,1] actions)",
+        "data": "synthetic (seeded: domain-randomised params, random initial states, "
+                "U[0,1] actions)",
         "config": {"workload": w.name, "envs": w.n_envs, "quads": Q,
                    "k_neighbors": w.k_neighbors, "substeps_per_call": args.nsub,
                    "dt": w.consts["dt"], "entry": "qs_step_observe"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     # the counters' bytes over the same launch time: below the
-                     # algorithmic rate where data stays in the 256 MB cache
-                     "traffic_achieved": (traffic / (kern_ms * 1e-3) / 1e9
-                                          if traffic else None),
-                     "traffic_frac": (traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-                                      if traffic else None),
-                     "kernel": "step_kernel (fused step + observe)",
-                     "kernel_ms": kern_ms, "bytes_per_launch": launch_bytes,
-                     "bytes_per_quad": bpq},
-        "host_ms_per_step": wall_ms,
-        "fused": extra,
+        "roofline": roof,
+        "host_ms_per_step": head["host_ms_per_call"],
+        "fused": fused,
     }
-    if args.fwdbwd:
-        wd = W.WORKLOADS[args.fwdbwd](seed=0)
-        line["fwd_bwd"] = time_fwd_bwd(wd, torch, args.fwdbwd_horizon, 1, 20, 3)
-    if args.batched:
-        line["batched"] = time_batched(W.WORKLOADS[args.batched](seed=0), torch)
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    if "fwd_bwd" in legs:
+        line["fwd_bwd"] = time_fwd_bwd(w, torch, args.fwdbwd_horizon, 1, 20, 3)
+        torch.cuda.empty_cache()
+    if "scale1" in legs and w.name != "scale_1048576x1":
+        line["scale1"] = dict(workload="scale_1048576x1",
+                              **step_leg(W.scale1(seed=0), torch, [1, 10], args.steps,
+                                         args.warmup))
+        torch.cuda.empty_cache()
+    if "swarm8" in legs and w.name != "swarm_4096x8":
+        line["swarm8"] = dict(workload="swarm_4096x8",
+                              **step_leg(W.swarm8(seed=0), torch, [1, 2, 10],
+                                         max(args.steps, 200), args.warmup))
+    if "batched" in legs:
+        line["batched"] = time_batched(W.uneven(seed=0), torch)
+    if "diff" in legs:
+        line["diff"] = time_fwd_bwd(W.diff(seed=0), torch, 200, 1, 20, 3)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
-    sim.close()
     print(json.dumps(line), flush=True)
 
 

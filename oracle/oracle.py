@@ -41,6 +41,39 @@ def build(force: bool = False) -> str:
     return LIB
 
 
+OPCOUNT_SRC = os.path.join(HERE, "opcount.cpp")
+OPCOUNT_LIB = os.path.join(HERE, "liboracle_opcount.so")
+
+
+def build_opcount(force: bool = False) -> str:
+    """Compile the op-counting build of the oracle (``opcount.cpp``, which
+    includes the oracle's source) into ``liboracle_opcount.so``: single
+    threaded, same IEEE double arithmetic, plus or_opcount_reset/get."""
+    newest = max(os.path.getmtime(SRC), os.path.getmtime(OPCOUNT_SRC))
+    if force or not os.path.exists(OPCOUNT_LIB) or os.path.getmtime(OPCOUNT_LIB) < newest:
+        tmp = OPCOUNT_LIB + ".tmp"
+        subprocess.check_call([
+            "g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+            "-fno-fast-math", "-Wall", "-Wno-unused-parameter", "-Wno-class-memaccess",
+            "-Wno-narrowing", "-Wno-unknown-pragmas", OPCOUNT_SRC, "-o", tmp])
+        os.replace(tmp, OPCOUNT_LIB)
+    return OPCOUNT_LIB
+
+
+def opcount_reset() -> None:
+    """Zero the counters (op-counting build loaded through QS_ORACLE_LIB)."""
+    lib().or_opcount_reset()
+
+
+def opcount_get() -> dict:
+    """Counters of the op-counting build since the last reset."""
+    o = (C.c_uint64 * 5)()
+    lib().or_opcount_get(o)
+    add, mul, div, sqrt, trans = (int(v) for v in o)
+    return dict(add=add, mul=mul, div=div, sqrt=sqrt, trans=trans,
+                total=add + mul + div + sqrt + trans)
+
+
 class _Desc(C.Structure):
     _fields_ = [
         ("n_envs", C.c_int32), ("env_offsets", C.POINTER(C.c_int32)),

@@ -164,6 +164,19 @@ static void upd_margin(double* mg, double v) {
   if (v < *mg) *mg = v;
 }
 
+/* Markers for the op-counting build (oracle/opcount.cpp), which defines them
+ * to leave what they wrap out of its count; here they are plain.
+ * OR_MARGIN: a threshold-margin update (diagnostic output, not the method).
+ * OR_CONST: a constant derived from a quad's parameters or the global
+ * constants (f_max, alpha_lag, ...), which this plain oracle recomputes on
+ * every substep although it is fixed for the quad. */
+#ifndef OR_MARGIN
+#define OR_MARGIN(mg, v) upd_margin(mg, v)
+#endif
+#ifndef OR_CONST
+#define OR_CONST(x) (x)
+#endif
+
 /* Intermediates of one substep of one quad, kept for the reverse sweep. */
 typedef struct {
   double uhat[4], u0[4], e0[4], z[4], u1[4], f[4];
@@ -190,11 +203,11 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
   memset(r, 0, sizeof(*r));
   const double dt = d->dt, g = d->gravity;
   const double m = p[PM], jx = p[PJX], jy = p[PJY], jz = p[PJZ];
-  const double f_max = 0.25 * m * g * p[PT2W];              /* §III-A.2 */
-  const double alpha_lag = 1.0 - exp(-dt / p[PTAU]);          /* §III-A.1 */
+  const double f_max = OR_CONST(0.25 * m * g * p[PT2W]);     /* §III-A.2 */
+  const double alpha_lag = OR_CONST(1.0 - exp(-dt / p[PTAU])); /* §III-A.1 */
   const double a_nd = d->motor_noise_decay;
-  const double a_ns = d->motor_noise_std * f_max * sqrt(1.0 - a_nd * a_nd);
-  const double arm_d = d->arm_length / sqrt(2.0);
+  const double a_ns = OR_CONST(d->motor_noise_std * f_max * sqrt(1.0 - a_nd * a_nd));
+  const double arm_d = OR_CONST(d->arm_length / sqrt(2.0));
 
   /* §III-A.1: normalised thrust command, then rotor speed command */
   double uhat[4];
@@ -252,7 +265,7 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
 
   int friction = (d->flags & OR_FLOOR) && s[IF] != 0.0 && F[2] <= m * g;
   r->rest = friction;
-  if ((d->flags & OR_FLOOR) && s[IF] != 0.0) upd_margin(mg, (F[2] - m * g) / (m * g));
+  if ((d->flags & OR_FLOOR) && s[IF] != 0.0) OR_MARGIN(mg, (F[2] - m * g) / (m * g));
   if (!friction) {
     if (s[IF] != 0.0) *ev |= EV_TAKEOFF;
     s[IF] = 0.0;
@@ -341,7 +354,7 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     v[2] = 0.0;
     double dot = v[0] * vxy0[0] + v[1] * vxy0[1];
     if (vxy0[0] != 0.0 || vxy0[1] != 0.0)
-      upd_margin(mg, dot / (vxy0[0] * vxy0[0] + vxy0[1] * vxy0[1]));
+      OR_MARGIN(mg, dot / (vxy0[0] * vxy0[0] + vxy0[1] * vxy0[1]));
     if (dot < 0.0) { v[0] = 0.0; v[1] = 0.0; r->guard = 1; }
     for (int k = 0; k < 3; ++k) x[k] += dt * v[k];
     w[0] = w[1] = w[2] = 0.0;
@@ -352,8 +365,8 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
     int bounced = 0;
     const double e = d->wall_restitution;
     for (int k = 0; k < 3; ++k) {
-      if (k < 2) upd_margin(mg, x[k] - d->room_min[k]);
-      upd_margin(mg, x[k] - d->room_max[k]);
+      if (k < 2) OR_MARGIN(mg, x[k] - d->room_min[k]);
+      OR_MARGIN(mg, x[k] - d->room_max[k]);
       if (k < 2 && x[k] < d->room_min[k]) {
         x[k] = d->room_min[k];
         r->clamp[k] = 1;
@@ -382,7 +395,7 @@ static void quad_substep(const or_desc* d, const double* p, double* s,
   }
 
   /* §III-B.3: floor hit */
-  if ((d->flags & OR_FLOOR) && s[IF] == 0.0) upd_margin(mg, x[2] - d->room_min[2]);
+  if ((d->flags & OR_FLOOR) && s[IF] == 0.0) OR_MARGIN(mg, x[2] - d->room_min[2]);
   if ((d->flags & OR_FLOOR) && x[2] < d->room_min[2]) {
     *ev |= EV_FLOOR_HIT;
     x[2] = d->room_min[2];
@@ -432,16 +445,15 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
   int marked[64];
   memset(dv, 0, sizeof(dv));
   memset(marked, 0, sizeof(marked));
-  const double dc2 = d->col_dist * d->col_dist;
+  const double dc2 = OR_CONST(d->col_dist * d->col_dist);
   for (int i = 0; i < n; ++i) {
     const double* si = S + (size_t)(q0 + i) * NS;
     for (int j = i + 1; j < n; ++j) {
       const double* sj = S + (size_t)(q0 + j) * NS;
       double dx[3] = {si[IX] - sj[IX], si[IX + 1] - sj[IX + 1], si[IX + 2] - sj[IX + 2]};
       double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
-      double dm = sqrt(d2) - d->col_dist;
-      upd_margin(&mg[q0 + i], dm);
-      upd_margin(&mg[q0 + j], dm);
+      OR_MARGIN(&mg[q0 + i], sqrt(d2) - d->col_dist);
+      OR_MARGIN(&mg[q0 + j], sqrt(d2) - d->col_dist);
       if (pen) {
         double h = 0.5 * softplus(beta * (d->col_dist - sqrt(d2))) / beta;
         pen[q0 + i] += h;
@@ -464,8 +476,8 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
       double sp = 0.0;
       for (int k = 0; k < 3; ++k) sp += (sj[IV + k] - si[IV + k]) * nrm[k];
       if (d->flags & OR_APPROACH_ONLY) {
-        upd_margin(&mg[q0 + i], sp);
-        upd_margin(&mg[q0 + j], sp);
+        OR_MARGIN(&mg[q0 + i], sp);
+        OR_MARGIN(&mg[q0 + j], sp);
       }
       if ((d->flags & OR_APPROACH_ONLY) && !(sp > 0.0)) continue;
       for (int k = 0; k < 3; ++k) {
@@ -482,6 +494,7 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
   memset(adw, 0, sizeof(adw));
   memset(dwhit, 0, sizeof(dwhit));
   if (d->flags & OR_DOWNWASH) {
+    const double dw_r2 = OR_CONST(d->dw_radius * d->dw_radius);
     for (int i = 0; i < n; ++i) {
       const double* si = S + (size_t)(q0 + i) * NS;
       if (si[IF] != 0.0) continue; /* resting on the floor */
@@ -489,10 +502,10 @@ static void env_pairs(const or_desc* d, double* S, int q0, int n, uint64_t t,
         if (j == i) continue;
         const double* sj = S + (size_t)(q0 + j) * NS;
         double hx = sj[IX] - si[IX], hy = sj[IX + 1] - si[IX + 1], dz = sj[IX + 2] - si[IX + 2];
-        upd_margin(&mg[q0 + i], sqrt(hx * hx + hy * hy) - d->dw_radius);
-        upd_margin(&mg[q0 + i], dz);
-        upd_margin(&mg[q0 + i], dz - d->dw_height);
-        if (hx * hx + hy * hy < d->dw_radius * d->dw_radius && dz > 0.0 && dz < d->dw_height) {
+        OR_MARGIN(&mg[q0 + i], sqrt(hx * hx + hy * hy) - d->dw_radius);
+        OR_MARGIN(&mg[q0 + i], dz);
+        OR_MARGIN(&mg[q0 + i], dz - d->dw_height);
+        if (hx * hx + hy * hy < dw_r2 && dz > 0.0 && dz < d->dw_height) {
           adw[i] += -d->dw_k1 * (d->dw_k2 * dz + d->dw_b1);
           dwhit[i] = 1;
         }
@@ -670,7 +683,7 @@ static void quad_vjp(const or_desc* d, const double* p, const or_rec* r, double*
                      double* guhat, double* gp) {
   const double dt = d->dt, g = d->gravity, m = p[PM];
   const double J[3] = {p[PJX], p[PJY], p[PJZ]};
-  const double arm_d = d->arm_length / sqrt(2.0);
+  const double arm_d = OR_CONST(d->arm_length / sqrt(2.0));
   double lx[3], lv[3], lR[9], lw[3], lu[4], le[4];
   for (int k = 0; k < 3; ++k) {
     lx[k] = lam[IX + k];
@@ -841,9 +854,9 @@ static void quad_vjp(const or_desc* d, const double* p, const or_rec* r, double*
     lalag += (r->uhat[i] - r->u0[i]) * lu[i];
   }
   /* f_max = m g t2w / 4, alpha_lag = 1 - exp(-dt/tau) */
-  lm += 0.25 * g * p[PT2W] * lfmax;
-  gp[PT2W] += 0.25 * m * g * lfmax;
-  gp[PTAU] += lalag * (-exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));
+  lm += OR_CONST(0.25 * g * p[PT2W]) * lfmax;
+  gp[PT2W] += OR_CONST(0.25 * m * g) * lfmax;
+  gp[PTAU] += lalag * OR_CONST(-exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));
   gp[PM] += lm;
   for (int k = 0; k < 3; ++k) gp[PJX + k] += lJ[k];
 
@@ -869,7 +882,7 @@ static void env_pairs_vjp(const or_desc* d, const double* S1, double* lam, int q
   double ldv[64][3];
   int marked[64];
   memset(marked, 0, sizeof(marked));
-  const double dc2 = d->col_dist * d->col_dist;
+  const double dc2 = OR_CONST(d->col_dist * d->col_dist);
   const int collide = (d->flags & OR_COLLIDE) != 0;
   /* which quads responded (recomputed exactly as in the forward pass) */
   if (collide) {

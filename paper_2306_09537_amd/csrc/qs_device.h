@@ -125,6 +125,11 @@ struct QuadPar {
   float m, inv_m, jx, jy, jz, ijx, ijy, ijz, f_max, a_lag, a_ns;
 };
 
+// Median of three unsigned words (one v_med3_u32).
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
 __device__ __forceinline__ float clampf(float a, float lo, float hi) {
   return fminf(fmaxf(a, lo), hi);
 }

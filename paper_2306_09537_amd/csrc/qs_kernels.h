@@ -347,22 +347,32 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 #pragma unroll
       for (int k = 0; k < 3; ++k) ov[15 + k] = s.w[k];
       if constexpr (KT > 0) {
-        // sorted (d^2, index) list of the KT nearest, kept in registers
-        float bd[KT];
-        int bj[KT];
+        // The KT nearest by (d^2, index).  Each candidate becomes a 32-bit
+        // key: the bits of d^2 (non-negative, so they order as the values)
+        // with the low six replaced by the partner's index (swarms hold at
+        // most 64).  A sorted list of KT + 1 keys takes a candidate x with
+        // one min and KT medians, all independent of each other:
+        // new[0] = min(old[0], x), new[k] = med3(old[k-1], x, old[k]).
+        // Keys order as (d^2 truncated to 2^-17 relative, index): the list
+        // is the exact (d^2, index) order unless two neighbouring entries
+        // share a truncated distance (an exact or near tie); such a lane
+        // selects again with exact comparisons below.  The quad itself and
+        // non-finite distances never enter.
+        constexpr uint32_t EMPTY = 0xffffffffu;
+        uint32_t key[KT + 1];
 #pragma unroll
-        for (int k = 0; k < KT; ++k) { bd[k] = INFINITY; bj[k] = -1; }
+        for (int k = 0; k <= KT; ++k) key[k] = EMPTY;
         auto cand = [&](int jj, float xj, float yj, float zj) {
           const float rx = xj - s.x[0], ry = yj - s.x[1], rz = zj - s.x[2];
-          const float d2 = jj == me ? INFINITY : rx * rx + ry * ry + rz * rz;
+          const float d2 = rx * rx + ry * ry + rz * rz;
+          const uint32_t kx = (jj != me && d2 < INFINITY)
+                                  ? ((__float_as_uint(d2) & ~63u) | (uint32_t)jj) : EMPTY;
+          uint32_t nk[KT + 1];
+          nk[0] = min(key[0], kx);
 #pragma unroll
-          for (int k = KT - 1; k > 0; --k) {
-            const bool shift = bd[k - 1] > d2;
-            const bool here = bd[k] > d2;
-            bd[k] = shift ? bd[k - 1] : (here ? d2 : bd[k]);
-            bj[k] = shift ? bj[k - 1] : (here ? jj : bj[k]);
-          }
-          if (bd[0] > d2) { bd[0] = d2; bj[0] = jj; }
+          for (int k = 1; k <= KT; ++k) nk[k] = umed3(key[k - 1], kx, key[k]);
+#pragma unroll
+          for (int k = 0; k <= KT; ++k) key[k] = nk[k];
         };
         if constexpr (NU > 1) {
           constexpr int CH = NU < 8 ? NU : 8;
@@ -387,6 +397,34 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
             for (int jj = 0; jj < n; ++jj)
               cand(jj, tile[0][ls + jj], tile[1][ls + jj], tile[2][ls + jj]);
         }
+        bool tie = false;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) tie |= key[k + 1] != EMPTY && (key[k] >> 6) == (key[k + 1] >> 6);
+        if (tie && live) {
+          // exact (d^2, index) insertion over the swarm (rare)
+          float bd[KT];
+          int bj[KT];
+#pragma unroll
+          for (int k = 0; k < KT; ++k) { bd[k] = INFINITY; bj[k] = -1; }
+          for (int jj = 0; jj < n; ++jj) {
+            const float rx = tile[0][ls + jj] - s.x[0], ry = tile[1][ls + jj] - s.x[1],
+                        rz = tile[2][ls + jj] - s.x[2];
+            const float d2 = jj == me ? INFINITY : rx * rx + ry * ry + rz * rz;
+#pragma unroll
+            for (int k = KT - 1; k > 0; --k) {
+              const bool shift = bd[k - 1] > d2;
+              const bool here = bd[k] > d2;
+              bd[k] = shift ? bd[k - 1] : (here ? d2 : bd[k]);
+              bj[k] = shift ? bj[k - 1] : (here ? jj : bj[k]);
+            }
+            if (bd[0] > d2) { bd[0] = d2; bj[0] = jj; }
+          }
+#pragma unroll
+          for (int k = 0; k < KT; ++k) key[k] = bj[k] >= 0 ? (uint32_t)bj[k] : EMPTY;
+        }
+        int bj[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) bj[k] = key[k] != EMPTY ? (int)(key[k] & 63u) : -1;
         // the slots' rows are read unconditionally (j is always a valid
         // column) and selected afterwards, so all reads are in flight at
         // once instead of one guarded read and wait per value

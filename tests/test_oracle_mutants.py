@@ -39,18 +39,19 @@ MUTANTS = [
      "s[IU + i] = alpha_lag * (uhat[i] - s[IU + i]) + s[IU + i];",
      "s[IU + i] = alpha_lag * (s[IU + i] - uhat[i]) + s[IU + i];"),
     ("lag_forward_euler", "§III-A.1",
-     "const double alpha_lag = 1.0 - exp(-dt / p[PTAU]);",
-     "const double alpha_lag = dt / p[PTAU];"),
+     "const double alpha_lag = OR_CONST(1.0 - exp(-dt / p[PTAU]));",
+     "const double alpha_lag = OR_CONST(dt / p[PTAU]);"),
     # §III-A.2 motor noise and thrust
     ("noise_scale_no_sqrt", "§III-A.2",
-     "const double a_ns = d->motor_noise_std * f_max * sqrt(1.0 - a_nd * a_nd);",
-     "const double a_ns = d->motor_noise_std * f_max * (1.0 - a_nd * a_nd);"),
+     "const double a_ns = OR_CONST(d->motor_noise_std * f_max * sqrt(1.0 - a_nd * a_nd));",
+     "const double a_ns = OR_CONST(d->motor_noise_std * f_max * (1.0 - a_nd * a_nd));"),
     ("noise_no_decay", "§III-A.2",
      "s[IE + i] = a_nd * s[IE + i] + a_ns * z[i];", "s[IE + i] = s[IE + i] + a_ns * z[i];"),
     ("thrust_not_squared", "§III-A.2",
      "f[i] = f_max * s[IU + i] * s[IU + i] + s[IE + i];", "f[i] = f_max * s[IU + i] + s[IE + i];"),
     ("f_max_half_weight", "§III-A.2",
-     "const double f_max = 0.25 * m * g * p[PT2W];", "const double f_max = 0.5 * m * g * p[PT2W];"),
+     "const double f_max = OR_CONST(0.25 * m * g * p[PT2W]);",
+     "const double f_max = OR_CONST(0.5 * m * g * p[PT2W]);"),
     # §III-A X mix and rigid body
     ("roll_mix_rotors", "§III-A mix",
      "tau[0] = arm_d * ((f[2] + f[3]) - (f[0] + f[1]));",
@@ -59,8 +60,8 @@ MUTANTS = [
      "tau[2] = d->k_tau * ((f[0] + f[2]) - (f[1] + f[3]));",
      "tau[2] = d->k_tau * ((f[1] + f[3]) - (f[0] + f[2]));"),
     ("arm_not_diagonal", "§III-A mix",
-     "const double arm_d = d->arm_length / sqrt(2.0);\n\n  /* §III-A.1",
-     "const double arm_d = d->arm_length;\n\n  /* §III-A.1"),
+     "const double arm_d = OR_CONST(d->arm_length / sqrt(2.0));\n\n  /* §III-A.1",
+     "const double arm_d = OR_CONST(d->arm_length);\n\n  /* §III-A.1"),
     ("thrust_along_row", "§III-A",
      "double F[3] = {T * R[2], T * R[5], T * R[8]};", "double F[3] = {T * R[6], T * R[7], T * R[8]};"),
     ("gravity_sign", "§III-A", "acc[2] -= g;", "acc[2] += g;"),
@@ -181,8 +182,8 @@ MUTANTS = [
     ("vjp_noise_decay", "reverse mode, §III-A.2",
      "le0[i] = d->motor_noise_decay * le[i];", "le0[i] = le[i];"),
     ("vjp_tau_derivative_sign", "reverse mode, §III-A.1",
-     "gp[PTAU] += lalag * (-exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));",
-     "gp[PTAU] += lalag * (exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));"),
+     "gp[PTAU] += lalag * OR_CONST(-exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));",
+     "gp[PTAU] += lalag * OR_CONST(exp(-dt / p[PTAU]) * dt / (p[PTAU] * p[PTAU]));"),
     ("vjp_wall_mirror", "reverse mode, §III-B.2",
      "if (r->flip[k]) lv[k] *= -d->wall_restitution;",
      "if (r->flip[k]) lv[k] *= d->wall_restitution;"),
@@ -218,7 +219,8 @@ MUTANTS = [
      "adw[i] += -d->dw_k1 * (d->dw_k2 * dz + d->dw_b1);",
      "adw[i] += -d->dw_k1 * (-d->dw_k2 * dz + d->dw_b1);"),
     ("downwash_radius_unsquared", "§III-B.4",
-     "hx * hx + hy * hy < d->dw_radius * d->dw_radius", "hx * hx + hy * hy < d->dw_radius"),
+     "const double dw_r2 = OR_CONST(d->dw_radius * d->dw_radius);",
+     "const double dw_r2 = OR_CONST(d->dw_radius);"),
     ("sensor_widths_swapped", "§III-C",
      "const double a = draw == 0 ? d->sn_x : d->sn_v;", "const double a = draw == 0 ? d->sn_v : d->sn_x;"),
     ("observe_padding_nonzero", "§III-C",
