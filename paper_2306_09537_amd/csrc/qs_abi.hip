@@ -258,13 +258,35 @@ int build_items(qs_handle* h, int bs) {
   return QS_OK;
 }
 
-// Launch one instantiation.  Observation rows are staged in LDS when the
-// staging area and the pair tile fit in 64 KiB per workgroup.
-// Calls of several substeps on small batches run the motor part one substep
-// ahead in a second wavefront (QS_STEP_PIPE=0/1 forces it off/on).
+// Launch one instantiation.  Calls of several substeps on small batches run
+// the motor part one substep ahead in a second wavefront (QS_STEP_PIPE=0/1
+// forces it off/on).
 bool use_step_pipe(const qs_handle* h) {
   if (const char* e = std::getenv("QS_STEP_PIPE")) return e[0] == '1';
   return h->nblk <= 1024;
+}
+
+// Observation rows per staging pass.  A grid of at most 2048 workgroups
+// has at most two per SIMD, which LDS never limits: the whole workgroup's
+// rows in one pass (fewest synchronisations; 4096 x 8: 6.7 us per launch
+// against 7.0 us in two passes).  Larger grids stage at most 8 KiB at a
+// time (K = 6, 64 quads: 2 passes of 32 rows, 6.9 KiB), so that LDS does
+// not hold the number of resident workgroups below what the registers
+// allow: at 32768 x 32 a 13.5 KiB staging area held the step to 2
+// wavefronts per SIMD instead of 3 (104 -> 98 us per one-substep launch,
+// 347 -> 278 us per ten-substep launch).  QS_STAGE_ROWS=n overrides (0:
+// every lane stores its own row, 131 us).
+int stage_rows(int bs, int od, int nblk) {
+  static const int forced = [] {
+    const char* e = std::getenv("QS_STAGE_ROWS");
+    return e ? std::atoi(e) : -1;
+  }();
+  if (forced >= 0 && forced <= bs && (forced & (forced - 1)) == 0) return forced;
+  const size_t row = (size_t)od * sizeof(float);
+  int r = bs;
+  const size_t cap = nblk <= 2048 ? 48 * 1024 : 8192;
+  while (r > 8 && (size_t)r * row > cap) r >>= 1;
+  return r;
 }
 
 template <int BS, int KT, int N>
@@ -273,11 +295,8 @@ void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs
   size_t dyn = 0;
   int stage = 0;
   if constexpr (KT >= 0) {
-    const size_t lds = (size_t)BS * (18 + 6 * KT) * sizeof(float);
-    if (lds + sizeof(float) * 2 * 9 * BS <= 64 * 1024) {
-      dyn = lds;
-      stage = 1;
-    }
+    stage = stage_rows(BS, 18 + 6 * KT, h->nblk);
+    dyn = (size_t)stage * (18 + 6 * KT) * sizeof(float);
   }
   if constexpr (BS == 64 && N == 8 && (KT == 6 || KT == -2)) {
     if (nsub >= 2 && use_step_pipe(h)) {

@@ -560,7 +560,9 @@ using PairMask = typename std::conditional<(N > 0 && N <= 32), uint32_t,
 template <int BS, int N, int XR = -1, typename T, typename F>
 __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
   if constexpr (N > 0) {
-    constexpr int CH = N < 8 ? N : 8;
+    // chunks of eight partners, four in swarms above 16 (32-quad swarms:
+    // 168 -> 120 VGPRs in the step, four wavefronts per SIMD instead of three)
+    constexpr int CH = N < 8 ? N : (N > 16 ? 4 : 8);
     auto chunk = [&](int j0) {
       float pj[CH][7];
 #pragma unroll

@@ -461,33 +461,41 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       }
       if (c.flags & F_SENSOR) sensor_noise(c, (uint32_t)q, t0 + nsub, &ov[0], &ov[3], &ov[15]);
       if (stage_obs) {
-        if (live) {
-          float2* r2 = reinterpret_cast<float2*>(st_obs + tid * OD);
+        // the workgroup's rows leave through LDS in passes of stage_obs
+        // rows, each copied out with contiguous stores: 16-byte stores when
+        // the destination allows, else 8-byte stores; non-temporal, since
+        // the rows go to their consumer and this kernel never reads them
+        // back (fewer dirty L2 lines left to write back when the kernel
+        // ends).  A small staging area (a few KiB) keeps LDS from limiting
+        // how many workgroups share a CU.
+        const int R = stage_obs;
+        for (int p0 = 0; p0 < cnt; p0 += R) {
+          if (live && tid >= p0 && tid < p0 + R) {
+            float2* r2 = reinterpret_cast<float2*>(st_obs + (tid - p0) * OD);
 #pragma unroll
-          for (int k = 0; k < OD / 2; ++k) r2[k] = make_float2(ov[2 * k], ov[2 * k + 1]);
-        }
-        quad_sync();
-        // contiguous copy of the workgroup's rows: 16-byte stores when the
-        // destination allows, else 8-byte stores; non-temporal, since the
-        // rows go to their consumer and this kernel never reads them back
-        // (fewer dirty L2 lines left to write back when the kernel ends)
-        const int total = cnt * OD;
-        float* dst = obs + (size_t)qb * OD;
-        if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-          const int n4 = total >> 2;
-          v4f* d4 = reinterpret_cast<v4f*>(dst);
-          const v4f* s4 = reinterpret_cast<const v4f*>(st_obs4);
+            for (int k = 0; k < OD / 2; ++k) r2[k] = make_float2(ov[2 * k], ov[2 * k + 1]);
+          }
+          quad_sync();
+          const int total = min(R, cnt - p0) * OD;
+          float* dst = obs + (size_t)(qb + p0) * OD;
+          if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+            const int n4 = total >> 2;
+            v4f* d4 = reinterpret_cast<v4f*>(dst);
+            const v4f* s4 = reinterpret_cast<const v4f*>(st_obs4);
 #pragma unroll 4
-          for (int i = tid; i < n4; i += BS) __builtin_nontemporal_store(s4[i], d4 + i);
-          if ((total & 3) && tid == 0)
-            __builtin_nontemporal_store(reinterpret_cast<const v2f*>(st_obs)[2 * n4],
-                                        reinterpret_cast<v2f*>(dst) + 2 * n4);
-        } else {
-          const int n2 = total >> 1;
-          v2f* d2p = reinterpret_cast<v2f*>(dst);
-          const v2f* s2p = reinterpret_cast<const v2f*>(st_obs);
+            for (int i = tid; i < n4; i += BS) __builtin_nontemporal_store(s4[i], d4 + i);
+            if ((total & 3) && tid == 0)
+              __builtin_nontemporal_store(reinterpret_cast<const v2f*>(st_obs)[2 * n4],
+                                          reinterpret_cast<v2f*>(dst) + 2 * n4);
+          } else {
+            const int n2 = total >> 1;
+            v2f* d2p = reinterpret_cast<v2f*>(dst);
+            const v2f* s2p = reinterpret_cast<const v2f*>(st_obs);
 #pragma unroll 4
-          for (int i = tid; i < n2; i += BS) __builtin_nontemporal_store(s2p[i], d2p + i);
+            for (int i = tid; i < n2; i += BS) __builtin_nontemporal_store(s2p[i], d2p + i);
+          }
+          // the copy has read this pass's rows before the next pass writes
+          if (p0 + R < cnt) quad_sync();
         }
       } else if (live) {
         float2* r2 = reinterpret_cast<float2*>(obs + (size_t)q * OD);
