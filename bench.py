@@ -367,27 +367,41 @@ def time_batched(w, torch, calls: int = 100, nsub: int = 10, reps: int = 3):
     obs = torch.empty((calls, Q, w.obs_dim), device="cuda")
     s0 = torch.from_numpy(w.state0).cuda()
     choice = sim.autotune(acts[0], nsub, goals, obs[0])
-    sim.set_graph_mode(True)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        for c in range(calls):
-            sim.step_observe(acts[c], nsub, goals, obs[c])
-    times = []
-    for r in range(reps + 1):
-        # episode reset (untimed); every replay runs the same seeded episode
-        sim.set_state(s0, 0)
+
+    def replay_ms():
+        """Capture the rollout as one graph and time its replays."""
+        sim.set_graph_mode(True)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        graph.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        if r:
-            times.append(e0.elapsed_time(e1))
-    nonfinite = sticky_nonfinite(sim, torch)
-    sim.set_graph_mode(False)
-    ms = float(np.median(times))
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for c in range(calls):
+                sim.step_observe(acts[c], nsub, goals, obs[c])
+        times = []
+        for r in range(reps + 1):
+            # episode reset (untimed); every replay runs the same seeded episode
+            sim.set_state(s0, 0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                times.append(e0.elapsed_time(e1))
+        nonfinite = sticky_nonfinite(sim, torch)
+        sim.set_graph_mode(False)
+        del graph
+        return float(np.median(times)), nonfinite
+
+    ms, nonfinite = replay_ms()
+    # the same launch without the per-slot choices (every slot on the
+    # one-partner body): what the autotuner's global search alone gives
+    chunked = [r["slot"] for r in choice["slots"] if r["chunked"]]
+    global_ms = ms
+    if chunked:
+        sim.set_partner_chunks([])
+        global_ms, _ = replay_ms()
+        sim.set_partner_chunks(chunked)
     value = Q * calls * nsub / (ms * 1e-3)
     # the one-substep launch (observation every substep) on the same swarms
     plain_ms, _ = time_calls(sim, w, acts, goals, obs[0], 1, 500, 20, torch, w.substeps)
@@ -400,6 +414,7 @@ def time_batched(w, torch, calls: int = 100, nsub: int = 10, reps: int = 3):
                 form="persistent bucketed launch, 10 substeps per call, 100-call rollout "
                      "replayed as one captured graph",
                 plain_value=plain, speedup_vs_plain=value / plain,
+                global_choice_value=Q * calls * nsub / (global_ms * 1e-3),
                 plain_roofline=hbm_roofline(algorithmic_bytes_per_quad(w.k_neighbors, 1) * Q,
                                             plain_ms),
                 roofline=alu_roofline(call_flops(w, nsub), ms / calls, PROFILES.get(key),

@@ -380,17 +380,44 @@ int qs_set_graph_mode(qs_handle* h, int32_t enable, void* stream);
 int qs_set_launch(qs_handle* h, int32_t block, int32_t grid);
 
 /*
- * Time candidate launch configurations of qs_step_observe (d_goals and d_obs
- * non-NULL) or qs_step (both NULL) with n_substeps substeps on the handle's
- * own swarms (each candidate from the same saved state), keep the fastest,
- * and restore the state, the substep counter and the sticky error word.
- * Candidates: workgroup size 64 or 128 and, for uneven swarm sizes, the
- * persistent grid size.  choice (optional, int32[3]) receives (workgroup
- * size, grid size or 0 for one workgroup per item, bucketed ? 1 : 0).
- * Not available in graph mode.  Synchronous.
+ * The project's autotuner: time candidate launch configurations of
+ * qs_step_observe (d_goals and d_obs non-NULL) or qs_step (both NULL) with
+ * n_substeps substeps on the handle's own swarms (each candidate from the
+ * same saved state), keep the fastest, and restore the state, the substep
+ * counter and the sticky error word.  Uniform swarm sizes: workgroup size
+ * 64 or 128.  Uneven sizes (the bucketed form): (1) workgroup sizes 64 and
+ * 128 and persistent grids, every slot size with the in-swarm loops taking
+ * one partner at a time; (2) per slot size of 16 and 32, its work items
+ * alone with that body and with the body that takes the partners in chunks
+ * of four; (3) the call with each slot size on its faster body, over the
+ * grids; the faster of (1) and (3) is kept.  choice (optional, int32[3])
+ * receives (workgroup size, grid size or 0 for one workgroup per item,
+ * bucketed ? 1 : 0); qs_launch_plan gives the per-slot table.  Not
+ * available in graph mode.  Synchronous.  This is the batching workload's
+ * schedule search; the paper has no counterpart.
  */
 int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const float* d_goals,
                 float* d_obs, int32_t* choice, void* stream);
+
+/*
+ * Bucketed form: the slot sizes whose work items take the in-swarm
+ * partners in chunks of four (their loads in flight together) instead of
+ * one at a time: bit k of slot_mask for slots of 2^k quads, k = 4 or 5
+ * (slots of 16 and 32; QS_ERR_INVALID for other bits).  Results are
+ * bit-identical either way.  Synchronises the device.  (qs_autotune sets it
+ * from its measurements.)
+ */
+int qs_set_partner_chunks(qs_handle* h, uint32_t slot_mask);
+
+/*
+ * The per-slot-size plan of the bucketed form, into plan [7][5] (host), one
+ * row per slot size present, largest first: slot size, swarms, 1 if its
+ * items take the chunked body else 0, and the times (ns per launch) the
+ * last qs_autotune measured for the slot's items alone with the
+ * one-partner and with the chunked body (0 where not measured).  *n_rows
+ * receives the number of rows (0 for handles of uniform sizes).
+ */
+int qs_launch_plan(const qs_handle* h, int32_t* plan, int32_t* n_rows);
 
 /* ---- diagnostics -------------------------------------------------------------
  * The noise of §III-A.2 (motor), §III-B (wall, pair and downwash kicks) and

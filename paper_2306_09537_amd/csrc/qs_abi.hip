@@ -46,7 +46,15 @@ struct qs_handle {
   int2* d_item_envs = nullptr;
   int n_items = 0;
   int item_bs = 64;      // workgroup size of the bucketed launch
-  int item_grid = 0;     // persistent grid size (0: one workgroup per item)
+  int item_grid = 0;     // persistent grid size of the shared launch (0: one workgroup per item)
+  // slot sizes (bit log2 N; 16 and 32) whose items take the partners in
+  // chunks of four instead of one at a time
+  uint32_t chunked = 0;
+  // per slot size: swarms, and the times the autotuner measured for the
+  // slot's items alone with each body (ns per call)
+  int slot_swarms[7] = {0, 0, 0, 0, 0, 0, 0};
+  float slot_ns_one[7] = {0, 0, 0, 0, 0, 0, 0};
+  float slot_ns_chunked[7] = {0, 0, 0, 0, 0, 0, 0};
   bool bucketed = false;
   // graph-safe substep counter
   bool graph_mode = false;
@@ -223,19 +231,31 @@ int build_table(qs_handle* h, int bs) {
 
 // Work items of the bucketed launch: every swarm gets a slot of the next
 // power of two >= its size; slots of one size are grouped bs/slot per item;
-// items are ordered by slot size, largest first (heaviest work first).
+// items are ordered by slot size, largest first (heaviest work first).  An
+// item's w field selects the chunked partner body (slot sizes in
+// h->chunked).
+int log2i(int n) {
+  int k = 0;
+  while ((1 << k) < n) ++k;
+  return k;
+}
+
+// Slot sizes with a second, chunked body in the bucketed kernel.
+constexpr uint32_t kChunkable = (1u << 4) | (1u << 5);
+
 int build_items(qs_handle* h, int bs) {
   std::vector<int4> items;
   std::vector<int2> envs;
+  for (int k = 0; k < 7; ++k) h->slot_swarms[k] = 0;
+  for (size_t e = 0; e < h->env_n.size(); ++e) ++h->slot_swarms[log2i(h->env_n[e])];
   for (int N = 64; N >= 1; N >>= 1) {
     const int per = bs / N;
+    const int w = (h->chunked & kChunkable) >> log2i(N) & 1u;
     int in_item = 0;
     for (size_t e = 0; e < h->env_n.size(); ++e) {
       const int n = h->env_n[e];
-      int slot = 1;
-      while (slot < n) slot <<= 1;
-      if (slot != N) continue;
-      if (in_item == 0) items.push_back(make_int4(N, (int)envs.size(), 0, 0));
+      if ((1 << log2i(n)) != N) continue;
+      if (in_item == 0) items.push_back(make_int4(N, (int)envs.size(), 0, w));
       envs.push_back(make_int2(h->env_start[e], n));
       items.back().z += 1;
       if (++in_item == per) in_item = 0;
@@ -312,15 +332,21 @@ void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs
                      ptrs(h), obs, stage, h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
 }
 
+// One launch of the bucketed kernel over items [item0, item0 + count).
+template <int BS, int KT>
+void go_range(qs_handle* h, int item0, int count, int grid, const float* act, int nsub,
+              const float* goals, float* obs, hipStream_t s, float* rw) {
+  hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), 0, s,
+                     h->d_st, h->d_par, act, goals, h->d_c, h->Qp, h->Q, nsub,
+                     (unsigned long long)h->t, ptrs(h), obs, item0, count,
+                     h->graph_mode ? h->d_t : nullptr, h->d_done, rw);
+}
+
 template <int BS, int KT>
 void go_items(qs_handle* h, const float* act, int nsub, const float* goals, float* obs,
               hipStream_t s, float* rw) {
   const int grid = h->item_grid > 0 ? std::min(h->item_grid, h->n_items) : h->n_items;
-  hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), 0, s,
-                     h->d_st, h->d_par, act, goals, h->d_c, h->Qp, h->Q, nsub,
-                     (unsigned long long)h->t, ptrs(h), obs, h->n_items,
-                     h->graph_mode ? h->d_t : nullptr,
-                     h->d_done, rw);
+  go_range<BS, KT>(h, 0, h->n_items, grid, act, nsub, goals, obs, s, rw);
 }
 
 template <int BS>
@@ -334,6 +360,21 @@ void launch_items(qs_handle* h, const float* act, int nsub, const float* goals, 
     go_items<BS, 0>(h, act, nsub, goals, obs, s, rw);
   else
     go_items<BS, -1>(h, act, nsub, goals, obs, s, rw);
+}
+
+// One launch over an item range alone (autotuner trials; not in graph
+// mode).
+template <int BS>
+void launch_range(qs_handle* h, int item0, int count, const float* act, int nsub,
+                  const float* goals, float* obs, bool with_obs, hipStream_t s) {
+  if (!with_obs)
+    go_range<BS, -2>(h, item0, count, count, act, nsub, goals, obs, s, nullptr);
+  else if (h->K == 6)
+    go_range<BS, 6>(h, item0, count, count, act, nsub, goals, obs, s, nullptr);
+  else if (h->K == 0)
+    go_range<BS, 0>(h, item0, count, count, act, nsub, goals, obs, s, nullptr);
+  else
+    go_range<BS, -1>(h, item0, count, count, act, nsub, goals, obs, s, nullptr);
 }
 
 template <int BS, int KT>
@@ -654,6 +695,131 @@ int noalloc_scratch(int dev, float** out) {
 
 }  // namespace
 
+namespace {
+
+// Autotuner trials: every trial starts from the saved state and substep
+// counter; times come from HIP events around `reps` launches after 2 untimed
+// ones.
+struct Trial {
+  qs_handle* h;
+  const float *act, *goals;
+  float* obs;
+  int nsub;
+  bool with_obs;
+  hipStream_t s;
+  float* saved;
+  size_t st_bytes;
+  uint64_t t_saved;
+  hipEvent_t e0, e1;
+
+  int restore() {
+    h->t = t_saved;
+    return hipMemcpyAsync(h->d_st, saved, st_bytes, hipMemcpyDeviceToDevice, s) == hipSuccess
+               ? QS_OK : QS_ERR_HIP;
+  }
+  template <typename F>
+  int time(F&& launch_once, float* ms_per_launch) {
+    int rc = restore();
+    for (int w = 0; rc == QS_OK && w < 2; ++w) rc = launch_once();
+    if (rc != QS_OK) return rc;
+    if (hipEventRecord(e0, s) != hipSuccess) return QS_ERR_HIP;
+    const int reps = 5;
+    for (int r = 0; rc == QS_OK && r < reps; ++r) rc = launch_once();
+    float ms = 0.f;
+    if (rc != QS_OK) return rc;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return QS_ERR_HIP;
+    *ms_per_launch = ms / reps;
+    return QS_OK;
+  }
+  int call(float* ms) {
+    return time([&] { return launch(h, act, nsub, goals, obs, with_obs, s); }, ms);
+  }
+  int range(int item0, int count, float* ms) {
+    return time([&] {
+      if (h->item_bs == 128)
+        launch_range<128>(h, item0, count, act, nsub, goals, obs, with_obs, s);
+      else
+        launch_range<64>(h, item0, count, act, nsub, goals, obs, with_obs, s);
+      return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+    }, ms);
+  }
+};
+
+// Launch configuration of a bucketed handle: workgroup size, persistent
+// grid and the slot sizes that take the chunked partner body.
+struct BucketConfig {
+  int bs, grid;
+  uint32_t chunked;
+};
+
+int apply(qs_handle* h, hipStream_t s, const BucketConfig& c) {
+  // no launch may still read the tables that are about to be rebuilt
+  if (hipStreamSynchronize(s) != hipSuccess) return QS_ERR_HIP;
+  h->chunked = c.chunked;
+  h->item_grid = c.grid;
+  return build_items(h, c.bs);
+}
+
+// Bucketed handles: (1) workgroup sizes 64 and 128 and persistent grids,
+// every slot size with the one-partner body; (2) per slot size with two
+// bodies (16 and 32), its items alone with each body, at the workgroup size
+// of (1); (3) the call with each slot size on its faster body, over the
+// grids; the faster of (1) and (3) is kept.
+int tune_buckets(Trial& tr, BucketConfig* best) {
+  qs_handle* h = tr.h;
+  float best_ms = 1e30f;
+  int rc = QS_OK;
+  for (int bs : {64, 128})
+    for (int g : {0, 1024, 2048, 4096}) {
+      const BucketConfig c{bs, g, 0u};
+      float ms = 0.f;
+      if ((rc = apply(h, tr.s, c)) != QS_OK || (rc = tr.call(&ms)) != QS_OK) return rc;
+      if (ms < best_ms) {
+        best_ms = ms;
+        *best = c;
+      }
+    }
+  for (int k = 0; k < 7; ++k) h->slot_ns_one[k] = h->slot_ns_chunked[k] = 0.f;
+  uint32_t mask = 0u;
+  for (int k = 0; k < 7; ++k) {
+    if (!(kChunkable >> k & 1u) || h->slot_swarms[k] == 0) continue;
+    float t[2] = {0.f, 0.f};
+    for (int v = 0; v < 2; ++v) {
+      if ((rc = apply(h, tr.s, {best->bs, 0, v ? 1u << k : 0u})) != QS_OK) return rc;
+      // the slot's item range (items are ordered by slot size)
+      std::vector<int4> items((size_t)h->n_items);
+      if (hipMemcpy(items.data(), h->d_items, items.size() * sizeof(int4),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return QS_ERR_HIP;
+      int i0 = -1, i1 = -1;
+      for (int i = 0; i < h->n_items; ++i)
+        if (items[(size_t)i].x == (1 << k)) {
+          if (i0 < 0) i0 = i;
+          i1 = i + 1;
+        }
+      if (i0 < 0 || (rc = tr.range(i0, i1 - i0, &t[v])) != QS_OK) return rc;
+    }
+    h->slot_ns_one[k] = t[0] * 1e6f;
+    h->slot_ns_chunked[k] = t[1] * 1e6f;
+    if (t[1] < t[0]) mask |= 1u << k;
+  }
+  if (mask == 0u) return QS_OK;
+  for (int g : {0, 1024, 2048, 4096}) {
+    const BucketConfig c{best->bs, g, mask};
+    float ms = 0.f;
+    if ((rc = apply(h, tr.s, c)) != QS_OK || (rc = tr.call(&ms)) != QS_OK) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = c;
+    }
+  }
+  return QS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* h_state0,
@@ -778,7 +944,8 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
   if (rc == QS_OK) rc = build_table(h, h->bs);
   if (rc == QS_OK && hipMalloc((void**)&h->d_t, sizeof(unsigned long long)) != hipSuccess)
     rc = QS_ERR_NOMEM;
-  if (rc == QS_OK && hipMalloc((void**)&h->d_done, sizeof(unsigned int)) != hipSuccess)
+  if (rc == QS_OK &&
+      hipMalloc((void**)&h->d_done, qs::DONE_WORDS * sizeof(unsigned int)) != hipSuccess)
     rc = QS_ERR_NOMEM;
   if (rc == QS_OK && hipMalloc((void**)&h->d_c, sizeof(Consts)) != hipSuccess) rc = QS_ERR_NOMEM;
   if (rc == QS_OK && h->uniform_n == 0) {
@@ -798,7 +965,7 @@ int qs_create(const qs_desc* desc, const qs_quad_params* h_params, const float* 
     ok = ok && hipMemset(h->d_contacts, 0, (size_t)h->Qp * sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMemset(h->d_err, 0, sizeof(int)) == hipSuccess;
     ok = ok && hipMemset(h->d_t, 0, sizeof(unsigned long long)) == hipSuccess;
-    ok = ok && hipMemset(h->d_done, 0, sizeof(unsigned int)) == hipSuccess;
+    ok = ok && hipMemset(h->d_done, 0, qs::DONE_WORDS * sizeof(unsigned int)) == hipSuccess;
     ok = ok && hipMemcpy(h->d_c, &h->c, sizeof(Consts), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (!ok) rc = QS_ERR_HIP;
@@ -883,6 +1050,30 @@ int qs_set_launch(qs_handle* h, int32_t block, int32_t grid) {
   return rc;
 }
 
+int qs_set_partner_chunks(qs_handle* h, uint32_t slot_mask) {
+  if (!h) return QS_ERR_NULL;
+  if (slot_mask & ~kChunkable) return QS_ERR_INVALID;
+  if (hipSetDevice(h->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return QS_ERR_HIP;
+  h->chunked = slot_mask;
+  return h->bucketed ? build_items(h, h->item_bs) : QS_OK;
+}
+
+int qs_launch_plan(const qs_handle* h, int32_t* plan, int32_t* n_rows) {
+  if (!h || !plan || !n_rows) return QS_ERR_NULL;
+  int r = 0;
+  for (int k = 6; k >= 0; --k) {
+    if (h->slot_swarms[k] == 0) continue;
+    int32_t* row = plan + 5 * r++;
+    row[0] = 1 << k;
+    row[1] = h->slot_swarms[k];
+    row[2] = h->bucketed && ((h->chunked & kChunkable) >> k & 1u) ? 1 : 0;
+    row[3] = (int32_t)std::lround(h->slot_ns_one[k]);
+    row[4] = (int32_t)std::lround(h->slot_ns_chunked[k]);
+  }
+  *n_rows = r;
+  return QS_OK;
+}
+
 int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const float* d_goals,
                 float* d_obs, int32_t* choice, void* stream) {
   if (!h || !d_actions) return QS_ERR_NULL;
@@ -891,20 +1082,6 @@ int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const 
   if (hipSetDevice(h->dev) != hipSuccess) return QS_ERR_HIP;
   if (h->graph_mode) return QS_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
-  const bool with_obs = d_obs != nullptr;
-  // candidates: (workgroup size, persistent grid) -- the grid only matters
-  // for the bucketed launch of uneven swarm sizes
-  struct Cand { int bs, grid; };
-  std::vector<Cand> cands;
-  if (h->bucketed) {
-    for (int bs : {64, 128})
-      for (int g : {0, 1024, 2048, 4096}) cands.push_back({bs, g});
-  } else if (h->uniform_n > 0) {
-    cands.push_back({64, 0});
-    cands.push_back({128, 0});
-  } else {
-    cands.push_back({h->bs, 0});
-  }
   // the trials must not change the simulation: every candidate starts from
   // the saved state, and the state, substep counter and sticky error word
   // are restored afterwards
@@ -912,65 +1089,45 @@ int qs_autotune(qs_handle* h, const float* d_actions, int32_t n_substeps, const 
   const size_t st_bytes = (size_t)qs::NSTATE * h->Qp * sizeof(float);
   if (hipMalloc((void**)&saved, st_bytes + 256) != hipSuccess) return QS_ERR_NOMEM;
   int* saved_err = reinterpret_cast<int*>(reinterpret_cast<char*>(saved) + st_bytes);
-  const uint64_t t_saved = h->t;
+  Trial tr{h, d_actions, d_goals, d_obs, (int)n_substeps, d_obs != nullptr, s, saved, st_bytes,
+           h->t, nullptr, nullptr};
   int rc = hipMemcpyAsync(saved, h->d_st, st_bytes, hipMemcpyDeviceToDevice, s) == hipSuccess &&
                    hipMemcpyAsync(saved_err, h->d_err, sizeof(int), hipMemcpyDeviceToDevice, s) ==
                        hipSuccess
                ? QS_OK : QS_ERR_HIP;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (rc == QS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+  if (rc == QS_OK && (hipEventCreate(&tr.e0) != hipSuccess || hipEventCreate(&tr.e1) != hipSuccess))
     rc = QS_ERR_HIP;
-  float best = 1e30f;
-  Cand best_c = cands[0];
-  for (size_t i = 0; rc == QS_OK && i < cands.size(); ++i) {
-    const Cand cd = cands[i];
-    // no launch may still read the tables that are about to be rebuilt
-    if (hipStreamSynchronize(s) != hipSuccess) {
-      rc = QS_ERR_HIP;
-      break;
-    }
-    if (h->bucketed) {
-      if (cd.bs != h->item_bs && (rc = build_items(h, cd.bs)) != QS_OK) break;
-      h->item_grid = cd.grid;
-    } else if (h->uniform_n > 0 && cd.bs != h->bs) {
-      if ((rc = build_table(h, cd.bs)) != QS_OK) break;
-    }
-    if (hipMemcpyAsync(h->d_st, saved, st_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-      rc = QS_ERR_HIP;
-      break;
-    }
-    h->t = t_saved;
-    for (int w = 0; rc == QS_OK && w < 2; ++w) rc = launch(h, d_actions, n_substeps, d_goals, d_obs, with_obs, s);
-    if (rc != QS_OK) break;
-    if (hipEventRecord(e0, s) != hipSuccess) { rc = QS_ERR_HIP; break; }
-    for (int r = 0; rc == QS_OK && r < 5; ++r) rc = launch(h, d_actions, n_substeps, d_goals, d_obs, with_obs, s);
-    float ms = 0.f;
-    if (rc != QS_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      rc = rc == QS_OK ? QS_ERR_HIP : rc;
-      break;
-    }
-    if (ms < best) {
-      best = ms;
-      best_c = cd;
-    }
-  }
-  if (rc == QS_OK && hipStreamSynchronize(s) != hipSuccess) rc = QS_ERR_HIP;
   if (rc == QS_OK) {
     if (h->bucketed) {
-      if (best_c.bs != h->item_bs) rc = build_items(h, best_c.bs);
-      h->item_grid = best_c.grid;
-    } else if (h->uniform_n > 0 && best_c.bs != h->bs) {
-      rc = build_table(h, best_c.bs);
+      BucketConfig best{h->item_bs, h->item_grid, h->chunked};
+      rc = tune_buckets(tr, &best);
+      if (rc == QS_OK) rc = apply(h, s, best);
+    } else if (h->uniform_n > 0) {
+      // uniform power-of-two swarms: workgroup size 64 or 128
+      int best_bs = h->bs;
+      float best_ms = 1e30f;
+      for (int bs : {64, 128}) {
+        if (bs % h->uniform_n != 0) continue;
+        float ms = 0.f;
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = QS_ERR_HIP; break; }
+        if (bs != h->bs && (rc = build_table(h, bs)) != QS_OK) break;
+        if ((rc = tr.call(&ms)) != QS_OK) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_bs = bs;
+        }
+      }
+      if (rc == QS_OK && hipStreamSynchronize(s) != hipSuccess) rc = QS_ERR_HIP;
+      if (rc == QS_OK && best_bs != h->bs) rc = build_table(h, best_bs);
     }
   }
   if (hipMemcpyAsync(h->d_st, saved, st_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(h->d_err, saved_err, sizeof(int), hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     rc = QS_ERR_HIP;
-  h->t = t_saved;
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  h->t = tr.t_saved;
+  if (tr.e0) (void)hipEventDestroy(tr.e0);
+  if (tr.e1) (void)hipEventDestroy(tr.e1);
   (void)hipFree(saved);
   if (rc == QS_OK && choice) {
     choice[0] = h->bucketed ? h->item_bs : h->bs;

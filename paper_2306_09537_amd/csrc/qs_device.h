@@ -560,9 +560,10 @@ using PairMask = typename std::conditional<(N > 0 && N <= 32), uint32_t,
 template <int BS, int N, int XR = -1, typename T, typename F>
 __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
   if constexpr (N > 0) {
-    // chunks of eight partners, four in swarms above 16 (32-quad swarms:
-    // 168 -> 120 VGPRs in the step, four wavefronts per SIMD instead of three)
-    constexpr int CH = N < 8 ? N : (N > 16 ? 4 : 8);
+    // chunks of eight partners, four in swarms of 16 and more (32-quad
+    // swarms: 168 -> 120 VGPRs in the step, four wavefronts per SIMD
+    // instead of three)
+    constexpr int CH = N < 8 ? N : (N >= 16 ? 4 : 8);
     auto chunk = [&](int j0) {
       float pj[CH][7];
 #pragma unroll
@@ -574,7 +575,7 @@ __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
 #pragma unroll
       for (int u = 0; u < CH; ++u) f(j0 + u, pj[u]);
     };
-    if constexpr (N > 16) {
+    if constexpr (N >= 16) {
       // large swarms: a run-time loop over the chunks keeps the registers
       // of an eight-partner body
 #pragma unroll 1

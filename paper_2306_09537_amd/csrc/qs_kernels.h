@@ -24,14 +24,52 @@ namespace qs {
 enum : int { MAP_DENSE = 0, MAP_TABLE = 1, MAP_ITEM = 2 };
 
 // Graph-safe substep counter: every workgroup reads the base substep index
-// from device memory at its start; the last workgroup to finish advances it
-// by nsub.  No ordering beyond atomicity is needed: the last workgroup
-// finishes after every other one has read the counter (each increments
-// `done` after its reads), and the next launch reads the new value after the
+// from device memory, after the loads of its first quads are in flight (the
+// read goes to the coherence point; issued first, it would hold back every
+// later load of the workgroup); the last workgroup to finish advances it by
+// nsub.  No ordering beyond atomicity is needed: the last workgroup
+// finishes after every other one has read the counter (each counts itself
+// done after its reads), and the next launch reads the new value after the
 // kernel boundary.  (A release here would write back the XCD's L2 from
 // every workgroup.)
+//
+// The completion count is two-level: workgroup b counts itself in
+// sub-counter b mod 64 (each on a 128-byte line of its own), and the last
+// workgroup of each sub-counter counts in the top one.  Returning atomics on
+// one address are performed one after another at the coherence point; with
+// one counter, 2,700 workgroups took ~70 us to count themselves out
+// (16384 uneven environments, ten substeps per call: 53 -> 71 us per call),
+// with 65 lines at most ~42 + 64 of them queue on any one.
+enum : int { DONE_SUBS = 64, DONE_STRIDE = 32, DONE_WORDS = (DONE_SUBS + 1) * DONE_STRIDE };
+
 __device__ __forceinline__ unsigned long long read_counter(const unsigned long long* tdev) {
   return __hip_atomic_load(tdev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// total: the workgroups of the launch; the last of them to finish advances
+// the counter.  done: DONE_WORDS words, zero between launches.
+__device__ __forceinline__ void advance_counter(unsigned long long* tdev, unsigned int* done,
+                                                int nsub, unsigned int total) {
+  __syncthreads();  // every thread of the workgroup has read the counter
+  if (threadIdx.x == 0) {
+    const unsigned int j = blockIdx.x % DONE_SUBS;
+    const unsigned int in_sub = (total - j + DONE_SUBS - 1) / DONE_SUBS;
+    unsigned int* sub = done + DONE_STRIDE * j;
+    const unsigned int prev = __hip_atomic_fetch_add(sub, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == in_sub - 1) {
+      __hip_atomic_store(sub, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned int* top = done + DONE_STRIDE * DONE_SUBS;
+      const unsigned int n_subs = total < DONE_SUBS ? total : DONE_SUBS;
+      const unsigned int p2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+      if (p2 == n_subs - 1) {
+        __hip_atomic_fetch_add(tdev, (unsigned long long)nsub, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
 }
 
 // Body of one step (+ observation) over one workgroup's quads.
@@ -385,7 +423,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 #pragma unroll
             for (int u = 0; u < CH; ++u) cand(j0 + u, px[u][0], px[u][1], px[u][2]);
           };
-          if constexpr (NU > 16) {
+          if constexpr (NU >= 16) {
 #pragma unroll 1
             for (int j0 = 0; j0 < NU; j0 += CH) chunk(j0);
           } else {
@@ -558,21 +596,6 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   }
 }
 
-// The last workgroup to finish advances the graph-mode counter by nsub.
-__device__ __forceinline__ void advance_counter(unsigned long long* tdev, unsigned int* done,
-                                                int nsub) {
-  __syncthreads();  // every thread of the workgroup has read the counter
-  if (threadIdx.x == 0) {
-    const unsigned int prev =
-        __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == gridDim.x - 1) {
-      __hip_atomic_fetch_add(tdev, (unsigned long long)nsub, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-
 // Kernel arguments: the leading ones (state, parameters, actions, goals,
 // constants, sizes) are what the dense mapping needs before its first load
 // and fit the fourteen SGPRs the hardware can preload where the firmware
@@ -599,7 +622,7 @@ __global__ __launch_bounds__(BS) void step_kernel(float* __restrict__ st,
   constexpr int MAP = (N > 0) ? MAP_DENSE : MAP_TABLE;
   step_body<BS, KT, N, MAP>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
                             reinterpret_cast<float*>(st_obs4), 0, reward, tdev);
-  if (tdev) advance_counter(tdev, done, nsub);
+  if (tdev) advance_counter(tdev, done, nsub, gridDim.x);
 }
 
 // Several substeps per call for small batches of swarms of 8: two
@@ -636,21 +659,28 @@ __global__ __launch_bounds__(128) void step_pipe_kernel(float* __restrict__ st,
     step_body<BS, KT, N, MAP_DENSE, N, 1>(c, p, act, nsub, t0, goals, obs, stage_obs, sxv,
                                           reinterpret_cast<float*>(st_obs4), 0, reward, tdev,
                                           ring, rx);
-  if (tdev) advance_counter(tdev, done, nsub);
+  if (tdev) advance_counter(tdev, done, nsub, gridDim.x);
 }
 
-// Persistent launch over the work items of uneven swarm sizes: items of the
-// same slot size N run the body specialised for N (unrolled in-swarm loops);
-// workgroups stride over the item list.
+// Persistent launch over the work items [item0, item0 + n_items) of uneven
+// swarm sizes; workgroups stride over them and run the body specialised for
+// each item's slot size N.  Slots of 4 and more loop over the swarm at run
+// time, one partner at a time: unrolled, their bodies would set the whole
+// kernel's register count, and with it the occupancy (135 VGPRs instead of
+// 381: 3 wavefronts per SIMD instead of 1).  Slots of 16 and 32 also have a
+// body that takes the partners in chunks of four (their loads in flight
+// together), chosen per item (items[it].w, set per slot size by the
+// autotuner); with both bodies the kernel stays at 3 wavefronts per SIMD.
 template <int BS, int KT>
-__global__ __launch_bounds__(BS) void bucket_kernel(float* __restrict__ st,
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void bucket_kernel(
+                                                    float* __restrict__ st,
                                                     const float* __restrict__ par,
                                                     const float* __restrict__ act,
                                                     const float* __restrict__ goals,
                                                     const Consts* __restrict__ cp, int Qp, int Q,
                                                     int nsub, unsigned long long t0, Ptrs p,
-                                                    float* __restrict__ obs, int n_items,
-                                                    unsigned long long* tdev,
+                                                    float* __restrict__ obs, int item0,
+                                                    int n_items, unsigned long long* tdev,
                                                     unsigned int* done,
                                                     float* __restrict__ reward) {
   __shared__ float sxv[2][9][BS];
@@ -659,33 +689,37 @@ __global__ __launch_bounds__(BS) void bucket_kernel(float* __restrict__ st,
   p.Qp = Qp;
   p.Q = Q;
   const Consts& c = *cp;
-  if (tdev) t0 = read_counter(tdev);
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const int N = p.items[it].x;
+  for (int it = item0 + blockIdx.x; it < item0 + n_items; it += gridDim.x) {
     __syncthreads();  // the previous item's readers of the tile are done
-    // slots of 4 and more loop over the swarm at run time: unrolled, their
-    // bodies would set the whole kernel's register count (one kernel holds
-    // every slot size), and with it the occupancy (135 VGPRs instead of 381:
-    // 3 waves per SIMD instead of 1)
-    switch (N) {
-      case 1: step_body<BS, KT, 1, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 2: step_body<BS, KT, 2, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 4: step_body<BS, KT, 4, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 8: step_body<BS, KT, 8, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 16: step_body<BS, KT, 16, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      case 32: step_body<BS, KT, 32, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
-      default: step_body<BS, KT, 64, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward); break;
+    const int4 item = p.items[it];
+    const bool chunked = item.w != 0;
+    switch (item.x) {
+      case 1: step_body<BS, KT, 1, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
+      case 2: step_body<BS, KT, 2, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
+      case 4: step_body<BS, KT, 4, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
+      case 8: step_body<BS, KT, 8, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
+      case 16:
+        if (chunked) step_body<BS, KT, 16, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
+        else step_body<BS, KT, 16, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
+        break;
+      case 32:
+        if (chunked) step_body<BS, KT, 32, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
+        else step_body<BS, KT, 32, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
+        break;
+      default: step_body<BS, KT, 64, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
     }
   }
-  if (tdev) advance_counter(tdev, done, nsub);
+  if (tdev) advance_counter(tdev, done, nsub, gridDim.x);
 }
 
+// Set the graph-mode counter and clear the completion counts (one
+// workgroup of 64 threads).
 __global__ void set_counter_kernel(unsigned long long* tdev, unsigned int* done,
                                    unsigned long long v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    __hip_atomic_exchange(tdev, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_exchange(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x == 0) __hip_atomic_exchange(tdev, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = threadIdx.x; i <= DONE_SUBS; i += blockDim.x)
+    __hip_atomic_exchange(done + DONE_STRIDE * i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per-quad parameters [Q][6] (mass, ixx, iyy, izz, thrust-to-weight, tau_m)

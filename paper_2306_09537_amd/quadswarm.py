@@ -27,7 +27,7 @@ EXPORTS = ("qs_create", "qs_destroy", "qs_sizes", "qs_substep_index", "qs_step",
            "qs_step_observe", "qs_get_state", "qs_set_state", "qs_record_contacts",
            "qs_debug_contacts", "qs_sync", "qs_rollout", "qs_rollout_backward",
            "qs_step_backward", "qs_step_backward_noalloc", "qs_set_graph_mode", "qs_set_launch",
-           "qs_autotune", "qs_set_reward_weights", "qs_step_observe_reward", "qs_set_params",
+           "qs_autotune", "qs_set_partner_chunks", "qs_launch_plan", "qs_set_reward_weights", "qs_step_observe_reward", "qs_set_params",
            "qs_debug_philox", "qs_error_string")
 
 
@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
         L.qs_set_graph_mode.argtypes = [vp, i32, vp]
         L.qs_autotune.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.qs_set_launch.argtypes = [vp, i32, i32]
+        L.qs_set_partner_chunks.argtypes = [vp, C.c_uint32]
+        L.qs_launch_plan.argtypes = [vp, vp, C.POINTER(i32)]
         L.qs_error_string.argtypes = [C.c_int]
         L.qs_error_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -372,14 +374,35 @@ class QuadSwarm:
         _check(lib().qs_set_launch(self._h, int(block), int(grid)), "qs_set_launch")
 
     def autotune(self, actions, n_substeps: int, goals=None, out=None) -> dict:
-        """qs_autotune: returns the chosen (block, grid, bucketed)."""
+        """qs_autotune: returns the chosen (block, grid, bucketed) and the
+        per-slot-size plan (launch_plan)."""
         self._dev(actions, (self.n_quads, 4))
         ch = (C.c_int32 * 3)()
         _check(lib().qs_autotune(self._h, _ptr(actions), int(n_substeps),
                                  None if goals is None else _ptr(goals),
                                  None if out is None else _ptr(out), ch, _stream(self._di)),
                "qs_autotune")
-        return {"block": ch[0], "grid": ch[1], "bucketed": bool(ch[2])}
+        return {"block": ch[0], "grid": ch[1], "bucketed": bool(ch[2]),
+                "slots": self.launch_plan()}
+
+    def set_partner_chunks(self, slots) -> None:
+        """qs_set_partner_chunks: the slot sizes (16, 32) whose items take
+        the in-swarm partners in chunks of four in the bucketed form."""
+        mask = 0
+        for n in slots:
+            mask |= 1 << (int(n).bit_length() - 1)
+        _check(lib().qs_set_partner_chunks(self._h, mask), "qs_set_partner_chunks")
+
+    def launch_plan(self) -> list:
+        """qs_launch_plan: per slot size, its swarms, whether its items take
+        the chunked body, and the autotuner's times (ns) for its items with
+        the one-partner and with the chunked body."""
+        buf = (C.c_int32 * 35)()
+        n = C.c_int32()
+        _check(lib().qs_launch_plan(self._h, buf, C.byref(n)), "qs_launch_plan")
+        return [{"slot": buf[5 * r], "swarms": buf[5 * r + 1], "chunked": bool(buf[5 * r + 2]),
+                 "ns_one": buf[5 * r + 3], "ns_chunked": buf[5 * r + 4]}
+                for r in range(n.value)]
 
     def sync(self) -> None:
         _check(lib().qs_sync(self._h, _stream(self._di)), "qs_sync")

@@ -58,6 +58,73 @@ def test_bucketed_equals_table_path_bitwise(k, monkeypatch):
         assert torch.equal(ca, cb)
 
 
+@pytest.mark.parametrize("k,obs", [(6, True), (6, False), (3, True), (0, True)])
+def test_chunked_partner_bodies_equal_table_path_bitwise(k, obs, monkeypatch):
+    """Slots of 16 and 32 with the chunked partner body: results equal the
+    table path bit for bit, in eager calls and replays of a captured graph."""
+    w = W.custom(mixed_sizes(3, 150), seed=3, k=k, name="mixed")
+    monkeypatch.setenv("QS_BUCKETED", "0")
+    ref = QuadSwarm.from_workload(w)
+    monkeypatch.setenv("QS_BUCKETED", "1")
+    sim = QuadSwarm.from_workload(w)
+    sim.set_partner_chunks([16, 32])
+    plan = sim.launch_plan()
+    assert [r["slot"] for r in plan] == [64, 32, 16, 8, 4, 2, 1]
+    assert [r["chunked"] for r in plan] == [False, True, True, False, False, False, False]
+    assert sum(r["swarms"] for r in plan) == w.n_envs
+    g = dev(w.goals)
+    for c in range(5):
+        a = dev(w.actions(c))
+        if obs:
+            assert torch.equal(sim.step_observe(a, 4, g), ref.step_observe(a, 4, g))
+        else:
+            sim.step(a, 4)
+            ref.step(a, 4)
+    assert torch.equal(sim.get_state()[0], ref.get_state()[0])
+    # graph mode
+    nsub, calls = 3, 3
+    acts = torch.stack([dev(w.actions(10 + c)) for c in range(calls)])
+    out = torch.empty((calls, w.n_quads, w.obs_dim), device="cuda")
+    sim.set_graph_mode(True)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for c in range(calls):
+            sim.step_observe(acts[c], nsub, g, out[c])
+    for r in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        for c in range(calls):
+            assert torch.equal(out[c], ref.step_observe(acts[c], nsub, g)), f"replay {r} call {c}"
+    sim.set_graph_mode(False)
+    sim.sync()
+
+
+def test_autotune_per_slot_table():
+    """The autotuner times the items of slots 16 and 32 alone with each
+    partner body and keeps the chunked one only where it was faster; the
+    table lists every slot size with its swarm count."""
+    w = W.uneven(seed=9, n_envs=4096)
+    sim = QuadSwarm.from_workload(w)
+    g = dev(w.goals)
+    out = torch.empty((w.n_quads, w.obs_dim), device="cuda")
+    choice = sim.autotune(dev(w.actions(0)), 10, g, out)
+    print("autotune", choice)
+    sizes, counts = np.unique(w.env_sizes, return_counts=True)
+    slots = {r["slot"]: r for r in choice["slots"]}
+    assert set(slots) == set(int(x) for x in sizes)
+    for n, cnt in zip(sizes, counts):
+        assert slots[int(n)]["swarms"] == cnt
+    for n in (16, 32):
+        r = slots[n]
+        assert r["ns_one"] > 0 and r["ns_chunked"] > 0
+        if r["chunked"]:
+            assert r["ns_chunked"] < r["ns_one"]
+    for n in (1, 2, 4, 8):
+        assert not slots[n]["chunked"] and slots[n]["ns_one"] == 0
+    sim.sync()
+
+
 def test_bucketed_uneven_parity_with_oracle():
     w = W.uneven(seed=3, n_envs=400)
     st = teacher_forced(w, 60)
