@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libquadswarm.so")
 SOURCES = [os.path.join(CSRC, "qs_abi.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("qs_device.h", "qs_kernels.h", "qs_adjoint.h",
-                                                  "qs_rollout.h")] + [
+                                                  "qs_rollout.h", "qs_checks.h")] + [
     os.path.join(INCLUDE, "quadswarm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -335,6 +335,46 @@ def _custom_sim(state, params=None, flags=0, k=0, sizes=None, **c):
     return QuadSwarm(offs, consts(**c), p, state, k, flags, 3)
 
 
+def test_high_spin_divergence_is_the_integrators():
+    """The oracle's own pin (test_explicit_euler_diverges_at_high_spin): a
+    torque-free symmetric top at 500 rad/s, whose transverse rate grows by
+    x2.16 per substep under the stated integrator until rounding of the
+    gyroscopic term moves the axial rate and the state turns non-finite
+    (substep 51 in double).  On the GPU, one substep per call: teacher-
+    forced parity with the oracle while the transverse rate is small enough
+    that float32 rounding of that term is negligible; the first non-finite
+    state comes earlier than in double (the same mechanism at float32's
+    epsilon, |w_xy| above ~1e6), and qs_sync reports QS_ERR_NONFINITE."""
+    from tests.test_oracle_pins import spin_divergence_state
+    s0 = spin_divergence_state()
+    sim = _custom_sim(s0.astype(np.float32), gravity=0.0)
+    orc = O.Oracle(np.array([0, 1], np.int32), consts(gravity=0.0), nominal_params(1), 0, 0, 3)
+    a = -np.ones((1, 4), np.float32)
+    fm = U.fmax_of(nominal_params(1))
+    prev = s0.astype(np.float32).astype(np.float64)
+    first_bad, last_wxy, checked = None, 0.0, 0
+    for n in range(1, 100):
+        sim.step(dev(a), 1)
+        st, _ = sim.get_state()
+        g = st.cpu().numpy().astype(np.float64)
+        if not np.isfinite(g).all():
+            first_bad = n
+            break
+        wxy = float(np.hypot(prev[0, W.SW], prev[0, W.SW + 1]))
+        if wxy < 1e4:
+            ref, _, _ = orc.step(prev, a.astype(np.float64), 1, n - 1)
+            assert U.rel_err(g, ref, fm).max() <= U.TOL, n
+            checked += 1
+        prev, last_wxy = g, float(np.hypot(g[0, W.SW], g[0, W.SW + 1]))
+    print("GPU first non-finite substep", first_bad, "last finite |w_xy|", last_wxy,
+          "teacher-forced substeps", checked)
+    assert first_bad is not None and first_bad < 51
+    assert checked >= 10 and last_wxy > 1e6
+    with pytest.raises(QuadSwarmError) as ei:
+        sim.sync()
+    assert ei.value.code == -5
+
+
 def test_gpu_hover_and_free_fall():
     s = blank_state(2, z=50.0)
     s[0, W.SU:W.SU + 4] = math.sqrt(0.5)

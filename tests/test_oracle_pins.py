@@ -248,6 +248,44 @@ def test_symmetric_top_precession():
         assert traj[n][0, W.SW + 2] == pytest.approx(w0[2], abs=1e-13)
 
 
+def spin_divergence_state():
+    """A torque-free symmetric top spinning at 500 rad/s about body z with a
+    small transverse rate (no thrust, no gravity)."""
+    s = blank_state(1)
+    s[0, W.SW:W.SW + 3] = [0.4, -0.3, 500.0]
+    s[0, W.SU:W.SU + 4] = 0.0
+    return s
+
+
+def test_explicit_euler_diverges_at_high_spin():
+    """The integrator the method states diverges by itself at very high spin:
+    the transverse body rate of a torque-free symmetric top grows by
+    sqrt(1 + kappa^2) per substep, kappa = dt w_z (Jz - Jx)/Jx = 1.91 at
+    w_z = 500 rad/s (x2.16 per substep), as the closed form says, until the
+    rounding of the gyroscopic term (|w_xy|^2 J eps, no longer small against
+    w_z once |w_xy| ~ 1e10 in double) moves w_z as well and the state turns
+    non-finite within a few dozen substeps.  Non-finite quads in long
+    random rollouts are this, not a kernel error: in float32 the same happens
+    earlier (|w_xy| ~ 1e7)."""
+    Jx, Jz = 1.66e-5, 2.93e-5
+    orc = make(1, gravity=0.0)
+    s = spin_divergence_state()
+    kap = DT * 500.0 * (Jz - Jx) / Jx
+    g = math.sqrt(1 + kap * kap)
+    a = -np.ones((1, 4))
+    first_bad = None
+    for n in range(1, 200):
+        s, _, _ = orc.step(s, a, 1, n - 1)
+        if not np.isfinite(s).all():
+            first_bad = n
+            break
+        if n in (5, 10, 15):
+            wxy = np.hypot(s[0, W.SW], s[0, W.SW + 1])
+            assert wxy == pytest.approx(0.5 * g ** n, rel=1e-9), n
+            assert s[0, W.SW + 2] == pytest.approx(500.0, rel=1e-9), n
+    assert first_bad is not None and 30 < first_bad < 100, first_bad
+
+
 def test_torque_free_energy_and_world_momentum():
     """General inertia, no torque: kinetic energy w.J.w and world angular
     momentum R J w are conserved up to the integrator's O(dt^2) per step.
