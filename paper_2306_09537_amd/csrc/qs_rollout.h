@@ -531,32 +531,34 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // reverse_pipe_kernel: the reverse sweep of reverse_kernel for small batches
-// (one wavefront per SIMD or fewer), split over two wavefronts per
-// workgroup of 64 quads.  Wavefront 0 re-runs the substeps from the tape
-// (quad_substep with its record, the post-motion exchange, the contact set,
-// the penalty's adjoint) one substep ahead and passes each quad's record
-// through a two-slot LDS ring; wavefront 1 differentiates the substep whose
-// record is ready (response adjoint, quad_vjp) and holds the adjoint state.
-// The two halves of a substep are independent across consecutive substeps,
-// so they run side by side on two SIMDs; one workgroup barrier per substep
-// hands a slot over.  Same arithmetic in the same order as reverse_kernel,
-// so the results are identical.
+// (one wavefront per SIMD or fewer), as a three-stage pipeline over the
+// substeps (last to first) on three wavefronts per workgroup of 64 quads:
+//  - wavefront 0 re-runs the motor part of a substep (lag, noise, thrust,
+//    mix) from the taped rotor state and draws, two substeps ahead of the
+//    differentiation, and hands the thrust, the torques and the rotor fields
+//    of the record on through a three-slot LDS ring;
+//  - wavefront 1 re-runs the body part of that substep from the taped pose
+//    and rates one substep later (body_step with its record, the post-motion
+//    exchange, the contact set, the penalty's adjoint) and hands the body
+//    fields of the record on through a two-slot ring;
+//  - wavefront 2 differentiates the substep whose record is complete
+//    (response adjoint, quad_vjp) and holds the adjoint state.
+// A substep's re-run starts from its taped state, so it does not wait for
+// the substep after it; one workgroup barrier per substep hands the slots
+// over.  Same arithmetic in the same order as reverse_kernel, so the results
+// are identical.
 // ---------------------------------------------------------------------------
-constexpr int REC_FLOATS = 61;  // the float fields of Rec
-// ring words of one quad and substep: Rec floats, Rec flags and the
-// response flag, contact set, penalty adjoint
-constexpr int RING_WORDS = REC_FLOATS + 1 + 1 + 3;
+constexpr int REC_BODY = 49;  // the float fields of Rec that body_step sets
+// ring words of one quad and substep: the body fields, Rec's flags and the
+// response flag, the contact set, the penalty's adjoint
+constexpr int RING_WORDS = REC_BODY + 1 + 1 + 3;
+// motor ring words: draws, rotor speeds before and after, thrust and torques
+constexpr int MOTOR_WORDS = 16;
 
 template <typename R, typename F>
-__device__ __forceinline__ void rec_floats(R& r, F&& f) {
+__device__ __forceinline__ void rec_body_floats(R& r, F&& f) {
   int w = 0;
   auto g = [&](auto& v) { f(w++, v); };
-#pragma unroll
-  for (int k = 0; k < 4; ++k) g(r.z[k]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) g(r.u0[k]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) g(r.u1[k]);
 #pragma unroll
   for (int k = 0; k < 9; ++k) g(r.P[k]);
 #pragma unroll
@@ -592,8 +594,35 @@ __device__ __forceinline__ bool rec_unflag(Rec& r, uint32_t b) {
   return (b >> 12) & 1u;
 }
 
+// The rotor state and the draws of one tape row.
+__device__ __forceinline__ void load_rotor(const Consts& c, const float* __restrict__ row,
+                                           long long ld, int q, float u[4], float e[4],
+                                           float z[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    u[k] = row[(S_U + k) * ld + q];
+    e[k] = row[(S_E + k) * ld + q];
+  }
+  load_draws(c, row, ld, q, z);
+}
+
+// Position, velocity, attitude, body rates and the floor flag of one tape row.
+__device__ __forceinline__ void load_body(const float* __restrict__ row, long long ld, int q,
+                                          Quad& s) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s.x[k] = row[(S_X + k) * ld + q];
+    s.v[k] = row[(S_V + k) * ld + q];
+    s.w[k] = row[(S_W + k) * ld + q];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s.R[k] = row[(S_R + k) * ld + q];
+  s.fl = row[S_F * ld + q];
+  s.ev = 0u;
+}
+
 template <int N, bool PEN>
-__global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
+__global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
                                                            const float* __restrict__ act,
                                                            int ncalls, int nsub,
                                                            unsigned long long t0,
@@ -604,11 +633,12 @@ __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restr
                                                            float* __restrict__ gpar) {
   constexpr int BS = 64;
   static_assert(N == 1 || N == 8, "pipelined reverse sweep for swarms of 1 or 8");
-  // tile slots as in reverse_kernel: rows 0-8 post-motion start position,
-  // displacement, velocity (wavefront 0); 9-11 adjoint of the collision
-  // velocity change (wavefront 1); 12 penalty weights (both slots)
+  // Slots are indexed by the substep k.  Tile rows 0-8 post-motion start
+  // position, displacement, velocity (wavefront 1); 9-11 adjoint of the
+  // collision velocity change (wavefront 2); 12 penalty weights.
   __shared__ float tl[2][13][BS];
   __shared__ float ring[2][RING_WORDS][BS];
+  __shared__ float mring[3][MOTOR_WORDS][BS];
   const Consts& c = *cp;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int tid = threadIdx.x & 63;
@@ -625,26 +655,22 @@ __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restr
   QuadPar pp;
   ParAdj pa;
   if (live) load_params(p, c, q, pp, pa);
-  if (PEN && wave == 1) {
+  if (PEN && wave == 2) {
     const float g = live ? gpen[q] : 0.f;
     tl[0][12][tid] = g;
     tl[1][12][tid] = g;
   }
-  wg_sync();
 
   if (wave == 0) {
-    // ---- re-run: substep k = n_steps - 1 - i at step i
-    Quad s, sn;
-    float z[4], zn[4] = {0.f, 0.f, 0.f, 0.f};
+    // ---- motor part of substep k = n_steps - 1 - i at step i
+    float un[4], en[4], zn[4] = {0.f, 0.f, 0.f, 0.f};
     float uhat[4] = {0.f, 0.f, 0.f, 0.f};
     float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live && n_steps > 0) {
-      const float* row = tape + (long long)(n_steps - 1) * NTAPE * Q;
-      load_state(row, Q, q, sn);
-      load_draws(c, row, Q, q, zn);
+      load_rotor(c, tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, un, en, zn);
       a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
     }
-    for (int i = 0; i <= n_steps; ++i) {
+    for (int i = 0; i < n_steps + 2; ++i) {
       if (i < n_steps) {
         const int k = n_steps - 1 - i;
         const int call = k / nsub, sub = k - call * nsub;
@@ -653,24 +679,59 @@ __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restr
           if (live && call > 0) a_nx = load_act(act + (long long)(call - 1) * Q * 4, q);
           if (live) act_uhat(c, p, a4, uhat);
         }
+        if (live) {
+          float u[4], e[4], zi[4], z[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            u[m] = un[m];
+            e[m] = en[m];
+            zi[m] = zn[m];
+          }
+          if (k > 0) load_rotor(c, tape + (long long)(k - 1) * NTAPE * Q, Q, q, un, en, zn);
+          float(*ms)[BS] = mring[k % 3];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) ms[4 + m][tid] = u[m];
+          const Drive d = motor_step<Z_IMPORT>(c, pp, u, e, uhat, (uint32_t)q,
+                                               t0 + (unsigned long long)k, z, zi);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            ms[m][tid] = z[m];
+            ms[8 + m][tid] = u[m];
+          }
+          ms[12][tid] = d.T;
+          ms[13][tid] = d.tx;
+          ms[14][tid] = d.ty;
+          ms[15][tid] = d.tz;
+        }
+      }
+      wg_sync();
+    }
+  } else if (wave == 1) {
+    // ---- body part of substep k = n_steps - i at step i >= 1
+    Quad sn;
+    if (live && n_steps > 0) load_body(tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, sn);
+    wg_sync();  // step 0: no thrust yet
+    for (int i = 1; i < n_steps + 2; ++i) {
+      if (i <= n_steps) {
+        const int k = n_steps - i;
+        Quad s;
         Rec r;
         if (live) {
           s = sn;
-#pragma unroll
-          for (int m = 0; m < 4; ++m) z[m] = zn[m];
-          if (k > 0) {
-            const float* row = tape + (long long)(k - 1) * NTAPE * Q;
-            load_state(row, Q, q, sn);
-            load_draws(c, row, Q, q, zn);
-          }
-          quad_substep<true, Z_IMPORT>(c, pp, s, uhat, (uint32_t)q, t0 + (unsigned long long)k,
-                                       &r, z);
+          if (k > 0) load_body(tape + (long long)(k - 1) * NTAPE * Q, Q, q, sn);
+          const float(*ms)[BS] = mring[k % 3];
+          Drive d;
+          d.T = ms[12][tid];
+          d.tx = ms[13][tid];
+          d.ty = ms[14][tid];
+          d.tz = ms[15][tid];
+          body_step<true>(c, pp, s, d, (uint32_t)q, t0 + (unsigned long long)k, &r);
         }
         unsigned long long cm = 0ull;
         bool hit = false;
         float pen3[3] = {0.f, 0.f, 0.f};
         if (pairs) {
-          float(*tile)[BS] = tl[i & 1];
+          float(*tile)[BS] = tl[k & 1];
           if (live) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
@@ -686,18 +747,18 @@ __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restr
           }
         }
         if (live) {
-          float(*slot)[BS] = ring[i & 1];
-          rec_floats(r, [&](int w, const float& v) { slot[w][tid] = v; });
-          slot[REC_FLOATS][tid] = __uint_as_float(rec_flags(r, hit));
-          slot[REC_FLOATS + 1][tid] = __uint_as_float((uint32_t)cm);
+          float(*slot)[BS] = ring[k & 1];
+          rec_body_floats(r, [&](int w, const float& v) { slot[w][tid] = v; });
+          slot[REC_BODY][tid] = __uint_as_float(rec_flags(r, hit));
+          slot[REC_BODY + 1][tid] = __uint_as_float((uint32_t)cm);
 #pragma unroll
-          for (int m = 0; m < 3; ++m) slot[REC_FLOATS + 2 + m][tid] = pen3[m];
+          for (int m = 0; m < 3; ++m) slot[REC_BODY + 2 + m][tid] = pen3[m];
         }
       }
       wg_sync();
     }
   } else {
-    // ---- differentiate: substep k = n_steps - i at step i >= 1
+    // ---- differentiate substep k = n_steps + 1 - i at step i >= 2
     Adj l;
     float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (live) {
@@ -719,9 +780,10 @@ __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restr
     float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live && n_steps > 0) a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
-    wg_sync();  // step 0: nothing to differentiate yet
-    for (int i = 1; i <= n_steps; ++i) {
-      const int k = n_steps - i;
+    wg_sync();  // steps 0 and 1: no record complete yet
+    wg_sync();
+    for (int i = 2; i < n_steps + 2; ++i) {
+      const int k = n_steps + 1 - i;
       const int call = k / nsub, sub = k - call * nsub;
       if (sub == nsub - 1) {
         a4 = a_nx;
@@ -730,19 +792,25 @@ __global__ __launch_bounds__(128) void reverse_pipe_kernel(const Consts* __restr
 #pragma unroll
         for (int m = 0; m < 4; ++m) gu[m] = 0.f;
       }
-      const int sl = (i - 1) & 1;
       if (live) {
-        const float(*slot)[BS] = ring[sl];
+        const float(*slot)[BS] = ring[k & 1];
+        const float(*ms)[BS] = mring[k % 3];
         Rec r;
-        rec_floats(r, [&](int w, float& v) { v = slot[w][tid]; });
-        const bool hit = rec_unflag(r, __float_as_uint(slot[REC_FLOATS][tid]));
-        const unsigned long long cm = __float_as_uint(slot[REC_FLOATS + 1][tid]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          r.z[m] = ms[m][tid];
+          r.u0[m] = ms[4 + m][tid];
+          r.u1[m] = ms[8 + m][tid];
+        }
+        rec_body_floats(r, [&](int w, float& v) { v = slot[w][tid]; });
+        const bool hit = rec_unflag(r, __float_as_uint(slot[REC_BODY][tid]));
+        const unsigned long long cm = __float_as_uint(slot[REC_BODY + 1][tid]);
         if constexpr (PEN) {
 #pragma unroll
-          for (int m = 0; m < 3; ++m) l.x[m] += slot[REC_FLOATS + 2 + m][tid];
+          for (int m = 0; m < 3; ++m) l.x[m] += slot[REC_BODY + 2 + m][tid];
         }
         if (pairs) {
-          float(*tile)[BS] = tl[sl];
+          float(*tile)[BS] = tl[k & 1];
           float ldv[3] = {0.f, 0.f, 0.f};
           if (hit) {
 #pragma unroll
