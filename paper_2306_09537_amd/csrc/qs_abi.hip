@@ -407,7 +407,7 @@ void go_recompute(qs_handle* h, const AdjScratch& sc, const float* ckpt, const f
                      ptrs(h), ckpt, act, ncalls, ce, nsub, (unsigned long long)t0, sc.tape);
 }
 
-// The three-wavefront reverse sweep pays where the batch leaves SIMDs idle:
+// The four-wavefront reverse sweep pays where the batch leaves SIMDs idle:
 // up to 1024 workgroups of 64 quads (QS_REVERSE_PIPE=0/1 forces it off/on).
 bool use_reverse_pipe(const qs_handle* h) {
   if (const char* e = std::getenv("QS_REVERSE_PIPE")) return e[0] == '1';
@@ -417,7 +417,7 @@ bool use_reverse_pipe(const qs_handle* h) {
 template <int N, bool PEN>
 void go_reverse_pipe(qs_handle* h, const AdjScratch& sc, const float* act, int ncalls, int nsub,
                      uint64_t t0, const float* gpen, float beta, float* gact, hipStream_t s) {
-  hipLaunchKernelGGL((qs::reverse_pipe_kernel<N, PEN>), dim3(h->nblk), dim3(192), 0, s, h->d_c,
+  hipLaunchKernelGGL((qs::reverse_pipe_kernel<N, PEN>), dim3(h->nblk), dim3(256), 0, s, h->d_c,
                      ptrs(h), act, ncalls, nsub, (unsigned long long)t0, sc.tape, sc.lam, gpen,
                      beta, gact, sc.gpar);
 }

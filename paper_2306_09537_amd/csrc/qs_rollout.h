@@ -531,29 +531,31 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // reverse_pipe_kernel: the reverse sweep of reverse_kernel for small batches
-// (one wavefront per SIMD or fewer), as a three-stage pipeline over the
-// substeps (last to first) on three wavefronts per workgroup of 64 quads:
-//  - wavefront 0 re-runs the motor part of a substep (lag, noise, thrust,
-//    mix) from the taped rotor state and draws, two substeps ahead of the
-//    differentiation, and hands the thrust, the torques and the rotor fields
-//    of the record on through a three-slot LDS ring;
-//  - wavefront 1 re-runs the body part of that substep from the taped pose
-//    and rates one substep later (body_step with its record, the post-motion
-//    exchange, the contact set, the penalty's adjoint) and hands the body
-//    fields of the record on through a two-slot ring;
-//  - wavefront 2 differentiates the substep whose record is complete
-//    (response adjoint, quad_vjp) and holds the adjoint state.
-// A substep's re-run starts from its taped state, so it does not wait for
-// the substep after it; one workgroup barrier per substep hands the slots
-// over.  Same arithmetic in the same order as reverse_kernel, so the results
-// are identical.
+// (one wavefront per SIMD or fewer), as a four-stage pipeline over the
+// substeps (last to first) on four wavefronts per workgroup of 64 quads, one
+// per SIMD of the compute unit.  Substep k passes through
+//  - wavefront 0 at step i: the motor part re-run (lag, noise, thrust, mix)
+//    from the taped rotor state and draws; the thrust, the torques and the
+//    rotor fields of the record go on through a four-slot LDS ring;
+//  - wavefront 1 at step i + 1: the body part re-run (body_step with its
+//    record) from the taped pose and rates; the post-motion exchange tile and
+//    the body fields of the record go on through three-slot rings;
+//  - wavefront 2 at step i + 2: the contact set, the approach test and the
+//    penalty's adjoint from the exchange tile, through a two-slot ring;
+//  - wavefront 3 at step i + 3: the derivative (response adjoint, quad_vjp);
+//    it holds the adjoint state.
+// A substep's re-run starts from its taped state, so no stage waits for the
+// substep after it; one workgroup barrier per step hands the slots over.
+// Same arithmetic in the same order as reverse_kernel, so the results are
+// identical.
 // ---------------------------------------------------------------------------
 constexpr int REC_BODY = 49;  // the float fields of Rec that body_step sets
-// ring words of one quad and substep: the body fields, Rec's flags and the
-// response flag, the contact set, the penalty's adjoint
-constexpr int RING_WORDS = REC_BODY + 1 + 1 + 3;
+// ring words of the body stage: the body fields and Rec's flags
+constexpr int RING_WORDS = REC_BODY + 1;
 // motor ring words: draws, rotor speeds before and after, thrust and torques
 constexpr int MOTOR_WORDS = 16;
+// contact ring words: response flag, contact set, penalty adjoint
+constexpr int CON_WORDS = 5;
 
 template <typename R, typename F>
 __device__ __forceinline__ void rec_body_floats(R& r, F&& f) {
@@ -570,16 +572,15 @@ __device__ __forceinline__ void rec_body_floats(R& r, F&& f) {
   g(r.hx); g(r.hy); g(r.nh); g(r.kx); g(r.ky); g(r.nk);
 }
 
-__device__ __forceinline__ uint32_t rec_flags(const Rec& r, bool pair_hit) {
+__device__ __forceinline__ uint32_t rec_flags(const Rec& r) {
   uint32_t b = (uint32_t)r.rest | (uint32_t)r.statik << 1 | (uint32_t)r.guard << 2 |
-               (uint32_t)r.bounced << 3 | (uint32_t)r.hit << 4 | (uint32_t)r.fallback << 5 |
-               (uint32_t)pair_hit << 12;
+               (uint32_t)r.bounced << 3 | (uint32_t)r.hit << 4 | (uint32_t)r.fallback << 5;
 #pragma unroll
   for (int k = 0; k < 3; ++k) b |= (uint32_t)r.clamp[k] << (6 + k) | (uint32_t)r.flip[k] << (9 + k);
   return b;
 }
 
-__device__ __forceinline__ bool rec_unflag(Rec& r, uint32_t b) {
+__device__ __forceinline__ void rec_unflag(Rec& r, uint32_t b) {
   r.rest = b & 1u;
   r.statik = (b >> 1) & 1u;
   r.guard = (b >> 2) & 1u;
@@ -591,7 +592,6 @@ __device__ __forceinline__ bool rec_unflag(Rec& r, uint32_t b) {
     r.clamp[k] = (b >> (6 + k)) & 1u;
     r.flip[k] = (b >> (9 + k)) & 1u;
   }
-  return (b >> 12) & 1u;
 }
 
 // The rotor state and the draws of one tape row.
@@ -622,7 +622,7 @@ __device__ __forceinline__ void load_body(const float* __restrict__ row, long lo
 }
 
 template <int N, bool PEN>
-__global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
+__global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
                                                            const float* __restrict__ act,
                                                            int ncalls, int nsub,
                                                            unsigned long long t0,
@@ -635,10 +635,11 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
   static_assert(N == 1 || N == 8, "pipelined reverse sweep for swarms of 1 or 8");
   // Slots are indexed by the substep k.  Tile rows 0-8 post-motion start
   // position, displacement, velocity (wavefront 1); 9-11 adjoint of the
-  // collision velocity change (wavefront 2); 12 penalty weights.
-  __shared__ float tl[2][13][BS];
-  __shared__ float ring[2][RING_WORDS][BS];
-  __shared__ float mring[3][MOTOR_WORDS][BS];
+  // collision velocity change (wavefront 3); 12 penalty weights.
+  __shared__ float tl[3][13][BS];
+  __shared__ float ring[3][RING_WORDS][BS];
+  __shared__ float mring[4][MOTOR_WORDS][BS];
+  __shared__ float cring[2][CON_WORDS][BS];
   const Consts& c = *cp;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int tid = threadIdx.x & 63;
@@ -651,14 +652,15 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
   const bool collide = (c.flags & F_COLLIDE) != 0;
   const bool pairs = N != 1 && (collide || PEN);
   const int n_steps = ncalls * nsub;
+  const int n_pipe = n_steps + 3;  // steps of the pipeline
 
   QuadPar pp;
   ParAdj pa;
   if (live) load_params(p, c, q, pp, pa);
   if (PEN && wave == 2) {
     const float g = live ? gpen[q] : 0.f;
-    tl[0][12][tid] = g;
-    tl[1][12][tid] = g;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) tl[m][12][tid] = g;
   }
 
   if (wave == 0) {
@@ -670,7 +672,7 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
       load_rotor(c, tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, un, en, zn);
       a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
     }
-    for (int i = 0; i < n_steps + 2; ++i) {
+    for (int i = 0; i < n_pipe; ++i) {
       if (i < n_steps) {
         const int k = n_steps - 1 - i;
         const int call = k / nsub, sub = k - call * nsub;
@@ -688,7 +690,7 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
             zi[m] = zn[m];
           }
           if (k > 0) load_rotor(c, tape + (long long)(k - 1) * NTAPE * Q, Q, q, un, en, zn);
-          float(*ms)[BS] = mring[k % 3];
+          float(*ms)[BS] = mring[k & 3];
 #pragma unroll
           for (int m = 0; m < 4; ++m) ms[4 + m][tid] = u[m];
           const Drive d = motor_step<Z_IMPORT>(c, pp, u, e, uhat, (uint32_t)q,
@@ -711,54 +713,63 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
     Quad sn;
     if (live && n_steps > 0) load_body(tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, sn);
     wg_sync();  // step 0: no thrust yet
-    for (int i = 1; i < n_steps + 2; ++i) {
-      if (i <= n_steps) {
+    for (int i = 1; i < n_pipe; ++i) {
+      if (i <= n_steps && live) {
         const int k = n_steps - i;
-        Quad s;
+        Quad s = sn;
+        if (k > 0) load_body(tape + (long long)(k - 1) * NTAPE * Q, Q, q, sn);
+        const float(*ms)[BS] = mring[k & 3];
+        Drive d;
+        d.T = ms[12][tid];
+        d.tx = ms[13][tid];
+        d.ty = ms[14][tid];
+        d.tz = ms[15][tid];
         Rec r;
-        if (live) {
-          s = sn;
-          if (k > 0) load_body(tape + (long long)(k - 1) * NTAPE * Q, Q, q, sn);
-          const float(*ms)[BS] = mring[k % 3];
-          Drive d;
-          d.T = ms[12][tid];
-          d.tx = ms[13][tid];
-          d.ty = ms[14][tid];
-          d.tz = ms[15][tid];
-          body_step<true>(c, pp, s, d, (uint32_t)q, t0 + (unsigned long long)k, &r);
-        }
-        unsigned long long cm = 0ull;
-        bool hit = false;
-        float pen3[3] = {0.f, 0.f, 0.f};
+        body_step<true>(c, pp, s, d, (uint32_t)q, t0 + (unsigned long long)k, &r);
         if (pairs) {
-          float(*tile)[BS] = tl[k & 1];
-          if (live) {
+          float(*tile)[BS] = tl[k % 3];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-              tile[m][tid] = s.xo[m];
-              tile[3 + m][tid] = s.inc[m];
-              tile[6 + m][tid] = s.v[m];
-            }
-          }
-          wave_sync();
-          if (live) {
-            cm = mark_contacts<BS, N, PEN>(c, tile, s, ls, n, me, beta, tile[12][tid], pen3);
-            hit = any_response<BS>(c, tile, s, ls, me, cm);
+          for (int m = 0; m < 3; ++m) {
+            tile[m][tid] = s.xo[m];
+            tile[3 + m][tid] = s.inc[m];
+            tile[6 + m][tid] = s.v[m];
           }
         }
-        if (live) {
-          float(*slot)[BS] = ring[k & 1];
-          rec_body_floats(r, [&](int w, const float& v) { slot[w][tid] = v; });
-          slot[REC_BODY][tid] = __uint_as_float(rec_flags(r, hit));
-          slot[REC_BODY + 1][tid] = __uint_as_float((uint32_t)cm);
+        float(*slot)[BS] = ring[k % 3];
+        rec_body_floats(r, [&](int w, const float& v) { slot[w][tid] = v; });
+        slot[REC_BODY][tid] = __uint_as_float(rec_flags(r));
+      }
+      wg_sync();
+    }
+  } else if (wave == 2) {
+    // ---- contacts of substep k = n_steps + 1 - i at step i >= 2
+    wg_sync();  // steps 0 and 1: no exchange tile yet
+    wg_sync();
+    for (int i = 2; i < n_pipe; ++i) {
+      if (pairs && i <= n_steps + 1 && live) {
+        const int k = n_steps + 1 - i;
+        const float(*tile)[BS] = tl[k % 3];
+        Quad so;  // the quad's post-motion position and velocity
 #pragma unroll
-          for (int m = 0; m < 3; ++m) slot[REC_BODY + 2 + m][tid] = pen3[m];
+        for (int m = 0; m < 3; ++m) {
+          so.xo[m] = tile[m][tid];
+          so.inc[m] = tile[3 + m][tid];
+          so.v[m] = tile[6 + m][tid];
         }
+        float pen3[3] = {0.f, 0.f, 0.f};
+        const unsigned long long cm =
+            mark_contacts<BS, N, PEN>(c, tile, so, ls, n, me, beta, tile[12][tid], pen3);
+        const bool hit = any_response<BS>(c, tile, so, ls, me, cm);
+        float(*cs)[BS] = cring[k & 1];
+        cs[0][tid] = hit ? 1.f : 0.f;
+        cs[1][tid] = __uint_as_float((uint32_t)cm);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) cs[2 + m][tid] = pen3[m];
       }
       wg_sync();
     }
   } else {
-    // ---- differentiate substep k = n_steps + 1 - i at step i >= 2
+    // ---- differentiate substep k = n_steps + 2 - i at step i >= 3
     Adj l;
     float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (live) {
@@ -780,10 +791,11 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
     float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live && n_steps > 0) a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
-    wg_sync();  // steps 0 and 1: no record complete yet
+    wg_sync();  // steps 0 to 2: no record complete yet
     wg_sync();
-    for (int i = 2; i < n_steps + 2; ++i) {
-      const int k = n_steps + 1 - i;
+    wg_sync();
+    for (int i = 3; i < n_pipe; ++i) {
+      const int k = n_steps + 2 - i;
       const int call = k / nsub, sub = k - call * nsub;
       if (sub == nsub - 1) {
         a4 = a_nx;
@@ -793,8 +805,8 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
         for (int m = 0; m < 4; ++m) gu[m] = 0.f;
       }
       if (live) {
-        const float(*slot)[BS] = ring[k & 1];
-        const float(*ms)[BS] = mring[k % 3];
+        const float(*slot)[BS] = ring[k % 3];
+        const float(*ms)[BS] = mring[k & 3];
         Rec r;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -803,14 +815,16 @@ __global__ __launch_bounds__(192) void reverse_pipe_kernel(const Consts* __restr
           r.u1[m] = ms[8 + m][tid];
         }
         rec_body_floats(r, [&](int w, float& v) { v = slot[w][tid]; });
-        const bool hit = rec_unflag(r, __float_as_uint(slot[REC_BODY][tid]));
-        const unsigned long long cm = __float_as_uint(slot[REC_BODY + 1][tid]);
-        if constexpr (PEN) {
-#pragma unroll
-          for (int m = 0; m < 3; ++m) l.x[m] += slot[REC_BODY + 2 + m][tid];
-        }
+        rec_unflag(r, __float_as_uint(slot[REC_BODY][tid]));
         if (pairs) {
-          float(*tile)[BS] = tl[k & 1];
+          const float(*cs)[BS] = cring[k & 1];
+          const bool hit = cs[0][tid] != 0.f;
+          const unsigned long long cm = __float_as_uint(cs[1][tid]);
+          if constexpr (PEN) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) l.x[m] += cs[2 + m][tid];
+          }
+          float(*tile)[BS] = tl[k % 3];
           float ldv[3] = {0.f, 0.f, 0.f};
           if (hit) {
 #pragma unroll
