@@ -381,7 +381,8 @@ void go_roll(qs_handle* h, const float* act, int ncalls, int nsub, float* ckpt, 
              float beta, hipStream_t s) {
   if constexpr (BS == 64 && (N == 1 || N == 8)) {
     if (use_rollout_pipe(h)) {
-      hipLaunchKernelGGL((qs::rollout_pipe_kernel<N, PEN>), dim3(h->nblk), dim3(128), 0, s, h->d_c,
+      hipLaunchKernelGGL((qs::rollout_pipe_kernel<N, PEN>), dim3(h->nblk),
+                         dim3(64 * qs::kRollWaves<N, PEN>), 0, s, h->d_c,
                          ptrs(h), act, ncalls, nsub, (unsigned long long)h->t, ckpt, ce, pen, beta);
       return;
     }

@@ -683,6 +683,22 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   return cmask;
 }
 
+// The smoothed collision penalty of one live lane alone: the PEN term of
+// pair_pass (same partners, same order, same arithmetic), for a wavefront
+// that sums it apart from the motion.
+template <int BS, int N>
+__device__ __forceinline__ void penalty_pass(const Consts& c, const float (*tile)[BS],
+                                             const Quad& s, int ls, int n, int me, float& pacc,
+                                             float beta) {
+  const float hb = 0.5f / beta;  // each quad of a pair carries half
+  for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
+    float dx, dy, dz, d2;
+    pair_geom_v(c, pj, s, dx, dy, dz, d2);
+    const float sp = hb * softplus_hw(beta * (c.dcol - __builtin_amdgcn_sqrtf(d2)));
+    pacc = jj != me ? pacc + sp : pacc;
+  });
+}
+
 // §III-C sensor noise on the own-state part of an observation row:
 // U(-sn_x, sn_x) on x - goal, U(-sn_v, sn_v) on v, N(0, sn_w^2) on omega,
 // from stream SENSOR at the observation's substep index.

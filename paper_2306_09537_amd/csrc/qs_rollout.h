@@ -883,18 +883,24 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
 }
 
 // ---------------------------------------------------------------------------
-// rollout_pipe_kernel: rollout_kernel for small batches, over two wavefronts
-// per workgroup of 64 quads.  The motor part of a substep (lag, noise,
-// thrust, mix) depends on the rotor state, the action and the substep's
-// draws only, so wavefront 0 runs it one substep ahead and hands the thrust
-// and torques (4 words per quad) to wavefront 1 through a two-slot LDS
-// ring; wavefront 1 runs the body part, the in-swarm pass and the penalty.
-// One workgroup barrier per substep; each wavefront stores its own fields
-// of the checkpoints and of the final state.  Same arithmetic in the same
-// order as rollout_kernel, so the results are identical.
+// rollout_pipe_kernel: rollout_kernel for small batches, over two or three
+// wavefronts per workgroup of 64 quads.  The motor part of a substep (lag,
+// noise, thrust, mix) depends on the rotor state, the action and the
+// substep's draws only, so wavefront 0 runs it one substep ahead and hands
+// the thrust and torques (4 words per quad) to wavefront 1 through a
+// two-slot LDS ring; wavefront 1 runs the body part and the in-swarm pass.
+// The smoothed collision penalty never feeds back into the motion, so in
+// swarms with a penalty wavefront 2 sums it one substep behind, from the
+// post-motion exchange tile.  One workgroup barrier per substep; each
+// wavefront stores its own fields of the checkpoints and of the final state.
+// Same arithmetic in the same order as rollout_kernel, so the results are
+// identical.
 // ---------------------------------------------------------------------------
 template <int N, bool PEN>
-__global__ __launch_bounds__(128) void rollout_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
+constexpr int kRollWaves = (PEN && N != 1) ? 3 : 2;
+
+template <int N, bool PEN>
+__global__ __launch_bounds__(192) void rollout_pipe_kernel(const Consts* __restrict__ cp, Ptrs p,
                                                            const float* __restrict__ act,
                                                            int ncalls, int nsub,
                                                            unsigned long long t0,
@@ -902,6 +908,7 @@ __global__ __launch_bounds__(128) void rollout_pipe_kernel(const Consts* __restr
                                                            int ckpt_every,
                                                            float* __restrict__ pen, float beta) {
   constexpr int BS = 64;
+  constexpr bool PW = kRollWaves<N, PEN> == 3;  // penalty on its own wavefront
   static_assert(N == 1 || N == 8, "pipelined rollout for swarms of 1 or 8");
   __shared__ float sxv[2][9][BS];
   __shared__ float ring[2][4][BS];
@@ -915,6 +922,7 @@ __global__ __launch_bounds__(128) void rollout_pipe_kernel(const Consts* __restr
   const int me = tid - ls;
   const long long Q = p.Q;
   const int n_steps = ncalls * nsub;
+  const int n_pipe = n_steps + (PW ? 2 : 1);  // steps of the pipeline
   QuadPar pp;
   ParAdj pa;
   if (live) load_params(p, c, q, pp, pa);
@@ -932,7 +940,7 @@ __global__ __launch_bounds__(128) void rollout_pipe_kernel(const Consts* __restr
     float uhat[4] = {0.f, 0.f, 0.f, 0.f};
     float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live && ncalls > 0) a_nx = load_act(act, q);
-    for (int i = 0; i <= n_steps; ++i) {
+    for (int i = 0; i < n_pipe; ++i) {
       if (i < n_steps) {
         const int call = i / nsub, sub = i - call * nsub;
         if (sub == 0) {
@@ -967,50 +975,54 @@ __global__ __launch_bounds__(128) void rollout_pipe_kernel(const Consts* __restr
         p.st[(S_E + k) * p.Qp + q] = e[k];
       }
     }
-  } else {
-    // ---- body part, in-swarm pass and penalty of substep i - 1 at step i
+  } else if (wave == 1) {
+    // ---- body part and in-swarm pass of substep i - 1 at step i
     Quad s;
     if (live) load_state(p.st, p.Qp, q, s);
     const bool pairs = N != 1 && ((c.flags & (F_COLLIDE | F_DOWNWASH)) != 0 || PEN);
     float pacc = 0.f;
     wg_sync();  // step 0: no thrust yet
-    for (int i = 1; i <= n_steps; ++i) {
-      const int sidx = i - 1;
-      const int call = sidx / nsub, sub = sidx - call * nsub;
-      if (sub == 0 && ckpt && call % ckpt_every == 0 && live) {
-        float* ck = ckpt + (long long)(call / ckpt_every) * NSTATE * Q;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          ck[(S_X + k) * Q + q] = s.x[k];
-          ck[(S_V + k) * Q + q] = s.v[k];
-          ck[(S_W + k) * Q + q] = s.w[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 9; ++k) ck[(S_R + k) * Q + q] = s.R[k];
-        ck[S_F * Q + q] = s.fl;
-      }
-      const unsigned long long t = t0 + (unsigned long long)sidx;
-      if (live) {
-        const float(*slot)[BS] = ring[sidx & 1];
-        Drive d;
-        d.T = slot[0][tid];
-        d.tx = slot[1][tid];
-        d.ty = slot[2][tid];
-        d.tz = slot[3][tid];
-        body_step(c, pp, s, d, (uint32_t)q, t);
-      }
-      if (pairs) {
-        float(*tile)[BS] = sxv[sidx & 1];
-        if (live) {
+    for (int i = 1; i < n_pipe; ++i) {
+      if (i <= n_steps) {
+        const int sidx = i - 1;
+        const int call = sidx / nsub, sub = sidx - call * nsub;
+        if (sub == 0 && ckpt && call % ckpt_every == 0 && live) {
+          float* ck = ckpt + (long long)(call / ckpt_every) * NSTATE * Q;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            tile[k][tid] = s.xo[k];
-            tile[3 + k][tid] = s.inc[k];
-            tile[6 + k][tid] = s.v[k];
+            ck[(S_X + k) * Q + q] = s.x[k];
+            ck[(S_V + k) * Q + q] = s.v[k];
+            ck[(S_W + k) * Q + q] = s.w[k];
           }
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ck[(S_R + k) * Q + q] = s.R[k];
+          ck[S_F * Q + q] = s.fl;
         }
-        wave_sync();
-        if (live) pair_pass<BS, kUnroll<N>, PEN>(c, tile, s, ls, n, me, (uint32_t)q, t, pacc, beta);
+        const unsigned long long t = t0 + (unsigned long long)sidx;
+        if (live) {
+          const float(*slot)[BS] = ring[sidx & 1];
+          Drive d;
+          d.T = slot[0][tid];
+          d.tx = slot[1][tid];
+          d.ty = slot[2][tid];
+          d.tz = slot[3][tid];
+          body_step(c, pp, s, d, (uint32_t)q, t);
+        }
+        if (pairs) {
+          float(*tile)[BS] = sxv[sidx & 1];
+          if (live) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              tile[k][tid] = s.xo[k];
+              tile[3 + k][tid] = s.inc[k];
+              tile[6 + k][tid] = s.v[k];
+            }
+          }
+          wave_sync();
+          if (live)
+            pair_pass<BS, kUnroll<N>, PEN && !PW>(c, tile, s, ls, n, me, (uint32_t)q, t, pacc,
+                                                 beta);
+        }
       }
       wg_sync();
     }
@@ -1031,11 +1043,31 @@ __global__ __launch_bounds__(128) void rollout_pipe_kernel(const Consts* __restr
       for (int k = 0; k < 9; ++k) chk += s.R[k];
       if (!isfinite(chk))
         __hip_atomic_fetch_or(p.err, ERRBIT_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if constexpr (PEN) pen[q] += pacc;
+      if constexpr (PEN && !PW) pen[q] += pacc;
     }
+  } else if constexpr (PW) {
+    // ---- penalty of substep i - 2 at step i, from the exchange tile
+    float pacc = 0.f;
+    wg_sync();  // steps 0 and 1: no tile yet
+    wg_sync();
+    for (int i = 2; i < n_pipe; ++i) {
+      if (live) {
+        const float(*tile)[BS] = sxv[(i - 2) & 1];
+        Quad so;  // the quad's start position and displacement
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          so.xo[k] = tile[k][tid];
+          so.inc[k] = tile[3 + k][tid];
+        }
+        penalty_pass<BS, kUnroll<N>>(c, tile, so, ls, n, me, pacc, beta);
+      }
+      wg_sync();
+    }
+    if (live) pen[q] += pacc;
   }
 }
 
+// ---------------------------------------------------------------------------
 // [rows][Q] field-major <-> [Q][rows] row-major conversions (optionally
 // adding into the destination).
 __global__ void fm_to_rm_kernel(const float* __restrict__ src, float* __restrict__ dst, int Q,
