@@ -594,6 +594,45 @@ __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
   }
 }
 
+// Rows of the exchange tile that hold each quad's post-motion position
+// (x after walls and floor), written beside rows 0-8 by kernels whose
+// in-swarm pass screens partners on it (pair_pass with CO).
+constexpr int XROW = 9;
+constexpr int TILE_ROWS_CO = XROW + 3;
+
+// Calls f(jj, pj) for every swarm-mate jj (itself included) with pj[0..2]
+// its post-motion position from rows XROW..XROW+2, read a chunk of
+// partners ahead of their arithmetic (chunk sizes as for_partners).
+template <int BS, int N, typename T, typename F>
+__device__ __forceinline__ void for_partner_pos(T tile, int ls, int n, F&& f) {
+  if constexpr (N > 0) {
+    constexpr int CH = N < 8 ? N : (N >= 16 ? 4 : 8);
+    auto chunk = [&](int j0) {
+      float pj[CH][3];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) pj[u][r] = tile[XROW + r][ls + j0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) f(j0 + u, pj[u]);
+    };
+    if constexpr (N >= 16) {
+#pragma unroll 1
+      for (int j0 = 0; j0 < N; j0 += CH) chunk(j0);
+    } else {
+#pragma unroll
+      for (int j0 = 0; j0 < N; j0 += CH) chunk(j0);
+    }
+  } else {
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = ls + jj;
+      const float pj[3] = {tile[XROW][j], tile[XROW + 1][j], tile[XROW + 2][j]};
+      f(jj, pj);
+    }
+  }
+}
+
 // In-swarm pass of one live lane after the tile (start positions,
 // displacements, velocities) is written and the workgroup synchronised:
 // §III-B.1 contact detection and Jacobi velocity exchange (every response
@@ -601,7 +640,15 @@ __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
 // and §III-B.4 downwash from the swarm-mates above, applied as a velocity
 // kick after the response.  N > 0 unrolls over the swarm slot; padding
 // partners hold far-away sentinels.  Returns the contact mask.
-template <int BS, int N, bool PEN>
+// CO (no penalty, tile rows XROW.. written): without downwash, partners are
+// first screened on the post-motion positions with a contact distance
+// widened by 1 mm, and the exact test runs for the survivors only.  The
+// screen never drops a pair the exact test would mark: for positions within
+// 1000 m of the origin, x differs from (start + displacement) by at most an
+// ulp of 1000 (6.1e-5 m) per quad and axis, well inside the 1 mm; a lane
+// further out tests every partner exactly.  So the contact set, and every
+// result, is the same as without the screen.
+template <int BS, int N, bool PEN, bool CO = false>
 __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const float (*tile)[BS],
                                                         Quad& s, int ls, int n, int me,
                                                         uint32_t q, unsigned long long t,
@@ -635,10 +682,29 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
       dwhit = dwhit | dwc;
     }
   };
-  if (c.flags & F_DOWNWASH)
+  if (c.flags & F_DOWNWASH) {
     for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, TrueT{}); });
-  else
+  } else if constexpr (CO && !PEN) {
+    const float dw = c.dcol + 1e-3f, thr = dw * dw;
+    M cand = 0;
+    for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
+      const float dx = pj[0] - s.x[0], dy = pj[1] - s.x[1], dz = pj[2] - s.x[2];
+      cand |= dx * dx + dy * dy + dz * dz < thr ? (M)1 << jj : (M)0;
+    });
+    const bool near_origin =
+        fmaxf(fabsf(s.x[0]), fmaxf(fabsf(s.x[1]), fabsf(s.x[2]))) <= 1000.0f;
+    if (!near_origin) cand = (M)(n >= 64 ? ~0ull : (1ull << n) - 1ull);
+    // the quad itself (distance 0) leaves the contact mask below anyway
+    cand &= ~((M)1 << me);
+    for (unsigned long long m = cand; m != 0ull; m &= m - 1ull) {
+      const int jj = __builtin_ctzll(m);
+      const int j = ls + jj;
+      const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
+      pair(jj, pj, FalseT{});
+    }
+  } else {
     for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, FalseT{}); });
+  }
   const unsigned long long cmask = collide ? (unsigned long long)(cm & ~((M)1 << me)) : 0ull;
   // The responses, for the partners in contact only, in partner order.
   for (unsigned long long m = cmask; m != 0ull; m &= m - 1ull) {

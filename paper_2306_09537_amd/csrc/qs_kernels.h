@@ -78,7 +78,7 @@ __device__ __forceinline__ void advance_counter(unsigned long long* tdev, unsign
 // N: swarm (slot) size known at compile time (MAP_DENSE, MAP_ITEM), or 0.
 // NU: partner count the in-swarm loops are unrolled for (N, or 0 for loops
 // over the swarm's runtime size: fewer registers for large slots).
-// sxv: LDS tile [2][9][BS]; st_obs: LDS staging of observation rows.
+// sxv: LDS tile [2][TILE_ROWS_CO][BS]; st_obs: LDS staging of observation rows.
 // ROLE: -1 one wavefront does everything; in a workgroup of two wavefronts
 // over the same 64 quads (step_pipe_kernel), 0 runs the motor part of every
 // substep one substep ahead and hands thrust and torques through ring, 1
@@ -90,7 +90,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
                                           unsigned long long t0,
                                           const float* __restrict__ goals,
                                           float* __restrict__ obs, int stage_obs,
-                                          float (*sxv)[9][BS], float* st_obs, int item,
+                                          float (*sxv)[TILE_ROWS_CO][BS], float* st_obs, int item,
                                           float* __restrict__ reward,
                                           const unsigned long long* tdev = nullptr,
                                           float (*ring)[4][BS] = nullptr,
@@ -273,6 +273,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           tile[k][tid] = s.xo[k];
           tile[3 + k][tid] = s.inc[k];
           tile[6 + k][tid] = s.v[k];
+          tile[XROW + k][tid] = s.x[k];
         }
       } else if constexpr (MAP == MAP_ITEM) {
         // padding lane: far away, so it is never in contact
@@ -281,13 +282,14 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           tile[k][tid] = 1e30f;
           tile[3 + k][tid] = 0.f;
           tile[6 + k][tid] = 0.f;
+          tile[XROW + k][tid] = 1e30f;
         }
       }
       quad_sync();
       cmask = 0ull;
       if (live) {
         float unused = 0.f;
-        cmask = pair_pass<BS, NU, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
+        cmask = pair_pass<BS, NU, false, true>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
       }
     }
   }
@@ -612,7 +614,7 @@ __global__ __launch_bounds__(BS) void step_kernel(float* __restrict__ st,
                                                   float* __restrict__ obs, int stage_obs,
                                                   unsigned long long* tdev, unsigned int* done,
                                                   float* __restrict__ reward) {
-  __shared__ float sxv[2][9][BS];
+  __shared__ float sxv[2][TILE_ROWS_CO][BS];
   extern __shared__ float4 st_obs4[];
   p.st = st;
   p.par = par;
@@ -641,7 +643,7 @@ __global__ __launch_bounds__(128) void step_pipe_kernel(float* __restrict__ st,
                                                         unsigned int* done,
                                                         float* __restrict__ reward) {
   constexpr int BS = 64;
-  __shared__ float sxv[2][9][BS];
+  __shared__ float sxv[2][TILE_ROWS_CO][BS];
   __shared__ float ring[2][4][BS];
   __shared__ float rx[12][BS];
   extern __shared__ float4 st_obs4[];
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void bu
                                                     int n_items, unsigned long long* tdev,
                                                     unsigned int* done,
                                                     float* __restrict__ reward) {
-  __shared__ float sxv[2][9][BS];
+  __shared__ float sxv[2][TILE_ROWS_CO][BS];
   p.st = st;
   p.par = par;
   p.Qp = Qp;

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
                                                        const float* __restrict__ act, int ncalls,
                                                        int ce, int nsub, unsigned long long t0,
                                                        float* __restrict__ tape) {
-  __shared__ float sxv[2][9][BS];
+  __shared__ float sxv[2][TILE_ROWS_CO][BS];
   const Consts& c = *cp;
   const int tid = threadIdx.x;
   int qb, cnt, ls, n;
@@ -278,11 +278,12 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
             tile[k][tid] = s.xo[k];
             tile[3 + k][tid] = s.inc[k];
             tile[6 + k][tid] = s.v[k];
+            tile[XROW + k][tid] = s.x[k];
           }
         }
         __syncthreads();
         float unused = 0.f;
-        if (live) pair_pass<BS, N, false>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
+        if (live) pair_pass<BS, N, false, true>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
       }
     }
   }
@@ -910,7 +911,7 @@ __global__ __launch_bounds__(192) void rollout_pipe_kernel(const Consts* __restr
   constexpr int BS = 64;
   constexpr bool PW = kRollWaves<N, PEN> == 3;  // penalty on its own wavefront
   static_assert(N == 1 || N == 8, "pipelined rollout for swarms of 1 or 8");
-  __shared__ float sxv[2][9][BS];
+  __shared__ float sxv[2][TILE_ROWS_CO][BS];
   __shared__ float ring[2][4][BS];
   const Consts& c = *cp;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1016,12 +1017,13 @@ __global__ __launch_bounds__(192) void rollout_pipe_kernel(const Consts* __restr
               tile[k][tid] = s.xo[k];
               tile[3 + k][tid] = s.inc[k];
               tile[6 + k][tid] = s.v[k];
+              tile[XROW + k][tid] = s.x[k];
             }
           }
           wave_sync();
           if (live)
-            pair_pass<BS, kUnroll<N>, PEN && !PW>(c, tile, s, ls, n, me, (uint32_t)q, t, pacc,
-                                                 beta);
+            pair_pass<BS, kUnroll<N>, PEN && !PW, !(PEN && !PW)>(c, tile, s, ls, n, me,
+                                                                (uint32_t)q, t, pacc, beta);
         }
       }
       wg_sync();
