@@ -229,13 +229,14 @@ bool use_step_pipe(const qs_handle* h) {
 // Observation rows per staging pass.  A grid of at most 2048 workgroups
 // has at most two per SIMD, which LDS never limits: the whole workgroup's
 // rows in one pass (fewest synchronisations; 4096 x 8: 6.7 us per launch
-// against 7.0 us in two passes).  Larger grids stage at most 8 KiB at a
-// time (K = 6, 64 quads: 2 passes of 32 rows, 6.9 KiB), so that LDS does
-// not hold the number of resident workgroups below what the registers
-// allow: at 32768 x 32 a 13.5 KiB staging area held the step to 2
-// wavefronts per SIMD instead of 3 (104 -> 98 us per one-substep launch,
-// 347 -> 278 us per ten-substep launch).  QS_STAGE_ROWS=n overrides (0:
-// every lane stores its own row, 131 us).
+// against 7.0 us in two passes).  Larger grids keep the staging area and the
+// exchange tile together within 10 KiB per wavefront of the workgroup
+// (160 KiB of LDS over the four wavefronts per SIMD that the step's
+// registers allow), so that LDS does not hold the resident workgroups below
+// what the registers allow.  At 32768 x 32 (K = 6, 64-quad workgroups, a
+// 6 KiB tile) that is 16 rows per pass: ten substeps per call 40.8 -> 50.9 G
+// quad-steps/s against 32 rows (13.0 KiB per workgroup, three wavefronts
+// per SIMD).  QS_STAGE_ROWS=n overrides (0: every lane stores its own row).
 int stage_rows(int bs, int od, int nblk) {
   static const int forced = [] {
     const char* e = std::getenv("QS_STAGE_ROWS");
@@ -243,8 +244,11 @@ int stage_rows(int bs, int od, int nblk) {
   }();
   if (forced >= 0 && forced <= bs && (forced & (forced - 1)) == 0) return forced;
   const size_t row = (size_t)od * sizeof(float);
+  const size_t tile = 2 * qs::TILE_ROWS_CO * (size_t)bs * sizeof(float);
+  const size_t budget = (size_t)(bs / 64) * 10 * 1024;
+  size_t cap = budget > tile ? budget - tile : 0;
+  if (nblk <= 2048) cap = 48 * 1024;
   int r = bs;
-  const size_t cap = nblk <= 2048 ? 48 * 1024 : 8192;
   while (r > 8 && (size_t)r * row > cap) r >>= 1;
   return r;
 }

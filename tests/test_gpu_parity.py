@@ -335,6 +335,46 @@ def _custom_sim(state, params=None, flags=0, k=0, sizes=None, **c):
     return QuadSwarm(offs, consts(**c), p, state, k, flags, 3)
 
 
+@pytest.mark.parametrize("center", [0.0, 990.0, 1010.0, 5000.0])
+def test_partner_screen_keeps_every_contact(center):
+    """The in-swarm pass screens partners on their post-motion positions
+    with the contact distance widened by 1 mm and runs the exact test for
+    the survivors only; a quad beyond 1000 m from the origin tests every
+    partner exactly.  Swarms of 8 strung out in chains whose links straddle
+    d_col (0.09 - 0.11 m), placed `center` metres from the origin (float32
+    position spacing there up to 4.9e-4 m): the contact sets equal the
+    oracle's apart from pairs within 1e-6 m of d_col."""
+    rng = np.random.default_rng(int(center) + 21)
+    n_sw, n = 64, 8
+    q = n_sw * n
+    s = blank_state(q, z=5.0)
+    for e in range(n_sw):
+        pos = [np.array([center, 3.0 * e, 5.0])]
+        for _ in range(1, n):
+            u = rng.normal(size=3)
+            pos.append(pos[-1] + 0.1 * (1 + rng.uniform(-0.1, 0.1)) * u / np.linalg.norm(u))
+        s[e * n:(e + 1) * n, 0:3] = pos
+    s[:, W.SV:W.SV + 3] = rng.normal(0, 0.05, size=(q, 3))
+    s32 = s.astype(np.float32)
+    sizes = [n] * n_sw
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    sim = _custom_sim(s32, flags=W.QS_COLLIDE, sizes=sizes, gravity=0.0)
+    sim.record_contacts(True)
+    a = np.full((q, 4), -1.0, np.float32)
+    sim.step(dev(a), 1)
+    out = sim.get_state()[0].cpu().numpy().astype(np.float64)
+    c_gpu = sim.debug_contacts().cpu().numpy().view(np.uint64)
+    sim.sync()
+    sim.close()
+    orc = O.Oracle(offs, consts(gravity=0.0), nominal_params(q), 0, W.QS_COLLIDE, 3)
+    ref, c_ref, _, _ = orc.step(s32.astype(np.float64), a.astype(np.float64), 1, 0, margins=True)
+    n_contacts = int(sum(bin(int(x)).count("1") for x in c_ref))
+    assert n_contacts > q // 2, n_contacts
+    ties = U.check_contacts(c_gpu, c_ref, out[:, 0:3], ref[:, 0:3], offs.astype(np.int64), 0.1)
+    print(f"center {center} m: {n_contacts} contact bits, {ties} ties")
+    assert ties <= 2
+
+
 def test_high_spin_divergence_is_the_integrators():
     """The oracle's own pin (test_explicit_euler_diverges_at_high_spin): a
     torque-free symmetric top at 500 rad/s, whose transverse rate grows by
