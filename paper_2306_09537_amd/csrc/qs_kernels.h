@@ -359,21 +359,23 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   if constexpr (OBS) {
     // §III-C observation from the post-collision state
     float(*tile)[BS] = sxv[nsub & 1];
-    if (live) {
+    if constexpr (KT != 0) {  // the neighbour slots come from the tile
+      if (live) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        tile[k][tid] = s.x[k];
-        tile[6 + k][tid] = s.v[k];
-      }
-    } else if constexpr (MAP == MAP_ITEM) {
-      // padding lane: never among the nearest
+        for (int k = 0; k < 3; ++k) {
+          tile[k][tid] = s.x[k];
+          tile[6 + k][tid] = s.v[k];
+        }
+      } else if constexpr (MAP == MAP_ITEM) {
+        // padding lane: never among the nearest
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        tile[k][tid] = 1e30f;
-        tile[6 + k][tid] = 0.f;
+        for (int k = 0; k < 3; ++k) {
+          tile[k][tid] = 1e30f;
+          tile[6 + k][tid] = 0.f;
+        }
       }
+      quad_sync();
     }
-    quad_sync();
     if constexpr (KT >= 0) {
       constexpr int OD = 18 + 6 * KT;
       float ov[OD];
