@@ -36,12 +36,17 @@
  *                            block instead of the persistent bucketed
  *                            launch, read by qs_create;
  *      QS_STEP_PIPE, QS_ROLLOUT_PIPE, QS_REVERSE_PIPE = 0|1
- *                            force the two-wavefront form of multi-substep
- *                            step calls (uniform 8-quad swarms), of
- *                            qs_rollout and of the reverse sweep of
- *                            qs_rollout_backward (swarms of 1 or 8) off or
- *                            on; default on up to 1024 workgroups; read on
+ *                            force the multi-wavefront forms off or on:
+ *                            multi-substep step calls on two wavefronts
+ *                            per workgroup (uniform 8-quad swarms),
+ *                            qs_rollout on two (three with the penalty in
+ *                            8-quad swarms) and the reverse sweep of
+ *                            qs_rollout_backward on four (swarms of 1 or
+ *                            8); default on up to 1024 workgroups; read on
  *                            every call;
+ *      QS_STAGE_ROWS=n       observation rows per LDS staging pass (a power
+ *                            of two up to the workgroup size; 0: each lane
+ *                            stores its own row), read once;
  *      QS_TAPE_BYTES         tape budget of qs_rollout_backward (below).
  *
  * Canonical layouts (row-major, float32):

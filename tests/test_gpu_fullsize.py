@@ -147,6 +147,18 @@ def test_scale1_full_size_sampled(nsub, calls):
     assert worst <= U.TOL * nsub
 
 
+def test_large_grid_ragged_tail_sampled():
+    """More than 2048 workgroups, so the observation rows leave in several
+    staging passes per workgroup, with a partly filled last workgroup:
+    16,390 swarms of 8 (2049 workgroups of 64 quads, 48 in the last).
+    Sampled at the start, the middle and the last swarms."""
+    w = W.custom([8] * 16390, seed=11, k=6, name="ragged_16390x8")
+    assert w.n_quads % 64 == 48
+    worst = sampled_teacher_forced(w, 3, 1, [(0, 8), (8000, 8016), (16374, 16390)], U.TOL)
+    print("ragged large grid worst", worst)
+    assert worst <= U.TOL
+
+
 def test_maximum_size_sampled():
     """The largest handle the library takes: 2^26 single-quad swarms (its
     quad limit), 64 tiles of the 1,048,576 x 1 workload's parameters and
