@@ -280,7 +280,8 @@ void go(qs_handle* h, const float* act, int nsub, const float* goals, float* obs
 template <int BS, int KT>
 void go_range(qs_handle* h, int item0, int count, int grid, const float* act, int nsub,
               const float* goals, float* obs, hipStream_t s, float* rw) {
-  hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), 0, s,
+  const size_t dyn = KT >= 0 ? (size_t)qs::BUCKET_STAGE_ROWS * (18 + 6 * KT) * sizeof(float) : 0;
+  hipLaunchKernelGGL((qs::bucket_kernel<BS, KT>), dim3(std::max(grid, 1)), dim3(BS), dyn, s,
                      h->d_st, h->d_par, act, goals, h->d_c, h->Qp, h->Q, nsub,
                      (unsigned long long)h->t, ptrs(h), obs, item0, count,
                      h->graph_mode ? h->d_t : nullptr, h->d_done, rw);

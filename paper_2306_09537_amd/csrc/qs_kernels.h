@@ -511,6 +511,29 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
         // ends).  A small staging area (a few KiB) keeps LDS from limiting
         // how many workgroups share a CU.
         const int R = stage_obs;
+        if constexpr (MAP == MAP_ITEM) {
+          // an item's swarms are separate runs of rows: a pass (whole
+          // swarms, R being a multiple of the slot size) leaves swarm by
+          // swarm, each run with contiguous 8-byte stores
+          const int4 itm = p.items[item];
+          for (int p0 = 0; p0 < itm.z * N; p0 += R) {
+            if (live && tid >= p0 && tid < p0 + R) {
+              float2* r2 = reinterpret_cast<float2*>(st_obs + (tid - p0) * OD);
+#pragma unroll
+              for (int k = 0; k < OD / 2; ++k) r2[k] = make_float2(ov[2 * k], ov[2 * k + 1]);
+            }
+            quad_sync();
+            const int k1 = min((p0 + R) / N, itm.z);
+            for (int k = p0 / N; k < k1; ++k) {
+              const int2 e = p.item_envs[itm.y + k];
+              const int n2 = e.y * OD / 2;
+              v2f* d2p = reinterpret_cast<v2f*>(obs + (size_t)e.x * OD);
+              const v2f* s2p = reinterpret_cast<const v2f*>(st_obs + (k * N - p0) * OD);
+              for (int i = tid; i < n2; i += BS) __builtin_nontemporal_store(s2p[i], d2p + i);
+            }
+            if (p0 + R < itm.z * N) quad_sync();
+          }
+        } else
         for (int p0 = 0; p0 < cnt; p0 += R) {
           if (live && tid >= p0 && tid < p0 + R) {
             float2* r2 = reinterpret_cast<float2*>(st_obs + (tid - p0) * OD);
@@ -666,6 +689,13 @@ __global__ __launch_bounds__(128) void step_pipe_kernel(float* __restrict__ st,
   if (tdev) advance_counter(tdev, done, nsub, gridDim.x);
 }
 
+// Observation rows per staging pass of the bucketed kernel (slots of 4 to
+// 32 quads, whose swarms are runs of several rows: per-lane row stores
+// measured 7 % slower on the one-substep uneven launch, 5.09 -> 5.48 G
+// quad-steps/s staged; slots of 1 and 2 would copy one short run per swarm
+// and keep per-lane stores).
+constexpr int BUCKET_STAGE_ROWS = 32;
+
 // Persistent launch over the work items [item0, item0 + n_items) of uneven
 // swarm sizes; workgroups stride over them and run the body specialised for
 // each item's slot size N.  Slots of 4 and more loop over the swarm at run
@@ -688,6 +718,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void bu
                                                     unsigned int* done,
                                                     float* __restrict__ reward) {
   __shared__ float sxv[2][TILE_ROWS_CO][BS];
+  extern __shared__ float4 st_obs4[];
+  float* so = reinterpret_cast<float*>(st_obs4);
+  // slots of 4 to 32 stage their observation rows, 32 rows a pass
+  constexpr int SR = KT >= 0 ? BUCKET_STAGE_ROWS : 0;
   p.st = st;
   p.par = par;
   p.Qp = Qp;
@@ -700,15 +734,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void bu
     switch (item.x) {
       case 1: step_body<BS, KT, 1, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
       case 2: step_body<BS, KT, 2, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
-      case 4: step_body<BS, KT, 4, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
-      case 8: step_body<BS, KT, 8, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
+      case 4: step_body<BS, KT, 4, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, SR, sxv, so, it, reward, tdev); break;
+      case 8: step_body<BS, KT, 8, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, SR, sxv, so, it, reward, tdev); break;
       case 16:
-        if (chunked) step_body<BS, KT, 16, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
-        else step_body<BS, KT, 16, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
+        if (chunked) step_body<BS, KT, 16, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, SR, sxv, so, it, reward, tdev);
+        else step_body<BS, KT, 16, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, SR, sxv, so, it, reward, tdev);
         break;
       case 32:
-        if (chunked) step_body<BS, KT, 32, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
-        else step_body<BS, KT, 32, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev);
+        if (chunked) step_body<BS, KT, 32, MAP_ITEM>(c, p, act, nsub, t0, goals, obs, SR, sxv, so, it, reward, tdev);
+        else step_body<BS, KT, 32, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, SR, sxv, so, it, reward, tdev);
         break;
       default: step_body<BS, KT, 64, MAP_ITEM, 0>(c, p, act, nsub, t0, goals, obs, 0, sxv, nullptr, it, reward, tdev); break;
     }
