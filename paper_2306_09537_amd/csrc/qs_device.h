@@ -687,10 +687,52 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   } else if constexpr (CO && !PEN) {
     const float dw = c.dcol + 1e-3f, thr = dw * dw;
     M cand = 0;
-    for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
-      const float dx = pj[0] - s.x[0], dy = pj[1] - s.x[1], dz = pj[2] - s.x[2];
-      cand |= dx * dx + dy * dy + dz * dz < thr ? (M)1 << jj : (M)0;
-    });
+    if constexpr (N == 8) {
+      // Each unordered pair screened once: the lane screens partner
+      // me + o (mod N) for o = 1 .. N/2 and takes from lane me - o its
+      // screen of the same pair (the squared distance is symmetric bit for
+      // bit); for o = N/2 both lanes of the pair screen it.  Bit b of rot
+      // stands for partner me + b (mod N).  A swarm never straddles a
+      // wavefront.  Half the screens for a lane permute per pair: in swarms
+      // of 8 the forward rollout at 1024 x 8 went from 0.242 to 0.225 ms;
+      // in swarms of 32 the per-lane tile reads and permutes cost more than
+      // the broadcast reads of the plain screen (ten substeps at
+      // 32768 x 32: 49.1 -> 47.4 G quad-steps/s), so larger swarms keep it.
+      const int base = ((ls + me) & 63) - me;  // the swarm's first lane
+      uint32_t rot = 0u;
+      // offsets four at a time (their reads ahead of their arithmetic); a
+      // run-time loop over the groups keeps the registers of one group
+#pragma unroll 1
+      for (int o0 = 1; o0 <= N / 2; o0 += 4) {
+        float pj[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = ls + ((me + o0 + u) & (N - 1));
+#pragma unroll
+          for (int r = 0; r < 3; ++r) pj[u][r] = tile[XROW + r][j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int o = o0 + u;
+          const float dx = pj[u][0] - s.x[0], dy = pj[u][1] - s.x[1], dz = pj[u][2] - s.x[2];
+          const uint32_t h = dx * dx + dy * dy + dz * dz < thr ? 1u : 0u;
+          rot |= h << o;
+          if (o < N / 2) {
+            const int src = base + ((me - o) & (N - 1));
+            const uint32_t g = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)h) & 1u;
+            rot |= g << (N - o);
+          }
+        }
+      }
+      constexpr uint32_t full = (1u << N) - 1u;
+      rot &= full;
+      cand = (M)(me == 0 ? rot : ((rot << me) | (rot >> (N - me))) & full);
+    } else {
+      for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
+        const float dx = pj[0] - s.x[0], dy = pj[1] - s.x[1], dz = pj[2] - s.x[2];
+        cand |= dx * dx + dy * dy + dz * dz < thr ? (M)1 << jj : (M)0;
+      });
+    }
     const bool near_origin =
         fmaxf(fabsf(s.x[0]), fmaxf(fabsf(s.x[1]), fabsf(s.x[2]))) <= 1000.0f;
     if (!near_origin) cand = (M)(n >= 64 ? ~0ull : (1ull << n) - 1ull);
