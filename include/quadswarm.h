@@ -35,15 +35,16 @@
  *      QS_BUCKETED=0         uneven swarm sizes run one workgroup per packed
  *                            block instead of the persistent bucketed
  *                            launch, read by qs_create;
- *      QS_STEP_PIPE, QS_ROLLOUT_PIPE, QS_REVERSE_PIPE = 0|1
+ *      QS_STEP_PIPE, QS_ROLLOUT_PIPE, QS_RECOMPUTE_PIPE,
+ *      QS_REVERSE_PIPE = 0|1
  *                            force the multi-wavefront forms off or on:
  *                            multi-substep step calls on two wavefronts
  *                            per workgroup (uniform 8-quad swarms),
  *                            qs_rollout on two (three with the penalty in
- *                            8-quad swarms) and the reverse sweep of
- *                            qs_rollout_backward on four (swarms of 1 or
- *                            8); default on up to 1024 workgroups; read on
- *                            every call;
+ *                            8-quad swarms), the recompute of
+ *                            qs_rollout_backward on two and its reverse
+ *                            sweep on four (swarms of 1 or 8); default on
+ *                            up to 1024 workgroups; read on every call;
  *      QS_STAGE_ROWS=n       observation rows per LDS staging pass (a power
  *                            of two up to the workgroup size; 0: each lane
  *                            stores its own row), read once;

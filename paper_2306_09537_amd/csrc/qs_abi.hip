@@ -405,10 +405,25 @@ struct AdjScratch {
   float* gpar;
 };
 
+// The two-wavefront recompute (motor part one substep ahead) for small
+// batches, as the rollout (QS_RECOMPUTE_PIPE=0/1 forces it off/on).
+bool use_recompute_pipe(const qs_handle* h) {
+  if (const char* e = std::getenv("QS_RECOMPUTE_PIPE")) return e[0] == '1';
+  return h->nblk <= 1024;
+}
+
 template <int BS, int N, bool PEN>
 void go_recompute(qs_handle* h, const AdjScratch& sc, const float* ckpt, const float* act,
                   int ncalls, int ce, int nsub, uint64_t t0, hipStream_t s) {
   const int nseg = (ncalls + ce - 1) / ce;
+  if constexpr (BS == 64 && (N == 1 || N == 8)) {
+    if (use_recompute_pipe(h)) {
+      hipLaunchKernelGGL((qs::recompute_pipe_kernel<N>), dim3(h->nblk, nseg), dim3(128), 0, s,
+                         h->d_c, ptrs(h), ckpt, act, ncalls, ce, nsub, (unsigned long long)t0,
+                         sc.tape);
+      return;
+    }
+  }
   hipLaunchKernelGGL((qs::recompute_kernel<BS, N>), dim3(h->nblk, nseg), dim3(BS), 0, s, h->d_c,
                      ptrs(h), ckpt, act, ncalls, ce, nsub, (unsigned long long)t0, sc.tape);
 }

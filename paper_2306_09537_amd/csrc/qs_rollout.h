@@ -289,6 +289,154 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
   }
 }
 
+// Position, velocity, attitude, body rates and the floor flag of one tape
+// or checkpoint row (field-major, leading dimension ld).
+__device__ __forceinline__ void load_body(const float* __restrict__ row, long long ld, int q,
+                                          Quad& s) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s.x[k] = row[(S_X + k) * ld + q];
+    s.v[k] = row[(S_V + k) * ld + q];
+    s.w[k] = row[(S_W + k) * ld + q];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s.R[k] = row[(S_R + k) * ld + q];
+  s.fl = row[S_F * ld + q];
+  s.ev = 0u;
+}
+
+// recompute_pipe_kernel: recompute_kernel for small batches (swarms of 1
+// or 8, up to 1024 workgroups of 64 quads), over two wavefronts per
+// workgroup as in rollout_pipe_kernel: wavefront 0 runs the motor part of
+// each substep one substep ahead (taping the rotor state and the draws) and
+// hands thrust and torques through a two-slot LDS ring; wavefront 1 tapes the
+// pose, velocity, rates and floor flag, runs the body part and the in-swarm
+// pass.  Same arithmetic in the same order as recompute_kernel, so the tape
+// is identical.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(128) void recompute_pipe_kernel(const Consts* __restrict__ cp,
+                                                             Ptrs p,
+                                                             const float* __restrict__ ckpt,
+                                                             const float* __restrict__ act,
+                                                             int ncalls, int ce, int nsub,
+                                                             unsigned long long t0,
+                                                             float* __restrict__ tape) {
+  constexpr int BS = 64;
+  static_assert(N == 1 || N == 8, "pipelined recompute for swarms of 1 or 8");
+  __shared__ float sxv[2][TILE_ROWS_CO][BS];
+  __shared__ float ring[2][4][BS];
+  const Consts& c = *cp;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tid = threadIdx.x & 63;
+  int qb, cnt, ls, n;
+  block_map<BS, N>(p, tid, qb, cnt, ls, n);
+  const bool live = tid < cnt;
+  const int q = qb + (live ? tid : 0);
+  const int me = tid - ls;
+  const long long Q = p.Q;
+  const int c0 = blockIdx.y * ce;
+  const int nc = min(ce, ncalls - c0);
+  const int n_steps = nc * nsub;  // substeps of the segment
+  const int s0 = c0 * nsub;       // its first substep within the chunk
+  const float* ck = ckpt + (long long)blockIdx.y * NSTATE * Q;
+  QuadPar pp;
+  ParAdj pa;
+  if (live) load_params(p, c, q, pp, pa);
+
+  if (wave == 0) {
+    // ---- motor part of substep i at step i
+    float u[4], e[4];
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        u[k] = ck[(S_U + k) * Q + q];
+        e[k] = ck[(S_E + k) * Q + q];
+      }
+    }
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+    float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live && nc > 0) a_nx = load_act(act + (long long)c0 * Q * 4, q);
+    for (int i = 0; i <= n_steps; ++i) {
+      if (i < n_steps) {
+        const int cl = i / nsub, sub = i - cl * nsub;
+        const int call = c0 + cl;
+        if (sub == 0) {
+          const float4 a4 = a_nx;
+          if (live && call + 1 < c0 + nc) a_nx = load_act(act + (long long)(call + 1) * Q * 4, q);
+          if (live) act_uhat(c, p, a4, uhat);
+        }
+        if (live) {
+          float* row = tape + (long long)(s0 + i) * NTAPE * Q;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            row[(S_U + k) * Q + q] = u[k];
+            row[(S_E + k) * Q + q] = e[k];
+          }
+          float z[4] = {0.f, 0.f, 0.f, 0.f}, zio[4];
+          const Drive d = motor_step<Z_EXPORT>(c, pp, u, e, uhat, (uint32_t)q,
+                                               t0 + (unsigned long long)(s0 + i), z, zio);
+          if (c.flags & F_NOISE) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) row[(NSTATE + k) * Q + q] = zio[k];
+          }
+          float(*slot)[BS] = ring[i & 1];
+          slot[0][tid] = d.T;
+          slot[1][tid] = d.tx;
+          slot[2][tid] = d.ty;
+          slot[3][tid] = d.tz;
+        }
+      }
+      wg_sync();
+    }
+  } else {
+    // ---- body part and in-swarm pass of substep i - 1 at step i
+    Quad s;
+    if (live) load_body(ck, Q, q, s);
+    const bool pairs = N != 1 && (c.flags & (F_COLLIDE | F_DOWNWASH)) != 0;
+    wg_sync();  // step 0: no thrust yet
+    for (int i = 1; i <= n_steps; ++i) {
+      const int sidx = i - 1;
+      const unsigned long long t = t0 + (unsigned long long)(s0 + sidx);
+      if (live) {
+        float* row = tape + (long long)(s0 + sidx) * NTAPE * Q;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          row[(S_X + k) * Q + q] = s.x[k];
+          row[(S_V + k) * Q + q] = s.v[k];
+          row[(S_W + k) * Q + q] = s.w[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) row[(S_R + k) * Q + q] = s.R[k];
+        row[S_F * Q + q] = s.fl;
+        const float(*slot)[BS] = ring[sidx & 1];
+        Drive d;
+        d.T = slot[0][tid];
+        d.tx = slot[1][tid];
+        d.ty = slot[2][tid];
+        d.tz = slot[3][tid];
+        body_step(c, pp, s, d, (uint32_t)q, t);
+      }
+      if (pairs) {
+        float(*tile)[BS] = sxv[sidx & 1];
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            tile[k][tid] = s.xo[k];
+            tile[3 + k][tid] = s.inc[k];
+            tile[6 + k][tid] = s.v[k];
+            tile[XROW + k][tid] = s.x[k];
+          }
+        }
+        wave_sync();
+        float unused = 0.f;
+        if (live) pair_pass<BS, N, false, true>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
+      }
+      wg_sync();
+    }
+  }
+}
+
 // One branch-free pass over the partners of a substep in the reverse sweep:
 // the contact set (the quad itself excluded) and, with the penalty, its
 // adjoint w.r.t. the quad's position,
@@ -605,21 +753,6 @@ __device__ __forceinline__ void load_rotor(const Consts& c, const float* __restr
     e[k] = row[(S_E + k) * ld + q];
   }
   load_draws(c, row, ld, q, z);
-}
-
-// Position, velocity, attitude, body rates and the floor flag of one tape row.
-__device__ __forceinline__ void load_body(const float* __restrict__ row, long long ld, int q,
-                                          Quad& s) {
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    s.x[k] = row[(S_X + k) * ld + q];
-    s.v[k] = row[(S_V + k) * ld + q];
-    s.w[k] = row[(S_W + k) * ld + q];
-  }
-#pragma unroll
-  for (int k = 0; k < 9; ++k) s.R[k] = row[(S_R + k) * ld + q];
-  s.fl = row[S_F * ld + q];
-  s.ev = 0u;
 }
 
 template <int N, bool PEN>

@@ -200,14 +200,16 @@ def test_table_path_adjoint_matches_oracle(sizes, pen):
 
 @pytest.mark.parametrize("n,pen", [(8, True), (8, False), (1, True)])
 def test_pipelined_reverse_sweep_is_bit_identical(n, pen, monkeypatch):
-    """Small batches differentiate in two wavefronts per workgroup (one
-    re-runs the substeps, the other differentiates them); the result equals
-    the one-wavefront sweep bit for bit."""
+    """Small batches recompute the checkpoint segments on two wavefronts per
+    workgroup and run the reverse sweep as a pipeline on four (motor re-run,
+    body re-run, contacts, derivative); the gradients equal those of the
+    one-wavefront kernels bit for bit."""
     w, acts, Wt, gpen = problem(7, 12, n_envs=20 if n == 8 else 150, n=n, spread=0.6)
     gp = gpen if pen else None
     out = {}
     for mode in ("0", "1"):
         monkeypatch.setenv("QS_REVERSE_PIPE", mode)
+        monkeypatch.setenv("QS_RECOMPUTE_PIPE", mode)
         sim = QuadSwarm.from_workload(w)
         a = dev(acts)
         ckpt = torch.empty((3, 27, w.n_quads), device="cuda")
