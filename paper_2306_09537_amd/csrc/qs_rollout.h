@@ -684,11 +684,13 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
 // substeps (last to first) on four wavefronts per workgroup of 64 quads, one
 // per SIMD of the compute unit.  Substep k passes through
 //  - wavefront 0 at step i: the motor part re-run (lag, noise, thrust, mix)
-//    from the taped rotor state and draws; the thrust, the torques and the
-//    rotor fields of the record go on through a four-slot LDS ring;
+//    from the taped rotor state and draws; the thrust, the torques, the
+//    rotor fields of the record and the call's rotor commands with their
+//    derivatives w.r.t. the action go on through a four-slot LDS ring;
 //  - wavefront 1 at step i + 1: the body part re-run (body_step with its
 //    record) from the taped pose and rates; the post-motion exchange tile and
-//    the body fields of the record go on through three-slot rings;
+//    the body fields of the record (in 16-byte groups) go on through
+//    three-slot rings;
 //  - wavefront 2 at step i + 2: the contact set, the approach test and the
 //    penalty's adjoint from the exchange tile, through a two-slot ring;
 //  - wavefront 3 at step i + 3: the derivative (response adjoint, quad_vjp);
@@ -699,10 +701,13 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
 // identical.
 // ---------------------------------------------------------------------------
 constexpr int REC_BODY = 49;  // the float fields of Rec that body_step sets
-// ring words of the body stage: the body fields and Rec's flags
+// ring of the body stage: the body fields and Rec's flags, in 16-byte
+// groups (one LDS vector access per group)
 constexpr int RING_WORDS = REC_BODY + 1;
-// motor ring words: draws, rotor speeds before and after, thrust and torques
-constexpr int MOTOR_WORDS = 16;
+constexpr int RING_VEC = (RING_WORDS + 3) / 4;
+// motor ring words: draws, rotor speeds before and after, thrust and
+// torques, the rotor commands and their derivatives w.r.t. the action
+constexpr int MOTOR_WORDS = 24;
 // contact ring words: response flag, contact set, penalty adjoint
 constexpr int CON_WORDS = 5;
 
@@ -771,7 +776,7 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
   // position, displacement, velocity (wavefront 1); 9-11 adjoint of the
   // collision velocity change (wavefront 3); 12 penalty weights.
   __shared__ float tl[3][13][BS];
-  __shared__ float ring[3][RING_WORDS][BS];
+  __shared__ float4 ring[3][RING_VEC][BS];
   __shared__ float mring[4][MOTOR_WORDS][BS];
   __shared__ float cring[2][CON_WORDS][BS];
   const Consts& c = *cp;
@@ -800,7 +805,7 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
   if (wave == 0) {
     // ---- motor part of substep k = n_steps - 1 - i at step i
     float un[4], en[4], zn[4] = {0.f, 0.f, 0.f, 0.f};
-    float uhat[4] = {0.f, 0.f, 0.f, 0.f};
+    float uhat[4] = {0.f, 0.f, 0.f, 0.f}, dua[4] = {0.f, 0.f, 0.f, 0.f};
     float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live && n_steps > 0) {
       load_rotor(c, tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, un, en, zn);
@@ -813,7 +818,13 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
         if (sub == nsub - 1) {  // the call's last substep comes first
           const float4 a4 = a_nx;
           if (live && call > 0) a_nx = load_act(act + (long long)(call - 1) * Q * 4, q);
-          if (live) act_uhat(c, p, a4, uhat);
+          if (live) {
+            act_uhat(c, p, a4, uhat);
+            dua[0] = duhat_da(c, a4.x, uhat[0]);
+            dua[1] = duhat_da(c, a4.y, uhat[1]);
+            dua[2] = duhat_da(c, a4.z, uhat[2]);
+            dua[3] = duhat_da(c, a4.w, uhat[3]);
+          }
         }
         if (live) {
           float u[4], e[4], zi[4], z[4] = {0.f, 0.f, 0.f, 0.f};
@@ -838,6 +849,11 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
           ms[13][tid] = d.tx;
           ms[14][tid] = d.ty;
           ms[15][tid] = d.tz;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            ms[16 + m][tid] = uhat[m];
+            ms[20 + m][tid] = dua[m];
+          }
         }
       }
       wg_sync();
@@ -869,9 +885,15 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
             tile[6 + m][tid] = s.v[m];
           }
         }
-        float(*slot)[BS] = ring[k % 3];
-        rec_body_floats(r, [&](int w, const float& v) { slot[w][tid] = v; });
-        slot[REC_BODY][tid] = __uint_as_float(rec_flags(r));
+        float w4[4 * RING_VEC];
+        rec_body_floats(r, [&](int w, const float& v) { w4[w] = v; });
+        w4[REC_BODY] = __uint_as_float(rec_flags(r));
+#pragma unroll
+        for (int w = RING_WORDS; w < 4 * RING_VEC; ++w) w4[w] = 0.f;
+        float4(*slot)[BS] = ring[k % 3];
+#pragma unroll
+        for (int g = 0; g < RING_VEC; ++g)
+          slot[g][tid] = make_float4(w4[4 * g], w4[4 * g + 1], w4[4 * g + 2], w4[4 * g + 3]);
       }
       wg_sync();
     }
@@ -921,10 +943,8 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
         l.e[k] = lam[(S_E + k) * Q + q];
       }
     }
-    float uhat[4] = {0.f, 0.f, 0.f, 0.f}, gu[4] = {0.f, 0.f, 0.f, 0.f};
-    float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 a_nx = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (live && n_steps > 0) a_nx = load_act(act + (long long)(ncalls - 1) * Q * 4, q);
+    // the rotor commands and their derivatives come from the motor stage
+    float gu[4] = {0.f, 0.f, 0.f, 0.f};
     wg_sync();  // steps 0 to 2: no record complete yet
     wg_sync();
     wg_sync();
@@ -932,24 +952,32 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
       const int k = n_steps + 2 - i;
       const int call = k / nsub, sub = k - call * nsub;
       if (sub == nsub - 1) {
-        a4 = a_nx;
-        if (live && call > 0) a_nx = load_act(act + (long long)(call - 1) * Q * 4, q);
-        if (live) act_uhat(c, p, a4, uhat);
 #pragma unroll
         for (int m = 0; m < 4; ++m) gu[m] = 0.f;
       }
       if (live) {
-        const float(*slot)[BS] = ring[k % 3];
+        const float4(*slot)[BS] = ring[k % 3];
         const float(*ms)[BS] = mring[k & 3];
         Rec r;
+        float uhat[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           r.z[m] = ms[m][tid];
           r.u0[m] = ms[4 + m][tid];
           r.u1[m] = ms[8 + m][tid];
+          uhat[m] = ms[16 + m][tid];
         }
-        rec_body_floats(r, [&](int w, float& v) { v = slot[w][tid]; });
-        rec_unflag(r, __float_as_uint(slot[REC_BODY][tid]));
+        float w4[4 * RING_VEC];
+#pragma unroll
+        for (int g = 0; g < RING_VEC; ++g) {
+          const float4 v4 = slot[g][tid];
+          w4[4 * g] = v4.x;
+          w4[4 * g + 1] = v4.y;
+          w4[4 * g + 2] = v4.z;
+          w4[4 * g + 3] = v4.w;
+        }
+        rec_body_floats(r, [&](int w, float& v) { v = w4[w]; });
+        rec_unflag(r, __float_as_uint(w4[REC_BODY]));
         if (pairs) {
           const float(*cs)[BS] = cring[k & 1];
           const bool hit = cs[0][tid] != 0.f;
@@ -984,10 +1012,10 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
         quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
         if (sub == 0) {
           float4 g;
-          g.x = gu[0] * duhat_da(c, a4.x, uhat[0]);
-          g.y = gu[1] * duhat_da(c, a4.y, uhat[1]);
-          g.z = gu[2] * duhat_da(c, a4.z, uhat[2]);
-          g.w = gu[3] * duhat_da(c, a4.w, uhat[3]);
+          g.x = gu[0] * ms[20][tid];
+          g.y = gu[1] * ms[21][tid];
+          g.z = gu[2] * ms[22][tid];
+          g.w = gu[3] * ms[23][tid];
           reinterpret_cast<float4*>(gact + (long long)call * Q * 4)[q] = g;
         }
       } else if (pairs) {
