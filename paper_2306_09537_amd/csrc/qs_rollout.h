@@ -705,9 +705,9 @@ constexpr int REC_BODY = 49;  // the float fields of Rec that body_step sets
 // groups (one LDS vector access per group)
 constexpr int RING_WORDS = REC_BODY + 1;
 constexpr int RING_VEC = (RING_WORDS + 3) / 4;
-// motor ring words: draws, rotor speeds before and after, thrust and
-// torques, the rotor commands and their derivatives w.r.t. the action
-constexpr int MOTOR_WORDS = 24;
+// motor ring, 16-byte groups: draws, rotor speeds before and after, thrust
+// and torques, the rotor commands and their derivatives w.r.t. the action
+constexpr int MOTOR_VEC = 6;
 // contact ring words: response flag, contact set, penalty adjoint
 constexpr int CON_WORDS = 5;
 
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
   // collision velocity change (wavefront 3); 12 penalty weights.
   __shared__ float tl[3][13][BS];
   __shared__ float4 ring[3][RING_VEC][BS];
-  __shared__ float mring[4][MOTOR_WORDS][BS];
+  __shared__ float4 mring[4][MOTOR_VEC][BS];
   __shared__ float cring[2][CON_WORDS][BS];
   const Consts& c = *cp;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -835,25 +835,15 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
             zi[m] = zn[m];
           }
           if (k > 0) load_rotor(c, tape + (long long)(k - 1) * NTAPE * Q, Q, q, un, en, zn);
-          float(*ms)[BS] = mring[k & 3];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) ms[4 + m][tid] = u[m];
+          float4(*ms)[BS] = mring[k & 3];
+          ms[1][tid] = make_float4(u[0], u[1], u[2], u[3]);
           const Drive d = motor_step<Z_IMPORT>(c, pp, u, e, uhat, (uint32_t)q,
                                                t0 + (unsigned long long)k, z, zi);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            ms[m][tid] = z[m];
-            ms[8 + m][tid] = u[m];
-          }
-          ms[12][tid] = d.T;
-          ms[13][tid] = d.tx;
-          ms[14][tid] = d.ty;
-          ms[15][tid] = d.tz;
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            ms[16 + m][tid] = uhat[m];
-            ms[20 + m][tid] = dua[m];
-          }
+          ms[0][tid] = make_float4(z[0], z[1], z[2], z[3]);
+          ms[2][tid] = make_float4(u[0], u[1], u[2], u[3]);
+          ms[3][tid] = make_float4(d.T, d.tx, d.ty, d.tz);
+          ms[4][tid] = make_float4(uhat[0], uhat[1], uhat[2], uhat[3]);
+          ms[5][tid] = make_float4(dua[0], dua[1], dua[2], dua[3]);
         }
       }
       wg_sync();
@@ -868,12 +858,12 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
         const int k = n_steps - i;
         Quad s = sn;
         if (k > 0) load_body(tape + (long long)(k - 1) * NTAPE * Q, Q, q, sn);
-        const float(*ms)[BS] = mring[k & 3];
+        const float4 dv = mring[k & 3][3][tid];
         Drive d;
-        d.T = ms[12][tid];
-        d.tx = ms[13][tid];
-        d.ty = ms[14][tid];
-        d.tz = ms[15][tid];
+        d.T = dv.x;
+        d.tx = dv.y;
+        d.ty = dv.z;
+        d.tz = dv.w;
         Rec r;
         body_step<true>(c, pp, s, d, (uint32_t)q, t0 + (unsigned long long)k, &r);
         if (pairs) {
@@ -957,16 +947,13 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
       }
       if (live) {
         const float4(*slot)[BS] = ring[k % 3];
-        const float(*ms)[BS] = mring[k & 3];
+        const float4(*ms)[BS] = mring[k & 3];
         Rec r;
-        float uhat[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          r.z[m] = ms[m][tid];
-          r.u0[m] = ms[4 + m][tid];
-          r.u1[m] = ms[8 + m][tid];
-          uhat[m] = ms[16 + m][tid];
-        }
+        const float4 z4 = ms[0][tid], u04 = ms[1][tid], u14 = ms[2][tid], uh4 = ms[4][tid];
+        r.z[0] = z4.x; r.z[1] = z4.y; r.z[2] = z4.z; r.z[3] = z4.w;
+        r.u0[0] = u04.x; r.u0[1] = u04.y; r.u0[2] = u04.z; r.u0[3] = u04.w;
+        r.u1[0] = u14.x; r.u1[1] = u14.y; r.u1[2] = u14.z; r.u1[3] = u14.w;
+        const float uhat[4] = {uh4.x, uh4.y, uh4.z, uh4.w};
         float w4[4 * RING_VEC];
 #pragma unroll
         for (int g = 0; g < RING_VEC; ++g) {
@@ -1011,11 +998,12 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
         }
         quad_vjp(c, pp, pa, r, uhat, l, gu, gp);
         if (sub == 0) {
+          const float4 da = ms[5][tid];
           float4 g;
-          g.x = gu[0] * ms[20][tid];
-          g.y = gu[1] * ms[21][tid];
-          g.z = gu[2] * ms[22][tid];
-          g.w = gu[3] * ms[23][tid];
+          g.x = gu[0] * da.x;
+          g.y = gu[1] * da.y;
+          g.z = gu[2] * da.z;
+          g.w = gu[3] * da.w;
           reinterpret_cast<float4*>(gact + (long long)call * Q * 4)[q] = g;
         }
       } else if (pairs) {
