@@ -198,3 +198,28 @@ def test_scale32_fwd_bwd_full_size_sampled():
     g_ref = oracle_grads(w, acts, nsub, Wt, gpen, env_range=(e0, e1))
     g_pert = oracle_pert(w, acts, nsub, Wt, gpen, 5, env_range=(e0, e1))
     check((gs[q0:q1], gact[:, q0:q1], gpar[q0:q1]), g_ref, g_pert, "32768 x 32 sampled")
+
+
+def test_diff_fwd_bwd_full_size_sampled():
+    """The benchmark's 1024 x 8 differentiable rollout in its launch
+    configuration (200 substeps, checkpoint every 20 calls, penalty on:
+    the three-wavefront forward, the two-wavefront recompute and the
+    four-wavefront reverse sweep): gradients of the first two, two middle
+    and the last two environments against the oracle's reverse mode, block
+    by block with the oracle-derived bounds of the other gradient tests."""
+    from tests.test_gpu_grad import check, gpu_grads, oracle_grads, oracle_pert
+    w = W.diff(seed=0)
+    T, nsub, ce = 200, 1, 20
+    acts = w.action_sequence(T)
+    rng = np.random.default_rng(6)
+    Wt = rng.normal(size=(w.n_quads, 27)).astype(np.float32)
+    Wt[:, 26] = 0
+    gpen = rng.uniform(0.5, 2.0, size=w.n_quads).astype(np.float32)
+    gs, gact, gpar, *_ = gpu_grads(w, acts, nsub, Wt, gpen, ce)
+    assert np.isfinite(gs).all() and np.isfinite(gact).all() and np.isfinite(gpar).all()
+    for e0, e1 in ((0, 2), (511, 513), (1022, 1024)):
+        q0, q1 = int(w.env_offsets[e0]), int(w.env_offsets[e1])
+        g_ref = oracle_grads(w, acts, nsub, Wt, gpen, env_range=(e0, e1))
+        g_pert = oracle_pert(w, acts, nsub, Wt, gpen, 5, env_range=(e0, e1))
+        check((gs[q0:q1], gact[:, q0:q1], gpar[q0:q1]), g_ref, g_pert,
+              f"1024 x 8 envs {e0}-{e1}")
