@@ -3,7 +3,8 @@
 // One lane owns one quad.  Its state lives in VGPRs for the whole call; a
 // workgroup owns whole environments (never split), so the in-env pair pass
 // and the nearest-neighbour search read swarm-mates' positions and
-// velocities from LDS after a workgroup barrier.
+// velocities from LDS after a workgroup barrier (swarms of at most 8 take
+// the neighbour candidates' positions from their lanes instead).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -540,6 +541,26 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The value of lane (lane xor D) for 1 <= D <= 7: a swarm of at most 8
+// quads in an aligned group of 8 lanes takes a swarm-mate's register by a
+// data-parallel-primitive move, with no LDS.  quad_perm covers D = 1, 2, 3
+// within groups of 4 lanes; row_half_mirror (lane i of each group of 8 from
+// lane 7 - i, i.e. xor 7) composed with one of them covers D = 4 .. 7.
+// Every source lane lies inside the destination's own group of 8; a source
+// lane switched off in the exec mask yields `none`.
+template <int D>
+__device__ __forceinline__ float lane_xor8(float v, float none) {
+  static_assert(D >= 1 && D <= 7, "partners within a group of 8 lanes");
+  constexpr int QP[4] = {0xE4, 0xB1, 0x4E, 0x1B};  // quad_perm: identity, xor 1, xor 2, xor 3
+  constexpr int HALF_MIRROR = 0x141;
+  const int o = __float_as_int(none);
+  int x = __float_as_int(v);
+  if constexpr (D >= 4) x = __builtin_amdgcn_update_dpp(o, x, HALF_MIRROR, 0xF, 0xF, false);
+  constexpr int r = D >= 4 ? (D ^ 7) : D;
+  if constexpr (r != 0) x = __builtin_amdgcn_update_dpp(o, x, QP[r], 0xF, 0xF, false);
+  return __int_as_float(x);
 }
 
 // compile-time booleans for generic lambdas

@@ -359,6 +359,10 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
   if constexpr (OBS) {
     // §III-C observation from the post-collision state
     float(*tile)[BS] = sxv[nsub & 1];
+    // swarms of 2 to 8 (aligned lane groups of the wavefront) take the
+    // candidates' positions from their lanes by cross-lane moves; the tile
+    // then serves the selected slots' rows only
+    constexpr bool LANE_KNN = KT > 0 && N > 1 && N <= 8;
     if constexpr (KT != 0) {  // the neighbour slots come from the tile
       if (live) {
 #pragma unroll
@@ -374,7 +378,7 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           tile[6 + k][tid] = 0.f;
         }
       }
-      quad_sync();
+      if constexpr (!LANE_KNN) quad_sync();
     }
     if constexpr (KT >= 0) {
       constexpr int OD = 18 + 6 * KT;
@@ -416,7 +420,24 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 #pragma unroll
           for (int k = 0; k <= KT; ++k) key[k] = nk[k];
         };
-        if constexpr (NU > 1) {
+        if constexpr (LANE_KNN) {
+          const float mx = live ? s.x[0] : 1e30f, my = live ? s.x[1] : 1e30f,
+                      mz = live ? s.x[2] : 1e30f;
+          auto mate = [&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            if constexpr (D < N)
+              cand(me ^ D, lane_xor8<D>(mx, 1e30f), lane_xor8<D>(my, 1e30f),
+                   lane_xor8<D>(mz, 1e30f));
+          };
+          mate(std::integral_constant<int, 1>{});
+          mate(std::integral_constant<int, 2>{});
+          mate(std::integral_constant<int, 3>{});
+          mate(std::integral_constant<int, 4>{});
+          mate(std::integral_constant<int, 5>{});
+          mate(std::integral_constant<int, 6>{});
+          mate(std::integral_constant<int, 7>{});
+          quad_sync();  // the tile rows, for the selected slots below
+        } else if constexpr (NU > 1) {
           constexpr int CH = NU < 8 ? NU : 8;
           auto chunk = [&](int j0) {
             float px[CH][3];
@@ -699,7 +720,8 @@ constexpr int BUCKET_STAGE_ROWS = 32;
 // Persistent launch over the work items [item0, item0 + n_items) of uneven
 // swarm sizes; workgroups stride over them and run the body specialised for
 // each item's slot size N.  Slots of 4 and more loop over the swarm at run
-// time, one partner at a time: unrolled, their bodies would set the whole
+// time, one partner at a time, in the pair pass (and slots of 16 and 32 in
+// the neighbour search as well): unrolled, their bodies would set the whole
 // kernel's register count, and with it the occupancy (135 VGPRs instead of
 // 381: 3 wavefronts per SIMD instead of 1).  Slots of 16 and 32 also have a
 // body that takes the partners in chunks of four (their loads in flight
