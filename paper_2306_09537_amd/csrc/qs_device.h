@@ -4,7 +4,8 @@
 // workgroup owns whole environments (never split), so the in-env pair pass
 // and the nearest-neighbour search read swarm-mates' positions and
 // velocities from LDS after a workgroup barrier (swarms of at most 8 take
-// the neighbour candidates' positions from their lanes instead).
+// the neighbour candidates' positions from their lanes instead, and larger
+// swarms take the neighbour keys from the last pair pass's screen).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -654,6 +655,36 @@ __device__ __forceinline__ void for_partner_pos(T tile, int ls, int n, F&& f) {
   }
 }
 
+// Neighbour keys (§III-C, the K nearest by (d^2, index)).  A candidate at
+// squared distance d2 becomes one 32-bit key: the bits of d2 (non-negative,
+// so they order as the values) with the low six replaced by the partner's
+// index jj within the swarm (swarms hold at most 64).  key[0..L-1] is a
+// sorted list of the L smallest keys so far; a candidate enters with one min
+// and L - 1 medians, all independent of each other:
+// new[0] = min(old[0], x), new[k] = med3(old[k-1], x, old[k]).  The quad
+// itself and non-finite distances never enter.  The list does not depend on
+// the order in which candidates arrive.
+constexpr uint32_t KEY_EMPTY = 0xffffffffu;
+template <int L>
+__device__ __forceinline__ void knn_insert(uint32_t key[L], int jj, int me, float d2) {
+  const uint32_t kx = (jj != me && d2 < INFINITY)
+                          ? ((__float_as_uint(d2) & ~63u) | (uint32_t)jj) : KEY_EMPTY;
+  uint32_t nk[L];
+  nk[0] = min(key[0], kx);
+#pragma unroll
+  for (int k = 1; k < L; ++k) nk[k] = umed3(key[k - 1], kx, key[k]);
+#pragma unroll
+  for (int k = 0; k < L; ++k) key[k] = nk[k];
+}
+
+// Squared distance from the lane's position to partner position pj[0..2]
+// (one expression for the partner screen and the neighbour search, so both
+// round identically).
+__device__ __forceinline__ float sq_dist(const float pj[3], const float x[3]) {
+  const float dx = pj[0] - x[0], dy = pj[1] - x[1], dz = pj[2] - x[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
 // In-swarm pass of one live lane after the tile (start positions,
 // displacements, velocities) is written and the workgroup synchronised:
 // §III-B.1 contact detection and Jacobi velocity exchange (every response
@@ -668,12 +699,18 @@ __device__ __forceinline__ void for_partner_pos(T tile, int ls, int n, F&& f) {
 // 1000 m of the origin, x differs from (start + displacement) by at most an
 // ulp of 1000 (6.1e-5 m) per quad and axis, well inside the 1 mm; a lane
 // further out tests every partner exactly.  So the contact set, and every
-// result, is the same as without the screen.
-template <int BS, int N, bool PEN, bool CO = false>
+// result, is the same as without the screen.  L > 0 (swarms other than 8,
+// with the screen): the screen's squared distances also enter the
+// neighbour key list key[0..L-1] (knn_insert); the pass changes only
+// velocities and body rates, so they are the distances of the post-pass
+// positions.
+template <int BS, int N, bool PEN, bool CO = false, int L = 0>
 __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const float (*tile)[BS],
                                                         Quad& s, int ls, int n, int me,
                                                         uint32_t q, unsigned long long t,
-                                                        float& pacc, float beta) {
+                                                        float& pacc, float beta,
+                                                        uint32_t* key = nullptr) {
+  static_assert(L == 0 || (CO && !PEN && N != 8), "keys from the plain screen only");
   const bool collide = (c.flags & F_COLLIDE) != 0;
   const bool dw = (c.flags & F_DOWNWASH) != 0 && s.fl == 0.0f;
   using M = PairMask<N>;
@@ -750,8 +787,9 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
       cand = (M)(me == 0 ? rot : ((rot << me) | (rot >> (N - me))) & full);
     } else {
       for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
-        const float dx = pj[0] - s.x[0], dy = pj[1] - s.x[1], dz = pj[2] - s.x[2];
-        cand |= dx * dx + dy * dy + dz * dz < thr ? (M)1 << jj : (M)0;
+        const float d2 = sq_dist(pj, s.x);
+        cand |= d2 < thr ? (M)1 << jj : (M)0;
+        if constexpr (L > 0) knn_insert<L>(key, jj, me, d2);
       });
     }
     const bool near_origin =

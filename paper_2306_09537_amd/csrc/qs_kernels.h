@@ -231,6 +231,17 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 
   const bool collide = N != 1 && (c.flags & (F_COLLIDE | F_DOWNWASH)) != 0;
   unsigned long long cmask = 0ull;
+  // Swarms of 16 and more (dense mapping): the last substep's partner screen
+  // also builds the neighbour key list, from the same squared distances
+  // (the pair pass moves no position), so the observation need not go over
+  // the swarm again.  Without the screen (no pair pass, or downwash on) the
+  // observation builds the list itself.
+  constexpr bool SCREEN_KEYS = OBS && KT > 0 && MAP == MAP_DENSE && NU >= 16 && ROLE < 0;
+  static_assert(!SCREEN_KEYS || N > 8, "swarms of up to 8 use cross-lane candidates");
+  constexpr int NKEY = KT > 0 ? KT + 1 : 1;
+  uint32_t skey[NKEY];
+#pragma unroll
+  for (int k = 0; k < NKEY; ++k) skey[k] = KEY_EMPTY;
   for (int sub = 0; sub < nsub; ++sub) {
     const unsigned long long t = t0 + (unsigned long long)sub;
     // this substep's motor-noise draws
@@ -289,7 +300,17 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
       cmask = 0ull;
       if (live) {
         float unused = 0.f;
-        cmask = pair_pass<BS, NU, false, true>(c, tile, s, ls, n, me, (uint32_t)q, t, unused, 0.f);
+        if constexpr (SCREEN_KEYS) {
+          if (sub == nsub - 1)
+            cmask = pair_pass<BS, NU, false, true, KT + 1>(c, tile, s, ls, n, me, (uint32_t)q, t,
+                                                            unused, 0.f, skey);
+          else
+            cmask = pair_pass<BS, NU, false, true>(c, tile, s, ls, n, me, (uint32_t)q, t, unused,
+                                                   0.f);
+        } else {
+          cmask = pair_pass<BS, NU, false, true>(c, tile, s, ls, n, me, (uint32_t)q, t, unused,
+                                                 0.f);
+        }
       }
     }
   }
@@ -393,72 +414,62 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 #pragma unroll
       for (int k = 0; k < 3; ++k) ov[15 + k] = s.w[k];
       if constexpr (KT > 0) {
-        // The KT nearest by (d^2, index).  Each candidate becomes a 32-bit
-        // key: the bits of d^2 (non-negative, so they order as the values)
-        // with the low six replaced by the partner's index (swarms hold at
-        // most 64).  A sorted list of KT + 1 keys takes a candidate x with
-        // one min and KT medians, all independent of each other:
-        // new[0] = min(old[0], x), new[k] = med3(old[k-1], x, old[k]).
-        // Keys order as (d^2 truncated to 2^-17 relative, index): the list
-        // is the exact (d^2, index) order unless two neighbouring entries
-        // share a truncated distance (an exact or near tie); such a lane
-        // selects again with exact comparisons below.  The quad itself and
-        // non-finite distances never enter.
-        constexpr uint32_t EMPTY = 0xffffffffu;
+        // The KT nearest by (d^2, index): a sorted list of KT + 1 keys
+        // (knn_insert).  Keys order as (d^2 truncated to 2^-17 relative,
+        // index): the list is the exact (d^2, index) order unless two
+        // neighbouring entries share a truncated distance (an exact or near
+        // tie); such a lane selects again with exact comparisons below.
+        constexpr uint32_t EMPTY = KEY_EMPTY;
         uint32_t key[KT + 1];
+        bool screened = false;  // the list came with the last pair pass
+        if constexpr (SCREEN_KEYS) screened = collide && nsub > 0 && !(c.flags & F_DOWNWASH);
 #pragma unroll
-        for (int k = 0; k <= KT; ++k) key[k] = EMPTY;
+        for (int k = 0; k <= KT; ++k) key[k] = SCREEN_KEYS ? skey[k] : EMPTY;
         auto cand = [&](int jj, float xj, float yj, float zj) {
-          const float rx = xj - s.x[0], ry = yj - s.x[1], rz = zj - s.x[2];
-          const float d2 = rx * rx + ry * ry + rz * rz;
-          const uint32_t kx = (jj != me && d2 < INFINITY)
-                                  ? ((__float_as_uint(d2) & ~63u) | (uint32_t)jj) : EMPTY;
-          uint32_t nk[KT + 1];
-          nk[0] = min(key[0], kx);
-#pragma unroll
-          for (int k = 1; k <= KT; ++k) nk[k] = umed3(key[k - 1], kx, key[k]);
-#pragma unroll
-          for (int k = 0; k <= KT; ++k) key[k] = nk[k];
+          const float pj[3] = {xj, yj, zj};
+          knn_insert<KT + 1>(key, jj, me, sq_dist(pj, s.x));
         };
-        if constexpr (LANE_KNN) {
-          const float mx = live ? s.x[0] : 1e30f, my = live ? s.x[1] : 1e30f,
-                      mz = live ? s.x[2] : 1e30f;
-          auto mate = [&](auto dc) {
-            constexpr int D = decltype(dc)::value;
-            if constexpr (D < N)
-              cand(me ^ D, lane_xor8<D>(mx, 1e30f), lane_xor8<D>(my, 1e30f),
-                   lane_xor8<D>(mz, 1e30f));
-          };
-          mate(std::integral_constant<int, 1>{});
-          mate(std::integral_constant<int, 2>{});
-          mate(std::integral_constant<int, 3>{});
-          mate(std::integral_constant<int, 4>{});
-          mate(std::integral_constant<int, 5>{});
-          mate(std::integral_constant<int, 6>{});
-          mate(std::integral_constant<int, 7>{});
-          quad_sync();  // the tile rows, for the selected slots below
-        } else if constexpr (NU > 1) {
-          constexpr int CH = NU < 8 ? NU : 8;
-          auto chunk = [&](int j0) {
-            float px[CH][3];
+        if (!screened) {
+          if constexpr (LANE_KNN) {
+            const float mx = live ? s.x[0] : 1e30f, my = live ? s.x[1] : 1e30f,
+                        mz = live ? s.x[2] : 1e30f;
+            auto mate = [&](auto dc) {
+              constexpr int D = decltype(dc)::value;
+              if constexpr (D < N)
+                cand(me ^ D, lane_xor8<D>(mx, 1e30f), lane_xor8<D>(my, 1e30f),
+                     lane_xor8<D>(mz, 1e30f));
+            };
+            mate(std::integral_constant<int, 1>{});
+            mate(std::integral_constant<int, 2>{});
+            mate(std::integral_constant<int, 3>{});
+            mate(std::integral_constant<int, 4>{});
+            mate(std::integral_constant<int, 5>{});
+            mate(std::integral_constant<int, 6>{});
+            mate(std::integral_constant<int, 7>{});
+            quad_sync();  // the tile rows, for the selected slots below
+          } else if constexpr (NU > 1) {
+            constexpr int CH = NU < 8 ? NU : 8;
+            auto chunk = [&](int j0) {
+              float px[CH][3];
 #pragma unroll
-            for (int u = 0; u < CH; ++u)
+              for (int u = 0; u < CH; ++u)
 #pragma unroll
-              for (int r = 0; r < 3; ++r) px[u][r] = tile[r][ls + j0 + u];
+                for (int r = 0; r < 3; ++r) px[u][r] = tile[r][ls + j0 + u];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) cand(j0 + u, px[u][0], px[u][1], px[u][2]);
-          };
-          if constexpr (NU >= 16) {
+              for (int u = 0; u < CH; ++u) cand(j0 + u, px[u][0], px[u][1], px[u][2]);
+            };
+            if constexpr (NU >= 16) {
 #pragma unroll 1
-            for (int j0 = 0; j0 < NU; j0 += CH) chunk(j0);
-          } else {
+              for (int j0 = 0; j0 < NU; j0 += CH) chunk(j0);
+            } else {
 #pragma unroll
-            for (int j0 = 0; j0 < NU; j0 += CH) chunk(j0);
+              for (int j0 = 0; j0 < NU; j0 += CH) chunk(j0);
+            }
+          } else if constexpr (NU == 0) {
+            if (live)
+              for (int jj = 0; jj < n; ++jj)
+                cand(jj, tile[0][ls + jj], tile[1][ls + jj], tile[2][ls + jj]);
           }
-        } else if constexpr (NU == 0) {
-          if (live)
-            for (int jj = 0; jj < n; ++jj)
-              cand(jj, tile[0][ls + jj], tile[1][ls + jj], tile[2][ls + jj]);
         }
         bool tie = false;
 #pragma unroll
@@ -649,17 +660,16 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
 // and fit the fourteen SGPRs the hardware can preload where the firmware
 // supports it; the constants live in device memory written at creation.
 
-// One workgroup per block of quads (dense or table mapping).
+// One workgroup per block of quads (dense or table mapping).  Held to 128
+// VGPRs (four wavefronts per SIMD): the neighbour keys that swarms of 16 and
+// more carry through the last pair pass would otherwise take the allocation
+// to 134 and the occupancy to three.
 template <int BS, int KT, int N>
-__global__ __launch_bounds__(BS) void step_kernel(float* __restrict__ st,
-                                                  const float* __restrict__ par,
-                                                  const float* __restrict__ act,
-                                                  const float* __restrict__ goals,
-                                                  const Consts* __restrict__ cp, int Qp, int Q,
-                                                  int nsub, unsigned long long t0, Ptrs p,
-                                                  float* __restrict__ obs, int stage_obs,
-                                                  unsigned long long* tdev, unsigned int* done,
-                                                  float* __restrict__ reward) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void step_kernel(
+    float* __restrict__ st, const float* __restrict__ par, const float* __restrict__ act,
+    const float* __restrict__ goals, const Consts* __restrict__ cp, int Qp, int Q, int nsub,
+    unsigned long long t0, Ptrs p, float* __restrict__ obs, int stage_obs,
+    unsigned long long* tdev, unsigned int* done, float* __restrict__ reward) {
   __shared__ float sxv[2][TILE_ROWS_CO][BS];
   extern __shared__ float4 st_obs4[];
   p.st = st;
