@@ -156,8 +156,11 @@ def test_swarm8_full_size_fused10_sampled():
     assert st["max_err"] <= 10 * U.TOL
 
 
-def test_dense_swarms_many_contacts():
-    """Swarms of 32 packed into 0.6 m cubes: many simultaneous contacts."""
+@pytest.mark.parametrize("fused", [False, True])
+def test_dense_swarms_many_contacts(fused):
+    """Swarms of 32 packed into 0.6 m cubes: many simultaneous contacts; the
+    observation from a separate observe call, or from step_observe (the
+    neighbour keys from the last substep's partner screen)."""
     w = W.custom([32] * 16, seed=3, k=6, name="dense")
     rng = np.random.default_rng(3)
     s0 = w.state0.copy()
@@ -165,8 +168,8 @@ def test_dense_swarms_many_contacts():
         c = rng.uniform(-2, 2, 3) + [0, 0, 4]
         s0[32 * e:32 * e + 32, 0:3] = c + rng.uniform(-0.3, 0.3, size=(32, 3))
     w = w.with_(state0=s0.astype(np.float32))
-    st = teacher_forced(w, 200)
-    print("dense", st)
+    st = teacher_forced(w, 200, fused=fused)
+    print("dense", fused, st)
     assert st["contacts"] > 200
     assert st["max_err"] <= U.TOL
 
@@ -502,6 +505,63 @@ def test_knn_exact_ties_follow_index_order(sizes, k):
             assert [int(j) for j in nbr[q0, :6]] == [7, 1, 2, 3, 4, 5]
         q0 += n
     np.testing.assert_array_equal(obs, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_screen_keys_equal_own_neighbour_pass_bitwise(n):
+    """Swarms of 16 and more take a step_observe call's neighbour keys from
+    the last substep's partner screen; step followed by observe (no pair
+    pass in the observing call) selects over the swarm itself.  Both give
+    the same observation bit for bit: on randomly placed swarms, and on a
+    dyadic lattice resting on the floor with the motors off, where the
+    positions stay exact and distances tie exactly, so the rows must also
+    equal the oracle's bit for bit (reading R20, (distance, index) order)."""
+    w = W.custom([n] * 24, seed=40 + n, k=6, name="screen")
+    g = dev(w.goals)
+    s1, s2 = QuadSwarm.from_workload(w), QuadSwarm.from_workload(w)
+    for call in range(3):
+        a = dev(w.actions(call))
+        o1 = s1.step_observe(a, 2, g)
+        s2.step(a, 2)
+        o2 = s2.observe(g)
+        assert torch.equal(o1, o2), call
+        assert torch.equal(s1.get_state()[0], s2.get_state()[0]), call
+    s1.close()
+    s2.close()
+
+    sizes = [n] * 6
+    w = W.custom(sizes, seed=41, k=6, name="lattice")
+    st = w.state0.astype(np.float64).copy()
+    grid = np.array([[i, j] for i in range(8) for j in range(8)], float)[:n] * 0.25
+    for e in range(len(sizes)):
+        q0 = int(w.env_offsets[e])
+        st[q0:q0 + n, 0] = grid[:, 0] - 3.0
+        st[q0:q0 + n, 1] = grid[:, 1] - 3.0 + 1.0 * e
+        st[q0:q0 + n, 2] = 0.0
+        st[q0:q0 + n, W.SV:W.SV + 3] = 0.0
+        st[q0:q0 + n, W.SR:W.SR + 9] = np.eye(3).reshape(9)
+        st[q0:q0 + n, W.SW:W.SF] = 0.0  # body rates, rotor state, motor noise
+        st[q0:q0 + n, W.SF] = 1.0  # resting on the floor
+    goals = np.tile(np.array([0.5, -0.25, 1.5]), (w.n_quads, 1))
+    a = dev(-np.ones((w.n_quads, 4)))
+    outs = []
+    for fused in (True, False):
+        sim = QuadSwarm.from_workload(w)
+        sim.set_state(dev(st), 0)
+        if fused:
+            o = sim.step_observe(a, 2, dev(goals))
+        else:
+            sim.step(a, 2)
+            o = sim.observe(dev(goals))
+        x = sim.get_state()[0]
+        sim.sync()
+        outs.append((o.cpu().numpy(), x.cpu().numpy()))
+        sim.close()
+    (o1, x1), (o2, x2) = outs
+    np.testing.assert_array_equal(x1[:, 0:3], st[:, 0:3].astype(np.float32))
+    np.testing.assert_array_equal(o1, o2)
+    ref, _ = O.Oracle.from_workload(w).observe(x1.astype(np.float64), goals)
+    np.testing.assert_array_equal(o1, ref.astype(np.float32))
 
 
 def test_gpu_static_friction_under_tilted_thrust():
