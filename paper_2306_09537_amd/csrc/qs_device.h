@@ -549,8 +549,10 @@ __device__ __forceinline__ void wave_sync() {
 // data-parallel-primitive move, with no LDS.  quad_perm covers D = 1, 2, 3
 // within groups of 4 lanes; row_half_mirror (lane i of each group of 8 from
 // lane 7 - i, i.e. xor 7) composed with one of them covers D = 4 .. 7.
-// Every source lane lies inside the destination's own group of 8; a source
-// lane switched off in the exec mask yields `none`.
+// Every source lane lies inside the destination's own group of 8.  Callers
+// run it with every lane of the wavefront active (uniform control flow);
+// `none` is only the value a move would leave where no source lane were
+// available.
 template <int D>
 __device__ __forceinline__ float lane_xor8(float v, float none) {
   static_assert(D >= 1 && D <= 7, "partners within a group of 8 lanes");
