@@ -624,9 +624,10 @@ __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
 constexpr int XROW = 9;
 constexpr int TILE_ROWS_CO = XROW + 3;
 
-// Calls f(jj, pj) for every swarm-mate jj (itself included) with pj[0..2]
-// its post-motion position from rows XROW..XROW+2, read a chunk of
-// partners ahead of their arithmetic (chunk sizes as for_partners).
+// Calls f(jj, pj) for every swarm-mate jj (itself included), in increasing
+// jj, with pj[0..2] its post-motion position from rows XROW..XROW+2, read a
+// chunk of partners ahead of their arithmetic (chunk sizes as
+// for_partners).
 template <int BS, int N, typename T, typename F>
 __device__ __forceinline__ void for_partner_pos(T tile, int ls, int n, F&& f) {
   if constexpr (N > 0) {
@@ -788,11 +789,25 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
       rot &= full;
       cand = (M)(me == 0 ? rot : ((rot << me) | (rot >> (N - me))) & full);
     } else {
-      for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
-        const float d2 = sq_dist(pj, s.x);
-        cand |= d2 < thr ? (M)1 << jj : (M)0;
-        if constexpr (L > 0) knn_insert<L>(key, jj, me, d2);
-      });
+      if constexpr (N >= 16 && N <= 32) {
+        // partners arrive in index order, so the mask is accumulated as
+        // acc = 2 acc + bit (one add with carry per partner instead of a
+        // shifted bit, a select and an OR) and bit-reversed once: partner
+        // jj's bit lands at position N - 1 - jj, then at jj
+        uint32_t acc = 0u;
+        for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
+          const float d2 = sq_dist(pj, s.x);
+          acc = acc + acc + (d2 < thr ? 1u : 0u);
+          if constexpr (L > 0) knn_insert<L>(key, jj, me, d2);
+        });
+        cand = (M)(__builtin_bitreverse32(acc) >> (32 - N));
+      } else {
+        for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
+          const float d2 = sq_dist(pj, s.x);
+          cand |= d2 < thr ? (M)1 << jj : (M)0;
+          if constexpr (L > 0) knn_insert<L>(key, jj, me, d2);
+        });
+      }
     }
     const bool near_origin =
         fmaxf(fabsf(s.x[0]), fmaxf(fabsf(s.x[1]), fabsf(s.x[2]))) <= 1000.0f;
