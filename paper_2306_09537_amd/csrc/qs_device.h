@@ -776,7 +776,9 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
         for (int u = 0; u < 4; ++u) {
           const int o = o0 + u;
           const float dx = pj[u][0] - s.x[0], dy = pj[u][1] - s.x[1], dz = pj[u][2] - s.x[2];
-          const uint32_t h = dx * dx + dy * dy + dz * dz < thr ? 1u : 0u;
+          // the sign of d^2 - thr as one FMA chain (as in larger swarms);
+          // dx -> -dx leaves it unchanged, so both lanes of a pair agree
+          const uint32_t h = __float_as_uint(fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -thr)))) >> 31;
           rot |= h << o;
           if (o < N / 2) {
             const int src = base + ((me - o) & (N - 1));
@@ -790,15 +792,25 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
       cand = (M)(me == 0 ? rot : ((rot << me) | (rot >> (N - me))) & full);
     } else {
       if constexpr (N >= 16 && N <= 32) {
-        // partners arrive in index order, so the mask is accumulated as
-        // acc = 2 acc + bit (one add with carry per partner instead of a
-        // shifted bit, a select and an OR) and bit-reversed once: partner
-        // jj's bit lands at position N - 1 - jj, then at jj
+        // Partners arrive in index order, so the mask is accumulated as
+        // acc = 2 acc + bit and bit-reversed once: partner jj's bit lands at
+        // position N - 1 - jj, then at jj.  Without keys the bit is the sign
+        // of e = d^2 - thr, evaluated as one chain of three FMAs, shifted in
+        // by one funnel shift ((acc << 1) | (e >> 31), v_alignbit) instead of
+        // a product, a compare and an add with carry; e rounds differently
+        // from d^2 - thr by about an ulp of thr, far inside the 1 mm widening,
+        // and any extra survivor only meets the exact test.
         uint32_t acc = 0u;
         for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
-          const float d2 = sq_dist(pj, s.x);
-          acc = acc + acc + (d2 < thr ? 1u : 0u);
-          if constexpr (L > 0) knn_insert<L>(key, jj, me, d2);
+          if constexpr (L > 0) {
+            const float d2 = sq_dist(pj, s.x);
+            acc = acc + acc + (d2 < thr ? 1u : 0u);
+            knn_insert<L>(key, jj, me, d2);
+          } else {
+            const float dx = pj[0] - s.x[0], dy = pj[1] - s.x[1], dz = pj[2] - s.x[2];
+            const float e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -thr)));
+            acc = __builtin_amdgcn_alignbit(acc, __float_as_uint(e), 31u);
+          }
         });
         cand = (M)(__builtin_bitreverse32(acc) >> (32 - N));
       } else {
