@@ -619,25 +619,50 @@ __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
 }
 
 // Rows of the exchange tile that hold each quad's post-motion position
-// (x after walls and floor), written beside rows 0-8 by kernels whose
-// in-swarm pass screens partners on it (pair_pass with CO).
+// (x after walls and floor) and its squared norm, written beside rows 0-8 by
+// kernels whose in-swarm pass screens partners on it (pair_pass with CO).
 constexpr int XROW = 9;
-constexpr int TILE_ROWS_CO = XROW + 3;
+constexpr int XSQ = XROW + 3;
+constexpr int TILE_ROWS_CO = XROW + 4;
+// Positions (every coordinate, metres) within which the screen of swarms of
+// 16 and 32 uses the expanded squared distance; the room of the workloads
+// spans [-5, 5] x [-5, 5] x [0, 10].
+constexpr float SCREEN_BOX = 10.0f;
+
+// Swarm slots whose screen reads the squared norms (row XSQ).
+template <int N>
+constexpr bool kScreenSq = N >= 16 && N <= 32;
+
+// The screen rows of one lane: x and, SQ, |x|^2 (one expression, so every
+// kernel writes the same value), or, for a padding lane, a far-away
+// sentinel.
+template <bool SQ, typename T>
+__device__ __forceinline__ void put_screen_rows(T tile, int tid, const float x[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tile[XROW + k][tid] = x[k];
+  if constexpr (SQ) tile[XSQ][tid] = fmaf(x[2], x[2], fmaf(x[1], x[1], x[0] * x[0]));
+}
+template <bool SQ, typename T>
+__device__ __forceinline__ void put_screen_pad(T tile, int tid) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tile[XROW + k][tid] = 1e30f;
+  if constexpr (SQ) tile[XSQ][tid] = INFINITY;
+}
 
 // Calls f(jj, pj) for every swarm-mate jj (itself included), in increasing
-// jj, with pj[0..2] its post-motion position from rows XROW..XROW+2, read a
-// chunk of partners ahead of their arithmetic (chunk sizes as
-// for_partners).
-template <int BS, int N, typename T, typename F>
+// jj, with pj[0..2] its post-motion position from rows XROW..XROW+2 (and,
+// NR = 4, pj[3] its squared norm from row XSQ), read a chunk of partners
+// ahead of their arithmetic (chunk sizes as for_partners).
+template <int BS, int N, int NR = 3, typename T, typename F>
 __device__ __forceinline__ void for_partner_pos(T tile, int ls, int n, F&& f) {
   if constexpr (N > 0) {
     constexpr int CH = N < 8 ? N : (N >= 16 ? 4 : 8);
     auto chunk = [&](int j0) {
-      float pj[CH][3];
+      float pj[CH][NR];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) pj[u][r] = tile[XROW + r][ls + j0 + u];
+        for (int r = 0; r < NR; ++r) pj[u][r] = tile[XROW + r][ls + j0 + u];
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) f(j0 + u, pj[u]);
@@ -652,7 +677,9 @@ __device__ __forceinline__ void for_partner_pos(T tile, int ls, int n, F&& f) {
   } else {
     for (int jj = 0; jj < n; ++jj) {
       const int j = ls + jj;
-      const float pj[3] = {tile[XROW][j], tile[XROW + 1][j], tile[XROW + 2][j]};
+      float pj[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) pj[r] = tile[XROW + r][j];
       f(jj, pj);
     }
   }
@@ -748,6 +775,7 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   } else if constexpr (CO && !PEN) {
     const float dw = c.dcol + 1e-3f, thr = dw * dw;
     M cand = 0;
+    bool in_box = true;  // the expanded screen's domain (swarms of 16 and 32)
     if constexpr (N == 8) {
       // Each unordered pair screened once: the lane screens partner
       // me + o (mod N) for o = 1 .. N/2 and takes from lane me - o its
@@ -794,24 +822,38 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
       if constexpr (N >= 16 && N <= 32) {
         // Partners arrive in index order, so the mask is accumulated as
         // acc = 2 acc + bit and bit-reversed once: partner jj's bit lands at
-        // position N - 1 - jj, then at jj.  Without keys the bit is the sign
-        // of e = d^2 - thr, evaluated as one chain of three FMAs, shifted in
-        // by one funnel shift ((acc << 1) | (e >> 31), v_alignbit) instead of
-        // a product, a compare and an add with carry; e rounds differently
-        // from d^2 - thr by about an ulp of thr, far inside the 1 mm widening,
-        // and any extra survivor only meets the exact test.
+        // position N - 1 - jj, then at jj.
         uint32_t acc = 0u;
-        for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
-          if constexpr (L > 0) {
+        if constexpr (L > 0) {
+          for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
             const float d2 = sq_dist(pj, s.x);
             acc = acc + acc + (d2 < thr ? 1u : 0u);
             knn_insert<L>(key, jj, me, d2);
-          } else {
-            const float dx = pj[0] - s.x[0], dy = pj[1] - s.x[1], dz = pj[2] - s.x[2];
-            const float e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -thr)));
+          });
+        } else {
+          // Without keys the bit is the sign of
+          //   e = |b|^2 + (|a|^2 - thr_x) - 2 a.b  (= |a - b|^2 - thr_x),
+          // three FMAs and an add per partner (|b|^2 from row XSQ, the rest
+          // once per lane), shifted in by one funnel shift
+          // ((acc << 1) | (e >> 31), v_alignbit).  Rounding: |e - (|a - b|^2
+          // - thr_x)| <= 7 u ((|a| + |b|)^2 + thr_x), u = 2^-24.  For a lane
+          // with every |a_k| <= SCREEN_BOX and a partner in contact,
+          // |a| + |b| <= reach = 2 sqrt(3) SCREEN_BOX + d_col + 1 mm, so the
+          // widening thr_x - d_col^2 = 3 err, err = 7 u (reach^2 + d_col^2)
+          // (+1 %), exceeds the rounding three times over and no contact is
+          // dropped; a lane outside the box tests every partner exactly.
+          // An extra survivor only meets the exact test.
+          const float reach = 2.0f * 1.7320508f * SCREEN_BOX + c.dcol + 1e-3f;
+          const float err = 1.01f * 7.0f * 5.9604645e-8f * (reach * reach + c.dcol2);
+          const float thr_x = c.dcol2 + 3.0f * err;
+          const float na = fmaf(s.x[2], s.x[2], fmaf(s.x[1], s.x[1], fmaf(s.x[0], s.x[0], -thr_x)));
+          const float a0 = -2.0f * s.x[0], a1 = -2.0f * s.x[1], a2 = -2.0f * s.x[2];
+          for_partner_pos<BS, N, 4>(tile, ls, n, [&](int, const float* pj) {
+            const float e = fmaf(a2, pj[2], fmaf(a1, pj[1], fmaf(a0, pj[0], pj[3] + na)));
             acc = __builtin_amdgcn_alignbit(acc, __float_as_uint(e), 31u);
-          }
-        });
+          });
+          in_box = fmaxf(fabsf(s.x[0]), fmaxf(fabsf(s.x[1]), fabsf(s.x[2]))) <= SCREEN_BOX;
+        }
         cand = (M)(__builtin_bitreverse32(acc) >> (32 - N));
       } else {
         for_partner_pos<BS, N>(tile, ls, n, [&](int jj, const float* pj) {
@@ -823,7 +865,7 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
     }
     const bool near_origin =
         fmaxf(fabsf(s.x[0]), fmaxf(fabsf(s.x[1]), fabsf(s.x[2]))) <= 1000.0f;
-    if (!near_origin) cand = (M)(n >= 64 ? ~0ull : (1ull << n) - 1ull);
+    if (!(near_origin && in_box)) cand = (M)(n >= 64 ? ~0ull : (1ull << n) - 1ull);
     // the quad itself (distance 0) leaves the contact mask below anyway
     cand &= ~((M)1 << me);
     for (unsigned long long m = cand; m != 0ull; m &= m - 1ull) {

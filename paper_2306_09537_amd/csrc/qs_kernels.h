@@ -284,8 +284,8 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           tile[k][tid] = s.xo[k];
           tile[3 + k][tid] = s.inc[k];
           tile[6 + k][tid] = s.v[k];
-          tile[XROW + k][tid] = s.x[k];
         }
+        put_screen_rows<kScreenSq<NU>>(tile, tid, s.x);
       } else if constexpr (MAP == MAP_ITEM) {
         // padding lane: far away, so it is never in contact
 #pragma unroll
@@ -293,8 +293,8 @@ __device__ __forceinline__ void step_body(const Consts& c, const Ptrs& p,
           tile[k][tid] = 1e30f;
           tile[3 + k][tid] = 0.f;
           tile[6 + k][tid] = 0.f;
-          tile[XROW + k][tid] = 1e30f;
         }
+        put_screen_pad<kScreenSq<NU>>(tile, tid);
       }
       quad_sync();
       cmask = 0ull;

@@ -278,8 +278,8 @@ __global__ __launch_bounds__(BS) void recompute_kernel(const Consts* __restrict_
             tile[k][tid] = s.xo[k];
             tile[3 + k][tid] = s.inc[k];
             tile[6 + k][tid] = s.v[k];
-            tile[XROW + k][tid] = s.x[k];
           }
+          put_screen_rows<kScreenSq<N>>(tile, tid, s.x);
         }
         __syncthreads();
         float unused = 0.f;
@@ -425,8 +425,8 @@ __global__ __launch_bounds__(128) void recompute_pipe_kernel(const Consts* __res
             tile[k][tid] = s.xo[k];
             tile[3 + k][tid] = s.inc[k];
             tile[6 + k][tid] = s.v[k];
-            tile[XROW + k][tid] = s.x[k];
           }
+          put_screen_rows<kScreenSq<N>>(tile, tid, s.x);
         }
         wave_sync();
         float unused = 0.f;
@@ -1166,8 +1166,8 @@ __global__ __launch_bounds__(192) void rollout_pipe_kernel(const Consts* __restr
               tile[k][tid] = s.xo[k];
               tile[3 + k][tid] = s.inc[k];
               tile[6 + k][tid] = s.v[k];
-              tile[XROW + k][tid] = s.x[k];
             }
+            put_screen_rows<kScreenSq<kUnroll<N>>>(tile, tid, s.x);
           }
           wave_sync();
           if (live)

@@ -378,6 +378,50 @@ def test_partner_screen_keeps_every_contact(center):
     assert ties <= 2
 
 
+@pytest.mark.parametrize("center", [0.0, 9.5, 9.8, 9.95, 12.0, 990.0])
+def test_large_swarm_screen_keeps_every_contact(center):
+    """Swarms of 32 screen partners with the expanded squared distance
+    |b|^2 + (|a|^2 - thr) - 2 a.b, widened by three times its rounding bound,
+    for quads with every coordinate within 10 m; a quad further out tests
+    every partner exactly.  Chains of 32 whose links straddle d_col
+    (0.09 - 0.11 m), centred `center` metres along x (at 9 and 9.8 m the
+    chains cross the 10 m bound, so both kinds of lane meet in one swarm):
+    the contact sets equal the oracle's apart from pairs within 1e-6 m of
+    d_col."""
+    rng = np.random.default_rng(int(center * 10) + 77)
+    n_sw, n = 16, 32
+    q = n_sw * n
+    s = blank_state(q, z=5.0)
+    for e in range(n_sw):
+        pos = [np.array([center, -8.0 + e, 5.0])]
+        for _ in range(1, n):
+            u = rng.normal(size=3)
+            pos.append(pos[-1] + 0.1 * (1 + rng.uniform(-0.1, 0.1)) * u / np.linalg.norm(u))
+        s[e * n:(e + 1) * n, 0:3] = pos
+    s[:, W.SV:W.SV + 3] = rng.normal(0, 0.05, size=(q, 3))
+    s32 = s.astype(np.float32)
+    sizes = [n] * n_sw
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    sim = _custom_sim(s32, flags=W.QS_COLLIDE, sizes=sizes, gravity=0.0)
+    sim.record_contacts(True)
+    a = np.full((q, 4), -1.0, np.float32)
+    sim.step(dev(a), 1)
+    out = sim.get_state()[0].cpu().numpy().astype(np.float64)
+    c_gpu = sim.debug_contacts().cpu().numpy().view(np.uint64)
+    sim.sync()
+    sim.close()
+    orc = O.Oracle(offs, consts(gravity=0.0), nominal_params(q), 0, W.QS_COLLIDE, 3)
+    ref, c_ref, _, _ = orc.step(s32.astype(np.float64), a.astype(np.float64), 1, 0, margins=True)
+    n_contacts = int(sum(bin(int(x)).count("1") for x in c_ref))
+    assert n_contacts > q // 2, n_contacts
+    far = np.abs(out[:, 0:3]).max(axis=1) > 10.0
+    if center in (9.8, 9.95):
+        assert far.any() and (~far).any()
+    ties = U.check_contacts(c_gpu, c_ref, out[:, 0:3], ref[:, 0:3], offs.astype(np.int64), 0.1)
+    print(f"center {center} m: {n_contacts} contact bits, {int(far.sum())} lanes beyond 10 m, {ties} ties")
+    assert ties <= 2
+
+
 def test_high_spin_divergence_is_the_integrators():
     """The oracle's own pin (test_explicit_euler_diverges_at_high_spin): a
     torque-free symmetric top at 500 rad/s, whose transverse rate grows by
