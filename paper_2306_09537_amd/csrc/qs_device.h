@@ -577,10 +577,11 @@ using PairMask = typename std::conditional<(N > 0 && N <= 32), uint32_t,
                                            unsigned long long>::type;
 
 // Calls f(jj, pj) for every swarm-mate jj of the lane's swarm (itself
-// included), pj[0..5] being its start position and displacement from rows
-// 0-5 of the tile and pj[6] row XR (XR < 0: none).  For a compile-time swarm
-// size the reads go out a chunk of eight partners at a time, ahead of the
-// per-pair branches, so they overlap instead of waiting one by one.
+// included), in increasing jj, pj[0..5] being its start position and
+// displacement from rows 0-5 of the tile and pj[6] row XR (XR < 0: none).
+// For a compile-time swarm size the reads go out a chunk of eight partners
+// at a time, ahead of the per-pair branches, so they overlap instead of
+// waiting one by one.
 template <int BS, int N, int XR = -1, typename T, typename F>
 __device__ __forceinline__ void for_partners(T tile, int ls, int n, F&& f) {
   if constexpr (N > 0) {

@@ -450,13 +450,24 @@ __device__ __forceinline__ unsigned long long mark_contacts(const Consts& c, T t
                                                             float g_me, float pen3[3]) {
   const bool collide = (c.flags & F_COLLIDE) != 0;
   PairMask<N> cm32 = 0;
+  // Swarms of 16 and 32: partners arrive in index order, so the contact
+  // bits are shifted in ((acc << 1) | sign bit of d^2 - d_col^2, one funnel
+  // shift; for finite d^2 the sign of the difference is exactly the outcome
+  // of the comparison)
+  // and bit-reversed once, as in the forward screen.
+  constexpr bool ACC = N >= 16 && N <= 32;
+  uint32_t acc = 0u;
   auto mark = [&](int jj, const float* pj) {
     float dx, dy, dz, d2;
     const bool con = pair_geom_v(c, pj, s, dx, dy, dz, d2);
-    cm32 |= (collide & con) ? (PairMask<N>)1 << jj : (PairMask<N>)0;
+    if constexpr (ACC)
+      acc = __builtin_amdgcn_alignbit(acc, __float_as_uint(d2 - c.dcol2), 31u);
+    else
+      cm32 |= (collide & con) ? (PairMask<N>)1 << jj : (PairMask<N>)0;
     if constexpr (PEN) {
+      // the quad itself has d^2 = 0 exactly, so d^2 > 0 also leaves it out
       const float rd = __builtin_amdgcn_rsqf(d2);
-      const float coef = (jj != me && d2 > 0.f)
+      const float coef = d2 > 0.f
                              ? -0.5f * (g_me + pj[6]) * sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
                              : 0.f;
       pen3[0] = fmaf(coef, dx, pen3[0]);
@@ -465,6 +476,7 @@ __device__ __forceinline__ unsigned long long mark_contacts(const Consts& c, T t
     }
   };
   for_partners<BS, N, PEN ? 12 : -1>(tile, ls, n, mark);
+  if constexpr (ACC) cm32 = collide ? (PairMask<N>)(__builtin_bitreverse32(acc) >> (32 - N)) : 0;
   return (unsigned long long)(cm32 & ~((PairMask<N>)1 << me));  // not the quad itself
 }
 
