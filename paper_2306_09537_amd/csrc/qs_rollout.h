@@ -12,14 +12,15 @@
 
 namespace qs {
 
-// Partner count the forward rollout's in-swarm loop is unrolled for:
-// swarms of 16 and more loop one partner at a time at run time (its
-// penalty terms otherwise set a register count that limits the occupancy;
-// 6.4 -> 4.2 ms at 32768 x 32).  The backward kernels use chunks of eight
-// partners in a run-time loop for large swarms (for_partners), which
-// measured faster there (14.6 -> 13.0 ms).
-template <int N>
-constexpr int kUnroll = N < 16 ? N : 0;
+// Partner count the forward rollout's in-swarm loop is specialised for.
+// With the penalty, swarms of 16 and more take their partners in chunks of
+// four in a run-time loop (for_partners; 118 VGPRs at 32768 x 32, four
+// wavefronts per SIMD), which measured faster than one partner at a time
+// (forward 3.76 -> 3.43 ms; a fully unrolled loop had taken 6.4 ms against
+// 4.2 for one at a time).  Without the penalty the chunked loop would
+// cross 128 VGPRs, so those rollouts loop one partner at a time.
+template <int N, bool PEN>
+constexpr int kUnroll = (PEN || N < 16) ? N : 0;
 
 // Workgroup -> quads mapping shared by the kernels (see step_kernel).
 template <int BS, int N>
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(BS) void rollout_kernel(const Consts* __restrict__ 
           }
         }
         __syncthreads();
-        if (live) pair_pass<BS, kUnroll<N>, PEN>(c, tile, s, ls, n, me, (uint32_t)q, t, pacc, beta);
+        if (live) pair_pass<BS, kUnroll<N, PEN>, PEN>(c, tile, s, ls, n, me, (uint32_t)q, t, pacc, beta);
       }
     }
   }
@@ -1179,11 +1180,11 @@ __global__ __launch_bounds__(192) void rollout_pipe_kernel(const Consts* __restr
               tile[3 + k][tid] = s.inc[k];
               tile[6 + k][tid] = s.v[k];
             }
-            put_screen_rows<kScreenSq<kUnroll<N>>>(tile, tid, s.x);
+            put_screen_rows<kScreenSq<kUnroll<N, PEN>>>(tile, tid, s.x);
           }
           wave_sync();
           if (live)
-            pair_pass<BS, kUnroll<N>, PEN && !PW, !(PEN && !PW)>(c, tile, s, ls, n, me,
+            pair_pass<BS, kUnroll<N, PEN>, PEN && !PW, !(PEN && !PW)>(c, tile, s, ls, n, me,
                                                                 (uint32_t)q, t, pacc, beta);
         }
       }
@@ -1222,7 +1223,7 @@ __global__ __launch_bounds__(192) void rollout_pipe_kernel(const Consts* __restr
           so.xo[k] = tile[k][tid];
           so.inc[k] = tile[3 + k][tid];
         }
-        penalty_pass<BS, kUnroll<N>>(c, tile, so, ls, n, me, pacc, beta);
+        penalty_pass<BS, kUnroll<N, PEN>>(c, tile, so, ls, n, me, pacc, beta);
       }
       wg_sync();
     }
