@@ -755,14 +755,23 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
   // arithmetic): the contact set, the penalty and, when it is on (a uniform
   // choice between two loops), downwash.
   const float dw_r2 = c.dw_r2, dw_h = c.dw_h, dw_k1 = c.dw_k1, dw_k2 = c.dw_k2, dw_b1 = c.dw_b1;
-  auto pair = [&](int jj, const float* pj, auto with_dw) {
+  // In passes over every partner in index order (in_order), swarms of 16
+  // and 32 shift the contact bits in (the sign bit of d^2 - d_col^2, for
+  // finite d^2 exactly the comparison's outcome, by one funnel shift) and
+  // bit-reverse them once after the pass.
+  constexpr bool ACC = N >= 16 && N <= 32;
+  uint32_t acc = 0u;
+  auto pair = [&](int jj, const float* pj, auto with_dw, auto in_order) {
     float dx, dy, dz, d2;
     const bool con = pair_geom_v(c, pj, s, dx, dy, dz, d2);
     if constexpr (PEN) {
       const float sp = hb * softplus_hw(beta * (c.dcol - __builtin_amdgcn_sqrtf(d2)));
       pacc = jj != me ? pacc + sp : pacc;
     }
-    cm |= con ? (M)1 << jj : (M)0;
+    if constexpr (ACC && decltype(in_order)::value)
+      acc = __builtin_amdgcn_alignbit(acc, __float_as_uint(d2 - c.dcol2), 31u);
+    else
+      cm |= con ? (M)1 << jj : (M)0;
     if constexpr (decltype(with_dw)::value) {
       // swarm-mate j above (z_j - z_i = -dz) and overlapping in xy (never
       // the quad itself: dz = 0 there)
@@ -772,7 +781,9 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
     }
   };
   if (c.flags & F_DOWNWASH) {
-    for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, TrueT{}); });
+    for_partners<BS, N>(tile, ls, n,
+                        [&](int jj, const float* pj) { pair(jj, pj, TrueT{}, TrueT{}); });
+    if constexpr (ACC) cm = (M)(__builtin_bitreverse32(acc) >> (32 - N));
   } else if constexpr (CO && !PEN) {
     const float dw = c.dcol + 1e-3f, thr = dw * dw;
     M cand = 0;
@@ -873,10 +884,12 @@ __device__ __forceinline__ unsigned long long pair_pass(const Consts& c, const f
       const int jj = __builtin_ctzll(m);
       const int j = ls + jj;
       const float pj[6] = {tile[0][j], tile[1][j], tile[2][j], tile[3][j], tile[4][j], tile[5][j]};
-      pair(jj, pj, FalseT{});
+      pair(jj, pj, FalseT{}, FalseT{});
     }
   } else {
-    for_partners<BS, N>(tile, ls, n, [&](int jj, const float* pj) { pair(jj, pj, FalseT{}); });
+    for_partners<BS, N>(tile, ls, n,
+                        [&](int jj, const float* pj) { pair(jj, pj, FalseT{}, TrueT{}); });
+    if constexpr (ACC) cm = (M)(__builtin_bitreverse32(acc) >> (32 - N));
   }
   const unsigned long long cmask = collide ? (unsigned long long)(cm & ~((M)1 << me)) : 0ull;
   // The responses, for the partners in contact only, in partner order.
