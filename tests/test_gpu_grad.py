@@ -97,8 +97,14 @@ def gpu_grads(w, acts, nsub, Wt, gpen, ce):
     return out
 
 
-def test_rollout_forward_matches_steps_and_oracle_penalty():
-    w, acts, Wt, gpen = problem(0, 24)
+@pytest.mark.parametrize("n", [8, 32])
+def test_rollout_forward_matches_steps_and_oracle_penalty(n):
+    """The differentiable rollout (penalty on) reaches the state of repeated
+    steps bit for bit, checkpoints included, and the oracle's penalty; in
+    swarms of 32 the two take different routes to the same contact sets
+    (the rollout's pass over every partner, the steps' screen and exact
+    test)."""
+    w, acts, Wt, gpen = problem(0, 24, n=n)
     T, nsub, ce = 24, 2, 5
     sim = QuadSwarm.from_workload(w)
     ckpt = torch.empty((5, 27, w.n_quads), device="cuda")
