@@ -443,12 +443,12 @@ __global__ __launch_bounds__(128) void recompute_pipe_kernel(const Consts* __res
 // adjoint w.r.t. the quad's position,
 //   d pen / d x_i = -(g_i + g_j)/2 sigmoid(beta (d_col - d)) (x_i - x_j) / d,
 // summed over the partners in partner order into pen3 (added to lambda_x by
-// the caller).  g_me: the quad's penalty weight; row 12 of the tile holds
-// the partners' weights.
+// the caller).  h_me = -g_me/2, and row 12 of the tile holds -g_j/2 for the
+// partners (halving is exact, so h_me + h_j rounds as -(g_me + g_j)/2).
 template <int BS, int N, bool PEN, typename T>
 __device__ __forceinline__ unsigned long long mark_contacts(const Consts& c, T tile, const Quad& s,
                                                             int ls, int n, int me, float beta,
-                                                            float g_me, float pen3[3]) {
+                                                            float h_me, float pen3[3]) {
   const bool collide = (c.flags & F_COLLIDE) != 0;
   PairMask<N> cm32 = 0;
   // Swarms of 16 and 32: partners arrive in index order, so the contact
@@ -469,7 +469,7 @@ __device__ __forceinline__ unsigned long long mark_contacts(const Consts& c, T t
       // the quad itself has d^2 = 0 exactly, so d^2 > 0 also leaves it out
       const float rd = __builtin_amdgcn_rsqf(d2);
       const float coef = d2 > 0.f
-                             ? -0.5f * (g_me + pj[6]) * sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
+                             ? (h_me + pj[6]) * sigmoid_hw(beta * (c.dcol - d2 * rd)) * rd
                              : 0.f;
       pen3[0] = fmaf(coef, dx, pen3[0]);
       pen3[1] = fmaf(coef, dy, pen3[1]);
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(BS) void reverse_kernel(const Consts* __restrict__ 
     load_draws(c, tape + (long long)(n_steps - 1) * NTAPE * Q, Q, q, zn);
   }
   if constexpr (PEN) {
-    tl[12][tid] = live ? gpen[q] : 0.f;
+    tl[12][tid] = live ? -0.5f * gpen[q] : 0.f;  // -g/2 (mark_contacts)
   }
 
   // ---- reverse sweep
@@ -810,7 +810,7 @@ __global__ __launch_bounds__(256) void reverse_pipe_kernel(const Consts* __restr
   ParAdj pa;
   if (live) load_params(p, c, q, pp, pa);
   if (PEN && wave == 2) {
-    const float g = live ? gpen[q] : 0.f;
+    const float g = live ? -0.5f * gpen[q] : 0.f;  // -g/2 (mark_contacts)
 #pragma unroll
     for (int m = 0; m < 3; ++m) tl[m][12][tid] = g;
   }
